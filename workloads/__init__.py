@@ -1,0 +1,146 @@
+"""Seeded synthetic workloads shared by the tests, the oracle and the benchmark.
+
+This module only draws inputs and states problem parameters.  It contains none
+of the method's steps: no neighbour search, rate, outcome, controller or push
+arithmetic.  Random numbers are numpy PCG64 streams keyed by the seed.
+
+Workloads (stand-ins for the paper's coagulation tests and disk benchmark,
+whose own setups and data are not available):
+
+  const_box      4096 particles, uniform in a periodic unit cube, m = m0 = 1,
+                 equal particle masses, constant kernel, k = 32 (App. A test).
+  additive_col   65,536 particles, x, y uniform in a periodic unit square,
+                 z ~ N(0, 1), St_mid log-uniform 1e-4..1e-1, m ~ Gamma(2, 1),
+                 equal particle masses, additive kernel, k = 32, local settling.
+  disk3d         1,048,576 particles in a 3D annulus r in [10, 100] au with
+                 dN/dr constant (Sigma_g ~ r^-1), z/r ~ N(0, h_g = 0.05),
+                 uniform azimuth, grain diameter 2 um (radius 1 um), density
+                 1.6 g/cm^3, dust-to-gas 0.01, alpha = 1e-3, v_frag = 1 m/s,
+                 k = 32, Keplerian initial velocities.  cgs units.
+  disk3d_warm    as disk3d but grain radius log-uniform 1 um .. 1 mm (a builder
+                 addition that exercises fragmentation, erosion and grouping).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# cgs constants
+G_CGS = 6.67430e-8
+MSUN = 1.98847e33
+AU = 1.495978707e13
+YR = 3.15576e7
+M_H = 1.6735575e-24
+
+PHYS_KEYS = ("r", "th", "ph", "vr", "lth", "lph")
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# --------------------------------------------------------------------------- #
+def const_box_params(n: int = 4096, k: int = 32) -> dict:
+    return dict(name="const_box", kernel="const", k=k, n=n, t0=1.0, m0=1.0, eps=0.08,
+                dt_fn_max=0.01, dt_coll=0.01, t_end=10.0, periodic=(1, 1, 1), L=(1.0, 1.0, 1.0),
+                erosion=0, grouping=1, push="none")
+
+
+def const_box(seed: int, n: int = 4096) -> dict:
+    g = _rng(seed)
+    pos = g.random((3, n))
+    return dict(id=np.arange(n, dtype=np.uint32), x=pos[0], y=pos[1], z=pos[2],
+                M=np.full(n, 1.0 / n), m=np.ones(n))
+
+
+def additive_col_params(n: int = 65536, k: int = 32) -> dict:
+    return dict(name="additive_col", kernel="additive", k=k, n=n, t0=1.0, m0=1.0, eps=0.08,
+                dt_fn_max=0.2, dt_coll=0.2, n_intervals=100, periodic=(1, 1, 0), L=(1.0, 1.0, 1.0),
+                erosion=0, grouping=1, push="local")
+
+
+def additive_col(seed: int, n: int = 65536) -> dict:
+    g = _rng(seed)
+    x = g.random(n)
+    y = g.random(n)
+    z = g.standard_normal(n)
+    st = 10.0 ** g.uniform(-4.0, -1.0, n)
+    m = g.gamma(2.0, 1.0, n)
+    return dict(id=np.arange(n, dtype=np.uint32), x=x, y=y, z=z, vz=np.zeros(n), st_mid=st,
+                M=np.full(n, 1.0 / n), m=m)
+
+
+def disk3d_params(n: int = 1 << 20, k: int = 32, alpha: float = 1e-3, v_frag: float = 100.0) -> dict:
+    GM = G_CGS * MSUN
+    R0 = 10.0 * AU
+    r_in, r_out = 10.0 * AU, 100.0 * AU
+    m_gas = 0.01 * MSUN
+    # Sigma_g = Sigma_g0 (R/R0)^-1 holding m_gas between r_in and r_out
+    sigma_g0 = m_gas / (2.0 * math.pi * R0 * (r_out - r_in))
+    rho_s = 1.6
+    s0 = 2.0e-4  # reference (= minimum) grain diameter: radius 1 um
+    # Epstein midplane Stokes number of the reference grain at R0
+    st0 = math.pi * rho_s * s0 / (4.0 * sigma_g0)
+    period10 = 2.0 * math.pi / math.sqrt(GM / R0 ** 3)
+    return dict(name="disk3d", kernel="physical", k=k, n=n, eps=0.08,
+                dt_fn_max=period10 / 50.0, dt_coll=period10 / 50.0,
+                periodic=(0, 0, 0), L=(1.0, 1.0, 1.0), erosion=1, grouping=1, push="global",
+                rho_s=rho_s, s_min=s0, s0=s0, St0=st0, v_frag=v_frag, GM=GM, Sigma_g0=sigma_g0,
+                R0=R0, p=-1.0, q=-1.0, h_g0=0.05, alpha=alpha, mu_mH=2.34 * M_H, sigma_H2=2.0e-15,
+                r_in=r_in, r_out=r_out, drag=1, brownian=1, turbulence=1, caps=1,
+                dust_to_gas=0.01, m_gas=m_gas)
+
+
+def disk3d(seed: int, n: int = 1 << 20, warm: bool = False, params: dict | None = None) -> dict:
+    P = params or disk3d_params(n)
+    g = _rng(seed)
+    r = g.uniform(P["r_in"], P["r_out"], n)
+    ph = g.uniform(0.0, 2.0 * math.pi, n)
+    zeta = np.clip(g.normal(0.0, P["h_g0"], n), -0.9, 0.9)  # cos(theta) = z/r
+    th = np.arccos(zeta)
+    st = np.sin(th)
+    x = r * st * np.cos(ph)
+    y = r * st * np.sin(ph)
+    z = r * np.cos(th)
+    if warm:
+        a = 10.0 ** g.uniform(-4.0, -1.0, n)  # grain radius 1 um .. 1 mm
+        s = 2.0 * a
+    else:
+        s = np.full(n, P["s0"])
+    m = math.pi * P["rho_s"] * s ** 3 / 6.0  # grain mass of a sphere of diameter s
+    Md = P["dust_to_gas"] * P["m_gas"]
+    R = r * st
+    lph = np.sqrt(P["GM"] * R)  # Keplerian specific angular momentum
+    return dict(id=np.arange(n, dtype=np.uint32), x=x, y=y, z=z, r=r, th=th, ph=ph,
+                vr=np.zeros(n), lth=np.zeros(n), lph=lph, M=np.full(n, Md / n), m=m)
+
+
+def lattice_box(nside: int, jitter: float = 0.0, seed: int = 0) -> dict:
+    """Particles on a cubic lattice in the periodic unit cube (exact distance ties)."""
+    g = _rng(seed)
+    c = (np.arange(nside) + 0.5) / nside
+    X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
+    x, y, z = X.ravel(), Y.ravel(), Z.ravel()
+    if jitter:
+        x = x + jitter * g.standard_normal(x.size)
+        y = y + jitter * g.standard_normal(x.size)
+        z = z + jitter * g.standard_normal(x.size)
+    n = x.size
+    return dict(id=np.arange(n, dtype=np.uint32), x=x, y=y, z=z, M=np.full(n, 1.0 / n), m=np.ones(n))
+
+
+def by_name(name: str, seed: int, n: int | None = None):
+    """(params, state) of a named workload."""
+    if name == "const_box":
+        P = const_box_params(n or 4096)
+        return P, const_box(seed, P["n"])
+    if name == "additive_col":
+        P = additive_col_params(n or 65536)
+        return P, additive_col(seed, P["n"])
+    if name in ("disk3d", "disk3d_warm"):
+        P = disk3d_params(n or (1 << 20))
+        if name == "disk3d_warm":
+            P["name"] = "disk3d_warm"
+        return P, disk3d(seed, P["n"], warm=(name == "disk3d_warm"), params=P)
+    raise KeyError(name)
