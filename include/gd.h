@@ -1,0 +1,216 @@
+/*
+ * gd.h -- C ABI of the MI355X (gfx950) library for the collision hot path of
+ * the representative-particle dust model of Bi, "GameDev: GPU-accelerated
+ * model for dust evolution" (arXiv 2609.35967).
+ *
+ * One frozen-neighbour interval of the method is the sequence
+ *
+ *     gd_build_neighbors -> gd_collision_rates -> gd_sample_collisions -> gd_push
+ *
+ * (Sect. 2.5.1 neighbourhoods, Sect. 2.5.3 rates/plan/sampling, Sect. 2.3.3
+ * push).  All four enqueue work on one HIP stream and return at once.
+ *
+ * Conventions that hold for every call:
+ *  - Ownership: every array pointer in gd_particles, gd_neighbors and
+ *    gd_interval, and the workspace, is DEVICE memory owned by the caller.
+ *    The library never allocates or frees device memory and keeps no pointer
+ *    after a call returns.  Struct arguments themselves are read on the host
+ *    during the call only.
+ *  - Workspace: every call takes the caller's workspace of at least
+ *    gd_workspace_size() bytes, 256-byte aligned; it carries state between the
+ *    calls of one interval (Morton keys, tree, controller sums, status word),
+ *    so one workspace serves one run at a time.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = default
+ *    stream).  Calls on different streams with different workspaces and state
+ *    are independent.
+ *  - Return value: GD_OK, or a negative gd_status when the arguments are
+ *    rejected on the host (nothing is enqueued then) or a HIP launch fails.
+ *    Conditions found on the device are latched in the workspace status word
+ *    and read with gd_status_read (the only call that synchronises).
+ *  - gd_last_error() returns the calling thread's last host-side message.
+ *  - Floating point: FP64 throughout.  Positions, separations and the
+ *    dimensionless kernels use only +, -, *, / and sqrt, each rounded
+ *    separately (no fused multiply-add), so they are reproducible bit for bit.
+ */
+#ifndef GD_H
+#define GD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gd_status {
+    GD_OK = 0,
+    GD_E_INVALID_ARG = -1,   /* NULL or inconsistent argument */
+    GD_E_WORKSPACE = -2,     /* workspace NULL, misaligned or too small */
+    GD_E_HIP = -3,           /* a HIP runtime call or launch failed */
+    GD_E_NONFINITE = -4,     /* device: non-finite mass or position met */
+    GD_E_LOG_OVERFLOW = -5,  /* device: event log truncated (results valid) */
+    GD_E_UNSUPPORTED = -6    /* option outside what this build supports */
+} gd_status;
+
+/* Device status-word bits (gd_status_read returns their OR). */
+#define GD_DEV_NONFINITE 0x1      /* a non-finite input was met */
+#define GD_DEV_LOG_OVERFLOW 0x2   /* a particle had more events than log_cap */
+#define GD_DEV_KNN_FALLBACK 0x4   /* kNN used its slow exact tie path (info only) */
+#define GD_DEV_TICK_FLOOR 0x8     /* dt_req fell below one tick; one tick executed */
+#define GD_DEV_MASS_RANGE 0x10    /* a grain mass fell outside the 2^-64..2^64 bin range */
+#define GD_DEV_INTERNAL 0x20      /* an internal consistency check failed (bad tree or neighbour index) */
+#define GD_DEV_EVENT_CAP 0x40     /* a particle reached 2^24 events in one interval and stopped there */
+
+typedef enum gd_kernel {
+    GD_KERNEL_CONST = 0,     /* K = 1                 (App. A, constant kernel) */
+    GD_KERNEL_ADDITIVE = 1,  /* K = (m_i + m_j)/m0    (App. A, linear kernel)   */
+    GD_KERNEL_PRODUCT = 2,   /* K = m_i m_j / m0^2    (App. A, product kernel)  */
+    GD_KERNEL_PHYSICAL = 3   /* K = pi (s_i+s_j)^2 dv/4 (eq:kernel), eq:rate      */
+} gd_kernel;
+
+typedef enum gd_push_kind {
+    GD_PUSH_NONE = 0,
+    GD_PUSH_LOCAL = 1,       /* vertical settling in a local column (Omega = H = 1) */
+    GD_PUSH_GLOBAL = 2       /* spherical staggered semi-analytic push (Sect. 2.3.3) */
+} gd_push_kind;
+
+/* Problem description (host struct, read during each call). */
+typedef struct gd_problem {
+    int64_t n;            /* length of every particle array */
+    int32_t k;            /* N_K: neighbours per particle including itself, 2..64 */
+    int32_t kernel;       /* gd_kernel */
+    int32_t push;         /* gd_push_kind */
+    int32_t nbin_min;     /* minimum particles per merged controller bin (0: max(2k, 64)) */
+    int32_t erosion;      /* 1: erosion outcome for psi <= 0.1 (Sect. 2.5.2) */
+    int32_t grouping;     /* 1: group small increments, N_coll = floor(1e-4/psi) */
+    int32_t periodic[3];  /* 1: minimum-image separation on that axis */
+    double L[3];          /* period of each periodic axis; positions in [0, L) */
+    double rmax;          /* maximum search scale (INFINITY: none) */
+    double t0, m0;        /* dimensionless kernels: unit time and mass (Sect. 3.3) */
+    double eps;           /* tolerance epsilon of the interval controller */
+    double dt_fn_max;     /* maximum frozen-neighbour interval */
+    double rho_s;         /* grain internal density */
+    double s_min;         /* minimum grain diameter of fragments (eq:frag) */
+    double v_frag;        /* fragmentation speed: dv >= v_frag is fast (INFINITY: sticking only) */
+    double GM;            /* gravitational parameter of the star */
+    double Sigma_g0, R0, p, q, h_g0;  /* gas disk (Sect. 2.2) */
+    double alpha;         /* turbulence parameter */
+    double mu_mH;         /* mean molecular mass (k_B T = mu_mH c_s^2) */
+    double sigma_H2;      /* molecular cross section (mean free path) */
+    double s0, St0;       /* reference diameter and its Stokes number at R0, midplane */
+    double r_in, r_out;   /* spherical domain (boundary caps, outflow) */
+    int32_t drag;         /* global push: 1 = gas drag on */
+    int32_t brownian;     /* 1: Brownian term in dv (eq:dv) */
+    int32_t turbulence;   /* 1: turbulent term in dv (Ormel & Cuzzi 2007) */
+    int32_t caps;         /* 1: subtract boundary caps from V_i */
+} gd_problem;
+
+/* Particle state, structure of arrays, device pointers, length n.
+ * id, x, y, z, M and m[0..1] are always required.  r..lph are required for
+ * GD_PUSH_GLOBAL, vz and st_mid for GD_PUSH_LOCAL; set unused ones to NULL.
+ * M_i <= 0 marks an inactive particle (no neighbours, no events, not pushed).
+ * m[cur] is the grain mass of the current interval; m[cur ^ 1] receives the
+ * masses after sampling. */
+typedef struct gd_particles {
+    uint32_t* id;                   /* identity (keys the random streams) */
+    double *x, *y, *z;              /* Cartesian positions */
+    double *r, *th, *ph;            /* spherical position (global push) */
+    double *vr, *lth, *lph;         /* y = (v_r, l_theta, l_phi) (global push) */
+    double *vz, *st_mid;            /* local column: v_z and midplane Stokes number */
+    double* M;                      /* particle mass M_i = N_i m_i */
+    double* m[2];                   /* grain mass, double buffer */
+    int32_t cur;                    /* which m buffer is current (0 or 1) */
+} gd_particles;
+
+/* Neighbourhoods (Sect. 2.5.1), device pointers, indices are slots of the
+ * Morton-ordered state written by gd_build_neighbors. */
+typedef struct gd_neighbors {
+    int32_t* nbr;       /* [n * k]: row i = i itself, then the retained others in
+                           ascending slot order, then -1 padding */
+    int32_t* cnt;       /* [n]: 1 + number of retained others (0: inactive) */
+    double* dmax;       /* [n]: distance to the farthest retained neighbour (d_i) */
+    int32_t* n_active;  /* [1]: active particles; they occupy slots 0..n_active-1 */
+} gd_neighbors;
+
+/* Interval state, one struct in DEVICE memory (initialise with
+ * gd_interval_init).  The collision step dt_coll holds 2^30 ticks. */
+typedef struct gd_interval {
+    double dt_coll;       /* collision time step split into intervals */
+    double dt_req;        /* requested interval (written by gd_collision_rates) */
+    double dt_exe;        /* executed interval (written by gd_collision_rates) */
+    double C;             /* adaptive safety factor, 0.25..1 */
+    double time;          /* simulated time advanced by executed intervals */
+    int64_t ticks;        /* ticks elapsed in the current collision step */
+    int64_t exe_ticks;    /* ticks of the planned interval */
+    int64_t n_intervals;  /* intervals completed */
+    int64_t n_events;     /* collision events in the last sampled interval */
+    double audit_worst;   /* largest realised mean |ln(s'/s)| of the last audit */
+    int32_t n_groups;     /* merged controller bins of the last plan */
+    int32_t pad;
+} gd_interval;
+
+/* Bytes of workspace needed for problem p (writes *bytes). */
+int32_t gd_workspace_size(const gd_problem* p, size_t* bytes);
+
+/* Set *iv (device) to dt_coll, C = 1, zero ticks/time/counters. */
+int32_t gd_interval_init(gd_interval* iv, double dt_coll, void* stream);
+
+/* Neighbourhoods (Sect. 2.5.1).  Sorts the active particles of `in` into
+ * Morton order (10 bits per axis in the cube spanned by the active particles;
+ * stable; inactive last) and writes the permuted copy of EVERY non-NULL array
+ * of `in` (and m[in->cur]) into `out` (which must not alias `in`; out->cur is
+ * set equal to in->cur).  Then, on the Morton-ordered state, for each active
+ * slot i: nbr row = i, then the k-1 nearest other active particles with
+ * d^2 <= rmax^2, nearest first by (d^2, slot), written in ascending slot order;
+ * d^2 = (dx*dx + dy*dy) + dz*dz with minimum image on periodic axes
+ * (d > L/2: d - L; d < -L/2: d + L).  Exact: no approximation in the search. */
+int32_t gd_build_neighbors(const gd_problem* p, const gd_particles* in, gd_particles* out,
+                           const gd_neighbors* nb, void* ws, size_t ws_bytes, void* stream);
+
+/* Rates over the frozen neighbourhood and the interval plan (Sect. 2.5.1-2.5.3).
+ * Snapshot = m[st->cur].  Per active particle: lambda*_i (the slot-order sum of
+ * the pairs' effective rates) into lam_i [n]; optional per-pair lambda*_ij into
+ * lam_pair [n*k] and controller moments a_i, b_i into ab [2n] (a then b).  Then
+ * bins of ilogb(m), merged to >= nbin_min particles, A_b, B_b, dt_req and the
+ * dyadic executed interval are written into *iv on the device. */
+int32_t gd_collision_rates(const gd_problem* p, const gd_particles* st, const gd_neighbors* nb,
+                           gd_interval* iv, double* lam_i, double* lam_pair, double* ab,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* Monte Carlo sampling over the planned interval (Sect. 2.5.3).  Reads
+ * m[st->cur] (frozen neighbours and own start state) and lam_i from
+ * gd_collision_rates; writes m[st->cur ^ 1] and, if non-NULL, the event count
+ * per particle into n_events [n] and a per-particle event log into log
+ * [n * log_cap] (entry = slot | channel << 16 | outcome << 24; -1 unused).
+ * Random numbers: Philox4x32-10, key = seed, counters (id, interval_index,
+ * event, 0 / 1).  Afterwards the safety factor C is audited and the ticks and
+ * time advance by the executed interval.  The caller then flips st->cur
+ * (the broadcast).  interval_index must be < 2^32. */
+int32_t gd_sample_collisions(const gd_problem* p, const gd_particles* st, const gd_neighbors* nb,
+                             gd_interval* iv, const double* lam_i, uint64_t seed,
+                             uint64_t interval_index, int32_t* n_events, int32_t* log,
+                             int32_t log_cap, void* ws, size_t ws_bytes, void* stream);
+
+/* Push (Sect. 2.3.3) of every active particle over iv->dt_exe (iv non-NULL,
+ * read on the device) or over dt (iv NULL).  GD_PUSH_LOCAL: z, vz by
+ * drift-kick-drift with exact drag for the force at the drifted position,
+ * t_s = st_mid exp(z^2/2).  GD_PUSH_GLOBAL: spherical state and Cartesian
+ * x, y, z; the grain size comes from m[st->cur]; particles leaving
+ * [r_in, r_out] get M = 0 (inactive). */
+int32_t gd_push(const gd_problem* p, const gd_particles* st, const gd_interval* iv, double dt,
+                void* ws, size_t ws_bytes, void* stream);
+
+/* Copy the device status word of the workspace to *out (bits GD_DEV_*), then
+ * clear it.  Synchronises `stream`. */
+int32_t gd_status_read(void* ws, void* stream, int32_t* out);
+
+/* Last host-side error message of the calling thread ("" if none). */
+const char* gd_last_error(void);
+
+/* Library version string. */
+const char* gd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GD_H */

@@ -97,12 +97,12 @@ def lib():
             L.orc_morton_keys.argtypes = [i64, vp, vp, vp, vp, vp]
             L.orc_knn.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp]
             L.orc_frag_moments.argtypes = [d, d, vp, vp]
-            L.orc_rates.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+            L.orc_rates.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
             L.orc_bin_of.argtypes = [d]
             L.orc_bin_of.restype = C.c_int32
             L.orc_plan.argtypes = [vp, i64, vp, vp, vp, vp, d, i64, d, vp, vp, vp, vp]
-            L.orc_mc.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, d, C.c_uint64, C.c_uint32,
-                                 vp, vp, vp, C.c_int32, vp, vp, vp]
+            L.orc_mc.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, d, C.c_uint64,
+                                 C.c_uint32, vp, vp, vp, C.c_int32, vp, vp, vp]
             L.orc_audit.argtypes = [vp, i64, vp, vp, vp, vp, vp, d, vp]
             L.orc_push_local.argtypes = [i64, vp, vp, vp, vp, d]
             L.orc_push_global.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, d]
@@ -176,17 +176,20 @@ def frag_moments(s_i: float, s_min: float):
     return a.value, b.value
 
 
-def rates(P: Problem, nbr, cnt, dmax, m_snap, M, x, y, z, want_pairs=False):
+def rates(P: Problem, nbr, cnt, dmax, m_snap, M, x, y, z, want_pairs=False, queries=None):
+    """Rates of every slot, or of the slots in `queries` (outputs in query order)."""
     n = len(cnt)
     nbr = _c(nbr, np.int32)
     cnt = _c(cnt, np.int32)
     dmax, m_snap, M, x, y, z = (_c(a, np.float64) for a in (dmax, m_snap, M, x, y, z))
-    lam = np.zeros(n)
-    a = np.zeros(n)
-    b = np.zeros(n)
-    pairs = np.zeros((n, P.k)) if want_pairs else None
-    lib().orc_rates(C.byref(P), n, _p(nbr), _p(cnt), _p(dmax), _p(m_snap), _p(M), _p(x), _p(y), _p(z),
-                    _p(lam), _p(a), _p(b), _p(pairs))
+    q = None if queries is None else _c(queries, np.int64)
+    nq = n if q is None else len(q)
+    lam = np.zeros(nq)
+    a = np.zeros(nq)
+    b = np.zeros(nq)
+    pairs = np.zeros((nq, P.k)) if want_pairs else None
+    lib().orc_rates(C.byref(P), n, nq, _p(q), _p(nbr), _p(cnt), _p(dmax), _p(m_snap), _p(M), _p(x), _p(y),
+                    _p(z), _p(lam), _p(a), _p(b), _p(pairs))
     return lam, a, b, pairs
 
 
@@ -207,8 +210,11 @@ def plan(P: Problem, m_snap, M, a, b, dt_coll: float, ticks: int, Cfac: float):
                 group_of=group_of, gM=gM)
 
 
-def mc(P: Problem, ids, nbr, cnt, dmax, m_snap, M, x, y, z, dt_exe, seed, interval, log_cap=0):
-    n = len(cnt)
+def mc(P: Problem, ids, nbr, cnt, dmax, m_snap, M, x, y, z, dt_exe, seed, interval, log_cap=0, queries=None):
+    """Sampling of every slot, or of the slots in `queries` (outputs in query order)."""
+    n_all = len(cnt)
+    q = None if queries is None else _c(queries, np.int64)
+    n = n_all if q is None else len(q)
     ids = _c(ids, np.uint32)
     nbr = _c(nbr, np.int32)
     cnt = _c(cnt, np.int32)
@@ -221,7 +227,8 @@ def mc(P: Problem, ids, nbr, cnt, dmax, m_snap, M, x, y, z, dt_exe, seed, interv
         ls = np.full((n, log_cap), -1, np.int32)
         lc = np.full((n, log_cap), -1, np.int32)
         lt = np.full((n, log_cap), -1, np.int32)
-    lib().orc_mc(C.byref(P), n, _p(ids), _p(nbr), _p(cnt), _p(dmax), _p(m_snap), _p(M), _p(x), _p(y), _p(z),
+    lib().orc_mc(C.byref(P), n_all, n, _p(q), _p(ids), _p(nbr), _p(cnt), _p(dmax), _p(m_snap), _p(M), _p(x),
+                 _p(y), _p(z),
                  float(dt_exe), C.c_uint64(seed), int(interval) & 0xFFFFFFFF, _p(m_out), _p(ev), _p(tie),
                  int(log_cap), _p(ls), _p(lc), _p(lt))
     return dict(m=m_out, events=ev, near_tie=tie.astype(bool), log_slot=ls, log_chan=lc, log_type=lt)

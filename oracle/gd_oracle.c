@@ -364,13 +364,18 @@ static double grain_size(const orc_problem* P, double m)
 
 /* Turbulent relative velocity squared, Ormel & Cuzzi (2007) closed forms:
  * tightly coupled (St1 < Re^-1/2), intermediate (Re^-1/2 <= St1 < 1) with
- * y_a = 1.6, heavy (St1 >= 1).  St1 >= St2. */
-static double oc07_dv2(double St1, double St2, double Vg2, double tke)
+ * y_a = 1.6, heavy (St1 >= 1).  St1 >= St2, dSt = St1 - St2 >= 0.
+ * The tightly coupled form
+ *   Vg^2 (St1 - St2)/(St1 + St2) [St1^2/(St1 + t) - St2^2/(St2 + t)]
+ * is evaluated as the algebraically equal
+ *   Vg^2 dSt^2 [St1 St2 + t (St1 + St2)] / [(St1 + St2)(St1 + t)(St2 + t)],
+ * which does not cancel when St1 and St2 are close. */
+static double oc07_dv2(double St1, double St2, double dSt, double Vg2, double tke)
 {
     if (St1 < tke) {
-        double a = St1 * St1 / (St1 + tke);
-        double b = St2 * St2 / (St2 + tke);
-        return Vg2 * ((St1 - St2) / (St1 + St2)) * (a - b);
+        double num = St1 * St2 + tke * (St1 + St2);
+        double den = (St1 + St2) * (St1 + tke) * (St2 + tke);
+        return Vg2 * (dSt * dSt) * num / den;
     }
     if (St1 < 1.0) {
         const double ya = 1.6;
@@ -457,14 +462,22 @@ static void pair_eval(const orc_problem* P, const orc_qctx* c, double mi, double
         si = grain_size(P, mi);
         sj = grain_size(P, mj);
         double Sti = c->g.stfac * si;
-        double Stj = Sti * (sj / si);          /* St_j at the query position */
+        double Stj = c->g.stfac * sj;          /* = St_i s_j/s_i at the query position */
+        /* St_i - St_j from the mass difference: s_i - s_j = (6/(pi rho)) (m_i - m_j)/(s_i^2 + s_i s_j + s_j^2),
+         * so nearly equal grains do not cancel */
+        double ds = (6.0 / (ORC_PI * P->rho_s)) * (mi - mj) / (si * si + si * sj + sj * sj);
+        double dSt = c->g.stfac * ds;
         double OR = c->g.OmK;
         double Rq = c->R;
-        double ai = Sti / (1.0 + Sti * Sti), aj = Stj / (1.0 + Stj * Stj);
-        double bi = 1.0 / (1.0 + Sti * Sti), bj = 1.0 / (1.0 + Stj * Stj);
-        double dvR = 2.0 * c->g.eta * Rq * OR * (ai - aj);
-        double dvZ = c->Z * OR * (fmin(Sti, 0.5) - fmin(Stj, 0.5));
-        double dvP = c->g.eta * Rq * OR * (bi - bj);
+        double qi = 1.0 + Sti * Sti, qj = 1.0 + Stj * Stj;
+        /* St_i/(1+St_i^2) - St_j/(1+St_j^2) and 1/(1+St_i^2) - 1/(1+St_j^2), factored through dSt */
+        double da = dSt * (1.0 - Sti * Stj) / (qi * qj);
+        double db = -dSt * (Sti + Stj) / (qi * qj);
+        double dvR = 2.0 * c->g.eta * Rq * OR * da;
+        double zi = fmin(Sti, 0.5), zj = fmin(Stj, 0.5);
+        double dz = (Sti < 0.5 && Stj < 0.5) ? dSt : zi - zj;
+        double dvZ = c->Z * OR * dz;
+        double dvP = c->g.eta * Rq * OR * db;
         double dvB = 0.0, dvT2 = 0.0;
         if (P->brownian) {
             dvB = sqrt(c->kT8pi * (1.0 / mi + 1.0 / mj));
@@ -472,7 +485,7 @@ static void pair_eval(const orc_problem* P, const orc_qctx* c, double mi, double
         }
         if (P->turbulence) {
             double St1 = Sti >= Stj ? Sti : Stj, St2 = Sti >= Stj ? Stj : Sti;
-            dvT2 = oc07_dv2(St1, St2, c->Vg2, c->tke);
+            dvT2 = oc07_dv2(St1, St2, fabs(dSt), c->Vg2, c->tke);
         }
         double dv2 = dvR * dvR + dvZ * dvZ;
         dv2 = dv2 + dvP * dvP;
@@ -553,14 +566,21 @@ static void pair_eval(const orc_problem* P, const orc_qctx* c, double mi, double
 /* lambda*_i = sum over slots (in slot order) of lambda*_ij;                */
 /* a_i = sum_j sum_o lambda*_o <J_o>, b_i = sum_j sum_o lambda*_o <J_o^2>.   */
 /* ------------------------------------------------------------------------ */
-void orc_rates(const orc_problem* P, int64_t n, const int32_t* nbr, const int32_t* cnt,
+void orc_rates(const orc_problem* P, int64_t n, int64_t nq, const int64_t* qidx,
+               const int32_t* nbr, const int32_t* cnt,
                const double* dmax, const double* m_snap, const double* M,
                const double* x, const double* y, const double* z,
-               double* lam_i, double* a_i, double* b_i, double* lam_pair)
+               double* lam_out, double* a_out, double* b_out, double* lam_pair_out)
 {
     const int k = P->k;
+    (void)n;
 #pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t i = 0; i < n; i++) {
+    for (int64_t t = 0; t < nq; t++) {
+        const int64_t i = qidx ? qidx[t] : t;   /* query slot; outputs at row t */
+        double* lam_pair = lam_pair_out ? lam_pair_out + t * k - i * k : NULL;
+        double* lam_i = lam_out + t - i;
+        double* a_i = a_out + t - i;
+        double* b_i = b_out + t - i;
         if (lam_pair) for (int s = 0; s < k; s++) lam_pair[i * k + s] = 0.0;
         double li = 0.0;
         orc_xsum sa, sb; xsum_init(&sa); xsum_init(&sb);
@@ -712,21 +732,30 @@ void orc_plan(const orc_problem* P, int64_t n, const double* m_snap, const doubl
 /* Event log (optional): per particle up to log_cap entries of              */
 /* (slot, channel, outcome type).                                            */
 /* ------------------------------------------------------------------------ */
-void orc_mc(const orc_problem* P, int64_t n, const uint32_t* id, const int32_t* nbr, const int32_t* cnt,
+void orc_mc(const orc_problem* P, int64_t n, int64_t nq, const int64_t* qidx,
+            const uint32_t* id, const int32_t* nbr, const int32_t* cnt,
             const double* dmax, const double* m_snap, const double* M,
             const double* x, const double* y, const double* z,
             double dt_exe, uint64_t seed, uint32_t interval,
-            double* m_out, int32_t* n_events, uint8_t* near_tie,
-            int32_t log_cap, int32_t* log_slot, int32_t* log_chan, int32_t* log_type)
+            double* m_res, int32_t* ev_res, uint8_t* tie_res,
+            int32_t log_cap, int32_t* log_slot_res, int32_t* log_chan_res, int32_t* log_type_res)
 {
     const int k = P->k;
+    (void)n;
 #pragma omp parallel
     {
         double* lam = (double*)malloc(sizeof(double) * (size_t)k);
         double* pre = (double*)malloc(sizeof(double) * (size_t)k);
         orc_pair* pr = (orc_pair*)malloc(sizeof(orc_pair) * (size_t)k);
 #pragma omp for schedule(dynamic, 16)
-        for (int64_t i = 0; i < n; i++) {
+        for (int64_t t_ = 0; t_ < nq; t_++) {
+            const int64_t i = qidx ? qidx[t_] : t_;   /* query slot; outputs at row t_ */
+            double* m_out = m_res + t_ - i;
+            int32_t* n_events = ev_res + t_ - i;
+            uint8_t* near_tie = tie_res + t_ - i;
+            int32_t* log_slot = log_slot_res ? log_slot_res + (t_ - i) * (int64_t)log_cap : NULL;
+            int32_t* log_chan = log_chan_res ? log_chan_res + (t_ - i) * (int64_t)log_cap : NULL;
+            int32_t* log_type = log_type_res ? log_type_res + (t_ - i) * (int64_t)log_cap : NULL;
             double m = m_snap[i];
             int32_t e = 0;
             uint8_t tie = 0;
@@ -968,7 +997,7 @@ void orc_gas_at(const orc_problem* P, double R, double Z, double* out)
     out[5] = g.rhog; out[6] = g.eta; out[7] = g.vgphi; out[8] = g.stfac;
 }
 
-double orc_oc07(double St1, double St2, double Vg2, double tke) { return oc07_dv2(St1, St2, Vg2, tke); }
+double orc_oc07(double St1, double St2, double Vg2, double tke) { return oc07_dv2(St1, St2, St1 - St2, Vg2, tke); }
 
 int orc_num_threads(void)
 {

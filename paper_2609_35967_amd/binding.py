@@ -1,0 +1,276 @@
+"""Thin ctypes binding of libgd.so (include/gd.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  PyTorch provides device memory and the stream.  The library must
+be built (``paper_2609_35967_amd.build``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgd.so")
+
+GD_OK = 0
+KERNELS = {"const": 0, "additive": 1, "product": 2, "physical": 3}
+PUSH = {"none": 0, "local": 1, "global": 2}
+DEV_BITS = {"nonfinite": 0x1, "log_overflow": 0x2, "knn_fallback": 0x4, "tick_floor": 0x8, "mass_range": 0x10,
+            "internal": 0x20, "event_cap": 0x40}
+T_TICKS = 1 << 30
+
+
+class GdProblem(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("k", C.c_int32), ("kernel", C.c_int32), ("push", C.c_int32), ("nbin_min", C.c_int32),
+        ("erosion", C.c_int32), ("grouping", C.c_int32), ("periodic", C.c_int32 * 3), ("L", C.c_double * 3),
+        ("rmax", C.c_double), ("t0", C.c_double), ("m0", C.c_double), ("eps", C.c_double), ("dt_fn_max", C.c_double),
+        ("rho_s", C.c_double), ("s_min", C.c_double), ("v_frag", C.c_double), ("GM", C.c_double),
+        ("Sigma_g0", C.c_double), ("R0", C.c_double), ("p", C.c_double), ("q", C.c_double), ("h_g0", C.c_double),
+        ("alpha", C.c_double), ("mu_mH", C.c_double), ("sigma_H2", C.c_double), ("s0", C.c_double),
+        ("St0", C.c_double), ("r_in", C.c_double), ("r_out", C.c_double), ("drag", C.c_int32),
+        ("brownian", C.c_int32), ("turbulence", C.c_int32), ("caps", C.c_int32),
+    ]
+
+
+class GdParticles(C.Structure):
+    _fields_ = [
+        ("id", C.c_void_p), ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
+        ("r", C.c_void_p), ("th", C.c_void_p), ("ph", C.c_void_p),
+        ("vr", C.c_void_p), ("lth", C.c_void_p), ("lph", C.c_void_p),
+        ("vz", C.c_void_p), ("st_mid", C.c_void_p), ("M", C.c_void_p),
+        ("m", C.c_void_p * 2), ("cur", C.c_int32),
+    ]
+
+
+class GdNeighbors(C.Structure):
+    _fields_ = [("nbr", C.c_void_p), ("cnt", C.c_void_p), ("dmax", C.c_void_p), ("n_active", C.c_void_p)]
+
+
+class GdInterval(C.Structure):
+    _fields_ = [
+        ("dt_coll", C.c_double), ("dt_req", C.c_double), ("dt_exe", C.c_double), ("C", C.c_double),
+        ("time", C.c_double), ("ticks", C.c_int64), ("exe_ticks", C.c_int64), ("n_intervals", C.c_int64),
+        ("n_events", C.c_int64), ("audit_worst", C.c_double), ("n_groups", C.c_int32), ("pad", C.c_int32),
+    ]
+
+
+EXPORTS = ("gd_workspace_size", "gd_interval_init", "gd_build_neighbors", "gd_collision_rates",
+           "gd_sample_collisions", "gd_push", "gd_status_read", "gd_last_error", "gd_version")
+
+_lib = None
+
+
+class GdError(RuntimeError):
+    pass
+
+
+def load(path: str | None = None):
+    """Load libgd.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise GdError(f"{p} is missing: build it with `python -m paper_2609_35967_amd.build` "
+                      "(no CPU fallback exists)")
+    L = C.CDLL(p)
+    vp = C.c_void_p
+    L.gd_workspace_size.argtypes = [C.POINTER(GdProblem), C.POINTER(C.c_size_t)]
+    L.gd_interval_init.argtypes = [vp, C.c_double, vp]
+    L.gd_build_neighbors.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.POINTER(GdParticles),
+                                     C.POINTER(GdNeighbors), vp, C.c_size_t, vp]
+    L.gd_collision_rates.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.POINTER(GdNeighbors), vp, vp,
+                                     vp, vp, vp, C.c_size_t, vp]
+    L.gd_sample_collisions.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.POINTER(GdNeighbors), vp, vp,
+                                       C.c_uint64, C.c_uint64, vp, vp, C.c_int32, vp, C.c_size_t, vp]
+    L.gd_push.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), vp, C.c_double, vp, C.c_size_t, vp]
+    L.gd_status_read.argtypes = [vp, vp, C.POINTER(C.c_int32)]
+    L.gd_last_error.restype = C.c_char_p
+    L.gd_version.restype = C.c_char_p
+    for name in ("gd_workspace_size", "gd_interval_init", "gd_build_neighbors", "gd_collision_rates",
+                 "gd_sample_collisions", "gd_push", "gd_status_read"):
+        getattr(L, name).restype = C.c_int32
+    if path is None:
+        _lib = L
+    return L
+
+
+def check(rc: int):
+    if rc != GD_OK:
+        msg = load().gd_last_error().decode()
+        raise GdError(f"gd status {rc}: {msg}")
+
+
+def make_problem(cfg: dict, n: int | None = None) -> GdProblem:
+    """gd_problem from a workload parameter dict."""
+    P = GdProblem()
+    P.n = int(cfg["n"] if n is None else n)
+    P.k = int(cfg["k"])
+    P.kernel = KERNELS[cfg["kernel"]]
+    P.push = PUSH[cfg.get("push", "none")]
+    P.nbin_min = int(cfg.get("nbin_min", 0))
+    P.erosion = int(cfg.get("erosion", 1))
+    P.grouping = int(cfg.get("grouping", 1))
+    per = cfg.get("periodic", (0, 0, 0))
+    Ls = cfg.get("L", (1.0, 1.0, 1.0))
+    for a in range(3):
+        P.periodic[a] = int(per[a])
+        P.L[a] = float(Ls[a])
+    P.rmax = float(cfg.get("rmax", math.inf))
+    for name in ("t0", "m0", "eps", "dt_fn_max", "rho_s", "s_min", "v_frag", "GM", "Sigma_g0", "R0", "p", "q",
+                 "h_g0", "alpha", "mu_mH", "sigma_H2", "s0", "St0", "r_in", "r_out"):
+        setattr(P, name, float(cfg.get(name, 0.0)))
+    for name in ("drag", "brownian", "turbulence", "caps"):
+        setattr(P, name, int(cfg.get(name, 0)))
+    return P
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+STATE_ARRAYS = ("x", "y", "z", "r", "th", "ph", "vr", "lth", "lph", "vz", "st_mid", "M")
+
+
+class DeviceState:
+    """One set of particle arrays on the GPU (torch tensors) and its gd_particles view."""
+
+    def __init__(self, torch, arrays: dict, n: int, device):
+        self.torch = torch
+        self.n = n
+        self.t = {}
+        for k in STATE_ARRAYS:
+            if k in arrays and arrays[k] is not None:
+                self.t[k] = torch.as_tensor(np.ascontiguousarray(arrays[k], np.float64), device=device).clone()
+        self.t["id"] = torch.as_tensor(np.ascontiguousarray(arrays["id"]).astype(np.int32), device=device).clone()
+        m = torch.as_tensor(np.ascontiguousarray(arrays["m"], np.float64), device=device)
+        self.t["m0"] = m.clone()
+        self.t["m1"] = torch.empty_like(m)
+        self.cur = 0
+
+    @classmethod
+    def like(cls, other: "DeviceState"):
+        self = cls.__new__(cls)
+        self.torch = other.torch
+        self.n = other.n
+        self.t = {k: other.torch.empty_like(v) for k, v in other.t.items()}
+        self.cur = other.cur
+        return self
+
+    def struct(self) -> GdParticles:
+        s = GdParticles()
+        s.id = self.t["id"].data_ptr()
+        for k in STATE_ARRAYS:
+            setattr(s, k, self.t[k].data_ptr() if k in self.t else None)
+        s.m[0] = self.t["m0"].data_ptr()
+        s.m[1] = self.t["m1"].data_ptr()
+        s.cur = self.cur
+        return s
+
+    def m(self):
+        return self.t["m0"] if self.cur == 0 else self.t["m1"]
+
+    def to_numpy(self) -> dict:
+        out = {k: v.cpu().numpy() for k, v in self.t.items() if k not in ("m0", "m1", "id")}
+        out["id"] = self.t["id"].cpu().numpy().view(np.uint32)
+        out["m"] = self.m().cpu().numpy()
+        return out
+
+
+class Engine:
+    """A run of the hot path on one GPU: state (double-buffered for the Morton
+    permutation), neighbourhoods, interval state and workspace, all resident in HBM."""
+
+    def __init__(self, params: dict, state: dict, seed: int = 0, device: str = "cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.params = params
+        n = len(state["x"])
+        self.n = n
+        self.P = make_problem(params, n)
+        self.device = torch.device(device)
+        self.stream = stream
+        self.seed = int(seed)
+        self.interval = 0
+        k = self.P.k
+        self.A = DeviceState(torch, state, n, self.device)
+        self.B = DeviceState.like(self.A)
+        i32 = dict(dtype=torch.int32, device=self.device)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self.nbr = torch.empty((n, k), **i32)
+        self.cnt = torch.empty(n, **i32)
+        self.dmax = torch.empty(n, **f64)
+        self.n_active = torch.zeros(1, **i32)
+        self.lam = torch.empty(n, **f64)
+        self.events = torch.zeros(n, **i32)
+        self.iv = torch.zeros(C.sizeof(GdInterval), dtype=torch.uint8, device=self.device)
+        sz = C.c_size_t()
+        check(self.lib.gd_workspace_size(C.byref(self.P), C.byref(sz)))
+        self.ws = torch.empty(sz.value + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) & ~255
+        self.ws_bytes = sz.value
+        self.nb = GdNeighbors(self.nbr.data_ptr(), self.cnt.data_ptr(), self.dmax.data_ptr(), self.n_active.data_ptr())
+        check(self.lib.gd_interval_init(C.c_void_p(self.iv.data_ptr()), float(params["dt_coll"]), self._s()))
+
+    def _s(self):
+        st = self.stream if self.stream is not None else self.torch.cuda.current_stream()
+        return C.c_void_p(st.cuda_stream)
+
+    # ---- the four calls --------------------------------------------------------
+    def build_neighbors(self):
+        sa, sb = self.A.struct(), self.B.struct()
+        check(self.lib.gd_build_neighbors(C.byref(self.P), C.byref(sa), C.byref(sb), C.byref(self.nb),
+                                          C.c_void_p(self.ws_ptr), self.ws_bytes, self._s()))
+        self.A, self.B = self.B, self.A
+        self.A.cur = sb.cur
+
+    def collision_rates(self, lam_pair=None, ab=None):
+        s = self.A.struct()
+        check(self.lib.gd_collision_rates(C.byref(self.P), C.byref(s), C.byref(self.nb),
+                                          C.c_void_p(self.iv.data_ptr()), _ptr(self.lam), _ptr(lam_pair), _ptr(ab),
+                                          C.c_void_p(self.ws_ptr), self.ws_bytes, self._s()))
+
+    def sample_collisions(self, log=None, log_cap=0, flip=True):
+        s = self.A.struct()
+        check(self.lib.gd_sample_collisions(C.byref(self.P), C.byref(s), C.byref(self.nb),
+                                            C.c_void_p(self.iv.data_ptr()), _ptr(self.lam), self.seed,
+                                            self.interval, _ptr(self.events), _ptr(log), int(log_cap),
+                                            C.c_void_p(self.ws_ptr), self.ws_bytes, self._s()))
+        self.interval += 1
+        if flip:
+            self.A.cur ^= 1
+
+    def push(self, dt: float | None = None):
+        s = self.A.struct()
+        ivp = None if dt is not None else C.c_void_p(self.iv.data_ptr())
+        check(self.lib.gd_push(C.byref(self.P), C.byref(s), ivp, 0.0 if dt is None else float(dt),
+                               C.c_void_p(self.ws_ptr), self.ws_bytes, self._s()))
+
+    def step(self, rebuild: bool = True):
+        """One frozen-neighbour interval: kNN, rates + plan, sampling, push."""
+        if rebuild:
+            self.build_neighbors()
+        self.collision_rates()
+        self.sample_collisions()
+        if self.P.push != 0:
+            self.push()
+
+    # ---- inspection (synchronising) -----------------------------------------------
+    def interval_state(self) -> dict:
+        raw = self.iv.cpu().numpy().tobytes()
+        s = GdInterval.from_buffer_copy(raw)
+        return {name: getattr(s, name) for name, _ in GdInterval._fields_}
+
+    def status(self) -> int:
+        v = C.c_int32()
+        check(self.lib.gd_status_read(C.c_void_p(self.ws_ptr), self._s(), C.byref(v)))
+        return v.value
+
+    def state_numpy(self) -> dict:
+        return self.A.to_numpy()

@@ -1,0 +1,259 @@
+// gd_api.hip -- host side of the C ABI declared in include/gd.h: argument
+// checks, workspace layout, launches on the caller's stream.  Allocates
+// nothing; errors are returned as gd_status with a thread-local message.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "gd_common.hpp"
+#include "gd_internal.hpp"
+
+namespace gd {
+
+static thread_local char g_err[512] = "";
+
+static int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+DevProblem to_dev(const gd_problem* p)
+{
+    DevProblem d{};
+    d.n = p->n;
+    d.k = p->k;
+    d.kernel = p->kernel;
+    d.push = p->push;
+    d.nbin_min = p->nbin_min > 0 ? p->nbin_min : (2 * p->k > 64 ? 2 * p->k : 64);
+    d.erosion = p->erosion;
+    d.grouping = p->grouping;
+    for (int a = 0; a < 3; ++a) {
+        d.periodic[a] = p->periodic[a];
+        d.L[a] = p->L[a];
+    }
+    d.rmax = p->rmax;
+    d.t0 = p->t0;
+    d.m0 = p->m0;
+    d.eps = p->eps;
+    d.dt_fn_max = p->dt_fn_max;
+    d.rho_s = p->rho_s;
+    d.s_min = p->s_min;
+    d.v_frag = p->v_frag;
+    d.GM = p->GM;
+    d.Sigma_g0 = p->Sigma_g0;
+    d.R0 = p->R0;
+    d.p = p->p;
+    d.q = p->q;
+    d.h_g0 = p->h_g0;
+    d.alpha = p->alpha;
+    d.mu_mH = p->mu_mH;
+    d.sigma_H2 = p->sigma_H2;
+    d.s0 = p->s0;
+    d.St0 = p->St0;
+    d.r_in = p->r_in;
+    d.r_out = p->r_out;
+    d.drag = p->drag;
+    d.brownian = p->brownian;
+    d.turbulence = p->turbulence;
+    d.caps = p->caps;
+    return d;
+}
+
+static int check_problem(const gd_problem* p)
+{
+    if (!p) return fail(GD_E_INVALID_ARG, "problem is NULL");
+    if (p->n < 0 || p->n >= (int64_t(1) << 31) - 1) return fail(GD_E_INVALID_ARG, "n = %lld out of range", (long long)p->n);
+    if (p->k < 2 || p->k > kMaxK) return fail(GD_E_INVALID_ARG, "k = %d outside 2..%d", p->k, kMaxK);
+    if (p->n * int64_t(p->k) >= (int64_t(1) << 31)) return fail(GD_E_UNSUPPORTED, "n * k must stay below 2^31");
+    if (p->kernel < 0 || p->kernel > 3) return fail(GD_E_INVALID_ARG, "kernel = %d unknown", p->kernel);
+    if (p->push < 0 || p->push > 2) return fail(GD_E_INVALID_ARG, "push = %d unknown", p->push);
+    for (int a = 0; a < 3; ++a)
+        if (p->periodic[a] && !(p->L[a] > 0.0)) return fail(GD_E_INVALID_ARG, "periodic axis %d needs L > 0", a);
+    if (!(p->rmax > 0.0)) return fail(GD_E_INVALID_ARG, "rmax must be > 0 (INFINITY for none)");
+    if (p->kernel != GD_KERNEL_PHYSICAL && (!(p->t0 > 0.0) || !(p->m0 > 0.0)))
+        return fail(GD_E_INVALID_ARG, "dimensionless kernels need t0 > 0 and m0 > 0");
+    if (p->kernel == GD_KERNEL_PHYSICAL &&
+        (!(p->rho_s > 0.0) || !(p->GM > 0.0) || !(p->s0 > 0.0) || !(p->R0 > 0.0) || !(p->s_min > 0.0)))
+        return fail(GD_E_INVALID_ARG, "physical kernel needs rho_s, GM, s0, R0, s_min > 0");
+    return GD_OK;
+}
+
+static int check_ws(const gd_problem* p, void* ws, size_t ws_bytes, Layout& L)
+{
+    L = make_layout(p->n, p->k);
+    if (!ws) return fail(GD_E_WORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(GD_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total)
+        return fail(GD_E_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+    return GD_OK;
+}
+
+static int check_state(const gd_problem* p, const gd_particles* s, bool need_other)
+{
+    if (!s) return fail(GD_E_INVALID_ARG, "particles is NULL");
+    if (s->cur != 0 && s->cur != 1) return fail(GD_E_INVALID_ARG, "cur must be 0 or 1");
+    if (!s->id || !s->x || !s->y || !s->z || !s->M || !s->m[s->cur])
+        return fail(GD_E_INVALID_ARG, "id, x, y, z, M and m[cur] are required");
+    if (need_other && !s->m[s->cur ^ 1]) return fail(GD_E_INVALID_ARG, "m[cur ^ 1] is required");
+    if (p->push == GD_PUSH_GLOBAL && (!s->r || !s->th || !s->ph || !s->vr || !s->lth || !s->lph))
+        return fail(GD_E_INVALID_ARG, "global push needs r, th, ph, vr, lth, lph");
+    if (p->push == GD_PUSH_LOCAL && (!s->vz || !s->st_mid))
+        return fail(GD_E_INVALID_ARG, "local push needs vz and st_mid");
+    return GD_OK;
+}
+
+static int check_nb(const gd_neighbors* nb)
+{
+    if (!nb || !nb->nbr || !nb->cnt || !nb->dmax) return fail(GD_E_INVALID_ARG, "neighbors nbr, cnt, dmax required");
+    return GD_OK;
+}
+
+static int hip_ok(const char* what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(GD_E_HIP, "%s: %s", what, hipGetErrorString(e));
+    return GD_OK;
+}
+
+__global__ void k_copy_na(const WsHeader* h, int32_t* out)
+{
+    if (threadIdx.x == 0) *out = h->n_active;
+}
+
+__global__ void k_clear_status(WsHeader* h)
+{
+    if (threadIdx.x == 0) h->status = 0;
+}
+
+}  // namespace gd
+
+using namespace gd;
+
+extern "C" {
+
+int32_t gd_workspace_size(const gd_problem* p, size_t* bytes)
+{
+    int rc = check_problem(p);
+    if (rc) return rc;
+    if (!bytes) return fail(GD_E_INVALID_ARG, "bytes is NULL");
+    *bytes = make_layout(p->n, p->k).total;
+    return GD_OK;
+}
+
+int32_t gd_interval_init(gd_interval* iv, double dt_coll, void* stream)
+{
+    if (!iv) return fail(GD_E_INVALID_ARG, "interval is NULL");
+    if (!(dt_coll > 0.0)) return fail(GD_E_INVALID_ARG, "dt_coll must be > 0");
+    launch_interval_init(iv, dt_coll, static_cast<hipStream_t>(stream));
+    return hip_ok("gd_interval_init");
+}
+
+int32_t gd_build_neighbors(const gd_problem* p, const gd_particles* in, gd_particles* out, const gd_neighbors* nb,
+                           void* ws, size_t ws_bytes, void* stream)
+{
+    int rc = check_problem(p);
+    if (!rc) rc = check_state(p, in, false);
+    if (!rc) rc = check_nb(nb);
+    if (rc) return rc;
+    if (!out) return fail(GD_E_INVALID_ARG, "out is NULL");
+    gd_particles o = *out;
+    o.cur = in->cur;
+    if (!o.id || !o.x || !o.y || !o.z || !o.M || !o.m[in->cur])
+        return fail(GD_E_INVALID_ARG, "out needs id, x, y, z, M and m[cur]");
+    const double* pairs[][2] = {{in->x, o.x}, {in->y, o.y}, {in->z, o.z}, {in->M, o.M}, {in->m[in->cur], o.m[in->cur]},
+                                {in->r, o.r}, {in->th, o.th}, {in->ph, o.ph}, {in->vr, o.vr}, {in->lth, o.lth},
+                                {in->lph, o.lph}, {in->vz, o.vz}, {in->st_mid, o.st_mid}};
+    for (auto& pr : pairs) {
+        if (pr[0] && !pr[1]) return fail(GD_E_INVALID_ARG, "out is missing an array that in provides");
+        if (pr[0] && pr[0] == pr[1]) return fail(GD_E_INVALID_ARG, "in and out must not alias");
+    }
+    if (in->id == o.id) return fail(GD_E_INVALID_ARG, "in and out must not alias");
+    Layout L;
+    rc = check_ws(p, ws, ws_bytes, L);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->n == 0) return GD_OK;
+    launch_morton_sort(p, in, &o, ws, L, st);
+    out->cur = in->cur;
+    launch_lbvh_knn(p, nb, ws, L, st);
+    if (nb->n_active) hipLaunchKernelGGL(k_copy_na, dim3(1), dim3(64), 0, st, at<WsHeader>(ws, L.hdr), nb->n_active);
+    return hip_ok("gd_build_neighbors");
+}
+
+int32_t gd_collision_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
+                           double* lam_i, double* lam_pair, double* ab, void* ws, size_t ws_bytes, void* stream)
+{
+    int rc = check_problem(p);
+    if (!rc) rc = check_state(p, s, false);
+    if (!rc) rc = check_nb(nb);
+    if (rc) return rc;
+    if (!iv || !lam_i) return fail(GD_E_INVALID_ARG, "interval and lam_i are required");
+    Layout L;
+    rc = check_ws(p, ws, ws_bytes, L);
+    if (rc) return rc;
+    if (!(p->eps > 0.0) || !(p->dt_fn_max > 0.0)) return fail(GD_E_INVALID_ARG, "eps and dt_fn_max must be > 0");
+    if (p->n == 0) return GD_OK;
+    launch_rates(p, s, nb, iv, lam_i, lam_pair, ab, ws, L, static_cast<hipStream_t>(stream));
+    return hip_ok("gd_collision_rates");
+}
+
+int32_t gd_sample_collisions(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
+                             const double* lam_i, uint64_t seed, uint64_t interval_index, int32_t* n_events,
+                             int32_t* log, int32_t log_cap, void* ws, size_t ws_bytes, void* stream)
+{
+    int rc = check_problem(p);
+    if (!rc) rc = check_state(p, s, true);
+    if (!rc) rc = check_nb(nb);
+    if (rc) return rc;
+    if (!iv || !lam_i) return fail(GD_E_INVALID_ARG, "interval and lam_i are required");
+    if (interval_index >> 32) return fail(GD_E_INVALID_ARG, "interval_index must be < 2^32");
+    if (log_cap < 0 || (log_cap > 0 && !log)) return fail(GD_E_INVALID_ARG, "log_cap > 0 needs a log array");
+    if (int64_t(log_cap) * p->n >= (int64_t(1) << 31)) return fail(GD_E_UNSUPPORTED, "n * log_cap must stay below 2^31");
+    Layout L;
+    rc = check_ws(p, ws, ws_bytes, L);
+    if (rc) return rc;
+    if (p->n == 0) return GD_OK;
+    launch_sample(p, s, nb, iv, lam_i, seed, uint32_t(interval_index), n_events, log, log_cap, ws, L,
+                  static_cast<hipStream_t>(stream));
+    return hip_ok("gd_sample_collisions");
+}
+
+int32_t gd_push(const gd_problem* p, const gd_particles* s, const gd_interval* iv, double dt, void* ws,
+                size_t ws_bytes, void* stream)
+{
+    int rc = check_problem(p);
+    if (!rc) rc = check_state(p, s, false);
+    if (rc) return rc;
+    if (!iv && !(dt >= 0.0)) return fail(GD_E_INVALID_ARG, "dt must be >= 0 when no interval is given");
+    Layout L;
+    rc = check_ws(p, ws, ws_bytes, L);
+    if (rc) return rc;
+    if (p->n == 0 || p->push == GD_PUSH_NONE) return GD_OK;
+    launch_push(p, s, iv, dt, ws, L, static_cast<hipStream_t>(stream));
+    return hip_ok("gd_push");
+}
+
+int32_t gd_status_read(void* ws, void* stream, int32_t* out)
+{
+    if (!ws || !out) return fail(GD_E_INVALID_ARG, "workspace and out are required");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    WsHeader* h = at<WsHeader>(ws, 0);
+    int32_t v = 0;
+    if (hipMemcpyAsync(&v, &h->status, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return hip_ok("gd_status_read");
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, st, h);
+    *out = v;
+    return hip_ok("gd_status_read");
+}
+
+const char* gd_last_error(void) { return g_err; }
+
+const char* gd_version(void) { return "gd 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,207 @@
+// gd_common.hpp -- internal definitions shared by the library's HIP sources:
+// workspace layout, the device copy of the problem, the counter-based
+// generator, double-double sums and wavefront reductions (wave64, gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gd.h"
+
+namespace gd {
+
+constexpr int kWave = 64;
+constexpr int kNBin = 128;          // controller bins: ilogb(m) in [-64, 63]
+constexpr int kBinOff = 64;
+constexpr int64_t kTicks = int64_t(1) << 30;  // ticks per collision step
+constexpr int kSortTile = 4096;     // keys per radix-sort block
+constexpr int kRedBlocks = 256;     // blocks of the bin reductions
+constexpr int kMaxK = 64;
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// Device copy of gd_problem (passed by value to kernels).
+struct DevProblem {
+    int64_t n;
+    int32_t k, kernel, push, nbin_min, erosion, grouping;
+    int32_t periodic[3];
+    double L[3];
+    double rmax;
+    double t0, m0, eps, dt_fn_max;
+    double rho_s, s_min, v_frag;
+    double GM, Sigma_g0, R0, p, q, h_g0, alpha, mu_mH, sigma_H2, s0, St0, r_in, r_out;
+    int32_t drag, brownian, turbulence, caps;
+};
+
+// LBVH internal node: box, covered slot range [first, last], split position.
+// Children: left = split (leaf if split == first), right = split + 1 (leaf if
+// split + 1 == last).  rope = next node in depth-first order after the
+// subtree (-1: end).  Child/rope references: >= 0 internal node, < 0 leaf ~ref.
+struct alignas(16) Node {
+    double lo[3];
+    double hi[3];
+    int32_t first, last, split, rope;
+};
+
+// Device-resident header at the start of the workspace.
+struct alignas(256) WsHeader {
+    int32_t status;
+    int32_t n_active;
+    int32_t n_groups;
+    int32_t pad0;
+    double lo[3];
+    double inv;                  // Morton scale 1024 / extent
+    int32_t group_of[kNBin];     // plan: raw bin -> merged group (-1 empty)
+    double gM[kNBin];            // plan: sum of M per merged group
+    double scratch[16];
+};
+
+// Workspace layout (byte offsets), identical on host and device.
+struct Layout {
+    size_t hdr, keys0, keys1, vals0, vals1, hist, red, pos4, nodes, parent, flags, rc,
+        snap_s, snap_N, a, b, part, total;
+    int64_t n;
+    int32_t k;
+    int32_t nsort_blocks;
+};
+
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+__host__ inline Layout make_layout(int64_t n, int32_t k)
+{
+    Layout L{};
+    L.n = n;
+    L.k = k;
+    L.nsort_blocks = int32_t((n + kSortTile - 1) / kSortTile);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    const size_t nn = size_t(n > 0 ? n : 1);
+    L.hdr = take(sizeof(WsHeader));
+    L.keys0 = take(4 * nn);
+    L.keys1 = take(4 * nn);
+    L.vals0 = take(4 * nn);
+    L.vals1 = take(4 * nn);
+    L.hist = take(4 * size_t(256) * (L.nsort_blocks + 1));
+    L.red = take(sizeof(double) * 8 * kRedBlocks);
+    L.pos4 = take(32 * nn);
+    L.nodes = take(sizeof(Node) * nn);
+    L.parent = take(4 * 2 * nn);
+    L.flags = take(4 * nn);
+    L.rc = take(4 * nn);
+    L.snap_s = take(8 * nn);
+    L.snap_N = take(8 * nn);
+    L.a = take(8 * nn);
+    L.b = take(8 * nn);
+    L.part = take(sizeof(double) * 8 * kNBin * kRedBlocks);
+    L.total = o;
+    return L;
+}
+
+template <typename T>
+__host__ __device__ inline T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + off); }
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw 2011): ten rounds of
+// multiply-xor on words 0 and 2 with the Weyl-incremented key.
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c[0];
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2];
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0;
+        const uint32_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// The four uniforms of one event: (U_w in (0,1], U_p, U_c, U_f in [0,1)).
+// Two generator calls with counters (id, interval, event, w), w = 0, 1.
+__device__ inline void event_uniforms(uint64_t seed, uint32_t id, uint32_t iv, uint32_t e, double u[4])
+{
+    const double two53 = 1.0 / 9007199254740992.0;
+    const uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
+#pragma unroll
+    for (uint32_t w = 0; w < 2; ++w) {
+        uint32_t c[4] = {id, iv, e, w};
+        philox4x32_10(c, k0, k1);
+        const uint64_t a = ((uint64_t(c[1]) << 32) | c[0]) >> 11;
+        const uint64_t b = ((uint64_t(c[3]) << 32) | c[2]) >> 11;
+        if (w == 0) {
+            u[0] = double(a + 1) * two53;
+            u[1] = double(b) * two53;
+        } else {
+            u[2] = double(a) * two53;
+            u[3] = double(b) * two53;
+        }
+    }
+}
+
+__device__ inline int bin_of(double m)
+{
+    int b = ilogb(m);
+    b = b < -kBinOff ? -kBinOff : b;
+    b = b > kNBin - 1 - kBinOff ? kNBin - 1 - kBinOff : b;
+    return b + kBinOff;
+}
+
+// ---------------------------------------------------------------------------
+// Double-double accumulation (Knuth two-sum); the reductions of the
+// controller are carried to ~2^-100 relative so that their final rounding
+// matches the exactly rounded sum.
+struct dd {
+    double hi, lo;
+};
+
+__device__ inline dd dd_add(dd a, dd b)
+{
+    const double s = a.hi + b.hi;
+    const double bb = s - a.hi;
+    double e = (a.hi - (s - bb)) + (b.hi - bb);
+    e = e + (a.lo + b.lo);
+    const double h = s + e;
+    return dd{h, e - (h - s)};
+}
+
+__device__ inline double shfl_xor_d(double v, int m)
+{
+    return __shfl_xor(v, m, kWave);
+}
+
+__device__ inline dd wave_sum_dd(dd v)
+{
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) {
+        dd o{shfl_xor_d(v.hi, m), shfl_xor_d(v.lo, m)};
+        v = dd_add(v, o);
+    }
+    return v;
+}
+
+__device__ inline double wave_min_d(double v)
+{
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) v = fmin(v, shfl_xor_d(v, m));
+    return v;
+}
+
+__device__ inline double wave_max_d(double v)
+{
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) v = fmax(v, shfl_xor_d(v, m));
+    return v;
+}
+
+__device__ inline void set_status(void* ws, int bits)
+{
+    atomicOr(&at<WsHeader>(ws, 0)->status, bits);
+}
+
+}  // namespace gd

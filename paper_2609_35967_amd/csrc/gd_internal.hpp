@@ -1,0 +1,36 @@
+// gd_internal.hpp -- launch functions of the library's kernels (host side).
+#pragma once
+
+#include "gd_common.hpp"
+
+namespace gd {
+
+struct PermuteArgs {
+    int64_t n;
+    const uint32_t* perm;
+    int32_t nd;
+    const double* src[16];
+    double* dst[16];
+    const uint32_t* id_src;
+    uint32_t* id_dst;
+    double4* pos4;
+};
+
+DevProblem to_dev(const gd_problem* p);
+
+int launch_morton_sort(const gd_problem* p, const gd_particles* in, gd_particles* out, void* ws, const Layout& L,
+                       hipStream_t st);
+void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t st);
+int launch_lbvh_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layout& L, hipStream_t st);
+int launch_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv, double* lam_i,
+                 double* lam_pair, double* ab, void* ws, const Layout& L, hipStream_t st);
+int launch_sample(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
+                  const double* lam_i, uint64_t seed, uint32_t interval, int32_t* n_events, int32_t* log,
+                  int32_t log_cap, void* ws, const Layout& L, hipStream_t st);
+int launch_push(const gd_problem* p, const gd_particles* s, const gd_interval* iv, double dt, void* ws,
+                const Layout& L, hipStream_t st);
+void launch_interval_init(gd_interval* iv, double dt_coll, hipStream_t st);
+void launch_bin_reduce(int mode, const double* msnap, const double* M, const double* va, const double* vb, int64_t n,
+                       double* part, void* ws, hipStream_t st);
+
+}  // namespace gd

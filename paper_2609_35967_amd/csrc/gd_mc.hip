@@ -1,0 +1,270 @@
+// gd_mc.hip -- Monte Carlo sampling of collision events against the frozen
+// neighbourhood (Sect. 2.5.3) and the post-interval audit.
+//
+// One lane per particle.  The particle draws waiting times
+// dt_w = -ln(U_w)/lambda*_i (Gillespie); an event happens iff dt_w fits in the
+// rest of the interval.  Its partner is the first slot whose inclusive prefix of
+// lambda*_ij exceeds U_p lambda*_i, its channel the first whose cumulative rate
+// exceeds U_c lambda*_ij; the outcome (Sect. 2.5.2) updates only this particle,
+// after which every lambda*_ij is recomputed from the new mass against the
+// frozen neighbours.  lambda*_i of the start state comes from the rates pass
+// (the same function of the same inputs), so particles without events never
+// evaluate their pairs here.  Random numbers: Philox4x32-10 keyed by the seed,
+// counters (id, interval, event, 0/1); every event uses both calls.
+//
+// Audit (a reading: the paper names what the audit monitors, not its rule):
+// per merged controller bin the mass-weighted mean realised |ln(s'/s)|; if the
+// largest exceeds 2 eps C, C halves (floor 0.25), else C grows by 1.25 (cap 1).
+#include "gd_common.hpp"
+#include "gd_internal.hpp"
+#include "gd_physics.hpp"
+
+namespace gd {
+
+struct McArgs {
+    DevProblem P;
+    const uint32_t* id;
+    const int32_t* nbr;
+    const int32_t* cnt;
+    const double* dmax;
+    const double* m;      // snapshot (frozen) masses
+    const double* x;
+    const double* y;
+    const double* z;
+    const double* snap_s;
+    const double* snap_N;
+    const double* lam_i;
+    const gd_interval* iv;
+    double* m_out;
+    int32_t* n_events;
+    int32_t* log;
+    int32_t log_cap;
+    uint64_t seed;
+    uint32_t interval;
+    void* ws;
+    unsigned long long* ev_counter;
+};
+
+constexpr int kEventCap = 1 << 24;  // safety stop per particle and interval (status-flagged)
+
+template <int KP2>
+__device__ inline double prefix_rates(const McArgs& A, const QCtx& q, const int32_t* row, int c, double mi,
+                                      double si, double Sti, double (&pre)[KP2])
+{
+    const bool phys = A.P.kernel == GD_KERNEL_PHYSICAL;
+    double li = 0.0;
+#pragma unroll
+    for (int s = 0; s < KP2; ++s) {
+        if (s < c) {
+            int j = row[s];
+            if (j < 0 || j >= A.P.n) {
+                set_status(A.ws, GD_DEV_INTERNAL);
+                j = 0;
+            }
+            Pair o;
+            pair_eval(A.P, q, mi, si, Sti, A.m[j], phys ? A.snap_s[j] : 0.0, phys ? A.snap_N[j] : 0.0, o);
+            li = li + o.lam_star;
+        }
+        pre[s] = li;
+    }
+    return li;
+}
+
+template <int KP2>
+__global__ __launch_bounds__(256) void k_mc(McArgs A)
+{
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int e = 0;
+    if (i < A.P.n) {
+        const int k = A.P.k;
+        const bool phys = A.P.kernel == GD_KERNEL_PHYSICAL;
+        const int c = A.cnt[i];
+        double m = A.m[i];
+        double li = A.lam_i[i];
+        const double dt_exe = A.iv->dt_exe;
+        if (c > 1 && li > 0.0) {
+            const uint32_t pid = A.id[i];
+            const int32_t* row = A.nbr + i * k;
+            QCtx q{};
+            bool have_ctx = false, have_pre = false;
+            double si = 0.0, Sti = 0.0;
+            double pre[KP2];
+            double t = 0.0;
+            for (;;) {
+                if (!(li > 0.0)) break;
+                if (e >= kEventCap) {
+                    set_status(A.ws, GD_DEV_EVENT_CAP);
+                    break;
+                }
+                double u[4];
+                event_uniforms(A.seed, pid, A.interval, uint32_t(e), u);
+                const double dtw = -log(u[0]) / li;
+                if (dtw > dt_exe - t) break;
+                t = t + dtw;
+                if (!have_ctx) {
+                    query_ctx(A.P, A.x[i], A.y[i], A.z[i], A.dmax[i], q);
+                    have_ctx = true;
+                }
+                if (!have_pre) {
+                    if (phys) {
+                        si = grain_size(A.P, m);
+                        Sti = q.stfac * si;
+                    }
+                    li = prefix_rates<KP2>(A, q, row, c, m, si, Sti, pre);
+                    have_pre = true;
+                }
+                const double target = u[1] * li;
+                int sel = c - 1;
+                bool found = false;
+#pragma unroll
+                for (int s = 0; s < KP2; ++s) {
+                    const bool hit = !found && s < c - 1 && pre[s] > target;
+                    sel = hit ? s : sel;
+                    found = found || hit;
+                }
+                int j = row[sel];
+                if (j < 0 || j >= A.P.n) j = 0;
+                const double mj = A.m[j];
+                const double sj = phys ? A.snap_s[j] : 0.0;
+                Pair o;
+                pair_eval(A.P, q, m, si, Sti, mj, sj, phys ? A.snap_N[j] : 0.0, o);
+                int ch = 0;
+                if (o.type == kErosion) ch = (o.r0 > u[2] * o.lam_star) ? 0 : 1;
+                double mnew;
+                if (o.type == kStick) {
+                    mnew = m + o.Ng * mj;
+                } else if (o.type == kErosion) {
+                    mnew = (ch == 0) ? m - o.Ng * mj : mj;
+                } else {
+                    const double a = sqrt(A.P.s_min);
+                    const double w = a + u[3] * (sqrt(si) - a);
+                    const double sn = w * w;
+                    mnew = kPi * A.P.rho_s * sn * sn * sn / 6.0;
+                }
+                if (A.log) {
+                    if (e < A.log_cap) A.log[i * A.log_cap + e] = sel | (ch << 16) | (o.type << 24);
+                    else set_status(A.ws, GD_DEV_LOG_OVERFLOW);
+                }
+                ++e;
+                if (mnew != m) {
+                    m = mnew;
+                    have_pre = false;
+                    if (phys) {
+                        si = grain_size(A.P, m);
+                        Sti = q.stfac * si;
+                    }
+                    li = prefix_rates<KP2>(A, q, row, c, m, si, Sti, pre);
+                    have_pre = true;
+                }
+            }
+        }
+        A.m_out[i] = m;
+        if (A.n_events) A.n_events[i] = e;
+        if (A.log)
+            for (int f = e; f < A.log_cap; ++f) A.log[i * A.log_cap + f] = -1;
+    }
+    // events of the interval, one atomic per wavefront
+    unsigned long long ev = (unsigned long long)e;
+#pragma unroll
+    for (int mk = 1; mk < 64; mk <<= 1) ev += __shfl_xor(ev, mk, 64);
+    if (lane == 0 && ev) atomicAdd(A.ev_counter, ev);
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kNBin) void k_audit(DevProblem P, const double* __restrict__ part, int nblk,
+                                                 gd_interval* iv, WsHeader* h)
+{
+    __shared__ double sv[kNBin][2];
+    const int b = threadIdx.x;
+    dd x{0.0, 0.0};
+    for (int blk = 0; blk < nblk; ++blk) {
+        const double* a = part + (int64_t(blk) * kNBin + b) * 8;
+        x = dd_add(x, dd{a[1], a[2]});
+    }
+    sv[b][0] = x.hi;
+    sv[b][1] = x.lo;
+    __syncthreads();
+    if (b != 0) return;
+    double worst = 0.0;
+    for (int g = 0; g < h->n_groups; ++g) {
+        if (!(h->gM[g] > 0.0)) continue;
+        dd s{0.0, 0.0};
+        for (int bb = 0; bb < kNBin; ++bb)
+            if (h->group_of[bb] == g) s = dd_add(s, dd{sv[bb][0], sv[bb][1]});
+        const double r = s.hi / h->gM[g];
+        if (r > worst) worst = r;
+    }
+    const double Cf = iv->C;
+    const double thr = 2.0 * P.eps * Cf;
+    iv->C = (worst > thr) ? fmax(0.25, 0.5 * Cf) : fmin(1.0, 1.25 * Cf);
+    iv->audit_worst = worst;
+    int64_t tk = iv->ticks + iv->exe_ticks;
+    if (tk >= kTicks) tk = 0;
+    iv->ticks = tk;
+    iv->time = iv->time + iv->dt_exe;
+    iv->n_intervals = iv->n_intervals + 1;
+    iv->n_events = int64_t(*reinterpret_cast<const unsigned long long*>(&h->scratch[0]));
+}
+
+__global__ void k_interval_init(gd_interval* iv, double dt_coll)
+{
+    if (threadIdx.x != 0) return;
+    iv->dt_coll = dt_coll;
+    iv->dt_req = 0.0;
+    iv->dt_exe = 0.0;
+    iv->C = 1.0;
+    iv->time = 0.0;
+    iv->ticks = 0;
+    iv->exe_ticks = 0;
+    iv->n_intervals = 0;
+    iv->n_events = 0;
+    iv->audit_worst = 0.0;
+    iv->n_groups = 0;
+    iv->pad = 0;
+}
+
+void launch_interval_init(gd_interval* iv, double dt_coll, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_interval_init, dim3(1), dim3(64), 0, st, iv, dt_coll);
+}
+
+int launch_sample(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
+                  const double* lam_i, uint64_t seed, uint32_t interval, int32_t* n_events, int32_t* log,
+                  int32_t log_cap, void* ws, const Layout& L, hipStream_t st)
+{
+    const DevProblem P = to_dev(p);
+    const int64_t n = p->n;
+    WsHeader* h = at<WsHeader>(ws, L.hdr);
+    McArgs A{};
+    A.P = P;
+    A.id = s->id;
+    A.nbr = nb->nbr;
+    A.cnt = nb->cnt;
+    A.dmax = nb->dmax;
+    A.m = s->m[s->cur];
+    A.x = s->x;
+    A.y = s->y;
+    A.z = s->z;
+    A.snap_s = at<double>(ws, L.snap_s);
+    A.snap_N = at<double>(ws, L.snap_N);
+    A.lam_i = lam_i;
+    A.iv = iv;
+    A.m_out = s->m[s->cur ^ 1];
+    A.n_events = n_events;
+    A.log = log_cap > 0 ? log : nullptr;
+    A.log_cap = log_cap;
+    A.seed = seed;
+    A.interval = interval;
+    A.ws = ws;
+    A.ev_counter = reinterpret_cast<unsigned long long*>(&h->scratch[0]);
+    const int g = int((n + 255) / 256);
+    if (p->k <= 32) hipLaunchKernelGGL(k_mc<32>, dim3(g), dim3(256), 0, st, A);
+    else hipLaunchKernelGGL(k_mc<64>, dim3(g), dim3(256), 0, st, A);
+    double* part = at<double>(ws, L.part);
+    launch_bin_reduce(1, A.m, s->M, A.m_out, nullptr, n, part, ws, st);
+    hipLaunchKernelGGL(k_audit, dim3(1), dim3(kNBin), 0, st, P, part, kRedBlocks, iv, h);
+    return 0;
+}
+
+}  // namespace gd

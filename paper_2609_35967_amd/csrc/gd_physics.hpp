@@ -1,0 +1,252 @@
+// gd_physics.hpp -- per-pair collision physics on the device.
+//
+//  * gas disk (Sect. 2.2): Sigma_g = Sigma_g0 (R/R0)^p, h_g = h_g0 (R/R0)^((q+1)/2),
+//    H_g = h_g R, c_s = H_g Omega_K, rho_g = Sigma_g/(sqrt(2 pi) H_g) exp(-(1-R/r)/h_g^2),
+//    eta = -[(p + q/2 - 3/2) h_g^2 + q (1 - R/r)]/2, v_g,phi = sqrt(1 - 2 eta) Omega_K R;
+//  * Stokes number (Sect. 2.3.1): St = St0 (s/s0) (R/R0)^-p exp((1-R/r)/h_g^2);
+//  * relative speed eq:dv: drift terms dv_R, dv_Z, dv_phi, Brownian speed capped
+//    at c_s, turbulence from the closed forms of Ormel & Cuzzi (2007), all at the
+//    query particle's position with St_j = St_i s_j/s_i; differences of Stokes-
+//    number functions are factored through St_i - St_j taken from m_i - m_j;
+//  * sampling measure V_i = 4 pi d_i^3/3 minus the caps beyond the boundaries
+//    r_in and r_out, each taken as a plane at its distance (Sect. 2.5.1);
+//  * eq:kernel K = pi (s_i+s_j)^2 dv/4 and eq:rate lambda_ij = N_j K/V_i, or the
+//    dimensionless lambda_ij = (1/t0)(1/N_K)(m0/m_j) K of Sect. 3.3;
+//  * outcomes (Sect. 2.5.2) with grouping N_coll = floor(1e-4/psi) for psi <= 1e-6:
+//    sticking [lambda/N_coll], erosion for psi <= 0.1 [remnant (1-psi) lambda/N_coll,
+//    debris psi lambda], fragmentation [lambda];
+//  * controller moments <J>, <J^2> of each channel (Sect. 2.5.3), fragments by
+//    integrating eq:frag over U.
+// Every expression keeps one evaluation order and each operation is rounded
+// on its own (the library is compiled without contraction).
+#pragma once
+
+#include "gd_common.hpp"
+
+namespace gd {
+
+struct Gas {
+    double OmK, hg, Hg, cs, r, rhog, eta, vgphi, stfac;
+};
+
+__device__ inline void gas_at(const DevProblem& P, double R, double Z, Gas& g)
+{
+    const double r = sqrt(R * R + Z * Z);
+    const double xr = R / P.R0;
+    g.r = r;
+    g.OmK = sqrt(P.GM / (R * R * R));
+    g.hg = P.h_g0 * pow(xr, (P.q + 1.0) * 0.5);
+    g.Hg = g.hg * R;
+    g.cs = g.Hg * g.OmK;
+    const double hg2 = g.hg * g.hg;
+    const double w = 1.0 - R / r;
+    const double Sig = P.Sigma_g0 * pow(xr, P.p);
+    g.rhog = Sig / (sqrt(2.0 * kPi) * g.Hg) * exp(-w / hg2);
+    g.eta = -0.5 * ((P.p + 0.5 * P.q - 1.5) * hg2 + P.q * w);
+    g.vgphi = sqrt(1.0 - 2.0 * g.eta) * g.OmK * R;
+    g.stfac = P.St0 / P.s0 * pow(xr, -P.p) * exp(w / hg2);
+}
+
+__device__ inline double grain_size(const DevProblem& P, double m)
+{
+    return cbrt(6.0 * m / (kPi * P.rho_s));
+}
+
+// Everything of the rate that depends on the query particle only.
+struct QCtx {
+    double V, R, Z, OmK, eta, cs, stfac, Vg2, tke, kT8pi;
+};
+
+__device__ inline void query_ctx(const DevProblem& P, double x, double y, double z, double d, QCtx& c)
+{
+    if (P.kernel != GD_KERNEL_PHYSICAL) {
+        c.V = 1.0;
+        return;
+    }
+    const double R = sqrt(x * x + y * y);
+    Gas g;
+    gas_at(P, R, z, g);
+    c.R = R;
+    c.Z = z;
+    c.OmK = g.OmK;
+    c.eta = g.eta;
+    c.cs = g.cs;
+    c.stfac = g.stfac;
+    double V = 4.0 * kPi * d * d * d / 3.0;
+    if (P.caps) {
+        const double de0 = g.r - P.r_in, de1 = P.r_out - g.r;
+        if (de0 < d) {
+            const double h = d - de0;
+            V = V - kPi * h * h * (3.0 * d - h) / 3.0;
+        }
+        if (de1 < d) {
+            const double h = d - de1;
+            V = V - kPi * h * h * (3.0 * d - h) / 3.0;
+        }
+    }
+    c.V = V;
+    c.Vg2 = 1.5 * P.alpha * g.cs * g.cs;
+    const double vth = sqrt(8.0 / kPi) * g.cs;
+    const double lmfp = P.mu_mH / (g.rhog * P.sigma_H2);
+    const double numol = 0.5 * vth * lmfp;
+    const double Re = P.alpha * g.cs * g.Hg / numol;
+    c.tke = 1.0 / sqrt(Re);
+    c.kT8pi = 8.0 * (P.mu_mH * g.cs * g.cs) / kPi;
+}
+
+// Ormel & Cuzzi (2007) turbulent relative speed squared, St1 >= St2,
+// dSt = St1 - St2: tightly coupled St1 < Re^-1/2 (written as
+// Vg^2 dSt^2 [St1 St2 + t(St1+St2)]/[(St1+St2)(St1+t)(St2+t)], equal to the
+// published form but free of cancellation for close St), intermediate up to
+// St1 = 1 (y_a = 1.6), heavy.
+__device__ inline double oc07_dv2(double St1, double St2, double dSt, double Vg2, double tke)
+{
+    if (St1 < tke) {
+        const double num = St1 * St2 + tke * (St1 + St2);
+        const double den = (St1 + St2) * (St1 + tke) * (St2 + tke);
+        return Vg2 * (dSt * dSt) * num / den;
+    }
+    if (St1 < 1.0) {
+        const double ya = 1.6;
+        const double e = St2 / St1;
+        const double br = 2.0 * ya - (1.0 + e) + 2.0 / (1.0 + e) * (1.0 / (1.0 + ya) + e * e * e / (ya + e));
+        return Vg2 * br * St1;
+    }
+    return Vg2 * (1.0 / (1.0 + St1) + 1.0 / (1.0 + St2));
+}
+
+// <J>, <J^2> of a fragment of a grain of diameter s_i: with x = sqrt(s_i/s_min),
+// d = x - 1: <J> = 2[1 - ln x/d], <J^2> = 4[2x - ln^2 x - 2 ln x - 2]/d, and for
+// d < 0.1 the power series <J> = 2 sum_n (-1)^(n+1) d^n/(n+1),
+// <J^2> = 8 sum_{m>=2} (-1)^(m+1) (1 - H_m) d^m/(m+1).
+__device__ inline void frag_moments(double s_i, double s_min, double& mJ, double& mJ2)
+{
+    const double x = sqrt(s_i / s_min);
+    const double d = x - 1.0;
+    if (!(d > 0.0)) {
+        mJ = 0.0;
+        mJ2 = 0.0;
+        return;
+    }
+    if (d < 0.1) {
+        double j1 = 0.0, j2 = 0.0, dn = d, H = 1.0, sg = 1.0;
+        for (int k = 1; k <= 40; ++k) {
+            j1 += sg * dn / double(k + 1);
+            if (k >= 2) j2 += sg * (1.0 - H) * dn / double(k + 1);
+            dn *= d;
+            sg = -sg;
+            H += 1.0 / double(k + 1);
+        }
+        mJ = 2.0 * j1;
+        mJ2 = 8.0 * j2;
+        return;
+    }
+    const double L = log1p(d);
+    mJ = 2.0 * (1.0 - L / d);
+    mJ2 = 4.0 * (2.0 * x - L * L - 2.0 * L - 2.0) / d;
+}
+
+enum { kStick = 0, kErosion = 1, kFrag = 2 };
+
+struct Pair {
+    int type;
+    double r0, r1;      // channel rates (r1 = 0 unless erosion)
+    double lam_star;
+    double Ng;
+};
+
+// Own particle: mass mi and (physical) diameter si and Stokes number Sti.
+// Neighbour: mass mj, diameter sj, grain count Nj (physical).
+__device__ inline void pair_eval(const DevProblem& P, const QCtx& c, double mi, double si, double Sti, double mj,
+                                 double sj, double Nj, Pair& o)
+{
+    double lam, dv = 0.0;
+    if (P.kernel == GD_KERNEL_PHYSICAL) {
+        // St_j = St_i s_j/s_i at the query position; St_i - St_j from the mass
+        // difference, s_i - s_j = (6/(pi rho))(m_i - m_j)/(s_i^2 + s_i s_j + s_j^2),
+        // so that close grains do not cancel.
+        const double Stj = c.stfac * sj;
+        const double ds = (6.0 / (kPi * P.rho_s)) * (mi - mj) / (si * si + si * sj + sj * sj);
+        const double dSt = c.stfac * ds;
+        const double OR = c.OmK;
+        const double qi = 1.0 + Sti * Sti, qj = 1.0 + Stj * Stj;
+        const double da = dSt * (1.0 - Sti * Stj) / (qi * qj);
+        const double db = -dSt * (Sti + Stj) / (qi * qj);
+        const double dvR = 2.0 * c.eta * c.R * OR * da;
+        const double zi = fmin(Sti, 0.5), zj = fmin(Stj, 0.5);
+        const double dz = (Sti < 0.5 && Stj < 0.5) ? dSt : zi - zj;
+        const double dvZ = c.Z * OR * dz;
+        const double dvP = c.eta * c.R * OR * db;
+        double dvB = 0.0, dvT2 = 0.0;
+        if (P.brownian) {
+            dvB = sqrt(c.kT8pi * (1.0 / mi + 1.0 / mj));
+            if (dvB > c.cs) dvB = c.cs;
+        }
+        if (P.turbulence) {
+            const bool ig = Sti >= Stj;
+            dvT2 = oc07_dv2(ig ? Sti : Stj, ig ? Stj : Sti, fabs(dSt), c.Vg2, c.tke);
+        }
+        double dv2 = dvR * dvR + dvZ * dvZ;
+        dv2 = dv2 + dvP * dvP;
+        dv2 = dv2 + dvB * dvB;
+        dv2 = dv2 + dvT2;
+        dv = sqrt(dv2);
+        const double ssum = si + sj;
+        const double K = kPi * ssum * ssum * dv / 4.0;
+        lam = Nj * K / c.V;
+        if (!(c.V > 0.0)) lam = 0.0;
+    } else {
+        double Kt;
+        if (P.kernel == GD_KERNEL_CONST) Kt = 1.0;
+        else if (P.kernel == GD_KERNEL_ADDITIVE) Kt = (mi + mj) / P.m0;
+        else Kt = (mi * mj) / (P.m0 * P.m0);
+        lam = ((P.m0 / mj) * Kt) / (P.t0 * double(P.k));
+    }
+    const double psi = mj / mi;
+    const bool fast = (P.kernel == GD_KERNEL_PHYSICAL) && (dv >= P.v_frag);
+    double Ng = 1.0;
+    if (P.grouping && psi <= 1e-6) Ng = floor(1e-4 / psi);
+    o.Ng = Ng;
+    if (!fast) {
+        o.type = kStick;
+        o.r0 = lam / Ng;
+        o.r1 = 0.0;
+        o.lam_star = o.r0;
+    } else if (P.erosion && psi <= 0.1) {
+        o.type = kErosion;
+        o.r0 = (1.0 - psi) * lam / Ng;
+        o.r1 = psi * lam;
+        o.lam_star = o.r0 + o.r1;
+    } else {
+        o.type = kFrag;
+        o.r0 = lam;
+        o.r1 = 0.0;
+        o.lam_star = lam;
+    }
+}
+
+// sum over the pair's channels of rate * <J> and rate * <J^2>
+__device__ inline void pair_moments(const DevProblem& P, const Pair& o, double mi, double si, double mj, double& a,
+                                    double& b)
+{
+    const double psi = mj / mi;
+    if (o.type == kStick) {
+        const double J = log1p(o.Ng * psi) / 3.0;
+        a = o.r0 * J;
+        b = o.r0 * (J * J);
+    } else if (o.type == kErosion) {
+        const double Jr = -log1p(-o.Ng * psi) / 3.0;
+        const double Jd = fabs(log(psi)) / 3.0;
+        a = o.r0 * Jr;
+        b = o.r0 * (Jr * Jr);
+        a = a + o.r1 * Jd;
+        b = b + o.r1 * (Jd * Jd);
+    } else {
+        double mJ, mJ2;
+        frag_moments(si, P.s_min, mJ, mJ2);
+        a = o.r0 * mJ;
+        b = o.r0 * mJ2;
+    }
+}
+
+}  // namespace gd

@@ -1,0 +1,94 @@
+"""The C-ABI library loads and exports every entry point of include/gd.h, and
+rejects bad arguments on the host before anything is enqueued (no GPU needed)."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2609_35967_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2609_35967_amd import build
+        build.build()
+    return binding.load()
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "gd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(gd_[a-z_]+)\s*\(", src, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert {"gd_build_neighbors", "gd_collision_rates", "gd_sample_collisions", "gd_push"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_2609_35967_amd import binding
+    assert set(binding.EXPORTS) == set(names)
+    assert lib.gd_version().startswith(b"gd ")
+
+
+def test_struct_layout_matches_header(tmp_path):
+    from paper_2609_35967_amd import binding
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include "gd.h"\nint main(){printf("%zu %zu %zu %zu", sizeof(gd_problem),'
+                   ' sizeof(gd_particles), sizeof(gd_interval), sizeof(gd_neighbors));}\n')
+    import subprocess
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [C.sizeof(binding.GdProblem), C.sizeof(binding.GdParticles), C.sizeof(binding.GdInterval),
+            C.sizeof(binding.GdNeighbors)]
+    assert got == want
+
+
+def test_host_validation(lib):
+    from paper_2609_35967_amd import binding
+    P = binding.make_problem(workloads.disk3d_params(1000))
+    sz = C.c_size_t()
+    assert lib.gd_workspace_size(C.byref(P), C.byref(sz)) == 0 and sz.value > 0
+    bad = binding.make_problem(dict(workloads.disk3d_params(1000), k=65))
+    assert lib.gd_workspace_size(C.byref(bad), C.byref(sz)) == -1
+    assert b"k = 65" in lib.gd_last_error()
+    bad = binding.make_problem(dict(workloads.const_box_params(1000), t0=0.0))
+    assert lib.gd_workspace_size(C.byref(bad), C.byref(sz)) == -1
+    assert lib.gd_interval_init(None, 1.0, None) == -1
+    s = binding.GdParticles()
+    nb = binding.GdNeighbors()
+    # NULL arrays are rejected before any launch
+    assert lib.gd_build_neighbors(C.byref(P), C.byref(s), C.byref(s), C.byref(nb), None, 0, None) == -1
+    assert lib.gd_push(C.byref(P), None, None, 1.0, None, 0, None) == -1
+    assert lib.gd_status_read(None, None, None) == -1
+    # a workspace that is too small is reported as such
+    fake = binding.GdParticles()
+    for k in ("id", "x", "y", "z", "M", "r", "th", "ph", "vr", "lth", "lph"):
+        setattr(fake, k, 256)
+    fake.m[0] = 256
+    fake.m[1] = 512
+    other = binding.GdParticles()
+    for k in ("id", "x", "y", "z", "M", "r", "th", "ph", "vr", "lth", "lph"):
+        setattr(other, k, 1024)
+    other.m[0] = 1024
+    other.m[1] = 2048
+    nb = binding.GdNeighbors(4096, 4096, 4096, None)
+    rc = lib.gd_build_neighbors(C.byref(P), C.byref(fake), C.byref(other), C.byref(nb), C.c_void_p(256), 16, None)
+    assert rc == -2 and b"workspace" in lib.gd_last_error()
+    rc = lib.gd_build_neighbors(C.byref(P), C.byref(fake), C.byref(fake), C.byref(nb), C.c_void_p(256), 1 << 40, None)
+    assert rc == -1 and b"alias" in lib.gd_last_error()
+    rc = lib.gd_sample_collisions(C.byref(P), C.byref(fake), C.byref(nb), C.c_void_p(256), C.c_void_p(256), 1,
+                                  1 << 33, None, None, 0, C.c_void_p(256), 1 << 40, None)
+    assert rc == -1 and b"interval_index" in lib.gd_last_error()
+
+
+def test_problem_rmax_default_is_infinite():
+    from paper_2609_35967_amd import binding
+    assert math.isinf(binding.make_problem(workloads.const_box_params()).rmax)

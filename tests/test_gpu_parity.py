@@ -1,0 +1,333 @@
+"""GPU parity of the C-ABI library against the CPU oracle.
+
+Bars: Morton permutation and neighbour lists bit-exact; dimensionless rates
+bit-exact, physical rates within 1e-12 relative; plan decisions identical;
+sampled events identical except particles the oracle flags as near-ties
+(a decision within 1e-12 of its threshold); push within a few ulp.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2609_35967_amd import Engine, load  # noqa: E402
+
+
+def _say(*a):
+    print("[gpu]", *a, flush=True)
+
+
+def _engine(params, st, seed=0):
+    load()
+    return Engine(params, st, seed=seed)
+
+
+def _check_permutation(eng, st):
+    got = eng.state_numpy()
+    keys = oracle.morton_keys(st["x"], st["y"], st["z"], st["M"])
+    perm = oracle.sort_perm(keys)
+    assert np.array_equal(got["id"].astype(np.int64), st["id"][perm].astype(np.int64))
+    for k in ("x", "y", "z", "M", "m"):
+        assert np.array_equal(got[k], st[k][perm]), k
+    return got
+
+
+def _knn_compare(eng, params, got, queries=None):
+    P = oracle.make_problem(params)
+    nbr_o, cnt_o, dmax_o = oracle.knn(P, got["x"], got["y"], got["z"], got["M"], queries=queries)
+    nbr = eng.nbr.cpu().numpy()
+    cnt = eng.cnt.cpu().numpy()
+    dmax = eng.dmax.cpu().numpy()
+    if queries is not None:
+        nbr, cnt, dmax = nbr[queries], cnt[queries], dmax[queries]
+    bad = np.nonzero((nbr != nbr_o).any(1) | (cnt != cnt_o) | (dmax != dmax_o))[0]
+    assert len(bad) == 0, f"{len(bad)} rows differ, first {bad[:5]}"
+
+
+def _perturb_inactive(st, every):
+    st = dict(st)
+    st["M"] = st["M"].copy()
+    st["M"][::every] = 0.0
+    return st
+
+
+# ------------------------------------------------------------------ kNN ----
+@pytest.mark.parametrize("case", ["const_box", "const_box_ragged", "lattice", "lattice_jitter", "inactive", "rmax",
+                                  "tiny", "k_small", "k_large"])
+def test_build_neighbors_box(case):
+    params = workloads.const_box_params(4096)
+    if case == "const_box":
+        st = workloads.const_box(1, 4096)
+    elif case == "const_box_ragged":
+        st = workloads.const_box(2, 4000 + 37)
+    elif case == "lattice":
+        st = workloads.lattice_box(16)
+    elif case == "lattice_jitter":
+        st = workloads.lattice_box(16, jitter=1e-9, seed=3)
+    elif case == "inactive":
+        st = _perturb_inactive(workloads.const_box(4, 3000), 7)
+    elif case == "rmax":
+        st = workloads.const_box(5, 3000)
+        params = dict(params, rmax=0.08)
+    elif case == "tiny":
+        st = workloads.const_box(6, 20)
+    elif case == "k_small":
+        st = workloads.const_box(7, 2500)
+        params = dict(params, k=2)
+    else:
+        st = workloads.const_box(8, 2500)
+        params = dict(params, k=64)
+    _say("knn", case, len(st["x"]))
+    eng = _engine(params, st)
+    eng.build_neighbors()
+    torch.cuda.synchronize()
+    got = _check_permutation(eng, st)
+    _knn_compare(eng, params, got)
+    assert int(eng.n_active.item()) == int((st["M"] > 0).sum())
+
+
+def test_build_neighbors_column_periodic_xy():
+    params = workloads.additive_col_params(65536)
+    st = workloads.additive_col(1, 65536)
+    _say("knn column 65536")
+    eng = _engine(params, st)
+    eng.build_neighbors()
+    torch.cuda.synchronize()
+    got = _check_permutation(eng, st)
+    _knn_compare(eng, params, got, queries=np.arange(0, 65536, 13))
+
+
+@pytest.mark.parametrize("n", [32768, 1 << 20])
+def test_build_neighbors_disk(n):
+    params = workloads.disk3d_params(n)
+    st = workloads.disk3d(3, n, params=params)
+    _say("knn disk", n)
+    eng = _engine(params, st)
+    eng.build_neighbors()
+    torch.cuda.synchronize()
+    got = _check_permutation(eng, st)
+    q = None if n <= 32768 else np.random.default_rng(0).choice(n, 1500, replace=False)
+    _knn_compare(eng, params, got, queries=q)
+
+
+# ---------------------------------------------------------------- rates ----
+def _rates_compare(params, st, rtol, queries=None):
+    eng = _engine(params, st)
+    eng.build_neighbors()
+    n, k = eng.n, eng.P.k
+    lp = torch.empty((n, k), dtype=torch.float64, device="cuda")
+    ab = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    eng.collision_rates(lam_pair=lp, ab=ab)
+    torch.cuda.synchronize()
+    got = eng.state_numpy()
+    P = oracle.make_problem(params)
+    nbr, cnt, dmax = eng.nbr.cpu().numpy(), eng.cnt.cpu().numpy(), eng.dmax.cpu().numpy()
+    lam_o, a_o, b_o, pairs_o = oracle.rates(P, nbr, cnt, dmax, got["m"], got["M"], got["x"], got["y"], got["z"],
+                                            want_pairs=True, queries=queries)
+    lam, lp, ab = eng.lam.cpu().numpy(), lp.cpu().numpy(), ab.cpu().numpy()
+    a, b = ab[:n], ab[n:]
+    if queries is not None:
+        lam, lp, a, b = lam[queries], lp[queries], a[queries], b[queries]
+    if rtol == 0:
+        assert np.array_equal(lam, lam_o)
+        assert np.array_equal(lp, pairs_o)
+    else:
+        np.testing.assert_allclose(lam, lam_o, rtol=rtol, atol=0)
+        np.testing.assert_allclose(lp, pairs_o, rtol=rtol, atol=0)
+    np.testing.assert_allclose(a, a_o, rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(b, b_o, rtol=1e-12, atol=1e-300)
+    return eng, got, (nbr, cnt, dmax), (lam_o, a_o, b_o)
+
+
+@pytest.mark.parametrize("kernel", ["const", "additive", "product"])
+def test_rates_dimensionless_bit_exact(kernel):
+    params = dict(workloads.additive_col_params(20000), kernel=kernel)
+    st = workloads.additive_col(2, 20000)
+    _say("rates", kernel)
+    _rates_compare(params, st, 0)
+
+
+@pytest.mark.parametrize("warm", [False, True])
+def test_rates_physical(warm):
+    n = 32768
+    params = workloads.disk3d_params(n)
+    st = workloads.disk3d(4, n, warm=warm, params=params)
+    _say("rates physical warm" if warm else "rates physical")
+    _rates_compare(params, st, 1e-12)
+
+
+def test_rates_physical_full_size_sampled():
+    n = 1 << 20
+    params = workloads.disk3d_params(n)
+    st = workloads.disk3d(5, n, warm=True, params=params)
+    _say("rates physical 1M sampled")
+    q = np.random.default_rng(1).choice(n, 4000, replace=False)
+    _rates_compare(params, st, 1e-12, queries=q)
+
+
+# ------------------------------------------------------- plan + sampling ----
+def _interval_compare(params, st, seed, interval_index=0, log_cap=8, queries=None):
+    eng = _engine(params, st, seed=seed)
+    eng.interval = interval_index
+    eng.build_neighbors()
+    eng.collision_rates()
+    n = eng.n
+    log = torch.full((n, log_cap), -1, dtype=torch.int32, device="cuda")
+    got = eng.state_numpy()
+    ivs0 = eng.interval_state()
+    eng.sample_collisions(log=log, log_cap=log_cap, flip=False)
+    torch.cuda.synchronize()
+    ivs = eng.interval_state()
+    P = oracle.make_problem(params)
+    nbr, cnt, dmax = eng.nbr.cpu().numpy(), eng.cnt.cpu().numpy(), eng.dmax.cpu().numpy()
+    lam_o, a_o, b_o, _ = oracle.rates(P, nbr, cnt, dmax, got["m"], got["M"], got["x"], got["y"], got["z"])
+    pl = oracle.plan(P, got["m"], got["M"], a_o, b_o, params["dt_coll"], 0, 1.0)
+    if pl["margin"] > 1e-12:
+        assert ivs0["dt_exe"] == pl["dt_exe"] and ivs0["exe_ticks"] == pl["exe_ticks"]
+        assert ivs0["dt_req"] == pytest.approx(pl["dt_req"], rel=1e-12)
+    res = oracle.mc(P, got["id"], nbr, cnt, dmax, got["m"], got["M"], got["x"], got["y"], got["z"],
+                    ivs0["dt_exe"], seed, interval_index, log_cap=log_cap, queries=queries)
+    m_new = (eng.A.t["m1"] if eng.A.cur == 0 else eng.A.t["m0"]).cpu().numpy()
+    ev = eng.events.cpu().numpy()
+    lg = log.cpu().numpy()
+    if queries is not None:
+        m_new, ev, lg = m_new[queries], ev[queries], lg[queries]
+    ok = ~res["near_tie"]
+    ntie = int((~ok).sum())
+    same_ev = ev[ok] == res["events"][ok]
+    assert same_ev.all(), f"event counts differ at {np.nonzero(~same_ev)[0][:5]}"
+    if params["kernel"] == "physical":
+        np.testing.assert_allclose(m_new[ok], res["m"][ok], rtol=1e-12, atol=0)
+    else:
+        assert np.array_equal(m_new[ok], res["m"][ok])
+    slot = np.where(lg >= 0, lg & 0xFFFF, -1)
+    ch = np.where(lg >= 0, (lg >> 16) & 0xFF, -1)
+    typ = np.where(lg >= 0, (lg >> 24) & 0xFF, -1)
+    assert np.array_equal(slot[ok], res["log_slot"][ok])
+    assert np.array_equal(ch[ok], res["log_chan"][ok])
+    assert np.array_equal(typ[ok], res["log_type"][ok])
+    au = oracle.audit(P, got["m"], res["m"] if queries is None else got["m"], got["M"], pl["group_of"], pl["gM"], 1.0)
+    if queries is None and au["margin"] > 1e-12 and ntie == 0:
+        assert ivs["C"] == au["C"]
+        assert ivs["audit_worst"] == pytest.approx(au["worst"], rel=1e-12, abs=1e-300)
+    assert ivs["n_events"] == int(ev.sum()) or queries is not None
+    return ntie, int(res["events"].sum())
+
+
+def test_sample_constant_kernel():
+    params = workloads.const_box_params(4096)
+    st = workloads.const_box(3, 4096)
+    # push the first interval's masses apart so later intervals are exercised too
+    ntie, nev = _interval_compare(dict(params, dt_fn_max=2.0, dt_coll=2.0, eps=1.0), st, seed=7)
+    _say("sample const: events", nev, "near-ties", ntie)
+    assert nev > 1000 and ntie <= 2
+
+
+def test_sample_additive_column():
+    params = dict(workloads.additive_col_params(30000), dt_fn_max=0.5, dt_coll=0.5, eps=1.0)
+    st = workloads.additive_col(5, 30000)
+    ntie, nev = _interval_compare(params, st, seed=11)
+    _say("sample additive: events", nev, "near-ties", ntie)
+    assert nev > 1000 and ntie <= 3
+
+
+@pytest.mark.parametrize("warm", [False, True])
+def test_sample_physical(warm):
+    n = 32768
+    params = dict(workloads.disk3d_params(n), eps=10.0)
+    st = workloads.disk3d(6, n, warm=warm, params=params)
+    ntie, nev = _interval_compare(params, st, seed=13, interval_index=5)
+    _say("sample physical warm" if warm else "sample physical", "events", nev, "near-ties", ntie)
+    assert ntie <= 5
+
+
+def test_sample_physical_fragmentation_erosion():
+    n = 16384
+    params = dict(workloads.disk3d_params(n), eps=10.0, v_frag=1e-3)
+    st = workloads.disk3d(7, n, warm=True, params=params)
+    ntie, nev = _interval_compare(params, st, seed=17, interval_index=2)
+    _say("sample physical fast: events", nev, "near-ties", ntie)
+    assert nev > 100 and ntie <= 5
+
+
+# ------------------------------------------------------------------ push ----
+def test_push_local_matches_oracle():
+    params = workloads.additive_col_params(50000)
+    st = workloads.additive_col(8, 50000)
+    st["vz"] = np.random.default_rng(3).normal(0, 0.1, 50000)
+    eng = _engine(params, st)
+    for dt in (0.2, 0.013):
+        eng.push(dt=dt)
+        torch.cuda.synchronize()
+        st["z"], st["vz"] = oracle.push_local(st["z"], st["vz"], st["st_mid"], st["M"], dt)
+        got = eng.state_numpy()
+        np.testing.assert_allclose(got["z"], st["z"], rtol=4e-15, atol=1e-300)
+        np.testing.assert_allclose(got["vz"], st["vz"], rtol=4e-15, atol=1e-300)
+
+
+@pytest.mark.parametrize("warm", [False, True])
+def test_push_global_matches_oracle(warm):
+    n = 50000
+    params = workloads.disk3d_params(n)
+    st = workloads.disk3d(9, n, warm=warm, params=params)
+    eng = _engine(params, st)
+    P = oracle.make_problem(params)
+    ref = {k: st[k].copy() for k in ("r", "th", "ph", "vr", "lth", "lph", "m", "M", "x", "y", "z")}
+    for dt in (params["dt_coll"], params["dt_coll"] / 7):
+        eng.push(dt=dt)
+        torch.cuda.synchronize()
+        ref = oracle.push_global(P, ref, dt)
+        got = eng.state_numpy()
+        for k in ("r", "th", "ph", "x", "y", "z"):
+            np.testing.assert_allclose(got[k], ref[k], rtol=1e-13, atol=0, err_msg=k)
+        for k in ("vr", "lth", "lph"):
+            scale = np.abs(ref["lph"]).max() if k != "vr" else np.abs(ref["vr"]).max() + 1.0
+            np.testing.assert_allclose(got[k], ref[k], rtol=1e-11, atol=1e-13 * scale, err_msg=k)
+        assert np.array_equal(got["M"], ref["M"])
+
+
+# ------------------------------------------------------- whole intervals ----
+def test_constant_kernel_run_free_running():
+    """Config-1 loop (kNN once, static positions) against the oracle, interval by interval."""
+    from oracle.pipeline import OracleRun
+    params = workloads.const_box_params(4096)
+    st = workloads.const_box(0, 4096)
+    eng = _engine(params, st, seed=0)
+    run = OracleRun(params, st, seed=0)
+    eng.build_neighbors()
+    run.build_neighbors()
+    for it in range(60):
+        eng.step(rebuild=False)
+        r = run.step(rebuild=False)
+        if r["mc"]["near_tie"].any():
+            _say("near tie at interval", it)
+            return
+    torch.cuda.synchronize()
+    got = eng.state_numpy()
+    assert np.array_equal(got["m"], run.st["m"])
+    ivs = eng.interval_state()
+    assert ivs["C"] == run.C and ivs["ticks"] == run.ticks and ivs["n_intervals"] == 60
+
+
+def test_determinism_and_status():
+    params = workloads.disk3d_params(65536)
+    st = workloads.disk3d(10, 65536, warm=True, params=params)
+    outs = []
+    for rep in range(2):
+        eng = _engine(dict(params, eps=5.0), st, seed=3)
+        for _ in range(3):
+            eng.step()
+        torch.cuda.synchronize()
+        outs.append(eng.state_numpy())
+        assert eng.status() & 0x1 == 0
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
