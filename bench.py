@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Throughput of the collision hot path on one MI355X.
+
+One step = one frozen-neighbour interval of the whole path on the 3D disk
+annulus (1,048,576 particles, k = 32, full physics):
+
+    gd_build_neighbors -> gd_collision_rates -> gd_sample_collisions -> gd_push
+
+Inputs are resident in HBM before the timed region.  Prints one JSON line:
+particle-intervals/s (the plain single-run form), per-interval p50/p99
+latency, the dominant kernel against its roofline (timed live with HIP
+events on the launch stream), and the CPU oracle timed on a bounded sample of
+the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VEC_PEAK_TFLOPS = 78.6    # MI355X FP64 vector (FMA = 2 flops)
+
+# Algorithmic (compulsory) HBM bytes per particle and launch, for the disk
+# workload (k = 32, FP64); see the design notes for the derivation.
+ALGO_BYTES = {
+    "sort": 40 + 4 * 16 + 232,     # keys (read pos 24 + M 8, write key+slot 8); 4 radix passes; permute state
+    "tree": 4 + 4 + 64,            # keys, parent links, node record
+    "knn_query": 24 + 128 + 4 + 8,  # own position; write nbr row, cnt, d_i
+    "rates": 128 + 4 + 8 + 24 + 8 + 16 + 24,  # nbr row, cnt, d_i, position, m, snapshot s/N; write lam, a, b
+    "mc": 4 + 8 + 8 + 4 + 8 + 4,   # cnt, lam, m, id; write m', events
+    "audit": 24,                   # m, m', M
+    "push": 64 + 72,               # read spherical state, m, M; write state and Cartesian cache
+}
+PROF_KERNELS = ("sort", "tree", "knn_query", "rates", "mc", "audit", "push")
+
+
+class HipEvents:
+    """Raw hipEvent_t handles (the library records them on its launch stream)."""
+
+    def __init__(self):
+        self.lib = C.CDLL("libamdhip64.so")
+        self.lib.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+        self.lib.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self.lib.hipEventDestroy.argtypes = [C.c_void_p]
+
+    def create(self):
+        e = C.c_void_p()
+        if self.lib.hipEventCreate(C.byref(e)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+        return e
+
+    def elapsed_ms(self, a, b) -> float:
+        ms = C.c_float()
+        rc = self.lib.hipEventElapsedTime(C.byref(ms), a, b)
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed ({rc})")
+        return float(ms.value)
+
+    def destroy(self, e):
+        self.lib.hipEventDestroy(e)
+
+
+def kernel_times(eng, hip, names, steps):
+    """Run `steps` intervals with events around each named kernel; mean ms per launch."""
+    import torch
+    from paper_2609_35967_amd import binding
+    pairs = {k: [(hip.create(), hip.create()) for _ in range(steps)] for k in names}
+    for s in range(steps):
+        for k in names:
+            a, b = pairs[k][s]
+            binding.check(eng.lib.gd_profile_events(binding.PROF[k], a, b))
+        eng.step()
+    torch.cuda.synchronize()
+    for k in names:
+        binding.check(eng.lib.gd_profile_events(binding.PROF[k], None, None))
+    out = {}
+    for k in names:
+        t = [hip.elapsed_ms(a, b) for a, b in pairs[k]]
+        out[k] = float(np.mean(t))
+        for a, b in pairs[k]:
+            hip.destroy(a)
+            hip.destroy(b)
+    return out
+
+
+def cpu_baseline(params, seed, n, nq):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload:
+    Morton order of all particles, then brute-force kNN, rates and sampling of
+    one interval for `nq` sampled particles."""
+    import oracle
+    st = workloads.disk3d(seed, n, params=params)
+    P = oracle.make_problem(params)
+    t0 = time.perf_counter()
+    perm = oracle.sort_perm(oracle.morton_keys(st["x"], st["y"], st["z"], st["M"]))
+    s = {k: v[perm] for k, v in st.items()}
+    q = np.sort(np.random.default_rng(seed).choice(n, nq, replace=False))
+    nbr_q, cnt_q, dmax_q = oracle.knn(P, s["x"], s["y"], s["z"], s["M"], queries=q)
+    nbr = np.full((n, P.k), -1, np.int32)
+    cnt = np.zeros(n, np.int32)
+    dmax = np.zeros(n)
+    nbr[q], cnt[q], dmax[q] = nbr_q, cnt_q, dmax_q
+    oracle.rates(P, nbr, cnt, dmax, s["m"], s["M"], s["x"], s["y"], s["z"], queries=q)
+    oracle.mc(P, s["id"], nbr, cnt, dmax, s["m"], s["M"], s["x"], s["y"], s["z"], params["dt_coll"], seed, 0,
+              queries=q)
+    t = time.perf_counter() - t0
+    return dict(value=nq / t, unit="particle-intervals/s", cores=oracle.num_threads(), kind="oracle",
+                sample=(f"one interval (Morton order of all {n} particles, brute-force kNN + rates + sampling "
+                        f"for {nq} sampled particles, dt = dt_coll) in {t:.1f} s"))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="disk3d", choices=["disk3d", "disk3d_warm"])
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-sample", type=int, default=4096, help="particles in the oracle's timed sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs the single-GPU path only (asked for --gpus {args.gpus}); the multi-GPU "
+              "split is a design note, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2609_35967_amd import Engine, load
+
+    load()
+    torch.cuda.set_device(0)
+    params, st = workloads.by_name(args.workload, seed=args.seed, n=args.n)
+    eng = Engine(params, st, seed=args.seed)
+    n = eng.n
+    hip = HipEvents()
+    for _ in range(args.warmup):
+        eng.step()
+    torch.cuda.synchronize()
+    # per-kernel breakdown on a short pass (untimed for the headline)
+    brk = kernel_times(eng, hip, PROF_KERNELS, max(5, min(20, args.steps // 4)))
+    dom = max(brk, key=brk.get)
+
+    # timed region: the headline loop; events per interval and around the dominant kernel
+    from paper_2609_35967_amd import binding
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    dpairs = [(hip.create(), hip.create()) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record()
+    for s in range(args.steps):
+        a, b = dpairs[s]
+        eng.lib.gd_profile_events(binding.PROF[dom], a, b)
+        eng.step()
+        ev[s + 1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    binding.check(eng.lib.gd_profile_events(binding.PROF[dom], None, None))
+    lat = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
+    dom_ms = float(np.mean([hip.elapsed_ms(a, b) for a, b in dpairs]))
+    ivs = eng.interval_state()
+    status = eng.status()
+    wall = t1 - t0
+    value = n * args.steps / wall
+
+    achieved = ALGO_BYTES[dom] * n / (dom_ms * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=None, kernel=dom,
+                    algo_bytes_per_particle=ALGO_BYTES[dom], launch_ms=round(dom_ms, 4))
+    path_bytes = sum(ALGO_BYTES.values())
+    out = dict(
+        metric="particle-intervals/s (kNN+rates+MC) at 1M; batched vs plain; p50/p99 latency",
+        value=round(value, 1), unit="particle-intervals/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(wall / args.steps * 1e3, 4), higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64", data="synthetic",
+        config=dict(workload=f"{args.workload}: 3D disk annulus r in [10,100] au, {n} particles, k=32, "
+                             "alpha=1e-3, v_frag=1 m/s, Brownian+OC07, sticking/erosion/fragmentation, "
+                             "one push per interval", n_particles=n, k=32, form="plain (single run)"),
+        p50_ms=round(float(np.percentile(lat, 50)), 4), p99_ms=round(float(np.percentile(lat, 99)), 4),
+        breakdown_ms={k: round(v, 4) for k, v in brk.items()},
+        path_fraction_of_hbm=round(path_bytes * value / (HBM_PEAK_GBS * 1e9), 5),
+        roofline=roofline,
+        interval=dict(dt_exe=ivs["dt_exe"], C=ivs["C"], n_events_last=ivs["n_events"], status=status),
+    )
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(params, args.seed, n, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

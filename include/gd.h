@@ -152,6 +152,11 @@ typedef struct gd_interval {
 /* Bytes of workspace needed for problem p (writes *bytes). */
 int32_t gd_workspace_size(const gd_problem* p, size_t* bytes);
 
+/* Prepare a fresh workspace for problem p: clear its device status word and
+ * header.  Call once after allocating the workspace (its contents are
+ * otherwise undefined); enqueued on `stream`. */
+int32_t gd_workspace_init(const gd_problem* p, void* ws, size_t ws_bytes, void* stream);
+
 /* Set *iv (device) to dt_coll, C = 1, zero ticks/time/counters. */
 int32_t gd_interval_init(gd_interval* iv, double dt_coll, void* stream);
 
@@ -199,6 +204,25 @@ int32_t gd_sample_collisions(const gd_problem* p, const gd_particles* st, const 
  * [r_in, r_out] get M = 0 (inactive). */
 int32_t gd_push(const gd_problem* p, const gd_particles* st, const gd_interval* iv, double dt,
                 void* ws, size_t ws_bytes, void* stream);
+
+/* Kernels that gd_profile_events can bracket. */
+typedef enum gd_prof_kernel {
+    GD_PROF_SORT = 0,       /* bounding box, Morton keys, radix sort, permutation */
+    GD_PROF_TREE = 1,       /* radix-tree build and boxes */
+    GD_PROF_KNN_QUERY = 2,  /* neighbour query */
+    GD_PROF_RATES = 3,      /* snapshot, pair rates, controller bins, plan */
+    GD_PROF_MC = 4,         /* sampling kernel */
+    GD_PROF_AUDIT = 5,      /* audit reduction */
+    GD_PROF_PUSH = 6,       /* push */
+    GD_PROF_COUNT = 7
+} gd_prof_kernel;
+
+/* Diagnostics for measurement: from now on, record the HIP events `before`
+ * and `after` (hipEvent_t passed as void*, created by the caller) on the
+ * launch stream immediately before and after the kernels named by `which`
+ * at every call.  NULL, NULL stops recording.  Process-wide setting; the
+ * events stay owned by the caller. */
+int32_t gd_profile_events(int32_t which, void* before, void* after);
 
 /* Copy the device status word of the workspace to *out (bits GD_DEV_*), then
  * clear it.  Synchronises `stream`. */

@@ -58,8 +58,9 @@ class GdInterval(C.Structure):
     ]
 
 
-EXPORTS = ("gd_workspace_size", "gd_interval_init", "gd_build_neighbors", "gd_collision_rates",
-           "gd_sample_collisions", "gd_push", "gd_status_read", "gd_last_error", "gd_version")
+EXPORTS = ("gd_workspace_size", "gd_workspace_init", "gd_interval_init", "gd_build_neighbors", "gd_collision_rates",
+           "gd_sample_collisions", "gd_push", "gd_profile_events", "gd_status_read", "gd_last_error", "gd_version")
+PROF = {"sort": 0, "tree": 1, "knn_query": 2, "rates": 3, "mc": 4, "audit": 5, "push": 6}
 
 _lib = None
 
@@ -81,6 +82,7 @@ def load(path: str | None = None):
     vp = C.c_void_p
     L.gd_workspace_size.argtypes = [C.POINTER(GdProblem), C.POINTER(C.c_size_t)]
     L.gd_interval_init.argtypes = [vp, C.c_double, vp]
+    L.gd_workspace_init.argtypes = [C.POINTER(GdProblem), vp, C.c_size_t, vp]
     L.gd_build_neighbors.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.POINTER(GdParticles),
                                      C.POINTER(GdNeighbors), vp, C.c_size_t, vp]
     L.gd_collision_rates.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.POINTER(GdNeighbors), vp, vp,
@@ -89,10 +91,11 @@ def load(path: str | None = None):
                                        C.c_uint64, C.c_uint64, vp, vp, C.c_int32, vp, C.c_size_t, vp]
     L.gd_push.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), vp, C.c_double, vp, C.c_size_t, vp]
     L.gd_status_read.argtypes = [vp, vp, C.POINTER(C.c_int32)]
+    L.gd_profile_events.argtypes = [C.c_int32, vp, vp]
     L.gd_last_error.restype = C.c_char_p
     L.gd_version.restype = C.c_char_p
-    for name in ("gd_workspace_size", "gd_interval_init", "gd_build_neighbors", "gd_collision_rates",
-                 "gd_sample_collisions", "gd_push", "gd_status_read"):
+    for name in ("gd_workspace_size", "gd_workspace_init", "gd_interval_init", "gd_build_neighbors", "gd_collision_rates",
+                 "gd_sample_collisions", "gd_push", "gd_status_read", "gd_profile_events"):
         getattr(L, name).restype = C.c_int32
     if path is None:
         _lib = L
@@ -216,6 +219,7 @@ class Engine:
         self.ws_ptr = (base + 255) & ~255
         self.ws_bytes = sz.value
         self.nb = GdNeighbors(self.nbr.data_ptr(), self.cnt.data_ptr(), self.dmax.data_ptr(), self.n_active.data_ptr())
+        check(self.lib.gd_workspace_init(C.byref(self.P), C.c_void_p(self.ws_ptr), self.ws_bytes, self._s()))
         check(self.lib.gd_interval_init(C.c_void_p(self.iv.data_ptr()), float(params["dt_coll"]), self._s()))
 
     def _s(self):

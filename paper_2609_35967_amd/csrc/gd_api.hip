@@ -12,6 +12,13 @@
 namespace gd {
 
 static thread_local char g_err[512] = "";
+static hipEvent_t g_prof[GD_PROF_COUNT][2] = {};
+
+void prof_mark(int which, int after, hipStream_t st)
+{
+    hipEvent_t e = g_prof[which][after ? 1 : 0];
+    if (e) (void)hipEventRecord(e, st);
+}
 
 static int fail(int code, const char* fmt, ...)
 {
@@ -145,6 +152,17 @@ int32_t gd_workspace_size(const gd_problem* p, size_t* bytes)
     return GD_OK;
 }
 
+int32_t gd_workspace_init(const gd_problem* p, void* ws, size_t ws_bytes, void* stream)
+{
+    int rc = check_problem(p);
+    if (rc) return rc;
+    Layout L;
+    rc = check_ws(p, ws, ws_bytes, L);
+    if (rc) return rc;
+    launch_fill_i32(at<int32_t>(ws, L.hdr), int64_t(sizeof(WsHeader) / 4), 0, static_cast<hipStream_t>(stream));
+    return hip_ok("gd_workspace_init");
+}
+
 int32_t gd_interval_init(gd_interval* iv, double dt_coll, void* stream)
 {
     if (!iv) return fail(GD_E_INVALID_ARG, "interval is NULL");
@@ -250,6 +268,14 @@ int32_t gd_status_read(void* ws, void* stream, int32_t* out)
     hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, st, h);
     *out = v;
     return hip_ok("gd_status_read");
+}
+
+int32_t gd_profile_events(int32_t which, void* before, void* after)
+{
+    if (which < 0 || which >= GD_PROF_COUNT) return fail(GD_E_INVALID_ARG, "which = %d unknown", which);
+    g_prof[which][0] = static_cast<hipEvent_t>(before);
+    g_prof[which][1] = static_cast<hipEvent_t>(after);
+    return GD_OK;
 }
 
 const char* gd_last_error(void) { return g_err; }

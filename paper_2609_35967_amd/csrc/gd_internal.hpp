@@ -17,6 +17,7 @@ struct PermuteArgs {
 };
 
 DevProblem to_dev(const gd_problem* p);
+void prof_mark(int which, int after, hipStream_t st);
 
 int launch_morton_sort(const gd_problem* p, const gd_particles* in, gd_particles* out, void* ws, const Layout& L,
                        hipStream_t st);

@@ -490,9 +490,11 @@ int launch_lbvh_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const
     int32_t* rc = at<int32_t>(ws, L.rc);
     const double4* pos = at<double4>(ws, L.pos4);
     const int nb_ = int((n + 255) / 256);
+    prof_mark(GD_PROF_TREE, 0, st);
     launch_fill_i32(flags, n, 0, st);
     hipLaunchKernelGGL(k_lbvh_internal, dim3(nb_), dim3(256), 0, st, keys, h, nodes, parent, rc, n);
     hipLaunchKernelGGL(k_lbvh_boxes, dim3(nb_), dim3(256), 0, st, pos, h, nodes, parent, flags, rc, n);
+    prof_mark(GD_PROF_TREE, 1, st);
     KnnArgs A{};
     A.pos = pos;
     A.nodes = nodes;
@@ -513,6 +515,7 @@ int launch_lbvh_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const
     A.dmax = nb->dmax;
     A.ws = ws;
     const dim3 grid(unsigned((n + kQBlock - 1) / kQBlock));
+    prof_mark(GD_PROF_KNN_QUERY, 0, st);
     if (p->k <= 33) {
         if (per) hipLaunchKernelGGL((k_knn_query<true, 32>), grid, dim3(kQBlock), 0, st, A);
         else hipLaunchKernelGGL((k_knn_query<false, 32>), grid, dim3(kQBlock), 0, st, A);
@@ -520,6 +523,7 @@ int launch_lbvh_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const
         if (per) hipLaunchKernelGGL((k_knn_query<true, 64>), grid, dim3(kQBlock), 0, st, A);
         else hipLaunchKernelGGL((k_knn_query<false, 64>), grid, dim3(kQBlock), 0, st, A);
     }
+    prof_mark(GD_PROF_KNN_QUERY, 1, st);
     return 0;
 }
 

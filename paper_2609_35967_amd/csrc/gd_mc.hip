@@ -259,11 +259,15 @@ int launch_sample(const gd_problem* p, const gd_particles* s, const gd_neighbors
     A.ws = ws;
     A.ev_counter = reinterpret_cast<unsigned long long*>(&h->scratch[0]);
     const int g = int((n + 255) / 256);
+    prof_mark(GD_PROF_MC, 0, st);
     if (p->k <= 32) hipLaunchKernelGGL(k_mc<32>, dim3(g), dim3(256), 0, st, A);
     else hipLaunchKernelGGL(k_mc<64>, dim3(g), dim3(256), 0, st, A);
+    prof_mark(GD_PROF_MC, 1, st);
     double* part = at<double>(ws, L.part);
+    prof_mark(GD_PROF_AUDIT, 0, st);
     launch_bin_reduce(1, A.m, s->M, A.m_out, nullptr, n, part, ws, st);
     hipLaunchKernelGGL(k_audit, dim3(1), dim3(kNBin), 0, st, P, part, kRedBlocks, iv, h);
+    prof_mark(GD_PROF_AUDIT, 1, st);
     return 0;
 }
 

@@ -136,6 +136,7 @@ int launch_push(const gd_problem* p, const gd_particles* s, const gd_interval* i
     (void)L;
     const int64_t n = p->n;
     const int g = int((n + 255) / 256);
+    prof_mark(GD_PROF_PUSH, 0, st);
     if (p->push == GD_PUSH_LOCAL) {
         hipLaunchKernelGGL(k_push_local, dim3(g), dim3(256), 0, st, n, s->z, s->vz, s->st_mid, s->M, iv, dt);
     } else if (p->push == GD_PUSH_GLOBAL) {
@@ -156,6 +157,7 @@ int launch_push(const gd_problem* p, const gd_particles* s, const gd_interval* i
         A.dt_host = dt;
         hipLaunchKernelGGL(k_push_global, dim3(g), dim3(256), 0, st, A);
     }
+    prof_mark(GD_PROF_PUSH, 1, st);
     return 0;
 }
 

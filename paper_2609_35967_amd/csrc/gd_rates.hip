@@ -294,6 +294,7 @@ int launch_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors*
     const double* m = s->m[s->cur];
     double* snap_s = at<double>(ws, L.snap_s);
     double* snap_N = at<double>(ws, L.snap_N);
+    prof_mark(GD_PROF_RATES, 0, st);
     if (p->kernel == GD_KERNEL_PHYSICAL)
         hipLaunchKernelGGL(k_snapshot, dim3(g), dim3(256), 0, st, P, m, s->M, n, snap_s, snap_N);
     RatesArgs A{};
@@ -316,6 +317,7 @@ int launch_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors*
     double* part = at<double>(ws, L.part);
     launch_bin_reduce(0, m, s->M, A.a, A.b, n, part, ws, st);
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(kNBin), 0, st, P, part, kRedBlocks, iv, at<WsHeader>(ws, L.hdr), ws);
+    prof_mark(GD_PROF_RATES, 1, st);
     return 0;
 }
 

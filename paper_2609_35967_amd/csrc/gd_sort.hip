@@ -225,6 +225,7 @@ int launch_morton_sort(const gd_problem* p, const gd_particles* in, gd_particles
     const int64_t n = p->n;
     WsHeader* h = at<WsHeader>(ws, L.hdr);
     double* red = at<double>(ws, L.red);
+    prof_mark(GD_PROF_SORT, 0, st);
     hipLaunchKernelGGL(k_bbox_partial, dim3(kRedBlocks), dim3(256), 0, st, in->x, in->y, in->z, in->M, n, red);
     hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, red, kRedBlocks, h);
     uint32_t* k0 = at<uint32_t>(ws, L.keys0);
@@ -275,6 +276,7 @@ int launch_morton_sort(const gd_problem* p, const gd_particles* in, gd_particles
     A.id_dst = out->id;
     A.pos4 = at<double4>(ws, L.pos4);
     hipLaunchKernelGGL(k_permute, dim3(nb), dim3(256), 0, st, A);
+    prof_mark(GD_PROF_SORT, 1, st);
     out->cur = in->cur;
     return 0;
 }
