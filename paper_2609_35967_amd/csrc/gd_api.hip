@@ -77,6 +77,7 @@ static int check_problem(const gd_problem* p)
     if (p->n < 0 || p->n >= (int64_t(1) << 31) - 1) return fail(GD_E_INVALID_ARG, "n = %lld out of range", (long long)p->n);
     if (p->k < 2 || p->k > kMaxK) return fail(GD_E_INVALID_ARG, "k = %d outside 2..%d", p->k, kMaxK);
     if (p->n * int64_t(p->k) >= (int64_t(1) << 31)) return fail(GD_E_UNSUPPORTED, "n * k must stay below 2^31");
+    if (p->n > (int64_t(kBucket) << (3 * kMaxTreeLevels))) return fail(GD_E_UNSUPPORTED, "n must stay below 2^26");
     if (p->kernel < 0 || p->kernel > 3) return fail(GD_E_INVALID_ARG, "kernel = %d unknown", p->kernel);
     if (p->push < 0 || p->push > 2) return fail(GD_E_INVALID_ARG, "push = %d unknown", p->push);
     for (int a = 0; a < 3; ++a)
@@ -198,7 +199,7 @@ int32_t gd_build_neighbors(const gd_problem* p, const gd_particles* in, gd_parti
     if (p->n == 0) return GD_OK;
     launch_morton_sort(p, in, &o, ws, L, st);
     out->cur = in->cur;
-    launch_lbvh_knn(p, nb, ws, L, st);
+    launch_knn(p, nb, ws, L, st);
     if (nb->n_active) hipLaunchKernelGGL(k_copy_na, dim3(1), dim3(64), 0, st, at<WsHeader>(ws, L.hdr), nb->n_active);
     return hip_ok("gd_build_neighbors");
 }

@@ -17,6 +17,9 @@ constexpr int64_t kTicks = int64_t(1) << 30;  // ticks per collision step
 constexpr int kSortTile = 4096;     // keys per radix-sort block
 constexpr int kRedBlocks = 256;     // blocks of the bin reductions
 constexpr int kMaxK = 64;
+constexpr int kBucket = 4;          // particles per leaf bucket of the search tree
+constexpr int kFan = 8;             // children per internal node of the search tree
+constexpr int kMaxTreeLevels = 8;   // stored box levels (n <= 4 * 8^8 = 2^26 particles)
 constexpr double kPi = 3.14159265358979323846;
 
 // ---------------------------------------------------------------------------
@@ -33,14 +36,11 @@ struct DevProblem {
     int32_t drag, brownian, turbulence, caps;
 };
 
-// LBVH internal node: box, covered slot range [first, last], split position.
-// Children: left = split (leaf if split == first), right = split + 1 (leaf if
-// split + 1 == last).  rope = next node in depth-first order after the
-// subtree (-1: end).  Child/rope references: >= 0 internal node, < 0 leaf ~ref.
-struct alignas(16) Node {
-    double lo[3];
-    double hi[3];
-    int32_t first, last, split, rope;
+// Box of a node of the search tree, single precision rounded outward (lo
+// down, hi up), so it always contains the exact box of its particles.
+struct FBox {
+    float lo[3];
+    float hi[3];
 };
 
 // Device-resident header at the start of the workspace.
@@ -58,11 +58,18 @@ struct alignas(256) WsHeader {
 
 // Workspace layout (byte offsets), identical on host and device.
 struct Layout {
-    size_t hdr, keys0, keys1, vals0, vals1, hist, red, pos4, nodes, parent, flags, rc,
-        snap_s, snap_N, a, b, part, total;
+    size_t hdr, keys0, keys1, vals0, vals1, hist, red, pos4, boxes,
+        snap_s, snap_N, a, b, part, stats, total;
     int64_t n;
     int32_t k;
     int32_t nsort_blocks;
+    // implicit search tree: level l holds cnt[l] boxes (padded to a multiple
+    // of kFan) starting at box index off[l]; level 0 = buckets of kBucket
+    // slots, node i of level l >= 1 = children kFan*i .. kFan*i+7 of level l-1;
+    // the root's children are the (<= kFan) boxes of the top level.
+    int32_t levels;
+    int64_t lvl_cnt[kMaxTreeLevels];
+    int64_t lvl_off[kMaxTreeLevels];
 };
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -84,15 +91,29 @@ __host__ inline Layout make_layout(int64_t n, int32_t k)
     L.hist = take(4 * size_t(256) * (L.nsort_blocks + 1));
     L.red = take(sizeof(double) * 8 * kRedBlocks);
     L.pos4 = take(32 * nn);
-    L.nodes = take(sizeof(Node) * nn);
-    L.parent = take(4 * 2 * nn);
-    L.flags = take(4 * nn);
-    L.rc = take(4 * nn);
+    {
+        int64_t cnt = (int64_t(nn) + kBucket - 1) / kBucket, off = 0;
+        int l = 0;
+        for (;;) {
+            const int64_t padded = (cnt + kFan - 1) / kFan * kFan;
+            L.lvl_cnt[l] = cnt;
+            L.lvl_off[l] = off;
+            off += padded;
+            ++l;
+            if (cnt <= kFan || l == kMaxTreeLevels) break;
+            cnt = (cnt + kFan - 1) / kFan;
+        }
+        L.levels = l;
+        L.boxes = take(sizeof(FBox) * size_t(off));
+    }
     L.snap_s = take(8 * nn);
     L.snap_N = take(8 * nn);
     L.a = take(8 * nn);
     L.b = take(8 * nn);
     L.part = take(sizeof(double) * 8 * kNBin * kRedBlocks);
+#ifdef GD_KNN_STATS
+    L.stats = take(32 * nn);
+#endif
     L.total = o;
     return L;
 }

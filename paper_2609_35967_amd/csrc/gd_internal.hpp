@@ -22,7 +22,7 @@ void prof_mark(int which, int after, hipStream_t st);
 int launch_morton_sort(const gd_problem* p, const gd_particles* in, gd_particles* out, void* ws, const Layout& L,
                        hipStream_t st);
 void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t st);
-int launch_lbvh_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layout& L, hipStream_t st);
+int launch_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layout& L, hipStream_t st);
 int launch_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv, double* lam_i,
                  double* lam_pair, double* ab, void* ws, const Layout& L, hipStream_t st);
 int launch_sample(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,

@@ -61,8 +61,14 @@ def _perturb_inactive(st, every):
 
 
 # ------------------------------------------------------------------ kNN ----
+def _with_positions(st, x, y, z):
+    st = dict(st)
+    st["x"], st["y"], st["z"] = x.copy(), y.copy(), z.copy()
+    return st
+
+
 @pytest.mark.parametrize("case", ["const_box", "const_box_ragged", "lattice", "lattice_jitter", "inactive", "rmax",
-                                  "tiny", "k_small", "k_large"])
+                                  "tiny", "k_small", "k_large", "coincident", "clusters", "scales", "line"])
 def test_build_neighbors_box(case):
     params = workloads.const_box_params(4096)
     if case == "const_box":
@@ -83,9 +89,39 @@ def test_build_neighbors_box(case):
     elif case == "k_small":
         st = workloads.const_box(7, 2500)
         params = dict(params, k=2)
-    else:
+    elif case == "k_large":
         st = workloads.const_box(8, 2500)
         params = dict(params, k=64)
+    elif case == "coincident":
+        # groups of 50 particles at one point: all-zero distances, ties by slot
+        st = workloads.const_box(9, 2000)
+        x, y, z = st["x"].copy(), st["y"].copy(), st["z"].copy()
+        g = np.arange(600) // 50
+        x[:600], y[:600], z[:600] = x[g], y[g], z[g]
+        st = _with_positions(st, x, y, z)
+    elif case == "clusters":
+        # eight clusters of 1e-6 extent in a uniform background
+        st = workloads.const_box(10, 3000)
+        rng = np.random.default_rng(10)
+        x, y, z = st["x"].copy(), st["y"].copy(), st["z"].copy()
+        c = rng.uniform(0.1, 0.9, (8, 3))
+        for i in range(8):
+            sl = slice(200 * i, 200 * i + 200)
+            x[sl], y[sl], z[sl] = (c[i][None, :] + 1e-6 * rng.uniform(-1, 1, (200, 3))).T
+        st = _with_positions(st, x, y, z)
+    elif case == "scales":
+        # density over 18 decades: radii 10^U(-6, -0.4) about the centre
+        st = workloads.const_box(11, 3000)
+        rng = np.random.default_rng(11)
+        d = rng.normal(size=(3000, 3))
+        d /= np.linalg.norm(d, axis=1)[:, None]
+        r = 10.0 ** rng.uniform(-6, -0.4, 3000)
+        p = 0.5 + d * r[:, None]
+        st = _with_positions(st, p[:, 0], p[:, 1], p[:, 2])
+    else:
+        # all particles on one line (flat boxes)
+        st = workloads.const_box(12, 2000)
+        st = _with_positions(st, st["x"], np.full(2000, 0.25), np.full(2000, 0.75))
     _say("knn", case, len(st["x"]))
     eng = _engine(params, st)
     eng.build_neighbors()
