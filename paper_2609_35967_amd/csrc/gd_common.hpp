@@ -51,6 +51,7 @@ struct alignas(256) WsHeader {
     int32_t pad0;
     double lo[3];
     double inv;                  // Morton scale 1024 / extent
+    double hi[3];                // bounding box of the active particles: lo .. hi
     int32_t group_of[kNBin];     // plan: raw bin -> merged group (-1 empty)
     double gM[kNBin];            // plan: sum of M per merged group
     double scratch[16];

@@ -5,24 +5,30 @@
 // consecutive Morton slots; node i of level l holds the union of children
 // 8i..8i+7 of level l-1; the root's children are the (<= 8) boxes of the top
 // level.  No pointers: children and parents are index arithmetic, and the
-// 8 child boxes of a node are contiguous (192 bytes in single precision,
-// rounded outward), so one step of a walk issues its loads together.  A
-// million particles give 6 levels.
+// 8 child boxes of a node are contiguous (192 bytes), so one step of a walk
+// issues its loads together.  A million particles give 6 levels.  Boxes are
+// single precision, rounded outward and widened by a margin that absorbs the
+// rounding of the single-precision box tests, so a box is never pruned while
+// it holds a point within the search radius.
 //
-// Query: one lane per particle, stackless depth-first walk that keeps, per
-// level, the 8-bit mask of children still to visit (all levels in one 64-bit
-// register).  Exact selection of the k-1 nearest others:
-//   1. trial radius from the density of the smallest ancestor holding >= k
-//      slots (its box also bounds the k-th distance);
-//   2. pass A: count candidates inside the radius into 32 bins of d^2 (grow the
-//      radius until k-1 others are inside);
+// Query: one lane per particle, stackless walk that keeps, per level, the
+// 8-bit mask of children still to visit (all levels in one 64-bit register).
+// It starts at the level-1 ancestor of the query's bucket and climbs one
+// ancestor at a time, so the space near the query is seen first.  Exact
+// selection of the k-1 nearest others:
+//   1. upper bound R2init of the (k-1)-th d^2: the smallest, over three
+//      windows of k consecutive slots holding the query, of the window's
+//      largest d^2;
+//   2. pass A: count others into per-lane bins, logarithmic in d^2 / R2init;
+//      whenever the bins below some bin already hold k-1 others, cut the
+//      radius to that bin's upper edge (the walk prunes with the cut radius);
 //   3. the bin holding the (k-1)-th other splits candidates into "sure" (lower
 //      bins) and "boundary"; an over-full boundary bin is re-binned (nested,
-//      still monotone bins) until it holds <= 16 candidates;
-//   4. pass B: walk again inside the tightened radius, append sure slots to the
+//      linear, still monotone bins) until it holds <= 16 candidates;
+//   4. pass B: walk again inside the final radius, append sure slots to the
 //      output row, keep boundary slots, rank them by (d^2, slot);
 //   5. sort the retained others by slot in registers.
-// Per-lane scratch lives in LDS columns (no synchronisation).  d^2 is
+// Per-lane bins live in LDS columns (no synchronisation).  d^2 is
 // (dx*dx + dy*dy) + dz*dz, each operation rounded on its own; every bin
 // function is monotone in d^2, so the result is exactly the k-1 smallest
 // (d^2, slot).
@@ -44,9 +50,25 @@ struct TreeLevels {
     int64_t cap[kMaxTreeLevels];  // padded capacity of each level
 };
 
-// level 0: box of every bucket of kBucket active slots (empty beyond)
+struct Periodicity {
+    int32_t per[3];
+    double L[3];
+};
+
+// Margin of the single-precision box tests on axis a: 2^-21 (M + L), M the
+// largest coordinate magnitude of the active set, L the period on periodic
+// axes (whose images q +- L are tested).  Rounding q or q +- L to float and
+// the float subtraction move a gap by less than 3 * 2^-24 (M + L).
+__device__ inline double box_margin(const WsHeader* h, const Periodicity& P, int a)
+{
+    double M = fmax(fabs(h->lo[a]), fabs(h->hi[a]));
+    if (P.per[a]) M += fabs(P.L[a]);
+    return M * 0x1p-21;
+}
+
+// level 0: widened box of every bucket of kBucket active slots (empty beyond)
 __global__ __launch_bounds__(256) void k_bucket_boxes(const double4* __restrict__ pos, const WsHeader* __restrict__ h,
-                                                      FBox* __restrict__ box0, int64_t cap0)
+                                                      FBox* __restrict__ box0, int64_t cap0, Periodicity P)
 {
     const int na = h->n_active;
     const int64_t b = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
@@ -66,14 +88,17 @@ __global__ __launch_bounds__(256) void k_bucket_boxes(const double4* __restrict_
     }
     FBox x;
     for (int a = 0; a < 3; ++a) {
-        x.lo[a] = __double2float_rd(lo[a]);
-        x.hi[a] = __double2float_ru(hi[a]);
+        const double del = box_margin(h, P, a);
+        x.lo[a] = __double2float_rd(lo[a] - del);
+        x.hi[a] = __double2float_ru(hi[a] + del);
     }
     box0[b] = x;
 }
 
-// level l >= 1: union of the 8 children (empty children are empty boxes)
-__global__ __launch_bounds__(256) void k_level_boxes(const FBox* __restrict__ child, FBox* __restrict__ cur, int64_t cap)
+// level l >= 1: union of the 8 children; children past the stored capacity
+// of level l-1 (the padding of the levels above) are empty
+__global__ __launch_bounds__(256) void k_level_boxes(const FBox* __restrict__ child, int64_t child_cap,
+                                                     FBox* __restrict__ cur, int64_t cap)
 {
     const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (i >= cap) return;
@@ -83,6 +108,7 @@ __global__ __launch_bounds__(256) void k_level_boxes(const FBox* __restrict__ ch
         x.hi[a] = -INFINITY;
     }
     for (int c = 0; c < kFan; ++c) {
+        if (i * kFan + c >= child_cap) break;
         const FBox y = child[i * kFan + c];
         for (int a = 0; a < 3; ++a) {
             x.lo[a] = fminf(x.lo[a], y.lo[a]);
@@ -105,7 +131,6 @@ struct KnnArgs {
     double rmax2;
     int32_t per[3];
     double L[3], hL[3];
-    double tol;  // absolute slack of box distances on periodic axes
     int32_t* nbr;
     int32_t* cnt;
     double* dmax;
@@ -113,9 +138,9 @@ struct KnnArgs {
 };
 
 template <bool PER>
-__device__ inline double sep2(const KnnArgs& A, const double q[3], const double4 p)
+__device__ inline double sep2(const KnnArgs& A, const double q[3], double px, double py, double pz)
 {
-    double dx = p.x - q[0], dy = p.y - q[1], dz = p.z - q[2];
+    double dx = px - q[0], dy = py - q[1], dz = pz - q[2];
     if (PER) {
         if (A.per[0]) { if (dx > A.hL[0]) dx = dx - A.L[0]; else if (dx < -A.hL[0]) dx = dx + A.L[0]; }
         if (A.per[1]) { if (dy > A.hL[1]) dy = dy - A.L[1]; else if (dy < -A.hL[1]) dy = dy + A.L[1]; }
@@ -125,114 +150,150 @@ __device__ inline double sep2(const KnnArgs& A, const double q[3], const double4
     return s + dz * dz;
 }
 
-__device__ inline double gap(double x, double lo, double hi)
+template <bool PER>
+__device__ inline double sep2_slot(const KnnArgs& A, const double q[3], int j)
 {
-    return x < lo ? lo - x : (x > hi ? x - hi : 0.0);
+    const double* pj = reinterpret_cast<const double*>(A.pos + j);
+    const double2 xy = *reinterpret_cast<const double2*>(pj);
+    return sep2<PER>(A, q, xy.x, xy.y, pj[2]);
 }
 
-// Squared distance from q to a box, minimum image on periodic axes.  On open
-// axes lo <= p exactly and rounding is monotone, so the result never exceeds
-// the rounded d^2 of a point in the box; periodic images are covered by the
-// absolute slack of the walk.
-template <bool PER>
-__device__ inline double box2(const KnnArgs& A, const double q[3], const FBox& b)
+// the query point in single precision, with its periodic images
+struct QF {
+    float c[3], p[3], m[3];
+};
+
+__device__ inline float gapf(float x, float lo, float hi)
 {
-    double g[3];
+    return fmaxf(fmaxf(lo - x, x - hi), 0.0f);
+}
+
+// Lower bound of the squared distance from q to a (widened) box, minimum
+// image on periodic axes; its own float rounding is covered by r2f below.
+template <bool PER>
+__device__ inline float box2f(const KnnArgs& A, const QF& f, const FBox& b)
+{
+    float g[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double lo = b.lo[a], hi = b.hi[a];
-        double v = gap(q[a], lo, hi);
-        if (PER && A.per[a]) v = fmin(v, fmin(gap(q[a] + A.L[a], lo, hi), gap(q[a] - A.L[a], lo, hi)));
+        float v = gapf(f.c[a], b.lo[a], b.hi[a]);
+        if (PER && A.per[a]) v = fminf(v, fminf(gapf(f.p[a], b.lo[a], b.hi[a]), gapf(f.m[a], b.lo[a], b.hi[a])));
         g[a] = v;
     }
-    const double s = g[0] * g[0] + g[1] * g[1];
+    const float s = g[0] * g[0] + g[1] * g[1];
     return s + g[2] * g[2];
 }
 
-// mask of the children of node `idx` at `level` (>= 1) whose box may hold a
-// point within R2 of q
-template <bool PER>
-__device__ inline uint32_t child_mask(const KnnArgs& A, int level, int64_t idx, const double q[3], double R2)
+// Single-precision threshold of the box tests for radius R2: at least
+// R2 (1 + 2^-19), above the three rounded float operations of box2f.
+__device__ inline float r2f(double R2)
 {
-    double R2box = R2 * (1.0 + 1e-12);
-    if (PER) {
-        const double rb = sqrt(R2) * (1.0 + 1e-12) + A.tol;
-        R2box = rb * rb;
-    }
-    const FBox* ch = A.boxes + A.T.off[level - 1] + idx * kFan;
+    return float(R2 * (1.0 + 0x1p-19)) * (1.0f + 0x1p-22f);
+}
+
+// mask of the children of node `idx` at `level` (>= 1) whose box may hold a
+// point within the radius; empty boxes (the padding of a level, lo > hi) are
+// never entered, so a walk only reads children of stored nodes
+template <bool PER>
+__device__ inline uint32_t child_mask(const KnnArgs& A, int level, int idx, const QF& f, float R2f)
+{
+    const FBox* ch = A.boxes + A.T.off[level - 1] + int64_t(idx) * kFan;
     FBox b[kFan];
 #pragma unroll
     for (int c = 0; c < kFan; ++c) b[c] = ch[c];
     uint32_t m = 0;
 #pragma unroll
-    for (int c = 0; c < kFan; ++c) m |= (box2<PER>(A, q, b[c]) <= R2box ? 1u : 0u) << c;
+    for (int c = 0; c < kFan; ++c) m |= (box2f<PER>(A, f, b[c]) <= R2f && b[c].lo[0] <= b[c].hi[0] ? 1u : 0u) << c;
     return m;
 }
 
 // Visit every active slot j with d^2(q, j) <= R2 (j == q included; the
-// visitor filters).  The walk starts at the level-1 ancestor of q's bucket
-// and climbs one ancestor at a time, expanding the ancestor's other children
-// depth first, so the space near q is seen first.  The visitor may shrink R2
-// (never grow it); pruning uses the current value.  Returns the walk steps.
+// visitor filters), nearest region first: the level-1 ancestor of q's bucket,
+// then the other children of each further ancestor, depth first.  The
+// visitor may lower R2; pruning uses the current value.  One iteration does
+// at most one node expansion and one bucket scan, so the two paths of a
+// diverged wavefront share iterations.  Returns the walk steps.
 template <bool PER, class F>
-__device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], double& R2, F&& f)
+__device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], const QF& qf, double& R2, F&& f)
 {
     const int top = A.T.levels;  // the root sits one level above the stored ones
     int climb = 1, level = 1;
-    int64_t idx = (q / kBucket) >> 3;
-    uint64_t masks = child_mask<PER>(A, 1, idx, qp, R2);
-    int steps = 1;
+    int idx = (q / kBucket) >> 3;
+    uint32_t excl = 0;
+    uint64_t masks = 0;
+    bool pend = true;
+    float R2f = r2f(R2);
+    int steps = 0;
     for (;;) {
-        const int sh = 8 * (level - 1);
-        const uint32_t m = uint32_t(masks >> sh) & 0xFFu;
-        if (m == 0) {
+        if (pend) {
+            masks |= uint64_t(child_mask<PER>(A, level, idx, qf, R2f) & ~excl) << (8 * (level - 1));
+            excl = 0;
+            pend = false;
+            ++steps;
+        }
+        // next child to visit; climb when the ancestor's subtree is exhausted
+        int c = -1;
+        for (;;) {
+            const int sh = 8 * (level - 1);
+            const uint32_t m = uint32_t(masks >> sh) & 0xFFu;
+            if (m != 0) {
+                c = __ffs(m) - 1;
+                masks &= ~(uint64_t(1) << (sh + c));
+                break;
+            }
             if (level < climb) {
                 ++level;
                 idx >>= 3;
                 continue;
             }
-            if (climb == top) break;
-            // the ancestor at `climb` is done: expand its parent's other children
-            const int from = int(idx & 7);
-            ++climb;
-            level = climb;
-            idx >>= 3;
-            masks |= uint64_t(child_mask<PER>(A, level, idx, qp, R2) & ~(1u << from)) << (8 * (level - 1));
-            ++steps;
+            if (climb < top) {
+                excl = 1u << (idx & 7);
+                ++climb;
+                level = climb;
+                idx >>= 3;
+                pend = true;
+            }
+            break;
+        }
+        if (pend) continue;
+        if (c < 0) break;
+        const int child = idx * kFan + c;
+        if (level > 1) {
+            --level;
+            idx = child;
+            pend = true;
             continue;
         }
-        const int c = __ffs(m) - 1;
-        masks &= ~(uint64_t(1) << (sh + c));
-        const int64_t child = idx * kFan + c;
+        // a bucket: its particles are candidates
         ++steps;
-        if (level == 1) {
-            // a bucket: its particles are candidates
-            double4 p[kBucket];
+        double px[kBucket], py[kBucket], pz[kBucket];
 #pragma unroll
-            for (int t = 0; t < kBucket; ++t) {
-                const int64_t j = child * kBucket + t;
-                if (j < na) p[t] = A.pos[j];
+        for (int t = 0; t < kBucket; ++t) {
+            const int j = child * kBucket + t;
+            if (j < na) {
+                const double* pj = reinterpret_cast<const double*>(A.pos + j);
+                const double2 xy = *reinterpret_cast<const double2*>(pj);
+                px[t] = xy.x;
+                py[t] = xy.y;
+                pz[t] = pj[2];
             }
-#pragma unroll
-            for (int t = 0; t < kBucket; ++t) {
-                const int64_t j = child * kBucket + t;
-                if (j < na) {
-                    const double d2 = sep2<PER>(A, qp, p[t]);
-                    if (d2 <= R2) f(int(j), d2);
-                }
-            }
-            continue;
         }
-        --level;
-        idx = child;
-        masks |= uint64_t(child_mask<PER>(A, level, idx, qp, R2)) << (8 * (level - 1));
+#pragma unroll
+        for (int t = 0; t < kBucket; ++t) {
+            const int j = child * kBucket + t;
+            if (j < na) {
+                const double d2 = sep2<PER>(A, qp, px[t], py[t], pz[t]);
+                if (d2 <= R2) f(j, d2);
+            }
+        }
+        R2f = r2f(R2);
     }
     return steps;
 }
 
 // First-level bins: logarithmic in x = d^2 / R2init, 8 per octave over 8
 // octaves, read off the bits of the double (monotone for x >= 0); bin 0 takes
-// everything below 2^-8 (x * 2^(1/8)), the last bin everything from 2^(-1/8).
+// everything below 2^-8 * 2^(1/8), the last bin everything from 2^(-1/8).
 constexpr int kLogShift = 49;
 constexpr int64_t kLogBase = int64_t(1023) * 8 - kNB;
 
@@ -299,6 +360,7 @@ __device__ inline int classify(const Chain& c, double d2)
 
 // Per-lane 16-bit bin counters in LDS: bin b of lane t is half (b & 1) of
 // word (b >> 1) * kQBlock + t (a private column, free of bank conflicts).
+// A lane counts fewer than 2^16 - 1 candidates in all, so no counter wraps.
 __device__ inline void hist_clear(uint32_t* lds, int tid)
 {
     for (int w = 0; w < kNB / 2; ++w) lds[w * kQBlock + tid] = 0;
@@ -309,14 +371,9 @@ __device__ inline int hist_get(const uint32_t* lds, int tid, int b)
     return int((lds[(b >> 1) * kQBlock + tid] >> (16 * (b & 1))) & 0xFFFFu);
 }
 
-// returns false (and counts nothing) once the counter is saturated
-__device__ inline bool hist_inc(uint32_t* lds, int tid, int b)
+__device__ inline void hist_inc(uint32_t* lds, int tid, int b)
 {
-    uint32_t* w = lds + (b >> 1) * kQBlock + tid;
-    const uint32_t v = *w;
-    if (((v >> (16 * (b & 1))) & 0xFFFFu) == 0xFFFFu) return false;
-    *w = v + (1u << (16 * (b & 1)));
-    return true;
+    lds[(b >> 1) * kQBlock + tid] += 1u << (16 * (b & 1));
 }
 
 template <int N>
@@ -339,6 +396,8 @@ __device__ inline void bitonic_sort(int32_t (&v)[N])
         }
     }
 }
+
+constexpr int kCandMax = 0xFFFF - 1;  // candidates counted per lane before the counters are distrusted
 
 template <bool PER, int KP2>
 __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
@@ -365,10 +424,10 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
     const double4 q4 = A.pos[q];
     const double qp[3] = {q4.x, q4.y, q4.z};
 
-    // 1. upper bound of the (k-1)-th distance: the smallest, over three windows
-    //    of k consecutive slots holding q (ending at, centred on, starting at
-    //    q), of the largest d^2 in the window; with fewer than k slots, all.
+    // 1. upper bound of the (k-1)-th d^2 from three windows of k slots holding
+    //    q (ending at, centred on, starting at q); with fewer than k slots, all
     double R2init;
+    int wlo, whi;  // the slots of the three windows
     {
         const int span = na < k ? na : k;
         const int fmaxs = na - span;
@@ -376,9 +435,11 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
         f0 = f0 < 0 ? 0 : (f0 > fmaxs ? fmaxs : f0);
         f1 = f1 < 0 ? 0 : (f1 > fmaxs ? fmaxs : f1);
         f2 = f2 < 0 ? 0 : (f2 > fmaxs ? fmaxs : f2);
+        wlo = f0;
+        whi = f2 + span;
         double w0 = 0.0, w1 = 0.0, w2 = 0.0;
-        for (int j = f0; j < f2 + span; ++j) {
-            const double d2 = sep2<PER>(A, qp, A.pos[j]);
+        for (int j = wlo; j < whi; ++j) {
+            const double d2 = sep2_slot<PER>(A, qp, j);
             if (j < f0 + span) w0 = fmax(w0, d2);
             if (j >= f1 && j < f1 + span) w1 = fmax(w1, d2);
             if (j >= f2) w2 = fmax(w2, d2);
@@ -394,34 +455,55 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
         return;
     }
     const double R2cap = fmin(R2init, A.rmax2);
+    QF qf;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        qf.c[a] = float(qp[a]);
+        qf.p[a] = PER ? float(qp[a] + A.L[a]) : 0.0f;
+        qf.m[a] = PER ? float(qp[a] - A.L[a]) : 0.0f;
+    }
     Chain c{};
     c.s = R2init > 0.0 ? 1.0 / R2init : 0.0;
     if (!(c.s < INFINITY)) c.s = 0.0;
 
-    // 2. pass A: count others into the log bins, cutting the radius down to
-    //    the upper edge of the bin that completes k-1 others
+    // 2. pass A: count others into the log bins; once the bins below the cut
+    //    bin hold k-1 others, lower the cut and the radius with it.  The
+    //    window slots go first (their d^2 are cheap to recompute), then the
+    //    walk, which skips them.
     hist_clear(s_lds, tid);
     double R2 = R2cap;
-    int bcut = kNB - 1, cle = 0, candA = 0;
+    int bcut = kNB - 1, cle = 0, hcut = 0, candA = 0;
     bool sat = false;
     const double sA = c.s;
-    const int visA = walk<PER>(A, na, q, qp, R2, [&](int j, double d2) {
-        if (j == q) return;
+    auto count = [&](int j, double d2) {
+        if (sat) return;
         const int b = log_bin(d2 * sA);
         if (b > bcut) return;
-        ++candA;
-        if (!hist_inc(s_lds, tid, b)) {
+        if (++candA > kCandMax) {
             sat = true;
             return;
         }
+        hist_inc(s_lds, tid, b);
         ++cle;
-        bool cut = false;
-        while (bcut > 0 && cle - hist_get(s_lds, tid, bcut) >= need) {
-            cle -= hist_get(s_lds, tid, bcut);
-            --bcut;
-            cut = true;
+        hcut += (b == bcut) ? 1 : 0;
+        if (bcut > 0 && cle - hcut >= need) {
+            do {
+                cle -= hcut;
+                --bcut;
+                hcut = hist_get(s_lds, tid, bcut);
+            } while (bcut > 0 && cle - hcut >= need);
+            // every x with log_bin(x) <= bcut has d^2 below this radius
+            if (sA > 0.0) R2 = fmin(R2cap, (log_edge(bcut + 1) * R2init) * (1.0 + 1e-12));
         }
-        if (cut) R2 = fmin(R2cap, (log_edge(bcut + 1) / sA) * (1.0 + 1e-12));
+    };
+    for (int j = wlo; j < whi; ++j) {
+        if (j == q) continue;
+        const double d2 = sep2_slot<PER>(A, qp, j);
+        if (d2 <= R2) count(j, d2);
+    }
+    const int visA = walk<PER>(A, na, q, qp, qf, R2, [&](int j, double d2) {
+        if (j == q || (j >= wlo && j < whi)) return;
+        count(j, d2);
     });
 
     // 3. the boundary bin; refine it with nested linear bins while over-full
@@ -429,7 +511,6 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
     bool fallback = sat;
     if (sat) {
         c.depth = 0;  // every candidate inside R2 is a boundary candidate
-        c.b0 = -1;
     } else if (cle < need) {
         c.depth = 1;
         c.b0 = kNB;  // fewer than k-1 others within the cap: keep them all
@@ -437,7 +518,7 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
     } else {
         c.depth = 1;
         c.b0 = bcut;
-        hb = hist_get(s_lds, tid, bcut);
+        hb = hcut;
         c0 = cle - hb;
         double loD = bcut == 0 ? 0.0 : log_edge(bcut);
         double sD = double(kNB) / (log_edge(bcut + 1) - loD);
@@ -450,15 +531,9 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
             c.set_level(D, loD, sD);
             ++refines;
             hist_clear(s_lds, tid);
-            bool sat2 = false;
-            walk<PER>(A, na, q, qp, R2, [&](int j, double d2) {
-                if (j != q && classify(c, d2) == kBoundary)
-                    sat2 |= !hist_inc(s_lds, tid, bin_at(d2 * c.s, loD, sD));
+            walk<PER>(A, na, q, qp, qf, R2, [&](int j, double d2) {
+                if (j != q && classify(c, d2) == kBoundary) hist_inc(s_lds, tid, bin_at(d2 * c.s, loD, sD));
             });
-            if (sat2) {
-                fallback = true;
-                break;
-            }
             const int needD = need - c0;
             int cum = 0, bs = kNB - 1, hv = 0;
             for (int b = 0; b < kNB; ++b) {
@@ -483,7 +558,7 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
     int nsel = 0, nb = 0;
     double maxd2 = 0.0;
     int32_t* s_bnd = reinterpret_cast<int32_t*>(s_lds);
-    const int visB = walk<PER>(A, na, q, qp, R2, [&](int j, double d2) {
+    const int visB = walk<PER>(A, na, q, qp, qf, R2, [&](int j, double d2) {
         if (j == q) return;
         const int cl = sat ? kBoundary : classify(c, d2);
         if (cl == kSure) {
@@ -506,7 +581,6 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
 #else
     (void)visA;
     (void)visB;
-    (void)candA;
     (void)refines;
 #endif
     if (nsel != c0) set_status(A.ws, GD_DEV_INTERNAL);
@@ -520,7 +594,7 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
             if (e < nb) {
                 const int j = s_bnd[e * kQBlock + tid];
                 bj[e] = j;
-                bd[e] = sep2<PER>(A, qp, A.pos[j]);
+                bd[e] = sep2_slot<PER>(A, qp, j);
             } else {
                 bj[e] = INT32_MAX;
                 bd[e] = INFINITY;
@@ -544,7 +618,7 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
         for (int t = 0; t < needb; ++t) {
             double bestd = INFINITY;
             int bestj = INT32_MAX;
-            walk<PER>(A, na, q, qp, R2, [&](int j, double d2) {
+            walk<PER>(A, na, q, qp, qf, R2, [&](int j, double d2) {
                 if (j == q || (!sat && classify(c, d2) != kBoundary)) return;
                 const bool after = (d2 > lastd) || (d2 == lastd && j > lastj);
                 const bool better = (d2 < bestd) || (d2 == bestd && j < bestj);
@@ -587,12 +661,19 @@ int launch_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layo
         T.off[l] = L.lvl_off[l];
         T.cap[l] = (L.lvl_cnt[l] + kFan - 1) / kFan * kFan;
     }
+    Periodicity P{};
+    bool per = false;
+    for (int a = 0; a < 3; ++a) {
+        P.per[a] = p->periodic[a] ? 1 : 0;
+        P.L[a] = p->L[a];
+        per = per || P.per[a];
+    }
     prof_mark(GD_PROF_TREE, 0, st);
     hipLaunchKernelGGL(k_bucket_boxes, dim3(unsigned((T.cap[0] + 255) / 256)), dim3(256), 0, st, pos, h,
-                       boxes + T.off[0], T.cap[0]);
+                       boxes + T.off[0], T.cap[0], P);
     for (int l = 1; l < L.levels; ++l)
         hipLaunchKernelGGL(k_level_boxes, dim3(unsigned((T.cap[l] + 255) / 256)), dim3(256), 0, st,
-                           boxes + T.off[l - 1], boxes + T.off[l], T.cap[l]);
+                           boxes + T.off[l - 1], T.cap[l - 1], boxes + T.off[l], T.cap[l]);
     prof_mark(GD_PROF_TREE, 1, st);
     KnnArgs A{};
 #ifdef GD_KNN_STATS
@@ -606,16 +687,11 @@ int launch_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layo
     A.n = n;
     A.k = p->k;
     A.rmax2 = p->rmax * p->rmax;
-    bool per = false;
-    double maxL = 0.0;
     for (int a = 0; a < 3; ++a) {
-        A.per[a] = p->periodic[a] ? 1 : 0;
+        A.per[a] = P.per[a];
         A.L[a] = p->L[a];
         A.hL[a] = 0.5 * p->L[a];
-        per = per || A.per[a];
-        if (A.per[a]) maxL = std::max(maxL, std::fabs(p->L[a]));
     }
-    A.tol = 1e-15 * maxL;
     A.nbr = nb->nbr;
     A.cnt = nb->cnt;
     A.dmax = nb->dmax;

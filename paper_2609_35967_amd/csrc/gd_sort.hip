@@ -49,26 +49,36 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const double* __restrict__
     }
 }
 
-__global__ void k_bbox_final(const double* __restrict__ red, int nblk, WsHeader* __restrict__ h)
+// one wavefront combines the per-block partials
+__global__ __launch_bounds__(64) void k_bbox_final(const double* __restrict__ red, int nblk, WsHeader* __restrict__ h)
 {
-    if (threadIdx.x != 0) return;
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    double cnt = 0.0;
-    for (int b = 0; b < nblk; ++b) {
+    const int lane = threadIdx.x;
+    double v[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0};
+    for (int b = lane; b < nblk; b += 64) {
+#pragma unroll
         for (int d = 0; d < 3; ++d) {
-            lo[d] = fmin(lo[d], red[b * 8 + d]);
-            hi[d] = fmax(hi[d], red[b * 8 + 3 + d]);
+            v[d] = fmin(v[d], red[b * 8 + d]);
+            v[3 + d] = fmax(v[3 + d], red[b * 8 + 3 + d]);
         }
-        cnt += red[b * 8 + 6];
+        v[6] += red[b * 8 + 6];
     }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        v[d] = wave_min_d(v[d]);
+        v[3 + d] = wave_max_d(v[3 + d]);
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v[6] += shfl_xor_d(v[6], m);
+    if (lane != 0) return;
     double ext = 0.0;
     for (int d = 0; d < 3; ++d) {
-        const double e = hi[d] - lo[d];
+        const double e = v[3 + d] - v[d];
         if (e > ext) ext = e;
-        h->lo[d] = lo[d];
+        h->lo[d] = v[d];
+        h->hi[d] = v[3 + d];
     }
     h->inv = ext > 0.0 ? 1024.0 / ext : 0.0;
-    h->n_active = int32_t(cnt);
+    h->n_active = int32_t(v[6]);
 }
 
 // ---------------------------------------------------------------------------
