@@ -45,6 +45,58 @@ ALGO_BYTES = {
     "push": 64 + 72,               # read spherical state, m, M; write state and Cartesian cache
 }
 PROF_KERNELS = ("sort", "tree", "knn_query", "rates", "mc", "audit", "push")
+# source file of each profiled stage (the HBM counter summary is tied to it)
+PROF_SOURCE = {"sort": "gd_sort.hip", "tree": "gd_knn.hip", "knn_query": "gd_knn.hip", "rates": "gd_rates.hip",
+               "mc": "gd_mc.hip", "audit": "gd_mc.hip", "push": "gd_push.hip"}
+COPY_BYTES = 1 << 30  # the plain copy that calibrates the HBM byte counters
+
+
+def source_digest(kernel):
+    import hashlib
+    path = os.path.join(ROOT, "paper_2609_35967_amd", "csrc", PROF_SOURCE[kernel])
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the same counter's
+    reading for a plain copy of known size); None if there is no summary or
+    the kernel's source has changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                a, b = line.split("=", 1)
+                kv[a.strip()] = b.strip()
+    try:
+        if kv.get("source_sha256_16") != source_digest(kernel):
+            return None
+        fetch = float(kv["fetch_kib_per_dispatch"]) * 1024 * float(kv["fetch_scale"])
+        write = float(kv["write_kib_per_dispatch"]) * 1024 * float(kv["write_scale"])
+    except (KeyError, ValueError):
+        return None
+    return fetch + write
+
+
+def copy_calibration(reps):
+    """A plain device copy of COPY_BYTES, `reps` times (run under rocprofv3 --pmc
+    to read what FETCH_SIZE / WRITE_SIZE report for a known byte count)."""
+    import torch
+    torch.cuda.set_device(0)
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "reps": reps,
+                      "GBps_read_plus_write": round(2 * COPY_BYTES / dt / 1e9, 1)}), flush=True)
 
 
 class HipEvents:
@@ -129,9 +181,14 @@ def main():
     ap.add_argument("--workload", default="disk3d", choices=["disk3d", "disk3d_warm"])
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=4096, help="particles in the oracle's timed sample")
+    ap.add_argument("--cpu-sample", type=int, default=98304, help="particles in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="REPS",
+                    help="only run a plain 1 GiB device copy REPS times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py runs the single-GPU path only (asked for --gpus {args.gpus}); the multi-GPU "
               "split is a design note, not built", file=sys.stderr)
@@ -176,9 +233,12 @@ def main():
     value = n * args.steps / wall
 
     achieved = ALGO_BYTES[dom] * n / (dom_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom)
     roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=None, kernel=dom,
-                    algo_bytes_per_particle=ALGO_BYTES[dom], launch_ms=round(dom_ms, 4))
+                    frac=round(achieved / HBM_PEAK_GBS, 5),
+                    traffic=None if traffic is None else round(traffic / (dom_ms * 1e-3) / 1e9, 2), kernel=dom,
+                    algo_bytes_per_particle=ALGO_BYTES[dom], launch_ms=round(dom_ms, 4),
+                    traffic_bytes_per_launch=None if traffic is None else round(traffic))
     path_bytes = sum(ALGO_BYTES.values())
     out = dict(
         metric="particle-intervals/s (kNN+rates+MC) at 1M; batched vs plain; p50/p99 latency",

@@ -177,14 +177,17 @@ int32_t gd_build_neighbors(const gd_problem* p, const gd_particles* in, gd_parti
  * the pairs' effective rates) into lam_i [n]; optional per-pair lambda*_ij into
  * lam_pair [n*k] and controller moments a_i, b_i into ab [2n] (a then b).  Then
  * bins of ilogb(m), merged to >= nbin_min particles, A_b, B_b, dt_req and the
- * dyadic executed interval are written into *iv on the device. */
+ * dyadic executed interval are written into *iv on the device.  The workspace
+ * keeps a packed copy of the snapshot (m, grain size, N) for the sampling
+ * call that follows. */
 int32_t gd_collision_rates(const gd_problem* p, const gd_particles* st, const gd_neighbors* nb,
                            gd_interval* iv, double* lam_i, double* lam_pair, double* ab,
                            void* ws, size_t ws_bytes, void* stream);
 
-/* Monte Carlo sampling over the planned interval (Sect. 2.5.3).  Reads
- * m[st->cur] (frozen neighbours and own start state) and lam_i from
- * gd_collision_rates; writes m[st->cur ^ 1] and, if non-NULL, the event count
+/* Monte Carlo sampling over the planned interval (Sect. 2.5.3).  Must follow
+ * gd_collision_rates of the same interval on the same workspace: reads the
+ * frozen neighbours from the snapshot copy it left there, m[st->cur] (own
+ * start state) and lam_i; writes m[st->cur ^ 1] and, if non-NULL, the event count
  * per particle into n_events [n] and a per-particle event log into log
  * [n * log_cap] (entry = slot | channel << 16 | outcome << 24; -1 unused).
  * Random numbers: Philox4x32-10, key = seed, counters (id, interval_index,
@@ -208,7 +211,7 @@ int32_t gd_push(const gd_problem* p, const gd_particles* st, const gd_interval* 
 /* Kernels that gd_profile_events can bracket. */
 typedef enum gd_prof_kernel {
     GD_PROF_SORT = 0,       /* bounding box, Morton keys, radix sort, permutation */
-    GD_PROF_TREE = 1,       /* radix-tree build and boxes */
+    GD_PROF_TREE = 1,       /* search-tree boxes */
     GD_PROF_KNN_QUERY = 2,  /* neighbour query */
     GD_PROF_RATES = 3,      /* snapshot, pair rates, controller bins, plan */
     GD_PROF_MC = 4,         /* sampling kernel */

@@ -11,6 +11,7 @@
 namespace gd {
 
 constexpr int kWave = 64;
+constexpr int kXcd = 8;             // accelerator dies, each with its own L2
 constexpr int kNBin = 128;          // controller bins: ilogb(m) in [-64, 63]
 constexpr int kBinOff = 64;
 constexpr int64_t kTicks = int64_t(1) << 30;  // ticks per collision step
@@ -60,7 +61,7 @@ struct alignas(256) WsHeader {
 // Workspace layout (byte offsets), identical on host and device.
 struct Layout {
     size_t hdr, keys0, keys1, vals0, vals1, hist, red, pos4, boxes,
-        snap_s, snap_N, a, b, part, stats, total;
+        snap, a, b, part, stats, total;
     int64_t n;
     int32_t k;
     int32_t nsort_blocks;
@@ -107,8 +108,7 @@ __host__ inline Layout make_layout(int64_t n, int32_t k)
         L.levels = l;
         L.boxes = take(sizeof(FBox) * size_t(off));
     }
-    L.snap_s = take(8 * nn);
-    L.snap_N = take(8 * nn);
+    L.snap = take(32 * nn);
     L.a = take(8 * nn);
     L.b = take(8 * nn);
     L.part = take(sizeof(double) * 8 * kNBin * kRedBlocks);
@@ -117,6 +117,17 @@ __host__ inline Layout make_layout(int64_t n, int32_t k)
 #endif
     L.total = o;
     return L;
+}
+
+// Workgroups are dealt to the XCDs in turn.  This maps the dispatch index to
+// a logical block so that each XCD runs one contiguous range of blocks: the
+// Morton-near particles that a block's lanes gather then sit in one L2.
+__device__ inline int64_t xcd_block()
+{
+    const int64_t nb = gridDim.x, w = blockIdx.x;
+    const int64_t x = w % kXcd, r = w / kXcd;
+    const int64_t per = nb / kXcd, rem = nb % kXcd;
+    return x * per + (x < rem ? x : rem) + r;
 }
 
 template <typename T>

@@ -134,6 +134,7 @@ struct KnnArgs {
     int32_t* nbr;
     int32_t* cnt;
     double* dmax;
+    int32_t row_vec;  // nbr is 16-byte aligned
     void* ws;
 };
 
@@ -399,14 +400,21 @@ __device__ inline void bitonic_sort(int32_t (&v)[N])
 
 constexpr int kCandMax = 0xFFFF - 1;  // candidates counted per lane before the counters are distrusted
 
+// LDS words per lane: the sure list (then the retained others) and the
+// boundary list; the bin counters use the first kNB / 2 words before that.
+template <int KP2>
+struct QueryLds {
+    static constexpr int kSure = KP2 > kNB / 2 ? KP2 : kNB / 2;
+    static constexpr int kWords = kSure + kC1;
+};
+
 template <bool PER, int KP2>
 __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
 {
-    // per-lane bin counters, later the boundary list (kC1 slots)
-    __shared__ uint32_t s_lds[(kNB / 2) * kQBlock];
-    static_assert(kC1 <= kNB / 2, "boundary list must fit the counter words");
+    using QL = QueryLds<KP2>;
+    __shared__ uint32_t s_lds[QL::kWords * kQBlock];
     const int tid = threadIdx.x;
-    const int64_t q64 = blockIdx.x * int64_t(kQBlock) + tid;
+    const int64_t q64 = xcd_block() * int64_t(kQBlock) + tid;
     if (q64 >= A.n) return;
     const int q = int(q64);
     const int na = A.h->n_active;
@@ -553,16 +561,17 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
         }
     }
 
-    // 4. pass B inside the final radius: sure slots go to the row, boundary
-    //    slots to the LDS list (the counters are no longer needed)
+    // 4. pass B inside the final radius: sure and boundary slots go to the
+    //    lane's LDS lists (the counters are no longer needed)
     int nsel = 0, nb = 0;
     double maxd2 = 0.0;
-    int32_t* s_bnd = reinterpret_cast<int32_t*>(s_lds);
+    int32_t* s_sel = reinterpret_cast<int32_t*>(s_lds);
+    int32_t* s_bnd = s_sel + QL::kSure * kQBlock;
     const int visB = walk<PER>(A, na, q, qp, qf, R2, [&](int j, double d2) {
         if (j == q) return;
         const int cl = sat ? kBoundary : classify(c, d2);
         if (cl == kSure) {
-            if (nsel < need) row[1 + nsel] = j;
+            if (nsel < need) s_sel[nsel * kQBlock + tid] = j;
             ++nsel;
             maxd2 = fmax(maxd2, d2);
         } else if (cl == kBoundary) {
@@ -606,7 +615,7 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
 #pragma unroll
             for (int f = 0; f < kC1; ++f) rank += (bd[f] < bd[e]) || (bd[f] == bd[e] && bj[f] < bj[e]);
             if (e < nb && rank < needb) {
-                row[1 + nsel_w + rank] = bj[e];
+                s_sel[(nsel_w + rank) * kQBlock + tid] = bj[e];
                 maxd2 = fmax(maxd2, bd[e]);
             }
         }
@@ -627,7 +636,7 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
                     bestj = j;
                 }
             });
-            row[1 + nsel_w + t] = bestj;
+            s_sel[(nsel_w + t) * kQBlock + tid] = bestj;
             maxd2 = fmax(maxd2, bestd);
             lastd = bestd;
             lastj = bestj;
@@ -635,15 +644,28 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
     }
     const int ntot = nsel_w + needb;
 
-    // 5. retained others in ascending slot order
+    // 5. retained others in ascending slot order; the row is written once
     int32_t v[KP2];
 #pragma unroll
-    for (int e = 0; e < KP2; ++e) v[e] = (e < ntot) ? row[1 + e] : INT32_MAX;
+    for (int e = 0; e < KP2; ++e) v[e] = (e < ntot) ? s_sel[e * kQBlock + tid] : INT32_MAX;
     bitonic_sort<KP2>(v);
-    row[0] = q;
+    if (k == KP2 && A.row_vec) {  // 16-byte aligned rows: vector stores
 #pragma unroll
-    for (int e = 0; e < KP2; ++e)
-        if (e < k - 1) row[1 + e] = (e < ntot) ? v[e] : -1;
+        for (int c4 = 0; c4 < KP2 / 4; ++c4) {
+            int32_t o[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int e = 4 * c4 + t;  // row element; others start at element 1
+                o[t] = e == 0 ? q : ((e - 1 < ntot) ? v[e - 1] : -1);
+            }
+            reinterpret_cast<int4*>(row)[c4] = make_int4(o[0], o[1], o[2], o[3]);
+        }
+    } else {
+        row[0] = q;
+#pragma unroll
+        for (int e = 0; e < KP2; ++e)
+            if (e < k - 1) row[1 + e] = (e < ntot) ? v[e] : -1;
+    }
     A.cnt[q] = 1 + ntot;
     A.dmax[q] = ntot > 0 ? sqrt(maxd2) : 0.0;
 }
@@ -693,6 +715,7 @@ int launch_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layo
         A.hL[a] = 0.5 * p->L[a];
     }
     A.nbr = nb->nbr;
+    A.row_vec = (reinterpret_cast<uintptr_t>(nb->nbr) & 15) == 0 ? 1 : 0;
     A.cnt = nb->cnt;
     A.dmax = nb->dmax;
     A.ws = ws;

@@ -31,8 +31,7 @@ struct McArgs {
     const double* x;
     const double* y;
     const double* z;
-    const double* snap_s;
-    const double* snap_N;
+    const double4* snap;  // packed (m, s, N, 0) of the frozen neighbourhood
     const double* lam_i;
     const gd_interval* iv;
     double* m_out;
@@ -61,8 +60,9 @@ __device__ inline double prefix_rates(const McArgs& A, const QCtx& q, const int3
                 set_status(A.ws, GD_DEV_INTERNAL);
                 j = 0;
             }
+            const double4 sn = A.snap[j];
             Pair o;
-            pair_eval(A.P, q, mi, si, Sti, A.m[j], phys ? A.snap_s[j] : 0.0, phys ? A.snap_N[j] : 0.0, o);
+            pair_eval(A.P, q, mi, si, Sti, sn.x, phys ? sn.y : 0.0, phys ? sn.z : 0.0, o);
             li = li + o.lam_star;
         }
         pre[s] = li;
@@ -73,7 +73,7 @@ __device__ inline double prefix_rates(const McArgs& A, const QCtx& q, const int3
 template <int KP2>
 __global__ __launch_bounds__(256) void k_mc(McArgs A)
 {
-    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int64_t i = xcd_block() * int64_t(blockDim.x) + threadIdx.x;
     const int lane = threadIdx.x & 63;
     int e = 0;
     if (i < A.P.n) {
@@ -125,10 +125,11 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
                 }
                 int j = row[sel];
                 if (j < 0 || j >= A.P.n) j = 0;
-                const double mj = A.m[j];
-                const double sj = phys ? A.snap_s[j] : 0.0;
+                const double4 sn = A.snap[j];
+                const double mj = sn.x;
+                const double sj = phys ? sn.y : 0.0;
                 Pair o;
-                pair_eval(A.P, q, m, si, Sti, mj, sj, phys ? A.snap_N[j] : 0.0, o);
+                pair_eval(A.P, q, m, si, Sti, mj, sj, phys ? sn.z : 0.0, o);
                 int ch = 0;
                 if (o.type == kErosion) ch = (o.r0 > u[2] * o.lam_star) ? 0 : 1;
                 double mnew;
@@ -172,29 +173,54 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kNBin) void k_audit(DevProblem P, const double* __restrict__ part, int nblk,
-                                                 gd_interval* iv, WsHeader* h)
+constexpr int kAuditGroups = 4;  // block-partial groups summed in parallel
+
+__global__ __launch_bounds__(kAuditGroups * kNBin) void k_audit(DevProblem P, const double* __restrict__ part, int nblk,
+                                                                gd_interval* iv, WsHeader* h)
 {
-    __shared__ double sv[kNBin][2];
-    const int b = threadIdx.x;
-    dd x{0.0, 0.0};
-    for (int blk = 0; blk < nblk; ++blk) {
-        const double* a = part + (int64_t(blk) * kNBin + b) * 8;
-        x = dd_add(x, dd{a[1], a[2]});
+    __shared__ double sh[kAuditGroups][kNBin], sl[kAuditGroups][kNBin];
+    __shared__ int32_t s_grp[kNBin];
+    const int t = threadIdx.x, b = t % kNBin, gq = t / kNBin;
+    {
+        dd x{0.0, 0.0};
+        for (int blk = gq; blk < nblk; blk += kAuditGroups) {
+            const double* a = part + (int64_t(blk) * kNBin + b) * 8;
+            x = dd_add(x, dd{a[1], a[2]});
+        }
+        sh[gq][b] = x.hi;
+        sl[gq][b] = x.lo;
     }
-    sv[b][0] = x.hi;
-    sv[b][1] = x.lo;
+    if (t < kNBin) s_grp[t] = h->group_of[t];
     __syncthreads();
-    if (b != 0) return;
-    double worst = 0.0;
-    for (int g = 0; g < h->n_groups; ++g) {
-        if (!(h->gM[g] > 0.0)) continue;
-        dd s{0.0, 0.0};
-        for (int bb = 0; bb < kNBin; ++bb)
-            if (h->group_of[bb] == g) s = dd_add(s, dd{sv[bb][0], sv[bb][1]});
-        const double r = s.hi / h->gM[g];
-        if (r > worst) worst = r;
+    if (t < kNBin) {  // the groups combined in a fixed order
+        dd x{sh[0][t], sl[0][t]};
+        for (int g = 1; g < kAuditGroups; ++g) x = dd_add(x, dd{sh[g][t], sl[g][t]});
+        sh[0][t] = x.hi;
+        sl[0][t] = x.lo;
     }
+    __syncthreads();
+    if (t != 0) return;
+    // groups are ascending runs of bins: one pass, each group's bins added in order
+    double worst = 0.0;
+    int g = -1;
+    dd s{0.0, 0.0};
+    auto close = [&]() {
+        if (g >= 0 && h->gM[g] > 0.0) {
+            const double r = s.hi / h->gM[g];
+            if (r > worst) worst = r;
+        }
+    };
+    for (int bb = 0; bb < kNBin; ++bb) {
+        const int gb = s_grp[bb];
+        if (gb < 0) continue;
+        if (gb != g) {
+            close();
+            g = gb;
+            s = dd{0.0, 0.0};
+        }
+        s = dd_add(s, dd{sh[0][bb], sl[0][bb]});
+    }
+    close();
     const double Cf = iv->C;
     const double thr = 2.0 * P.eps * Cf;
     iv->C = (worst > thr) ? fmax(0.25, 0.5 * Cf) : fmin(1.0, 1.25 * Cf);
@@ -246,8 +272,7 @@ int launch_sample(const gd_problem* p, const gd_particles* s, const gd_neighbors
     A.x = s->x;
     A.y = s->y;
     A.z = s->z;
-    A.snap_s = at<double>(ws, L.snap_s);
-    A.snap_N = at<double>(ws, L.snap_N);
+    A.snap = at<double4>(ws, L.snap);
     A.lam_i = lam_i;
     A.iv = iv;
     A.m_out = s->m[s->cur ^ 1];
@@ -266,7 +291,7 @@ int launch_sample(const gd_problem* p, const gd_particles* s, const gd_neighbors
     double* part = at<double>(ws, L.part);
     prof_mark(GD_PROF_AUDIT, 0, st);
     launch_bin_reduce(1, A.m, s->M, A.m_out, nullptr, n, part, ws, st);
-    hipLaunchKernelGGL(k_audit, dim3(1), dim3(kNBin), 0, st, P, part, kRedBlocks, iv, h);
+    hipLaunchKernelGGL(k_audit, dim3(1), dim3(kAuditGroups * kNBin), 0, st, P, part, kRedBlocks, iv, h);
     prof_mark(GD_PROF_AUDIT, 1, st);
     return 0;
 }

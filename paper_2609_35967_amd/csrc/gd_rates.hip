@@ -15,15 +15,16 @@
 
 namespace gd {
 
+// packed snapshot of every particle: (m_j, s_j, N_j = M_j / m_j, 0), one
+// 32-byte record per neighbour gather
 __global__ __launch_bounds__(256) void k_snapshot(DevProblem P, const double* __restrict__ m,
-                                                  const double* __restrict__ M, int64_t n, double* __restrict__ s,
-                                                  double* __restrict__ N)
+                                                  const double* __restrict__ M, int64_t n, double4* __restrict__ snap)
 {
     const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (i >= n) return;
     const double mi = m[i];
-    s[i] = grain_size(P, mi);
-    N[i] = M[i] / mi;
+    const bool phys = P.kernel == GD_KERNEL_PHYSICAL;
+    snap[i] = make_double4(mi, phys ? grain_size(P, mi) : 0.0, phys ? M[i] / mi : 0.0, 0.0);
 }
 
 struct RatesArgs {
@@ -35,8 +36,7 @@ struct RatesArgs {
     const double* x;
     const double* y;
     const double* z;
-    const double* snap_s;
-    const double* snap_N;
+    const double4* snap;
     double* lam;
     double* lam_pair;
     double* a;
@@ -46,7 +46,7 @@ struct RatesArgs {
 
 __global__ __launch_bounds__(256) void k_rates(RatesArgs A)
 {
-    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int64_t i = xcd_block() * int64_t(blockDim.x) + threadIdx.x;
     if (i >= A.P.n) return;
     const int k = A.P.k;
     const bool phys = A.P.kernel == GD_KERNEL_PHYSICAL;
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void k_rates(RatesArgs A)
         QCtx q;
         query_ctx(A.P, A.x[i], A.y[i], A.z[i], A.dmax[i], q);
         const double mi = A.m[i];
-        const double si = phys ? A.snap_s[i] : 0.0;
+        const double si = phys ? A.snap[i].y : 0.0;
         const double Sti = phys ? q.stfac * si : 0.0;
         if (!(mi > 0.0) || !isfinite(mi)) set_status(A.ws, GD_DEV_NONFINITE);
         for (int s = 0; s < c && s < k; ++s) {
@@ -66,9 +66,10 @@ __global__ __launch_bounds__(256) void k_rates(RatesArgs A)
                 set_status(A.ws, GD_DEV_INTERNAL);
                 continue;
             }
-            const double mj = A.m[j];
-            const double sj = phys ? A.snap_s[j] : 0.0;
-            const double Nj = phys ? A.snap_N[j] : 0.0;
+            const double4 sn = A.snap[j];
+            const double mj = sn.x;
+            const double sj = phys ? sn.y : 0.0;
+            const double Nj = phys ? sn.z : 0.0;
             Pair o;
             pair_eval(A.P, q, mi, si, Sti, mj, sj, Nj, o);
             lam = lam + o.lam_star;
@@ -182,100 +183,136 @@ __global__ __launch_bounds__(256) void k_bin_reduce(int mode, const double* __re
 // A_b = sum M a/sum M, B_b = sum M b/sum M;
 // dt_req = min(dt_remain, dt_fn_max, eps C/A_b, (eps C)^2/B_b);
 // dt_exe = dt_coll 2^-n, the largest aligned dyadic fraction <= dt_req.
-__global__ __launch_bounds__(kNBin) void k_plan(DevProblem P, const double* __restrict__ part, int nblk,
-                                                gd_interval* iv, WsHeader* h, void* ws)
+constexpr int kPlanGroups = 4;  // block-partial groups summed in parallel
+
+__global__ __launch_bounds__(kPlanGroups * kNBin) void k_plan(DevProblem P, const double* __restrict__ part, int nblk,
+                                                              gd_interval* iv, WsHeader* h, void* ws)
 {
-    __shared__ double cnt[kNBin];
-    __shared__ double sM[kNBin][2], sA[kNBin][2], sB[kNBin][2];
-    const int b = threadIdx.x;
-    double c = 0.0;
-    dd x0{0.0, 0.0}, x1{0.0, 0.0}, x2{0.0, 0.0};
-    for (int blk = 0; blk < nblk; ++blk) {
-        const double* a = part + (int64_t(blk) * kNBin + b) * 8;
-        c += a[0];
-        x0 = dd_add(x0, dd{a[1], a[2]});
-        x1 = dd_add(x1, dd{a[3], a[4]});
-        x2 = dd_add(x2, dd{a[5], a[6]});
+    __shared__ double pc[kPlanGroups][kNBin];
+    __shared__ double ph[kPlanGroups][3][kNBin], pl[kPlanGroups][3][kNBin];
+    __shared__ int32_t s_grp[kNBin];
+    __shared__ int32_t s_ng;
+    const int t = threadIdx.x, b = t % kNBin, gq = t / kNBin;
+    {
+        double c = 0.0;
+        dd x0{0.0, 0.0}, x1{0.0, 0.0}, x2{0.0, 0.0};
+        for (int blk = gq; blk < nblk; blk += kPlanGroups) {
+            const double* a = part + (int64_t(blk) * kNBin + b) * 8;
+            c += a[0];
+            x0 = dd_add(x0, dd{a[1], a[2]});
+            x1 = dd_add(x1, dd{a[3], a[4]});
+            x2 = dd_add(x2, dd{a[5], a[6]});
+        }
+        pc[gq][b] = c;
+        ph[gq][0][b] = x0.hi;
+        pl[gq][0][b] = x0.lo;
+        ph[gq][1][b] = x1.hi;
+        pl[gq][1][b] = x1.lo;
+        ph[gq][2][b] = x2.hi;
+        pl[gq][2][b] = x2.lo;
     }
-    cnt[b] = c;
-    sM[b][0] = x0.hi;
-    sM[b][1] = x0.lo;
-    sA[b][0] = x1.hi;
-    sA[b][1] = x1.lo;
-    sB[b][0] = x2.hi;
-    sB[b][1] = x2.lo;
     __syncthreads();
-    if (b != 0) return;
-    // merge rule
-    int ng = 0;
-    double acc = 0.0;
-    bool open = false;
-    for (int bb = 0; bb < kNBin; ++bb) {
-        h->group_of[bb] = -1;
-        if (cnt[bb] == 0.0) continue;
-        if (!open) {
-            open = true;
-            acc = 0.0;
+    if (t < kNBin) {  // the groups combined in a fixed order: row 0 holds the bin totals
+        double c = pc[0][t];
+        dd x[3];
+        for (int v = 0; v < 3; ++v) x[v] = dd{ph[0][v][t], pl[0][v][t]};
+        for (int g = 1; g < kPlanGroups; ++g) {
+            c += pc[g][t];
+            for (int v = 0; v < 3; ++v) x[v] = dd_add(x[v], dd{ph[g][v][t], pl[g][v][t]});
         }
-        h->group_of[bb] = ng;
-        acc += cnt[bb];
-        if (acc >= double(P.nbin_min)) {
-            ++ng;
-            open = false;
+        pc[0][t] = c;
+        for (int v = 0; v < 3; ++v) {
+            ph[0][v][t] = x[v].hi;
+            pl[0][v][t] = x[v].lo;
         }
     }
-    if (open) {
-        if (ng > 0) {
-            for (int bb = 0; bb < kNBin; ++bb)
-                if (h->group_of[bb] == ng) h->group_of[bb] = ng - 1;
-        } else {
-            ng = 1;
-        }
-    }
-    const double dt_coll = iv->dt_coll;
-    const double Cf = iv->C;
-    const int64_t ticks = iv->ticks;
-    const double tick = ldexp(dt_coll, -30);
-    double req = double(kTicks - ticks) * tick;
-    if (P.dt_fn_max < req) req = P.dt_fn_max;
-    const double eC = P.eps * Cf;
-    for (int g = 0; g < ng; ++g) {
-        dd m{0.0, 0.0}, a{0.0, 0.0}, bsum{0.0, 0.0};
+    __syncthreads();
+    if (t == 0) {
+        // merge rule in one ascending pass: a group opens at a non-empty bin
+        // and closes once it holds nbin_min particles; a short open tail
+        // joins the previous group (or is the only group).  Each group's sums
+        // add its bins in ascending order.
+        const double dt_coll = iv->dt_coll;
+        const double Cf = iv->C;
+        const int64_t ticks = iv->ticks;
+        const double tick = ldexp(dt_coll, -30);
+        double req = double(kTicks - ticks) * tick;
+        if (P.dt_fn_max < req) req = P.dt_fn_max;
+        const double eC = P.eps * Cf;
+        auto finalize = [&](const dd (&x)[3], int g) {
+            h->gM[g] = x[0].hi;
+            const double A_ = x[0].hi > 0.0 ? x[1].hi / x[0].hi : 0.0;
+            const double B_ = x[0].hi > 0.0 ? x[2].hi / x[0].hi : 0.0;
+            if (A_ > 0.0) {
+                const double tt = eC / A_;
+                if (tt < req) req = tt;
+            }
+            if (B_ > 0.0) {
+                const double tt = (eC * eC) / B_;
+                if (tt < req) req = tt;
+            }
+        };
+        int ng = 0, tail = -1;
+        double acc = 0.0;
+        bool open = false, has_pend = false;
+        dd cur[3], pend[3];
         for (int bb = 0; bb < kNBin; ++bb) {
-            if (h->group_of[bb] != g) continue;
-            m = dd_add(m, dd{sM[bb][0], sM[bb][1]});
-            a = dd_add(a, dd{sA[bb][0], sA[bb][1]});
-            bsum = dd_add(bsum, dd{sB[bb][0], sB[bb][1]});
+            s_grp[bb] = -1;
+            if (pc[0][bb] == 0.0) continue;
+            if (!open) {
+                open = true;
+                acc = 0.0;
+                tail = bb;
+                for (int v = 0; v < 3; ++v) cur[v] = dd{0.0, 0.0};
+            }
+            s_grp[bb] = ng;
+            acc += pc[0][bb];
+            for (int v = 0; v < 3; ++v) cur[v] = dd_add(cur[v], dd{ph[0][v][bb], pl[0][v][bb]});
+            if (acc >= double(P.nbin_min)) {
+                if (has_pend) finalize(pend, ng - 1);
+                for (int v = 0; v < 3; ++v) pend[v] = cur[v];
+                has_pend = true;
+                ++ng;
+                open = false;
+            }
         }
-        h->gM[g] = m.hi;
-        const double A_ = m.hi > 0.0 ? a.hi / m.hi : 0.0;
-        const double B_ = m.hi > 0.0 ? bsum.hi / m.hi : 0.0;
-        if (A_ > 0.0) {
-            const double tt = eC / A_;
-            if (tt < req) req = tt;
+        if (open) {
+            if (has_pend) {
+                for (int bb = tail; bb < kNBin; ++bb) {
+                    if (pc[0][bb] == 0.0) continue;
+                    s_grp[bb] = ng - 1;
+                    for (int v = 0; v < 3; ++v) pend[v] = dd_add(pend[v], dd{ph[0][v][bb], pl[0][v][bb]});
+                }
+            } else {
+                for (int v = 0; v < 3; ++v) pend[v] = cur[v];
+                has_pend = true;
+                ng = 1;
+            }
         }
-        if (B_ > 0.0) {
-            const double tt = (eC * eC) / B_;
-            if (tt < req) req = tt;
+        if (has_pend) finalize(pend, ng - 1);
+        int64_t size = kTicks;
+        int nh = 0;
+        for (nh = 0; nh <= 30; ++nh) {
+            size = kTicks >> nh;
+            if (double(size) * tick <= req && (ticks % size) == 0) break;
         }
+        if (nh > 30) {
+            size = 1;
+            atomicOr(&h->status, GD_DEV_TICK_FLOOR);
+        }
+        h->n_groups = ng;
+        iv->dt_req = req;
+        iv->dt_exe = double(size) * tick;
+        iv->exe_ticks = size;
+        iv->n_groups = ng;
+        h->scratch[0] = 0.0;  // event counter of the coming interval
+        s_ng = ng;
     }
-    for (int g = ng; g < kNBin; ++g) h->gM[g] = 0.0;
-    int64_t size = kTicks;
-    int nh = 0;
-    for (nh = 0; nh <= 30; ++nh) {
-        size = kTicks >> nh;
-        if (double(size) * tick <= req && (ticks % size) == 0) break;
+    __syncthreads();
+    if (t < kNBin) {
+        h->group_of[t] = s_grp[t];
+        if (t >= s_ng) h->gM[t] = 0.0;
     }
-    if (nh > 30) {
-        size = 1;
-        atomicOr(&h->status, GD_DEV_TICK_FLOOR);
-    }
-    h->n_groups = ng;
-    iv->dt_req = req;
-    iv->dt_exe = double(size) * tick;
-    iv->exe_ticks = size;
-    iv->n_groups = ng;
-    h->scratch[0] = 0.0;  // event counter of the coming interval
 }
 
 // ---------------------------------------------------------------------------
@@ -292,11 +329,9 @@ int launch_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors*
     const int64_t n = p->n;
     const int g = int((n + 255) / 256);
     const double* m = s->m[s->cur];
-    double* snap_s = at<double>(ws, L.snap_s);
-    double* snap_N = at<double>(ws, L.snap_N);
+    double4* snap = at<double4>(ws, L.snap);
     prof_mark(GD_PROF_RATES, 0, st);
-    if (p->kernel == GD_KERNEL_PHYSICAL)
-        hipLaunchKernelGGL(k_snapshot, dim3(g), dim3(256), 0, st, P, m, s->M, n, snap_s, snap_N);
+    hipLaunchKernelGGL(k_snapshot, dim3(g), dim3(256), 0, st, P, m, s->M, n, snap);
     RatesArgs A{};
     A.P = P;
     A.nbr = nb->nbr;
@@ -306,8 +341,7 @@ int launch_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors*
     A.x = s->x;
     A.y = s->y;
     A.z = s->z;
-    A.snap_s = snap_s;
-    A.snap_N = snap_N;
+    A.snap = snap;
     A.lam = lam_i;
     A.lam_pair = lam_pair;
     A.a = ab ? ab : at<double>(ws, L.a);
@@ -316,7 +350,7 @@ int launch_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors*
     hipLaunchKernelGGL(k_rates, dim3(g), dim3(256), 0, st, A);
     double* part = at<double>(ws, L.part);
     launch_bin_reduce(0, m, s->M, A.a, A.b, n, part, ws, st);
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kNBin), 0, st, P, part, kRedBlocks, iv, at<WsHeader>(ws, L.hdr), ws);
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanGroups * kNBin), 0, st, P, part, kRedBlocks, iv, at<WsHeader>(ws, L.hdr), ws);
     prof_mark(GD_PROF_RATES, 1, st);
     return 0;
 }

@@ -119,7 +119,9 @@ __global__ __launch_bounds__(256) void k_morton(const double* __restrict__ x, co
 
 // ---------------------------------------------------------------------------
 // LSD radix sort, 8-bit digits.  Block b owns keys [b*4096, (b+1)*4096).
-// hist is digit-major: hist[d * nblk + b], exclusive-scanned in place.
+// hist is digit-major: hist[d * nblk + b]; each digit's row is exclusive-
+// scanned in place by its own block, and the scatter adds the exclusive scan
+// of the digit totals.
 __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
                                                     uint32_t* __restrict__ hist, int nblk)
 {
@@ -135,39 +137,57 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__
     hist[int64_t(threadIdx.x) * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* __restrict__ a, int64_t len)
+// Exclusive scan of 256 values held one per thread of a 256-thread block;
+// returns this thread's prefix, and the total in *total.
+__device__ inline uint32_t block_scan_excl_256(uint32_t v, uint32_t* s_w, uint32_t* total)
 {
-    __shared__ uint32_t part[1024];
-    const int64_t per = (len + 1023) / 1024;
-    const int64_t b = threadIdx.x * per;
-    const int64_t e = b + per < len ? b + per : len;
-    uint32_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += a[i];
-    part[threadIdx.x] = s;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
+    uint32_t before = 0;
+    for (int ww = 0; ww < w; ++ww) before += s_w[ww];
+    *total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    __syncthreads();
+    return before + x - v;
+}
+
+// Row d of the digit-major histogram (the counts of digit d in every block)
+// becomes its exclusive prefix; the row total goes to tot[d].
+__global__ __launch_bounds__(256) void k_scan_rows(uint32_t* __restrict__ hist, int nblk, uint32_t* __restrict__ tot)
+{
+    __shared__ uint32_t s_w[4];
+    uint32_t* row = hist + int64_t(blockIdx.x) * nblk;
+    uint32_t carry = 0;
+    for (int c = 0; c < nblk; c += 256) {
+        const int i = c + int(threadIdx.x);
+        const uint32_t v = i < nblk ? row[i] : 0u;
+        uint32_t chunk;
+        const uint32_t pre = block_scan_excl_256(v, s_w, &chunk);
+        if (i < nblk) row[i] = carry + pre;
+        carry += chunk;
     }
-    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-    for (int64_t i = b; i < e; ++i) {
-        const uint32_t v = a[i];
-        a[i] = run;
-        run += v;
-    }
+    if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                        uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                       int64_t n, int shift, const uint32_t* __restrict__ hist, int nblk)
+                                                       int64_t n, int shift, const uint32_t* __restrict__ hist, int nblk,
+                                                       const uint32_t* __restrict__ tot)
 {
     __shared__ uint32_t goff[256];   // global offset of each digit for this block
     __shared__ uint32_t run[256];    // items of each digit placed in earlier rounds
     __shared__ uint32_t wcnt[4][256];
+    __shared__ uint32_t s_w[4];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    goff[t] = hist[int64_t(t) * nblk + blockIdx.x];
+    uint32_t all;
+    const uint32_t below = block_scan_excl_256(tot[t], s_w, &all);  // keys of smaller digits
+    goff[t] = below + hist[int64_t(t) * nblk + blockIdx.x];
     run[t] = 0;
     const int64_t base = int64_t(blockIdx.x) * kSortTile;
     const uint64_t lt = (uint64_t(1) << lane) - 1;
@@ -246,6 +266,7 @@ int launch_morton_sort(const gd_problem* p, const gd_particles* in, gd_particles
     const int nb = int((n + 255) / 256);
     hipLaunchKernelGGL(k_morton, dim3(nb), dim3(256), 0, st, in->x, in->y, in->z, in->M, n, h, k0, v0);
     const int nsb = L.nsort_blocks;
+    uint32_t* tot = hist + int64_t(256) * nsb;  // per-digit totals (the spare row of hist)
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 8 * pass;
         const uint32_t* ki = (pass & 1) ? k1 : k0;
@@ -253,8 +274,8 @@ int launch_morton_sort(const gd_problem* p, const gd_particles* in, gd_particles
         uint32_t* ko = (pass & 1) ? k0 : k1;
         uint32_t* vo = (pass & 1) ? v0 : v1;
         hipLaunchKernelGGL(k_radix_hist, dim3(nsb), dim3(256), 0, st, ki, n, shift, hist, nsb);
-        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, hist, int64_t(256) * nsb);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nsb), dim3(256), 0, st, ki, vi, ko, vo, n, shift, hist, nsb);
+        hipLaunchKernelGGL(k_scan_rows, dim3(256), dim3(256), 0, st, hist, nsb, tot);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nsb), dim3(256), 0, st, ki, vi, ko, vo, n, shift, hist, nsb, tot);
     }
     // sorted (key, slot) pairs are back in (k0, v0)
     PermuteArgs A{};
