@@ -29,6 +29,12 @@
  *
  * Readings of passages the paper leaves open are listed where they are used
  * and collected in the design notes of the repository.
+ *
+ * Parity unpinned (no independent value to check against; GPU parity is
+ * against this code only): the five-term composition of eq:dv at a point
+ * where all terms are non-zero (its parts are pinned separately), the OC07
+ * branch constants away from the tested regimes and limits, and the disk's
+ * gas normalisation.
  */
 #include <math.h>
 #include <stdint.h>

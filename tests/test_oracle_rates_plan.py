@@ -156,6 +156,39 @@ def test_physical_rate_limits():
         assert abs(Ka - Kb) < 1e-12 * Ka
 
 
+@pytest.mark.parametrize("St_i,St_j", [(0.02, 0.005), (2.0, 0.3), (0.4, 0.9), (0.1, 0.1)])
+def test_physical_rate_drift_terms(St_i, St_j):
+    # Brownian and turbulent terms off: the collision speed is the three
+    # prescribed relative motions of eq:dv (Sect. 2.5.2), written out here term
+    # by term, and the rate is eq:rate with eq:kernel and an uncapped sphere
+    p, P = _disk_problem(brownian=0, turbulence=0, v_frag=1e30)
+    au = workloads.AU
+    R, Z, di = 30 * au, 0.6 * au, 0.05 * au
+    g = oracle.gas_at(P, R, Z)
+    rho = p["rho_s"]
+    s_i, s_j = St_i / g["stfac"], St_j / g["stfac"]
+    m_i, m_j = math.pi * rho * s_i ** 3 / 6, math.pi * rho * s_j ** 3 / 6
+    M_j = 7.0 * m_j
+    r = oracle.pair_rate(P, R, 0.0, Z, di, m_i, m_j, M_j)
+    # the grain sizes the oracle derives from the masses (Stokes numbers follow)
+    s_i = (6 * m_i / (math.pi * rho)) ** (1 / 3)
+    s_j = (6 * m_j / (math.pi * rho)) ** (1 / 3)
+    St_i, St_j = g["stfac"] * s_i, g["stfac"] * s_j
+    vK = R * g["OmK"]
+    dvR = 2 * g["eta"] * vK * (St_i / (1 + St_i ** 2) - St_j / (1 + St_j ** 2))
+    dvZ = Z * g["OmK"] * (min(St_i, 0.5) - min(St_j, 0.5))
+    dvP = g["eta"] * vK * (1 / (1 + St_i ** 2) - 1 / (1 + St_j ** 2))
+    dv = math.sqrt(dvR ** 2 + dvZ ** 2 + dvP ** 2)
+    K = math.pi * (s_i + s_j) ** 2 * dv / 4
+    lam = (M_j / m_j) * K / (4 * math.pi * di ** 3 / 3)
+    assert r["type"] == 0 and r["Ng"] == 1.0
+    assert abs(r["V"] - 4 * math.pi * di ** 3 / 3) <= 1e-14 * r["V"]
+    if St_i == St_j:
+        assert r["lam_star"] <= 1e-13 * (M_j / m_j) * math.pi * (2 * s_i) ** 2 * vK / r["V"]
+    else:
+        assert abs(r["lam_star"] - lam) <= 1e-11 * lam
+
+
 def test_oc07_regimes():
     Vg2 = 2.0
     tke = 1e-3
