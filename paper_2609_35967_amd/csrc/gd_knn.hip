@@ -209,7 +209,9 @@ __device__ inline uint32_t child_mask(const KnnArgs& A, int level, int idx, cons
 }
 
 // Visit every active slot j with d^2(q, j) <= R2 (j == q included; the
-// visitor filters), nearest region first: the level-1 ancestor of q's bucket,
+// visitor filters), a bucket at a time: f(j0, d2[kBucket], mask) gets the
+// bucket's first slot, the d^2 of its slots and the mask of those within R2.
+// Nearest region first: the level-1 ancestor of q's bucket,
 // then the other children of each further ancestor, depth first.  The
 // visitor may lower R2; pruning uses the current value.  One iteration does
 // at most one node expansion and one bucket scan, so the two paths of a
@@ -265,28 +267,28 @@ __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], 
             pend = true;
             continue;
         }
-        // a bucket: its particles are candidates
+        // a bucket: its particles within R2 go to the visitor together
         ++steps;
+        const int j0 = child * kBucket;
         double px[kBucket], py[kBucket], pz[kBucket];
 #pragma unroll
         for (int t = 0; t < kBucket; ++t) {
-            const int j = child * kBucket + t;
-            if (j < na) {
-                const double* pj = reinterpret_cast<const double*>(A.pos + j);
+            if (j0 + t < na) {
+                const double* pj = reinterpret_cast<const double*>(A.pos + j0 + t);
                 const double2 xy = *reinterpret_cast<const double2*>(pj);
                 px[t] = xy.x;
                 py[t] = xy.y;
                 pz[t] = pj[2];
             }
         }
+        double d2[kBucket];
+        uint32_t vm = 0;
 #pragma unroll
         for (int t = 0; t < kBucket; ++t) {
-            const int j = child * kBucket + t;
-            if (j < na) {
-                const double d2 = sep2<PER>(A, qp, px[t], py[t], pz[t]);
-                if (d2 <= R2) f(j, d2);
-            }
+            d2[t] = j0 + t < na ? sep2<PER>(A, qp, px[t], py[t], pz[t]) : INFINITY;
+            vm |= (d2[t] <= R2 ? 1u : 0u) << t;
         }
+        if (vm) f(j0, d2, vm);
         R2f = r2f(R2);
     }
     return steps;
@@ -372,9 +374,10 @@ __device__ inline int hist_get(const uint32_t* lds, int tid, int b)
     return int((lds[(b >> 1) * kQBlock + tid] >> (16 * (b & 1))) & 0xFFFFu);
 }
 
+// an LDS add whose result is not read (no wait on the lane's path)
 __device__ inline void hist_inc(uint32_t* lds, int tid, int b)
 {
-    lds[(b >> 1) * kQBlock + tid] += 1u << (16 * (b & 1));
+    atomicAdd(lds + (b >> 1) * kQBlock + tid, 1u << (16 * (b & 1)));
 }
 
 template <int N>
@@ -398,7 +401,9 @@ __device__ inline void bitonic_sort(int32_t (&v)[N])
     }
 }
 
-constexpr int kCandMax = 0xFFFF - 1;  // candidates counted per lane before the counters are distrusted
+// candidates a lane counts before its 16-bit counters are distrusted (a
+// bucket may add kBucket past the check)
+constexpr int kCandMax = 0xFFFF - 2 * kBucket;
 
 // LDS words per lane: the sure list (then the retained others) and the
 // boundary list; the bin counters use the first kNB / 2 words before that.
@@ -483,17 +488,8 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
     int bcut = kNB - 1, cle = 0, hcut = 0, candA = 0;
     bool sat = false;
     const double sA = c.s;
-    auto count = [&](int j, double d2) {
-        if (sat) return;
-        const int b = log_bin(d2 * sA);
-        if (b > bcut) return;
-        if (++candA > kCandMax) {
-            sat = true;
-            return;
-        }
-        hist_inc(s_lds, tid, b);
-        ++cle;
-        hcut += (b == bcut) ? 1 : 0;
+    // lower the cut while the bins below it already hold k-1 others
+    auto cut = [&]() {
         if (bcut > 0 && cle - hcut >= need) {
             do {
                 cle -= hcut;
@@ -507,11 +503,33 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
     for (int j = wlo; j < whi; ++j) {
         if (j == q) continue;
         const double d2 = sep2_slot<PER>(A, qp, j);
-        if (d2 <= R2) count(j, d2);
+        if (!(d2 <= R2)) continue;
+        const int b = log_bin(d2 * sA);
+        if (b > bcut) continue;
+        hist_inc(s_lds, tid, b);
+        ++cle;
+        ++candA;
+        hcut += (b == bcut) ? 1 : 0;
+        cut();
     }
-    const int visA = walk<PER>(A, na, q, qp, qf, R2, [&](int j, double d2) {
-        if (j == q || (j >= wlo && j < whi)) return;
-        count(j, d2);
+    const int visA = walk<PER>(A, na, q, qp, qf, R2, [&](int j0, const double (&d2)[kBucket], uint32_t vm) {
+        if (sat) return;
+#pragma unroll
+        for (int t = 0; t < kBucket; ++t) {
+            const int j = j0 + t;
+            const int b = log_bin(d2[t] * sA);
+            if (((vm >> t) & 1u) && j != q && (j < wlo || j >= whi) && b <= bcut) {
+                hist_inc(s_lds, tid, b);
+                ++cle;
+                ++candA;
+                hcut += (b == bcut) ? 1 : 0;
+            }
+        }
+        if (candA > kCandMax) {
+            sat = true;
+            return;
+        }
+        cut();
     });
 
     // 3. the boundary bin; refine it with nested linear bins while over-full
@@ -539,8 +557,11 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
             c.set_level(D, loD, sD);
             ++refines;
             hist_clear(s_lds, tid);
-            walk<PER>(A, na, q, qp, qf, R2, [&](int j, double d2) {
-                if (j != q && classify(c, d2) == kBoundary) hist_inc(s_lds, tid, bin_at(d2 * c.s, loD, sD));
+            walk<PER>(A, na, q, qp, qf, R2, [&](int j0, const double (&d2)[kBucket], uint32_t vm) {
+#pragma unroll
+                for (int t = 0; t < kBucket; ++t)
+                    if (((vm >> t) & 1u) && j0 + t != q && classify(c, d2[t]) == kBoundary)
+                        hist_inc(s_lds, tid, bin_at(d2[t] * c.s, loD, sD));
             });
             const int needD = need - c0;
             int cum = 0, bs = kNB - 1, hv = 0;
@@ -567,16 +588,20 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
     double maxd2 = 0.0;
     int32_t* s_sel = reinterpret_cast<int32_t*>(s_lds);
     int32_t* s_bnd = s_sel + QL::kSure * kQBlock;
-    const int visB = walk<PER>(A, na, q, qp, qf, R2, [&](int j, double d2) {
-        if (j == q) return;
-        const int cl = sat ? kBoundary : classify(c, d2);
-        if (cl == kSure) {
-            if (nsel < need) s_sel[nsel * kQBlock + tid] = j;
-            ++nsel;
-            maxd2 = fmax(maxd2, d2);
-        } else if (cl == kBoundary) {
-            if (nb < kC1) s_bnd[nb * kQBlock + tid] = j;
-            ++nb;
+    const int visB = walk<PER>(A, na, q, qp, qf, R2, [&](int j0, const double (&d2)[kBucket], uint32_t vm) {
+#pragma unroll
+        for (int t = 0; t < kBucket; ++t) {
+            const int j = j0 + t;
+            if (!((vm >> t) & 1u) || j == q) continue;
+            const int cl = sat ? kBoundary : classify(c, d2[t]);
+            if (cl == kSure) {
+                if (nsel < need) s_sel[nsel * kQBlock + tid] = j;
+                ++nsel;
+                maxd2 = fmax(maxd2, d2[t]);
+            } else if (cl == kBoundary) {
+                if (nb < kC1) s_bnd[nb * kQBlock + tid] = j;
+                ++nb;
+            }
         }
     });
 #ifdef GD_KNN_STATS
@@ -627,13 +652,16 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
         for (int t = 0; t < needb; ++t) {
             double bestd = INFINITY;
             int bestj = INT32_MAX;
-            walk<PER>(A, na, q, qp, qf, R2, [&](int j, double d2) {
-                if (j == q || (!sat && classify(c, d2) != kBoundary)) return;
-                const bool after = (d2 > lastd) || (d2 == lastd && j > lastj);
-                const bool better = (d2 < bestd) || (d2 == bestd && j < bestj);
-                if (after && better) {
-                    bestd = d2;
-                    bestj = j;
+            walk<PER>(A, na, q, qp, qf, R2, [&](int j0, const double (&d2)[kBucket], uint32_t vm) {
+                for (int t = 0; t < kBucket; ++t) {
+                    const int j = j0 + t;
+                    if (!((vm >> t) & 1u) || j == q || (!sat && classify(c, d2[t]) != kBoundary)) continue;
+                    const bool after = (d2[t] > lastd) || (d2[t] == lastd && j > lastj);
+                    const bool better = (d2[t] < bestd) || (d2[t] == bestd && j < bestj);
+                    if (after && better) {
+                        bestd = d2[t];
+                        bestj = j;
+                    }
                 }
             });
             s_sel[(nsel_w + t) * kQBlock + tid] = bestj;
