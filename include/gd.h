@@ -168,7 +168,10 @@ int32_t gd_interval_init(gd_interval* iv, double dt_coll, void* stream);
  * slot i: nbr row = i, then the k-1 nearest other active particles with
  * d^2 <= rmax^2, nearest first by (d^2, slot), written in ascending slot order;
  * d^2 = (dx*dx + dy*dy) + dz*dz with minimum image on periodic axes
- * (d > L/2: d - L; d < -L/2: d + L).  Exact: no approximation in the search. */
+ * (d > L/2: d - L; d < -L/2: d + L).  Exact: no approximation in the search.
+ * On entry nb->dmax is read as a per-slot search hint in the order of `in`
+ * (in a stepping loop it holds the previous call's distances, and `in` is that
+ * call's output); any content is allowed and the result never depends on it. */
 int32_t gd_build_neighbors(const gd_problem* p, const gd_particles* in, gd_particles* out,
                            const gd_neighbors* nb, void* ws, size_t ws_bytes, void* stream);
 

@@ -207,7 +207,7 @@ class Engine:
         f64 = dict(dtype=torch.float64, device=self.device)
         self.nbr = torch.empty((n, k), **i32)
         self.cnt = torch.empty(n, **i32)
-        self.dmax = torch.empty(n, **f64)
+        self.dmax = torch.zeros(n, **f64)  # read back as the next search's hint
         self.n_active = torch.zeros(1, **i32)
         self.lam = torch.empty(n, **f64)
         self.events = torch.zeros(n, **i32)

@@ -197,7 +197,7 @@ int32_t gd_build_neighbors(const gd_problem* p, const gd_particles* in, gd_parti
     if (rc) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (p->n == 0) return GD_OK;
-    launch_morton_sort(p, in, &o, ws, L, st);
+    launch_morton_sort(p, in, &o, nb->dmax, ws, L, st);
     out->cur = in->cur;
     launch_knn(p, nb, ws, L, st);
     if (nb->n_active) hipLaunchKernelGGL(k_copy_na, dim3(1), dim3(64), 0, st, at<WsHeader>(ws, L.hdr), nb->n_active);

@@ -56,12 +56,13 @@ struct alignas(256) WsHeader {
     int32_t group_of[kNBin];     // plan: raw bin -> merged group (-1 empty)
     double gM[kNBin];            // plan: sum of M per merged group
     double scratch[16];
+    int32_t xq[4][8];            // per-die work queues of the gather-heavy kernels
 };
 
 // Workspace layout (byte offsets), identical on host and device.
 struct Layout {
     size_t hdr, keys0, keys1, vals0, vals1, hist, red, pos4, boxes,
-        snap, a, b, part, stats, total;
+        snap, a, b, part, hint, stats, total;
     int64_t n;
     int32_t k;
     int32_t nsort_blocks;
@@ -112,6 +113,7 @@ __host__ inline Layout make_layout(int64_t n, int32_t k)
     L.a = take(8 * nn);
     L.b = take(8 * nn);
     L.part = take(sizeof(double) * 8 * kNBin * kRedBlocks);
+    L.hint = take(8 * nn);
 #ifdef GD_KNN_STATS
     L.stats = take(32 * nn);
 #endif
@@ -119,15 +121,47 @@ __host__ inline Layout make_layout(int64_t n, int32_t k)
     return L;
 }
 
-// Workgroups are dealt to the XCDs in turn.  This maps the dispatch index to
-// a logical block so that each XCD runs one contiguous range of blocks: the
-// Morton-near particles that a block's lanes gather then sit in one L2.
+// Workgroups are dealt to the XCDs (dies, each with its own L2) in turn.
+// xcd_take() gives each wavefront one item of 64 consecutive particles: the
+// items are split into kXcd contiguous Morton ranges, one per die, and a
+// wavefront takes the next item of its die's range from that range's counter
+// (slot x of `q`), so the Morton-near particles its lanes gather stay in one
+// L2.  A die whose range is exhausted takes the next items of the following
+// ranges, so spatial variations of cost cannot leave dies idle.  Every
+// wavefront takes exactly one item whatever the hardware's dealing order,
+// provided the grid holds exactly `nitems` wavefronts and the counters start
+// at zero.  No LDS, no barrier.
+enum { kQueueKnn = 0 };
+
+__device__ inline int32_t xcd_range_lo(int x, int32_t nitems)
+{
+    return (nitems / kXcd) * x + (x < nitems % kXcd ? x : nitems % kXcd);
+}
+
+__device__ inline int32_t xcd_take(int32_t* q, int32_t nitems)
+{
+    int32_t got = -1;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        const int x0 = int(blockIdx.x % kXcd);
+        for (int d = 0; d < kXcd && got < 0; ++d) {
+            const int x = (x0 + d) % kXcd;
+            const int32_t lo = xcd_range_lo(x, nitems), size = xcd_range_lo(x + 1, nitems) - lo;
+            if (size <= 0) continue;
+            const int32_t idx = atomicAdd(q + x, 1);
+            if (idx < size) got = lo + idx;
+        }
+    }
+    return __builtin_amdgcn_readfirstlane(got);
+}
+
+// Static form for short kernels of even cost (no atomics): the workgroup the
+// hardware deals to die x as its r-th becomes block r of die x's contiguous
+// range of the nb = gridDim.x blocks (a bijection for any nb).
 __device__ inline int64_t xcd_block()
 {
     const int64_t nb = gridDim.x, w = blockIdx.x;
     const int64_t x = w % kXcd, r = w / kXcd;
-    const int64_t per = nb / kXcd, rem = nb % kXcd;
-    return x * per + (x < rem ? x : rem) + r;
+    return (nb / kXcd) * x + (x < nb % kXcd ? x : nb % kXcd) + r;
 }
 
 template <typename T>

@@ -14,12 +14,15 @@ struct PermuteArgs {
     const uint32_t* id_src;
     uint32_t* id_dst;
     double4* pos4;
+    const double* hint_src;  // previous neighbour distance per input slot, or null
+    double* hint_dst;        // into Morton order (0 when absent)
 };
 
 DevProblem to_dev(const gd_problem* p);
 void prof_mark(int which, int after, hipStream_t st);
 
-int launch_morton_sort(const gd_problem* p, const gd_particles* in, gd_particles* out, void* ws, const Layout& L,
+int launch_morton_sort(const gd_problem* p, const gd_particles* in, gd_particles* out, const double* hint, void* ws,
+                       const Layout& L,
                        hipStream_t st);
 void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t st);
 int launch_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layout& L, hipStream_t st);

@@ -40,6 +40,8 @@ namespace gd {
 constexpr int kNB = 64;   // bins of the per-lane distance histograms
 constexpr int kC1 = 16;   // largest boundary bin ranked in registers
 constexpr int kDMax = 3;  // levels of the nested bin chain
+constexpr int kRescales = 4;  // restarts of pass A on a finer distance scale
+constexpr double kHintSlack = 1.15;  // first radius: previous neighbour distance times this
 constexpr int kQBlock = 256;
 
 // ---------------------------------------------------------------------------
@@ -135,6 +137,8 @@ struct KnnArgs {
     int32_t* cnt;
     double* dmax;
     int32_t row_vec;  // nbr is 16-byte aligned
+    int32_t* xq;      // per-die work queue counters
+    const double* hint;  // previous neighbour distance per slot (search hint only)
     void* ws;
 };
 
@@ -211,6 +215,7 @@ __device__ inline uint32_t child_mask(const KnnArgs& A, int level, int idx, cons
 // Visit every active slot j with d^2(q, j) <= R2 (j == q included; the
 // visitor filters), a bucket at a time: f(j0, d2[kBucket], mask) gets the
 // bucket's first slot, the d^2 of its slots and the mask of those within R2.
+// A visitor that sets R2 negative ends the walk.
 // Nearest region first: the level-1 ancestor of q's bucket,
 // then the other children of each further ancestor, depth first.  The
 // visitor may lower R2; pruning uses the current value.  One iteration does
@@ -228,6 +233,7 @@ __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], 
     float R2f = r2f(R2);
     int steps = 0;
     for (;;) {
+        if (!(R2 >= 0.0)) break;  // the visitor ended the walk
         if (pend) {
             masks |= uint64_t(child_mask<PER>(A, level, idx, qf, R2f) & ~excl) << (8 * (level - 1));
             excl = 0;
@@ -419,7 +425,8 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
     using QL = QueryLds<KP2>;
     __shared__ uint32_t s_lds[QL::kWords * kQBlock];
     const int tid = threadIdx.x;
-    const int64_t q64 = xcd_block() * int64_t(kQBlock) + tid;
+    const int32_t item = xcd_take(A.xq, int32_t(gridDim.x * (kQBlock / kWave)));
+    const int64_t q64 = item < 0 ? A.n : int64_t(item) * kWave + (tid & (kWave - 1));
     if (q64 >= A.n) return;
     const int q = int(q64);
     const int na = A.h->n_active;
@@ -467,7 +474,6 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
         A.dmax[q] = 0.0;
         return;
     }
-    const double R2cap = fmin(R2init, A.rmax2);
     QF qf;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -476,64 +482,99 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
         qf.m[a] = PER ? float(qp[a] - A.L[a]) : 0.0f;
     }
     Chain c{};
-    c.s = R2init > 0.0 ? 1.0 / R2init : 0.0;
-    if (!(c.s < INFINITY)) c.s = 0.0;
 
     // 2. pass A: count others into the log bins; once the bins below the cut
     //    bin hold k-1 others, lower the cut and the radius with it.  The
     //    window slots go first (their d^2 are cheap to recompute), then the
-    //    walk, which skips them.
-    hist_clear(s_lds, tid);
-    double R2 = R2cap;
-    int bcut = kNB - 1, cle = 0, hcut = 0, candA = 0;
-    bool sat = false;
-    const double sA = c.s;
-    // lower the cut while the bins below it already hold k-1 others
-    auto cut = [&]() {
-        if (bcut > 0 && cle - hcut >= need) {
-            do {
-                cle -= hcut;
-                --bcut;
-                hcut = hist_get(s_lds, tid, bcut);
-            } while (bcut > 0 && cle - hcut >= need);
-            // every x with log_bin(x) <= bcut has d^2 below this radius
-            if (sA > 0.0) R2 = fmin(R2cap, (log_edge(bcut + 1) * R2init) * (1.0 + 1e-12));
-        }
-    };
-    for (int j = wlo; j < whi; ++j) {
-        if (j == q) continue;
-        const double d2 = sep2_slot<PER>(A, qp, j);
-        if (!(d2 <= R2)) continue;
-        const int b = log_bin(d2 * sA);
-        if (b > bcut) continue;
-        hist_inc(s_lds, tid, b);
-        ++cle;
-        ++candA;
-        hcut += (b == bcut) ? 1 : 0;
-        cut();
+    //    walk, which skips them.  The particle's neighbour distance from the
+    //    previous search, widened by kHintSlack, sets the first radius: only
+    //    others inside it are counted, and if fewer than k-1 turn up the pass
+    //    runs again on the guaranteed bound.  If bin 0 alone comes to hold
+    //    k-1 others, the scale was too coarse (the window bound far above
+    //    the (k-1)-th distance): bin 0's upper edge is a new, 256 times
+    //    smaller bound and the pass starts again on it (at most kRescales
+    //    times).
+    double R2hint = INFINITY;
+    {
+        const double hv = A.hint[q] * kHintSlack;
+        if (hv > 0.0 && hv < INFINITY) R2hint = hv * hv;
     }
-    const int visA = walk<PER>(A, na, q, qp, qf, R2, [&](int j0, const double (&d2)[kBucket], uint32_t vm) {
-        if (sat) return;
-#pragma unroll
-        for (int t = 0; t < kBucket; ++t) {
-            const int j = j0 + t;
-            const int b = log_bin(d2[t] * sA);
-            if (((vm >> t) & 1u) && j != q && (j < wlo || j >= whi) && b <= bcut) {
-                hist_inc(s_lds, tid, b);
-                ++cle;
-                ++candA;
-                hcut += (b == bcut) ? 1 : 0;
+    bool use_hint = true;
+    double R2cap, R2;
+    int bcut, cle, hcut, candA, visA = 0, rescales = 0;
+    bool sat;
+    for (;;) {
+        R2cap = fmin(R2init, A.rmax2);
+        c.s = R2init > 0.0 ? 1.0 / R2init : 0.0;
+        if (!(c.s < INFINITY)) c.s = 0.0;
+        const double sA = c.s;
+        hist_clear(s_lds, tid);
+        R2 = use_hint ? fmin(R2cap, R2hint) : R2cap;
+        bcut = kNB - 1;
+        cle = hcut = candA = 0;
+        sat = false;
+        bool deep = false;
+        // lower the cut while the bins below it already hold k-1 others
+        auto cut = [&]() {
+            if (bcut > 0 && cle - hcut >= need) {
+                do {
+                    cle -= hcut;
+                    --bcut;
+                    hcut = hist_get(s_lds, tid, bcut);
+                } while (bcut > 0 && cle - hcut >= need);
+                // every x with log_bin(x) <= bcut has d^2 below this radius
+                // (the radius never grows: boxes already pruned stay pruned)
+                if (sA > 0.0) R2 = fmin(R2, (log_edge(bcut + 1) * R2init) * (1.0 + 1e-12));
             }
+            if (bcut == 0 && hcut >= need && sA > 0.0 && rescales < kRescales) {
+                deep = true;
+                R2 = -1.0;  // ends the walk
+            }
+        };
+        for (int j = wlo; j < whi && !deep; ++j) {
+            if (j == q) continue;
+            const double d2 = sep2_slot<PER>(A, qp, j);
+            if (!(d2 <= R2)) continue;
+            const int b = log_bin(d2 * sA);
+            if (b > bcut) continue;
+            hist_inc(s_lds, tid, b);
+            ++cle;
+            ++candA;
+            hcut += (b == bcut) ? 1 : 0;
+            cut();
         }
-        if (candA > kCandMax) {
-            sat = true;
-            return;
+        if (!deep)
+            visA += walk<PER>(A, na, q, qp, qf, R2, [&](int j0, const double (&d2)[kBucket], uint32_t vm) {
+                if (sat || deep) return;
+#pragma unroll
+                for (int t = 0; t < kBucket; ++t) {
+                    const int j = j0 + t;
+                    const int b = log_bin(d2[t] * sA);
+                    if (((vm >> t) & 1u) && j != q && (j < wlo || j >= whi) && b <= bcut) {
+                        hist_inc(s_lds, tid, b);
+                        ++cle;
+                        ++candA;
+                        hcut += (b == bcut) ? 1 : 0;
+                    }
+                }
+                if (candA > kCandMax) {
+                    sat = true;
+                    return;
+                }
+                cut();
+            });
+        if (!deep && use_hint && cle < need && R2hint < R2cap) {
+            use_hint = false;  // the hint was too small: count again on the bound
+            continue;
         }
-        cut();
-    });
+        if (!deep) break;
+        // bin 0 holds k-1 others: x < log_edge(1), so d^2 < log_edge(1) R2init
+        R2init = (log_edge(1) * R2init) * (1.0 + 1e-12);
+        ++rescales;
+    }
 
     // 3. the boundary bin; refine it with nested linear bins while over-full
-    int c0 = 0, hb = 0, refines = 0;
+    int c0 = 0, hb = 0, refines = 0, visR = 0;
     bool fallback = sat;
     if (sat) {
         c.depth = 0;  // every candidate inside R2 is a boundary candidate
@@ -557,7 +598,7 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
             c.set_level(D, loD, sD);
             ++refines;
             hist_clear(s_lds, tid);
-            walk<PER>(A, na, q, qp, qf, R2, [&](int j0, const double (&d2)[kBucket], uint32_t vm) {
+            visR += walk<PER>(A, na, q, qp, qf, R2, [&](int j0, const double (&d2)[kBucket], uint32_t vm) {
 #pragma unroll
                 for (int t = 0; t < kBucket; ++t)
                     if (((vm >> t) & 1u) && j0 + t != q && classify(c, d2[t]) == kBoundary)
@@ -605,16 +646,18 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
         }
     });
 #ifdef GD_KNN_STATS
-    A.stats[q * 8 + 0] = refines;
+    A.stats[q * 8 + 0] = refines + 16 * rescales;
     A.stats[q * 8 + 1] = visA;
     A.stats[q * 8 + 2] = candA;
     A.stats[q * 8 + 3] = visB;
     A.stats[q * 8 + 4] = c.depth;
     A.stats[q * 8 + 5] = fallback;
     A.stats[q * 8 + 6] = hb;
+    A.stats[q * 8 + 7] = visA + visB + visR;
 #else
     (void)visA;
     (void)visB;
+    (void)visR;
     (void)refines;
 #endif
     if (nsel != c0) set_status(A.ws, GD_DEV_INTERNAL);
@@ -652,7 +695,7 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
         for (int t = 0; t < needb; ++t) {
             double bestd = INFINITY;
             int bestj = INT32_MAX;
-            walk<PER>(A, na, q, qp, qf, R2, [&](int j0, const double (&d2)[kBucket], uint32_t vm) {
+            visR += walk<PER>(A, na, q, qp, qf, R2, [&](int j0, const double (&d2)[kBucket], uint32_t vm) {
                 for (int t = 0; t < kBucket; ++t) {
                     const int j = j0 + t;
                     if (!((vm >> t) & 1u) || j == q || (!sat && classify(c, d2[t]) != kBoundary)) continue;
@@ -746,8 +789,11 @@ int launch_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layo
     A.row_vec = (reinterpret_cast<uintptr_t>(nb->nbr) & 15) == 0 ? 1 : 0;
     A.cnt = nb->cnt;
     A.dmax = nb->dmax;
+    A.hint = at<double>(ws, L.hint);
     A.ws = ws;
+    A.xq = at<WsHeader>(ws, L.hdr)->xq[kQueueKnn];
     const dim3 grid(unsigned((n + kQBlock - 1) / kQBlock));
+    launch_fill_i32(A.xq, kXcd, 0, st);
     prof_mark(GD_PROF_KNN_QUERY, 0, st);
     if (p->k <= 33) {
         if (per) hipLaunchKernelGGL((k_knn_query<true, 32>), grid, dim3(kQBlock), 0, st, A);

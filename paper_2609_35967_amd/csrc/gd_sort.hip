@@ -240,6 +240,7 @@ __global__ __launch_bounds__(256) void k_permute(PermuteArgs A)
     p.z = A.src[2][s];
     p.w = 0.0;
     A.pos4[i] = p;
+    A.hint_dst[i] = A.hint_src ? A.hint_src[s] : 0.0;
 }
 
 __global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v)
@@ -249,7 +250,7 @@ __global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v)
 }
 
 // ---------------------------------------------------------------------------
-int launch_morton_sort(const gd_problem* p, const gd_particles* in, gd_particles* out, void* ws,
+int launch_morton_sort(const gd_problem* p, const gd_particles* in, gd_particles* out, const double* hint, void* ws,
                        const Layout& L, hipStream_t st)
 {
     const int64_t n = p->n;
@@ -306,6 +307,8 @@ int launch_morton_sort(const gd_problem* p, const gd_particles* in, gd_particles
     A.id_src = in->id;
     A.id_dst = out->id;
     A.pos4 = at<double4>(ws, L.pos4);
+    A.hint_src = hint;
+    A.hint_dst = at<double>(ws, L.hint);
     hipLaunchKernelGGL(k_permute, dim3(nb), dim3(256), 0, st, A);
     prof_mark(GD_PROF_SORT, 1, st);
     out->cur = in->cur;

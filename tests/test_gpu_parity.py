@@ -131,6 +131,31 @@ def test_build_neighbors_box(case):
     assert int(eng.n_active.item()) == int((st["M"] > 0).sum())
 
 
+@pytest.mark.parametrize("hint", ["previous", 0.0, 1e-300, 1e300, float("nan"), -1.0, "mixed"])
+def test_build_neighbors_search_hint(hint):
+    # the previous distances are read back as a search hint; the result must
+    # not depend on them (too small, too large, non-finite or stale)
+    params = workloads.disk3d_params(32768)
+    st = workloads.disk3d(5, 32768, params=params)
+    _say("knn hint", hint)
+    eng = _engine(params, st)
+    eng.build_neighbors()
+    torch.cuda.synchronize()
+    if hint == "mixed":
+        g = torch.Generator(device="cpu").manual_seed(7)
+        v = torch.rand(eng.n, generator=g, dtype=torch.float64) * 2 * eng.dmax.cpu()
+        v[::7] = 1e-20
+        eng.dmax.copy_(v.to(eng.dmax.device))
+    elif hint != "previous":
+        eng.dmax.fill_(hint)
+    eng.build_neighbors()
+    torch.cuda.synchronize()
+    got = eng.state_numpy()
+    q = np.random.default_rng(1).choice(eng.n, 3000, replace=False)
+    _knn_compare(eng, params, got, queries=q)
+    assert eng.status() & 0x20 == 0  # no internal inconsistency
+
+
 def test_build_neighbors_column_periodic_xy():
     params = workloads.additive_col_params(65536)
     st = workloads.additive_col(1, 65536)
