@@ -19,16 +19,22 @@
 //   1. upper bound R2init of the (k-1)-th d^2: the smallest, over three
 //      windows of k consecutive slots holding the query, of the window's
 //      largest d^2;
-//   2. pass A: count others into per-lane bins, logarithmic in d^2 / R2init;
-//      whenever the bins below some bin already hold k-1 others, cut the
-//      radius to that bin's upper edge (the walk prunes with the cut radius);
-//   3. the bin holding the (k-1)-th other splits candidates into "sure" (lower
-//      bins) and "boundary"; an over-full boundary bin is re-binned (nested,
-//      linear, still monotone bins) until it holds <= 16 candidates;
-//   4. pass B: walk again inside the final radius, append sure slots to the
-//      output row, keep boundary slots, rank them by (d^2, slot);
-//   5. sort the retained others by slot in registers.
-// Per-lane bins live in LDS columns (no synchronisation).  d^2 is
+//   2. pass A: count others into per-lane bins, logarithmic in d^2 over the
+//      pass's first radius (the particle's distance from the previous search
+//      when one is given, else R2init); whenever the bins below some bin
+//      already hold k-1 others, cut the radius to that bin's upper edge (the
+//      walk prunes with the cut radius).  Every counted other is also kept,
+//      with its bin, in a per-lane list (entries above the cut are dropped
+//      when it fills);
+//   3. the bin holding the (k-1)-th other splits the list into "sure" (lower
+//      bins) and "boundary" entries; the boundary ones are ranked by
+//      (d^2, slot);
+//   4. only a lane whose list overflowed walks again (pass B) inside the final
+//      radius, after re-binning an over-full boundary bin with nested linear
+//      bins;
+//   5. the retained others are sorted by slot in registers and the row is
+//      written once.
+// Per-lane bins and lists live in LDS columns (no synchronisation).  d^2 is
 // (dx*dx + dy*dy) + dz*dz, each operation rounded on its own; every bin
 // function is monotone in d^2, so the result is exactly the k-1 smallest
 // (d^2, slot).
@@ -37,12 +43,12 @@
 
 namespace gd {
 
-constexpr int kNB = 64;   // bins of the per-lane distance histograms
+constexpr int kNB = 32;   // bins of the per-lane distance histograms
 constexpr int kC1 = 16;   // largest boundary bin ranked in registers
 constexpr int kDMax = 3;  // levels of the nested bin chain
 constexpr int kRescales = 4;  // restarts of pass A on a finer distance scale
 constexpr double kHintSlack = 1.15;  // first radius: previous neighbour distance times this
-constexpr int kQBlock = 256;
+constexpr int kQBlock = 128;
 
 // ---------------------------------------------------------------------------
 // Tree build
@@ -300,9 +306,10 @@ __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], 
     return steps;
 }
 
-// First-level bins: logarithmic in x = d^2 / R2init, 8 per octave over 8
-// octaves, read off the bits of the double (monotone for x >= 0); bin 0 takes
-// everything below 2^-8 * 2^(1/8), the last bin everything from 2^(-1/8).
+// First-level bins: logarithmic in x = d^2 / (the pass's first radius), 8 per
+// octave over the kNB / 8 octaves below 1, read off the bits of the double
+// (monotone for x >= 0); bin 0 also takes everything below, the last bin
+// everything from 2^(-1/8).
 constexpr int kLogShift = 49;
 constexpr int64_t kLogBase = int64_t(1023) * 8 - kNB;
 
@@ -411,13 +418,17 @@ __device__ inline void bitonic_sort(int32_t (&v)[N])
 // bucket may add kBucket past the check)
 constexpr int kCandMax = 0xFFFF - 2 * kBucket;
 
-// LDS words per lane: the sure list (then the retained others) and the
-// boundary list; the bin counters use the first kNB / 2 words before that.
+// LDS words per lane: the bin counters (kNB / 2 words, later the boundary
+// list) and the candidate list (later the retained others).  The list holds
+// the k-1 nearest plus a boundary bin of up to 16 and a little slack.
 template <int KP2>
 struct QueryLds {
-    static constexpr int kSure = KP2 > kNB / 2 ? KP2 : kNB / 2;
-    static constexpr int kWords = kSure + kC1;
+    static constexpr int kList = KP2 > 32 ? 80 : 48;
+    static constexpr int kWords = kNB / 2 + kList;
 };
+constexpr uint32_t kSlotMask = (1u << 26) - 1;  // list word: mark << 31 | bin << 26 | slot
+static_assert(kC1 <= kNB / 2, "the boundary list reuses the counter words");
+static_assert(kNB <= 32, "list words keep the bin in 5 bits");
 
 template <bool PER, int KP2>
 __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
@@ -491,8 +502,8 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
     //    others inside it are counted, and if fewer than k-1 turn up the pass
     //    runs again on the guaranteed bound.  If bin 0 alone comes to hold
     //    k-1 others, the scale was too coarse (the window bound far above
-    //    the (k-1)-th distance): bin 0's upper edge is a new, 256 times
-    //    smaller bound and the pass starts again on it (at most kRescales
+    //    the (k-1)-th distance): bin 0's upper edge, 2^(-31/8) of the scale,
+    //    is a new bound and the pass starts again on it (at most kRescales
     //    times).
     double R2hint = INFINITY;
     {
@@ -503,16 +514,21 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
     double R2cap, R2;
     int bcut, cle, hcut, candA, visA = 0, rescales = 0;
     bool sat;
+    uint32_t* s_list = s_lds + (kNB / 2) * kQBlock;  // entry e of lane tid at s_list[e * kQBlock + tid]
+    constexpr int cap = QL::kList;
+    int len;
+    bool ovf;
     for (;;) {
         R2cap = fmin(R2init, A.rmax2);
-        c.s = R2init > 0.0 ? 1.0 / R2init : 0.0;
+        const double R2s = use_hint ? fmin(R2cap, R2hint) : R2cap;  // first radius and bin scale
+        c.s = R2s > 0.0 ? 1.0 / R2s : 0.0;
         if (!(c.s < INFINITY)) c.s = 0.0;
         const double sA = c.s;
         hist_clear(s_lds, tid);
-        R2 = use_hint ? fmin(R2cap, R2hint) : R2cap;
+        R2 = R2s;
         bcut = kNB - 1;
-        cle = hcut = candA = 0;
-        sat = false;
+        cle = hcut = candA = len = 0;
+        sat = ovf = false;
         bool deep = false;
         // lower the cut while the bins below it already hold k-1 others
         auto cut = [&]() {
@@ -524,12 +540,35 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
                 } while (bcut > 0 && cle - hcut >= need);
                 // every x with log_bin(x) <= bcut has d^2 below this radius
                 // (the radius never grows: boxes already pruned stay pruned)
-                if (sA > 0.0) R2 = fmin(R2, (log_edge(bcut + 1) * R2init) * (1.0 + 1e-12));
+                if (sA > 0.0) R2 = fmin(R2, (log_edge(bcut + 1) * R2s) * (1.0 + 1e-12));
             }
             if (bcut == 0 && hcut >= need && sA > 0.0 && rescales < kRescales) {
                 deep = true;
                 R2 = -1.0;  // ends the walk
             }
+        };
+        // count one other and record it (with its bin) in the list; a full
+        // list drops the entries above the cut, and a list still full after
+        // that is given up (the lane then walks again for its neighbours)
+        auto take = [&](int j, int b) {
+            hist_inc(s_lds, tid, b);
+            ++cle;
+            ++candA;
+            hcut += (b == bcut) ? 1 : 0;
+            if (ovf) return;
+            if (len == cap) {
+                int kept = 0;
+                for (int e = 0; e < cap; ++e) {
+                    const uint32_t w = s_list[e * kQBlock + tid];
+                    if (int(w >> 26) <= bcut) s_list[(kept++) * kQBlock + tid] = w;
+                }
+                len = kept;
+                if (len == cap) {
+                    ovf = true;
+                    return;
+                }
+            }
+            s_list[(len++) * kQBlock + tid] = (uint32_t(b) << 26) | uint32_t(j);
         };
         for (int j = wlo; j < whi && !deep; ++j) {
             if (j == q) continue;
@@ -537,10 +576,7 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
             if (!(d2 <= R2)) continue;
             const int b = log_bin(d2 * sA);
             if (b > bcut) continue;
-            hist_inc(s_lds, tid, b);
-            ++cle;
-            ++candA;
-            hcut += (b == bcut) ? 1 : 0;
+            take(j, b);
             cut();
         }
         if (!deep)
@@ -550,12 +586,7 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
                 for (int t = 0; t < kBucket; ++t) {
                     const int j = j0 + t;
                     const int b = log_bin(d2[t] * sA);
-                    if (((vm >> t) & 1u) && j != q && (j < wlo || j >= whi) && b <= bcut) {
-                        hist_inc(s_lds, tid, b);
-                        ++cle;
-                        ++candA;
-                        hcut += (b == bcut) ? 1 : 0;
-                    }
+                    if (((vm >> t) & 1u) && j != q && (j < wlo || j >= whi) && b <= bcut) take(j, b);
                 }
                 if (candA > kCandMax) {
                     sat = true;
@@ -568,85 +599,212 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
             continue;
         }
         if (!deep) break;
-        // bin 0 holds k-1 others: x < log_edge(1), so d^2 < log_edge(1) R2init
-        R2init = (log_edge(1) * R2init) * (1.0 + 1e-12);
+        // bin 0 holds k-1 others: x < log_edge(1), so d^2 < log_edge(1) R2s
+        R2init = (log_edge(1) * R2s) * (1.0 + 1e-12);
         ++rescales;
     }
 
-    // 3. the boundary bin; refine it with nested linear bins while over-full
-    int c0 = 0, hb = 0, refines = 0, visR = 0;
-    bool fallback = sat;
-    if (sat) {
-        c.depth = 0;  // every candidate inside R2 is a boundary candidate
-    } else if (cle < need) {
-        c.depth = 1;
-        c.b0 = kNB;  // fewer than k-1 others within the cap: keep them all
-        c0 = cle;
-    } else {
-        c.depth = 1;
-        c.b0 = bcut;
-        hb = hcut;
-        c0 = cle - hb;
-        double loD = bcut == 0 ? 0.0 : log_edge(bcut);
-        double sD = double(kNB) / (log_edge(bcut + 1) - loD);
-        while (hb > kC1) {
-            const int D = c.depth;
-            if (D >= kDMax || !(c.s > 0.0) || !(sD < 1e300) || !(sD > 0.0) || loD + 1.0 / sD == loD) {
-                fallback = true;
-                break;
-            }
-            c.set_level(D, loD, sD);
-            ++refines;
-            hist_clear(s_lds, tid);
-            visR += walk<PER>(A, na, q, qp, qf, R2, [&](int j0, const double (&d2)[kBucket], uint32_t vm) {
-#pragma unroll
-                for (int t = 0; t < kBucket; ++t)
-                    if (((vm >> t) & 1u) && j0 + t != q && classify(c, d2[t]) == kBoundary)
-                        hist_inc(s_lds, tid, bin_at(d2[t] * c.s, loD, sD));
-            });
-            const int needD = need - c0;
-            int cum = 0, bs = kNB - 1, hv = 0;
-            for (int b = 0; b < kNB; ++b) {
-                hv = hist_get(s_lds, tid, b);
-                if (cum + hv >= needD) {
-                    bs = b;
-                    break;
-                }
-                cum += hv;
-            }
-            c.set_b(D, bs);
-            c.depth = D + 1;
-            c0 += cum;
-            hb = hv;
-            loD = loD + double(bs) / sD;
-            sD = sD * double(kNB);
-        }
-    }
-
-    // 4. pass B inside the final radius: sure and boundary slots go to the
-    //    lane's LDS lists (the counters are no longer needed)
-    int nsel = 0, nb = 0;
+    // 3. sure and boundary others.  From the list when it kept every counted
+    //    other (the usual case); otherwise (sat / overflow) by refining an
+    //    over-full boundary bin with nested linear bins and walking again.
+    //    Either way the retained others end in list words [0, ntot).
+    int32_t* s_bnd = reinterpret_cast<int32_t*>(s_lds);  // the counters are no longer needed
+    const bool from_list = !sat && !ovf;
+    const bool keep = cle < need;  // fewer than k-1 others within the cap: keep them all
+    int c0 = 0, hb = 0, refines = 0, visB = 0, visR = 0, nsel = 0, nb = 0, ntot = 0;
     double maxd2 = 0.0;
-    int32_t* s_sel = reinterpret_cast<int32_t*>(s_lds);
-    int32_t* s_bnd = s_sel + QL::kSure * kQBlock;
-    const int visB = walk<PER>(A, na, q, qp, qf, R2, [&](int j0, const double (&d2)[kBucket], uint32_t vm) {
-#pragma unroll
-        for (int t = 0; t < kBucket; ++t) {
-            const int j = j0 + t;
-            if (!((vm >> t) & 1u) || j == q) continue;
-            const int cl = sat ? kBoundary : classify(c, d2[t]);
-            if (cl == kSure) {
-                if (nsel < need) s_sel[nsel * kQBlock + tid] = j;
-                ++nsel;
-                maxd2 = fmax(maxd2, d2[t]);
-            } else if (cl == kBoundary) {
-                if (nb < kC1) s_bnd[nb * kQBlock + tid] = j;
+    bool fallback = sat;
+    if (from_list) {
+        const int b0 = keep ? kNB : bcut;
+        c0 = keep ? cle : cle - hcut;
+        hb = keep ? 0 : hcut;
+        // boundary entries: their list positions
+        for (int e = 0; e < len; ++e)
+            if (int((s_list[e * kQBlock + tid] >> 26) & 31u) == b0) {
+                if (nb < kC1) s_bnd[nb * kQBlock + tid] = e;
                 ++nb;
             }
+        const int needb = need - c0 < nb ? need - c0 : nb;
+        if (nb <= kC1) {
+            // rank by (d^2, slot) in registers; mark the chosen entries
+            double bd[kC1];
+            int32_t bj[kC1], bp[kC1];
+#pragma unroll
+            for (int e = 0; e < kC1; ++e) {
+                bp[e] = e < nb ? s_bnd[e * kQBlock + tid] : 0;
+                bj[e] = e < nb ? int32_t(s_list[bp[e] * kQBlock + tid] & kSlotMask) : INT32_MAX;
+                bd[e] = e < nb ? sep2_slot<PER>(A, qp, bj[e]) : INFINITY;
+            }
+#pragma unroll
+            for (int e = 0; e < kC1; ++e) {
+                int rank = 0;
+#pragma unroll
+                for (int f = 0; f < kC1; ++f) rank += (bd[f] < bd[e]) || (bd[f] == bd[e] && bj[f] < bj[e]);
+                if (e < nb && rank < needb) {
+                    s_list[bp[e] * kQBlock + tid] |= 0x80000000u;
+                    maxd2 = fmax(maxd2, bd[e]);
+                }
+            }
+        } else {
+            // many boundary entries (rare): repeated minimum over the list
+            double lastd = -1.0;
+            int lastj = -1;
+            for (int t = 0; t < needb; ++t) {
+                double bestd = INFINITY;
+                int bestj = INT32_MAX, beste = -1;
+                for (int e = 0; e < len; ++e) {
+                    const uint32_t w = s_list[e * kQBlock + tid];
+                    if (int((w >> 26) & 31u) != b0) continue;
+                    const int j = int(w & kSlotMask);
+                    const double d2 = sep2_slot<PER>(A, qp, j);
+                    const bool after = (d2 > lastd) || (d2 == lastd && j > lastj);
+                    const bool better = (d2 < bestd) || (d2 == bestd && j < bestj);
+                    if (after && better) {
+                        bestd = d2;
+                        bestj = j;
+                        beste = e;
+                    }
+                }
+                if (beste >= 0) s_list[beste * kQBlock + tid] |= 0x80000000u;
+                maxd2 = fmax(maxd2, bestd);
+                lastd = bestd;
+                lastj = bestj;
+            }
         }
-    });
+        // keep the sure and the chosen entries, in place at the front
+        for (int e = 0; e < len; ++e) {
+            const uint32_t w = s_list[e * kQBlock + tid];
+            if (int((w >> 26) & 31u) < b0 || (w >> 31)) {
+                const int j = int(w & kSlotMask);
+                s_list[(ntot++) * kQBlock + tid] = uint32_t(j);
+                if (keep) maxd2 = fmax(maxd2, sep2_slot<PER>(A, qp, j));
+            }
+        }
+        nsel = c0;
+        if (ntot != c0 + needb) set_status(A.ws, GD_DEV_INTERNAL);
+    } else {
+        if (sat) {
+            c.depth = 0;  // every candidate inside R2 is a boundary candidate
+        } else if (keep) {
+            c.depth = 1;
+            c.b0 = kNB;
+            c0 = cle;
+        } else {
+            c.depth = 1;
+            c.b0 = bcut;
+            hb = hcut;
+            c0 = cle - hb;
+            double loD = bcut == 0 ? 0.0 : log_edge(bcut);
+            double sD = double(kNB) / (log_edge(bcut + 1) - loD);
+            while (hb > kC1) {
+                const int D = c.depth;
+                if (D >= kDMax || !(c.s > 0.0) || !(sD < 1e300) || !(sD > 0.0) || loD + 1.0 / sD == loD) {
+                    fallback = true;
+                    break;
+                }
+                c.set_level(D, loD, sD);
+                ++refines;
+                hist_clear(s_lds, tid);
+                visR += walk<PER>(A, na, q, qp, qf, R2, [&](int j0, const double (&d2)[kBucket], uint32_t vm) {
+#pragma unroll
+                    for (int t = 0; t < kBucket; ++t)
+                        if (((vm >> t) & 1u) && j0 + t != q && classify(c, d2[t]) == kBoundary)
+                            hist_inc(s_lds, tid, bin_at(d2[t] * c.s, loD, sD));
+                });
+                const int needD = need - c0;
+                int cum = 0, bs = kNB - 1, hv = 0;
+                for (int b = 0; b < kNB; ++b) {
+                    hv = hist_get(s_lds, tid, b);
+                    if (cum + hv >= needD) {
+                        bs = b;
+                        break;
+                    }
+                    cum += hv;
+                }
+                c.set_b(D, bs);
+                c.depth = D + 1;
+                c0 += cum;
+                hb = hv;
+                loD = loD + double(bs) / sD;
+                sD = sD * double(kNB);
+            }
+        }
+        // 4. pass B inside the final radius: sure slots to the list words,
+        //    boundary slots to the boundary words
+        visB = walk<PER>(A, na, q, qp, qf, R2, [&](int j0, const double (&d2)[kBucket], uint32_t vm) {
+#pragma unroll
+            for (int t = 0; t < kBucket; ++t) {
+                const int j = j0 + t;
+                if (!((vm >> t) & 1u) || j == q) continue;
+                const int cl = sat ? kBoundary : classify(c, d2[t]);
+                if (cl == kSure) {
+                    if (nsel < need) s_list[nsel * kQBlock + tid] = uint32_t(j);
+                    ++nsel;
+                    maxd2 = fmax(maxd2, d2[t]);
+                } else if (cl == kBoundary) {
+                    if (nb < kC1) s_bnd[nb * kQBlock + tid] = j;
+                    ++nb;
+                }
+            }
+        });
+        if (nsel != c0) set_status(A.ws, GD_DEV_INTERNAL);
+        const int nsel_w = nsel < need ? nsel : need;
+        const int needb = need - nsel_w < nb ? need - nsel_w : nb;
+        if (nb > kC1) fallback = true;
+        if (!fallback) {
+            double bd[kC1];
+            int32_t bj[kC1];
+#pragma unroll
+            for (int e = 0; e < kC1; ++e) {
+                if (e < nb) {
+                    const int j = s_bnd[e * kQBlock + tid];
+                    bj[e] = j;
+                    bd[e] = sep2_slot<PER>(A, qp, j);
+                } else {
+                    bj[e] = INT32_MAX;
+                    bd[e] = INFINITY;
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < kC1; ++e) {
+                int rank = 0;
+#pragma unroll
+                for (int f = 0; f < kC1; ++f) rank += (bd[f] < bd[e]) || (bd[f] == bd[e] && bj[f] < bj[e]);
+                if (e < nb && rank < needb) {
+                    s_list[(nsel_w + rank) * kQBlock + tid] = uint32_t(bj[e]);
+                    maxd2 = fmax(maxd2, bd[e]);
+                }
+            }
+        } else {
+            // exact selection among the boundary candidates (rare): repeated minimum
+            set_status(A.ws, GD_DEV_KNN_FALLBACK);
+            double lastd = -1.0;
+            int lastj = -1;
+            for (int t = 0; t < needb; ++t) {
+                double bestd = INFINITY;
+                int bestj = INT32_MAX;
+                visR += walk<PER>(A, na, q, qp, qf, R2, [&](int j0, const double (&d2)[kBucket], uint32_t vm) {
+                    for (int t2 = 0; t2 < kBucket; ++t2) {
+                        const int j = j0 + t2;
+                        if (!((vm >> t2) & 1u) || j == q || (!sat && classify(c, d2[t2]) != kBoundary)) continue;
+                        const bool after = (d2[t2] > lastd) || (d2[t2] == lastd && j > lastj);
+                        const bool better = (d2[t2] < bestd) || (d2[t2] == bestd && j < bestj);
+                        if (after && better) {
+                            bestd = d2[t2];
+                            bestj = j;
+                        }
+                    }
+                });
+                s_list[(nsel_w + t) * kQBlock + tid] = uint32_t(bestj);
+                maxd2 = fmax(maxd2, bestd);
+                lastd = bestd;
+                lastj = bestj;
+            }
+        }
+        ntot = nsel_w + needb;
+    }
 #ifdef GD_KNN_STATS
-    A.stats[q * 8 + 0] = refines + 16 * rescales;
+    A.stats[q * 8 + 0] = refines + 16 * rescales + (ovf ? 1024 : 0);
     A.stats[q * 8 + 1] = visA;
     A.stats[q * 8 + 2] = candA;
     A.stats[q * 8 + 3] = visB;
@@ -659,66 +817,13 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
     (void)visB;
     (void)visR;
     (void)refines;
+    (void)hb;
 #endif
-    if (nsel != c0) set_status(A.ws, GD_DEV_INTERNAL);
-    const int nsel_w = nsel < need ? nsel : need;
-    const int needb = need - nsel_w < nb ? need - nsel_w : nb;
-    if (!fallback) {
-        double bd[kC1];
-        int32_t bj[kC1];
-#pragma unroll
-        for (int e = 0; e < kC1; ++e) {
-            if (e < nb) {
-                const int j = s_bnd[e * kQBlock + tid];
-                bj[e] = j;
-                bd[e] = sep2_slot<PER>(A, qp, j);
-            } else {
-                bj[e] = INT32_MAX;
-                bd[e] = INFINITY;
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < kC1; ++e) {
-            int rank = 0;
-#pragma unroll
-            for (int f = 0; f < kC1; ++f) rank += (bd[f] < bd[e]) || (bd[f] == bd[e] && bj[f] < bj[e]);
-            if (e < nb && rank < needb) {
-                s_sel[(nsel_w + rank) * kQBlock + tid] = bj[e];
-                maxd2 = fmax(maxd2, bd[e]);
-            }
-        }
-    } else {
-        // exact selection among the boundary candidates (rare): repeated minimum
-        set_status(A.ws, GD_DEV_KNN_FALLBACK);
-        double lastd = -1.0;
-        int lastj = -1;
-        for (int t = 0; t < needb; ++t) {
-            double bestd = INFINITY;
-            int bestj = INT32_MAX;
-            visR += walk<PER>(A, na, q, qp, qf, R2, [&](int j0, const double (&d2)[kBucket], uint32_t vm) {
-                for (int t = 0; t < kBucket; ++t) {
-                    const int j = j0 + t;
-                    if (!((vm >> t) & 1u) || j == q || (!sat && classify(c, d2[t]) != kBoundary)) continue;
-                    const bool after = (d2[t] > lastd) || (d2[t] == lastd && j > lastj);
-                    const bool better = (d2[t] < bestd) || (d2[t] == bestd && j < bestj);
-                    if (after && better) {
-                        bestd = d2[t];
-                        bestj = j;
-                    }
-                }
-            });
-            s_sel[(nsel_w + t) * kQBlock + tid] = bestj;
-            maxd2 = fmax(maxd2, bestd);
-            lastd = bestd;
-            lastj = bestj;
-        }
-    }
-    const int ntot = nsel_w + needb;
 
     // 5. retained others in ascending slot order; the row is written once
     int32_t v[KP2];
 #pragma unroll
-    for (int e = 0; e < KP2; ++e) v[e] = (e < ntot) ? s_sel[e * kQBlock + tid] : INT32_MAX;
+    for (int e = 0; e < KP2; ++e) v[e] = (e < ntot) ? int32_t(s_list[e * kQBlock + tid]) : INT32_MAX;
     bitonic_sort<KP2>(v);
     if (k == KP2 && A.row_vec) {  // 16-byte aligned rows: vector stores
 #pragma unroll
