@@ -37,9 +37,9 @@ FP64_VEC_PEAK_TFLOPS = 78.6    # MI355X FP64 vector (FMA = 2 flops)
 # workload (k = 32, FP64); see the design notes for the derivation.
 ALGO_BYTES = {
     "sort": 40 + 4 * 16 + 232,     # keys (read pos 24 + M 8, write key+slot 8); 4 radix passes; permute state
-    "tree": 4 + 4 + 64,            # keys, parent links, node record
+    "tree": 32 + 7,                # read packed positions; write 24-byte boxes of 4-particle buckets and above
     "knn_query": 24 + 128 + 4 + 8,  # own position; write nbr row, cnt, d_i
-    "rates": 128 + 4 + 8 + 24 + 8 + 16 + 24,  # nbr row, cnt, d_i, position, m, snapshot s/N; write lam, a, b
+    "rates": 128 + 4 + 8 + 24 + 16 + 32 + 24,  # nbr row, cnt, d_i, position, m and M; write snapshot record; write lam, a, b
     "mc": 4 + 8 + 8 + 4 + 8 + 4,   # cnt, lam, m, id; write m', events
     "audit": 24,                   # m, m', M
     "push": 64 + 72,               # read spherical state, m, M; write state and Cartesian cache
