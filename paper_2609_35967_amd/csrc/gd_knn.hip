@@ -455,11 +455,21 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
     const double4 q4 = A.pos[q];
     const double qp[3] = {q4.x, q4.y, q4.z};
 
+    if (!(fabs(qp[0]) < INFINITY && fabs(qp[1]) < INFINITY && fabs(qp[2]) < INFINITY)) {
+        set_status(A.ws, GD_DEV_NONFINITE);  // non-finite position: self only
+        row[0] = q;
+        for (int s = 1; s < k; ++s) row[s] = -1;
+        A.cnt[q] = 1;
+        A.dmax[q] = 0.0;
+        return;
+    }
+
     // 1. upper bound of the (k-1)-th d^2 from three windows of k slots holding
-    //    q (ending at, centred on, starting at q); with fewer than k slots, all
-    double R2init;
-    int wlo, whi;  // the slots of the three windows
-    {
+    //    q (ending at, centred on, starting at q); with fewer than k slots, all.
+    //    Needed only when there is no usable hint, or the hint falls short.
+    double R2init = INFINITY;
+    int wlo = 0, whi = 0;  // the slots of the three windows (none yet)
+    auto window_bound = [&]() {
         const int span = na < k ? na : k;
         const int fmaxs = na - span;
         int f0 = q - span + 1, f1 = q - span / 2 + 1, f2 = q;
@@ -476,15 +486,7 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
             if (j >= f2) w2 = fmax(w2, d2);
         }
         R2init = fmin(w0, fmin(w1, w2));
-    }
-    if (!(R2init < INFINITY)) {  // non-finite positions
-        set_status(A.ws, GD_DEV_NONFINITE);
-        row[0] = q;
-        for (int s = 1; s < k; ++s) row[s] = -1;
-        A.cnt[q] = 1;
-        A.dmax[q] = 0.0;
-        return;
-    }
+    };
     QF qf;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -508,9 +510,26 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
     double R2hint = INFINITY;
     {
         const double hv = A.hint[q] * kHintSlack;
-        if (hv > 0.0 && hv < INFINITY) R2hint = hv * hv;
+        if (hv > 0.0 && hv < INFINITY) {
+            // a radius beyond the diagonal of the active set's box is no hint
+            const FBox* tb = A.boxes + A.T.off[A.T.levels - 1];
+            double e2 = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                float lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+                for (int c = 0; c < kFan; ++c) {
+                    lo = fminf(lo, tb[c].lo[a]);
+                    hi = fmaxf(hi, tb[c].hi[a]);
+                }
+                const double ext = double(hi) - double(lo);
+                e2 += ext * ext;
+            }
+            if (hv * hv <= e2) R2hint = hv * hv;
+        }
     }
-    bool use_hint = true;
+    bool use_hint = R2hint < INFINITY;
+    if (!use_hint) window_bound();
     double R2cap, R2;
     int bcut, cle, hcut, candA, visA = 0, rescales = 0;
     bool sat;
@@ -596,6 +615,7 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
             });
         if (!deep && use_hint && cle < need && R2hint < R2cap) {
             use_hint = false;  // the hint was too small: count again on the bound
+            window_bound();
             continue;
         }
         if (!deep) break;

@@ -131,7 +131,7 @@ def test_build_neighbors_box(case):
     assert int(eng.n_active.item()) == int((st["M"] > 0).sum())
 
 
-@pytest.mark.parametrize("hint", ["previous", 0.0, 1e-300, 1e300, float("nan"), -1.0, "mixed"])
+@pytest.mark.parametrize("hint", ["previous", 0.0, 1e-300, 1e300, 1e17, float("nan"), -1.0, "mixed"])
 def test_build_neighbors_search_hint(hint):
     # the previous distances are read back as a search hint; the result must
     # not depend on them (too small, too large, non-finite or stale)
