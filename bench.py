@@ -183,6 +183,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=98304, help="particles in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rates-fp32", action="store_true",
+                    help="the single-precision pair-rate form (FP64 positions, distances and push)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="REPS",
                     help="only run a plain 1 GiB device copy REPS times (HBM counter calibration)")
     args = ap.parse_args()
@@ -200,6 +202,8 @@ def main():
     load()
     torch.cuda.set_device(0)
     params, st = workloads.by_name(args.workload, seed=args.seed, n=args.n)
+    if args.rates_fp32:
+        params["rates_fp32"] = 1
     eng = Engine(params, st, seed=args.seed)
     n = eng.n
     hip = HipEvents()
@@ -244,10 +248,11 @@ def main():
         metric="particle-intervals/s (kNN+rates+MC) at 1M; batched vs plain; p50/p99 latency",
         value=round(value, 1), unit="particle-intervals/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
         ms_per_step=round(wall / args.steps * 1e3, 4), higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="f64", data="synthetic",
+        dtype="f64+f32-rates" if args.rates_fp32 else "f64", data="synthetic",
         config=dict(workload=f"{args.workload}: 3D disk annulus r in [10,100] au, {n} particles, k=32, "
                              "alpha=1e-3, v_frag=1 m/s, Brownian+OC07, sticking/erosion/fragmentation, "
-                             "one push per interval", n_particles=n, k=32, form="plain (single run)"),
+                             "one push per interval", n_particles=n, k=32, form="plain (single run)",
+                    rates="fp32 pairs, fp64 sums" if args.rates_fp32 else "fp64"),
         p50_ms=round(float(np.percentile(lat, 50)), 4), p99_ms=round(float(np.percentile(lat, 99)), 4),
         breakdown_ms={k: round(v, 4) for k, v in brk.items()},
         path_fraction_of_hbm=round(path_bytes * value / (HBM_PEAK_GBS * 1e9), 5),

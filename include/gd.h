@@ -103,6 +103,9 @@ typedef struct gd_problem {
     int32_t brownian;     /* 1: Brownian term in dv (eq:dv) */
     int32_t turbulence;   /* 1: turbulent term in dv (Ormel & Cuzzi 2007) */
     int32_t caps;         /* 1: subtract boundary caps from V_i */
+    int32_t rates_fp32;   /* 0: FP64 pair rates (the reference form); 1: pair collision speeds,
+                             kernels, channel rates and moments in FP32, summed in FP64 (the
+                             context per particle, N_j/V_i, psi and grouping stay FP64) */
 } gd_problem;
 
 /* Particle state, structure of arrays, device pointers, length n.

@@ -288,3 +288,8 @@ def num_threads() -> int:
 
 def set_threads(n: int) -> None:
     lib().orc_set_threads(int(n))
+
+
+def set_tie_margin(eps: float) -> None:
+    """Relative margin below which mc() flags a decision as a near-tie (default 1e-12)."""
+    lib().orc_set_tie_margin(C.c_double(eps))

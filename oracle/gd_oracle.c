@@ -46,7 +46,10 @@
 #endif
 
 #define ORC_PI 3.14159265358979323846
-#define ORC_TIE 1e-12
+/* Relative margin below which a sampling decision counts as a near-tie
+ * (1e-12 for the FP64 path; a comparison of a lower-precision form of the
+ * rates sets a larger one). */
+static double ORC_TIE = 1e-12;
 
 /* ------------------------------------------------------------------------ */
 /* Problem description (the oracle's own struct; mirrored by ctypes).        */
@@ -1004,6 +1007,8 @@ void orc_gas_at(const orc_problem* P, double R, double Z, double* out)
 }
 
 double orc_oc07(double St1, double St2, double Vg2, double tke) { return oc07_dv2(St1, St2, St1 - St2, Vg2, tke); }
+
+void orc_set_tie_margin(double eps) { ORC_TIE = eps > 0.0 ? eps : 1e-12; }
 
 int orc_num_threads(void)
 {

@@ -32,7 +32,7 @@ class GdProblem(C.Structure):
         ("Sigma_g0", C.c_double), ("R0", C.c_double), ("p", C.c_double), ("q", C.c_double), ("h_g0", C.c_double),
         ("alpha", C.c_double), ("mu_mH", C.c_double), ("sigma_H2", C.c_double), ("s0", C.c_double),
         ("St0", C.c_double), ("r_in", C.c_double), ("r_out", C.c_double), ("drag", C.c_int32),
-        ("brownian", C.c_int32), ("turbulence", C.c_int32), ("caps", C.c_int32),
+        ("brownian", C.c_int32), ("turbulence", C.c_int32), ("caps", C.c_int32), ("rates_fp32", C.c_int32),
     ]
 
 
@@ -127,7 +127,7 @@ def make_problem(cfg: dict, n: int | None = None) -> GdProblem:
     for name in ("t0", "m0", "eps", "dt_fn_max", "rho_s", "s_min", "v_frag", "GM", "Sigma_g0", "R0", "p", "q",
                  "h_g0", "alpha", "mu_mH", "sigma_H2", "s0", "St0", "r_in", "r_out"):
         setattr(P, name, float(cfg.get(name, 0.0)))
-    for name in ("drag", "brownian", "turbulence", "caps"):
+    for name in ("drag", "brownian", "turbulence", "caps", "rates_fp32"):
         setattr(P, name, int(cfg.get(name, 0)))
     return P
 

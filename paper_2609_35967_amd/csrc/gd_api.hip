@@ -68,6 +68,7 @@ DevProblem to_dev(const gd_problem* p)
     d.brownian = p->brownian;
     d.turbulence = p->turbulence;
     d.caps = p->caps;
+    d.rates_fp32 = p->rates_fp32;
     return d;
 }
 
@@ -80,6 +81,7 @@ static int check_problem(const gd_problem* p)
     if (p->n > (int64_t(kBucket) << (3 * kMaxTreeLevels))) return fail(GD_E_UNSUPPORTED, "n must stay below 2^26");
     if (p->kernel < 0 || p->kernel > 3) return fail(GD_E_INVALID_ARG, "kernel = %d unknown", p->kernel);
     if (p->push < 0 || p->push > 2) return fail(GD_E_INVALID_ARG, "push = %d unknown", p->push);
+    if (p->rates_fp32 != 0 && p->rates_fp32 != 1) return fail(GD_E_INVALID_ARG, "rates_fp32 must be 0 or 1");
     for (int a = 0; a < 3; ++a)
         if (p->periodic[a] && !(p->L[a] > 0.0)) return fail(GD_E_INVALID_ARG, "periodic axis %d needs L > 0", a);
     if (!(p->rmax > 0.0)) return fail(GD_E_INVALID_ARG, "rmax must be > 0 (INFINITY for none)");

@@ -35,6 +35,7 @@ struct DevProblem {
     double rho_s, s_min, v_frag;
     double GM, Sigma_g0, R0, p, q, h_g0, alpha, mu_mH, sigma_H2, s0, St0, r_in, r_out;
     int32_t drag, brownian, turbulence, caps;
+    int32_t rates_fp32;
 };
 
 // Box of a node of the search tree, single precision rounded outward (lo

@@ -47,6 +47,30 @@ struct McArgs {
 constexpr int kEventCap = 1 << 24;  // safety stop per particle and interval (status-flagged)
 
 template <int KP2>
+__device__ inline double prefix_rates_f32(const McArgs& A, const QCtxF& q, const int32_t* row, int c, double mi,
+                                          float si, float Sti, double (&pre)[KP2])
+{
+    const bool phys = A.P.kernel == GD_KERNEL_PHYSICAL;
+    double li = 0.0;
+#pragma unroll
+    for (int s = 0; s < KP2; ++s) {
+        if (s < c) {
+            int j = row[s];
+            if (j < 0 || j >= A.P.n) {
+                set_status(A.ws, GD_DEV_INTERNAL);
+                j = 0;
+            }
+            const double4 sn = A.snap[j];
+            PairF o;
+            pair_eval_f32(A.P, q, mi, 1.0 / mi, si, Sti, sn.x, phys ? float(sn.y) : 0.0f, phys ? sn.z : 0.0, o);
+            li = li + double(o.lam_star);
+        }
+        pre[s] = li;
+    }
+    return li;
+}
+
+template <int KP2>
 __device__ inline double prefix_rates(const McArgs& A, const QCtx& q, const int32_t* row, int c, double mi,
                                       double si, double Sti, double (&pre)[KP2])
 {
@@ -70,7 +94,7 @@ __device__ inline double prefix_rates(const McArgs& A, const QCtx& q, const int3
     return li;
 }
 
-template <int KP2>
+template <int KP2, bool F32>
 __global__ __launch_bounds__(256) void k_mc(McArgs A)
 {
     const int64_t i = xcd_block() * int64_t(blockDim.x) + threadIdx.x;
@@ -87,6 +111,7 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
             const uint32_t pid = A.id[i];
             const int32_t* row = A.nbr + i * k;
             QCtx q{};
+            QCtxF qf{};
             bool have_ctx = false, have_pre = false;
             double si = 0.0, Sti = 0.0;
             double pre[KP2];
@@ -104,14 +129,16 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
                 t = t + dtw;
                 if (!have_ctx) {
                     query_ctx(A.P, A.x[i], A.y[i], A.z[i], A.dmax[i], q);
+                    if (F32) query_ctx_f32(A.P, q, qf);
                     have_ctx = true;
                 }
                 if (!have_pre) {
                     if (phys) {
                         si = grain_size(A.P, m);
-                        Sti = q.stfac * si;
+                        Sti = F32 ? double(qf.stfac * float(si)) : q.stfac * si;
                     }
-                    li = prefix_rates<KP2>(A, q, row, c, m, si, Sti, pre);
+                    li = F32 ? prefix_rates_f32<KP2>(A, qf, row, c, m, float(si), float(Sti), pre)
+                             : prefix_rates<KP2>(A, q, row, c, m, si, Sti, pre);
                     have_pre = true;
                 }
                 const double target = u[1] * li;
@@ -129,7 +156,17 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
                 const double mj = sn.x;
                 const double sj = phys ? sn.y : 0.0;
                 Pair o;
-                pair_eval(A.P, q, m, si, Sti, mj, sj, phys ? sn.z : 0.0, o);
+                if (F32) {
+                    PairF of;
+                    pair_eval_f32(A.P, qf, m, 1.0 / m, float(si), float(Sti), mj, float(sj), phys ? sn.z : 0.0, of);
+                    o.type = of.type;
+                    o.r0 = of.r0;
+                    o.r1 = of.r1;
+                    o.lam_star = double(of.r0) + double(of.r1);
+                    o.Ng = of.Ng;
+                } else {
+                    pair_eval(A.P, q, m, si, Sti, mj, sj, phys ? sn.z : 0.0, o);
+                }
                 int ch = 0;
                 if (o.type == kErosion) ch = (o.r0 > u[2] * o.lam_star) ? 0 : 1;
                 double mnew;
@@ -153,9 +190,10 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
                     have_pre = false;
                     if (phys) {
                         si = grain_size(A.P, m);
-                        Sti = q.stfac * si;
+                        Sti = F32 ? double(qf.stfac * float(si)) : q.stfac * si;
                     }
-                    li = prefix_rates<KP2>(A, q, row, c, m, si, Sti, pre);
+                    li = F32 ? prefix_rates_f32<KP2>(A, qf, row, c, m, float(si), float(Sti), pre)
+                             : prefix_rates<KP2>(A, q, row, c, m, si, Sti, pre);
                     have_pre = true;
                 }
             }
@@ -285,8 +323,13 @@ int launch_sample(const gd_problem* p, const gd_particles* s, const gd_neighbors
     A.ev_counter = reinterpret_cast<unsigned long long*>(&h->scratch[0]);
     const int g = int((n + 255) / 256);
     prof_mark(GD_PROF_MC, 0, st);
-    if (p->k <= 32) hipLaunchKernelGGL(k_mc<32>, dim3(g), dim3(256), 0, st, A);
-    else hipLaunchKernelGGL(k_mc<64>, dim3(g), dim3(256), 0, st, A);
+    if (p->rates_fp32) {
+        if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, true>), dim3(g), dim3(256), 0, st, A);
+        else hipLaunchKernelGGL((k_mc<64, true>), dim3(g), dim3(256), 0, st, A);
+    } else {
+        if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, false>), dim3(g), dim3(256), 0, st, A);
+        else hipLaunchKernelGGL((k_mc<64, false>), dim3(g), dim3(256), 0, st, A);
+    }
     prof_mark(GD_PROF_MC, 1, st);
     double* part = at<double>(ws, L.part);
     prof_mark(GD_PROF_AUDIT, 0, st);

@@ -249,4 +249,151 @@ __device__ inline void pair_moments(const DevProblem& P, const Pair& o, double m
     }
 }
 
+// ---------------------------------------------------------------------------
+// Single-precision form of the pair rate (optional; gd_problem.rates_fp32).
+// The query context is computed in FP64 once per particle and rounded to
+// float; the collision speed, kernel, channel rates and moments of each pair
+// are float; the particle-count weight N_j / V_i (whose factors overflow
+// float in cgs units) and the mass ratio psi = m_j (1/m_i) with its grouping
+// factor stay FP64.  Callers sum the float pair terms in FP64.
+struct QCtxF {
+    float Z, OmK, cs, stfac, Vg2, tke, kT8pi, vdrift, vset;  // vdrift = eta R Omega_K, vset = Z Omega_K
+    double invV;                                              // 1 / V_i (0 when V_i <= 0)
+    double k6;                                                // 6 / (pi rho_s)
+    double kdl;                                               // m0 / (t0 N_K) (dimensionless kernels)
+};
+
+__device__ inline void query_ctx_f32(const DevProblem& P, const QCtx& c, QCtxF& f)
+{
+    if (P.kernel != GD_KERNEL_PHYSICAL) {
+        f.invV = 1.0;
+        f.kdl = P.m0 / (P.t0 * double(P.k));
+        return;
+    }
+    f.k6 = 6.0 / (kPi * P.rho_s);
+    f.Z = float(c.Z);
+    f.OmK = float(c.OmK);
+    f.cs = float(c.cs);
+    f.stfac = float(c.stfac);
+    f.Vg2 = float(c.Vg2);
+    f.tke = float(c.tke);
+    f.kT8pi = float(c.kT8pi);
+    f.vdrift = float(c.eta * c.R * c.OmK);
+    f.vset = float(c.Z * c.OmK);
+    f.invV = c.V > 0.0 ? 1.0 / c.V : 0.0;
+}
+
+// hardware reciprocal and square root (1 ulp): the single-precision form's
+// error budget is set by its float arithmetic anyway
+__device__ inline float rcpf_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline float sqrtf_(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+__device__ inline float oc07_dv2_f32(float St1, float St2, float dSt, float Vg2, float tke)
+{
+    if (St1 < tke) {
+        const float num = St1 * St2 + tke * (St1 + St2);
+        const float den = (St1 + St2) * (St1 + tke) * (St2 + tke);
+        return Vg2 * (dSt * dSt) * num * rcpf_(den);
+    }
+    if (St1 < 1.0f) {
+        const float ya = 1.6f;
+        const float e = St2 * rcpf_(St1);
+        const float br = 2.0f * ya - (1.0f + e) + 2.0f * rcpf_(1.0f + e) * (1.0f / (1.0f + ya) + e * e * e * rcpf_(ya + e));
+        return Vg2 * br * St1;
+    }
+    return Vg2 * (rcpf_(1.0f + St1) + rcpf_(1.0f + St2));
+}
+
+struct PairF {
+    int type;
+    float r0, r1;  // channel rates
+    float lam_star;
+    double Ng;
+    double psi;
+};
+
+// Own particle: mass mi (and its reciprocal rmi), diameter si and Stokes
+// number Sti.  Neighbour: mass mj, diameter sj, grain count Nj.
+__device__ inline void pair_eval_f32(const DevProblem& P, const QCtxF& c, double mi, double rmi, float si, float Sti,
+                                     double mj, float sj, double Nj, PairF& o)
+{
+    float lam, dv = 0.0f;
+    if (P.kernel == GD_KERNEL_PHYSICAL) {
+        const float Stj = c.stfac * sj;
+        const float ds = float(c.k6 * (mi - mj)) * rcpf_(si * si + si * sj + sj * sj);
+        const float dSt = c.stfac * ds;
+        const float qi = 1.0f + Sti * Sti, qj = 1.0f + Stj * Stj;
+        const float rq = dSt * rcpf_(qi * qj);
+        const float da = (1.0f - Sti * Stj) * rq;
+        const float db = -(Sti + Stj) * rq;
+        const float dvR = 2.0f * c.vdrift * da;
+        const float dz = (Sti < 0.5f && Stj < 0.5f) ? dSt : fminf(Sti, 0.5f) - fminf(Stj, 0.5f);
+        const float dvZ = c.vset * dz;
+        const float dvP = c.vdrift * db;
+        float dvB = 0.0f, dvT2 = 0.0f;
+        if (P.brownian) {
+            dvB = sqrtf_(c.kT8pi * (float(rmi) + rcpf_(float(mj))));
+            if (dvB > c.cs) dvB = c.cs;
+        }
+        if (P.turbulence) {
+            const bool ig = Sti >= Stj;
+            dvT2 = oc07_dv2_f32(ig ? Sti : Stj, ig ? Stj : Sti, fabsf(dSt), c.Vg2, c.tke);
+        }
+        float dv2 = dvR * dvR + dvZ * dvZ;
+        dv2 = dv2 + dvP * dvP;
+        dv2 = dv2 + dvB * dvB;
+        dv2 = dv2 + dvT2;
+        dv = sqrtf_(dv2);
+        const float ssum = si + sj;
+        lam = float(Nj * c.invV) * (float(kPi / 4.0) * ssum * ssum * dv);
+    } else {
+        float Kt;
+        if (P.kernel == GD_KERNEL_CONST) Kt = 1.0f;
+        else if (P.kernel == GD_KERNEL_ADDITIVE) Kt = float((mi + mj) / P.m0);
+        else Kt = float((mi * mj) / (P.m0 * P.m0));
+        lam = float(c.kdl / mj) * Kt;
+    }
+    const double psi = mj * rmi;
+    const bool fast = (P.kernel == GD_KERNEL_PHYSICAL) && (double(dv) >= P.v_frag);
+    double Ng = 1.0;
+    if (P.grouping && psi <= 1e-6) Ng = floor(1e-4 / psi);
+    o.Ng = Ng;
+    o.psi = psi;
+    if (!fast) {
+        o.type = kStick;
+        o.r0 = Ng == 1.0 ? lam : lam * float(1.0 / Ng);
+        o.r1 = 0.0f;
+        o.lam_star = o.r0;
+    } else if (P.erosion && psi <= 0.1) {
+        o.type = kErosion;
+        o.r0 = float((1.0 - psi) / Ng) * lam;
+        o.r1 = float(psi) * lam;
+        o.lam_star = o.r0 + o.r1;
+    } else {
+        o.type = kFrag;
+        o.r0 = lam;
+        o.r1 = 0.0f;
+        o.lam_star = lam;
+    }
+}
+
+// rate * <J> and rate * <J^2> of the pair's channels; mJf, mJ2f are the
+// fragment moments of the own grain (computed once per particle)
+__device__ inline void pair_moments_f32(const PairF& o, float mJf, float mJ2f, float& a, float& b)
+{
+    if (o.type == kStick) {
+        const float J = log1pf(float(o.Ng * o.psi)) / 3.0f;
+        a = o.r0 * J;
+        b = o.r0 * (J * J);
+    } else if (o.type == kErosion) {
+        const float Jr = -log1pf(float(-o.Ng * o.psi)) / 3.0f;
+        const float Jd = float(fabs(log(o.psi)) / 3.0);
+        a = o.r0 * Jr + o.r1 * Jd;
+        b = o.r0 * (Jr * Jr) + o.r1 * (Jd * Jd);
+    } else {
+        a = o.r0 * mJf;
+        b = o.r0 * mJ2f;
+    }
+}
+
 }  // namespace gd

@@ -44,6 +44,19 @@ struct RatesArgs {
     void* ws;
 };
 
+constexpr int kGather = 4;  // neighbours whose slot and record loads are in flight together
+
+// slots row[s0 .. s0+kGather) (those below cmax) and the snapshot records of
+// the valid ones; invalid slots are left for the caller to flag
+__device__ inline void gather_neighbours(const int32_t* row, int s0, int cmax, int64_t n, const double4* snap,
+                                         int (&jj)[kGather], double4 (&rec)[kGather])
+{
+#pragma unroll
+    for (int t = 0; t < kGather; ++t) jj[t] = s0 + t < cmax ? row[s0 + t] : -1;
+#pragma unroll
+    for (int t = 0; t < kGather; ++t) rec[t] = (jj[t] >= 0 && jj[t] < n) ? snap[jj[t]] : make_double4(0.0, 0.0, 0.0, 0.0);
+}
+
 __global__ __launch_bounds__(256) void k_rates(RatesArgs A)
 {
     const int64_t i = xcd_block() * int64_t(blockDim.x) + threadIdx.x;
@@ -52,7 +65,6 @@ __global__ __launch_bounds__(256) void k_rates(RatesArgs A)
     const bool phys = A.P.kernel == GD_KERNEL_PHYSICAL;
     const int c = A.cnt[i];
     double lam = 0.0, sa = 0.0, sb = 0.0;
-    const int32_t* row = A.nbr + i * k;
     if (c > 1) {
         QCtx q;
         query_ctx(A.P, A.x[i], A.y[i], A.z[i], A.dmax[i], q);
@@ -60,13 +72,23 @@ __global__ __launch_bounds__(256) void k_rates(RatesArgs A)
         const double si = phys ? A.snap[i].y : 0.0;
         const double Sti = phys ? q.stfac * si : 0.0;
         if (!(mi > 0.0) || !isfinite(mi)) set_status(A.ws, GD_DEV_NONFINITE);
-        for (int s = 0; s < c && s < k; ++s) {
-            const int j = row[s];
+        const int cmax = c < k ? c : k;
+        // neighbours four at a time: their slots, then their records, in flight
+        // together; the pairs are then taken in slot order as before
+        for (int s0 = 0; s0 < cmax; s0 += kGather) {
+            int jj[kGather];
+            double4 rec[kGather];
+            gather_neighbours(A.nbr + i * k, s0, cmax, A.P.n, A.snap, jj, rec);
+#pragma unroll
+            for (int t = 0; t < kGather; ++t) {
+            const int s = s0 + t;
+            if (s >= cmax) break;
+            const int j = jj[t];
             if (j < 0 || j >= A.P.n) {
                 set_status(A.ws, GD_DEV_INTERNAL);
                 continue;
             }
-            const double4 sn = A.snap[j];
+            const double4 sn = rec[t];
             const double mj = sn.x;
             const double sj = phys ? sn.y : 0.0;
             const double Nj = phys ? sn.z : 0.0;
@@ -78,6 +100,67 @@ __global__ __launch_bounds__(256) void k_rates(RatesArgs A)
             pair_moments(A.P, o, mi, si, mj, pa, pb);
             sa = sa + pa;
             sb = sb + pb;
+            }
+        }
+    }
+    if (A.lam_pair)
+        for (int s = (c > 1 ? c : 0); s < k; ++s) A.lam_pair[i * k + s] = 0.0;
+    A.lam[i] = lam;
+    A.a[i] = sa;
+    A.b[i] = sb;
+}
+
+// The same pass with the single-precision pair form (gd_problem.rates_fp32):
+// float pair terms, summed in FP64 in slot order.
+__global__ __launch_bounds__(256) void k_rates_f32(RatesArgs A)
+{
+    const int64_t i = xcd_block() * int64_t(blockDim.x) + threadIdx.x;
+    if (i >= A.P.n) return;
+    const int k = A.P.k;
+    const bool phys = A.P.kernel == GD_KERNEL_PHYSICAL;
+    const int c = A.cnt[i];
+    double lam = 0.0, sa = 0.0, sb = 0.0;
+    if (c > 1) {
+        QCtx q;
+        query_ctx(A.P, A.x[i], A.y[i], A.z[i], A.dmax[i], q);
+        QCtxF qf;
+        query_ctx_f32(A.P, q, qf);
+        const double mi = A.m[i];
+        const float si = phys ? float(A.snap[i].y) : 0.0f;
+        const float Sti = phys ? qf.stfac * si : 0.0f;
+        const double rmi = 1.0 / mi;
+        float mJf = 0.0f, mJ2f = 0.0f;
+        if (phys) {
+            double mJ, mJ2;
+            frag_moments(A.snap[i].y, A.P.s_min, mJ, mJ2);
+            mJf = float(mJ);
+            mJ2f = float(mJ2);
+        }
+        if (!(mi > 0.0) || !isfinite(mi)) set_status(A.ws, GD_DEV_NONFINITE);
+        const int cmax = c < k ? c : k;
+        for (int s0 = 0; s0 < cmax; s0 += kGather) {
+            int jj[kGather];
+            double4 rec[kGather];
+            gather_neighbours(A.nbr + i * k, s0, cmax, A.P.n, A.snap, jj, rec);
+#pragma unroll
+            for (int t = 0; t < kGather; ++t) {
+            const int s = s0 + t;
+            if (s >= cmax) break;
+            const int j = jj[t];
+            if (j < 0 || j >= A.P.n) {
+                set_status(A.ws, GD_DEV_INTERNAL);
+                continue;
+            }
+            const double4 sn = rec[t];
+            PairF o;
+            pair_eval_f32(A.P, qf, mi, rmi, si, Sti, sn.x, phys ? float(sn.y) : 0.0f, phys ? sn.z : 0.0, o);
+            lam = lam + double(o.lam_star);
+            if (A.lam_pair) A.lam_pair[i * k + s] = double(o.lam_star);
+            float pa, pb;
+            pair_moments_f32(o, mJf, mJ2f, pa, pb);
+            sa = sa + double(pa);
+            sb = sb + double(pb);
+            }
         }
     }
     if (A.lam_pair)
@@ -347,7 +430,8 @@ int launch_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors*
     A.a = ab ? ab : at<double>(ws, L.a);
     A.b = ab ? ab + n : at<double>(ws, L.b);
     A.ws = ws;
-    hipLaunchKernelGGL(k_rates, dim3(g), dim3(256), 0, st, A);
+    if (p->rates_fp32) hipLaunchKernelGGL(k_rates_f32, dim3(g), dim3(256), 0, st, A);
+    else hipLaunchKernelGGL(k_rates, dim3(g), dim3(256), 0, st, A);
     double* part = at<double>(ws, L.part);
     launch_bin_reduce(0, m, s->M, A.a, A.b, n, part, ws, st);
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanGroups * kNBin), 0, st, P, part, kRedBlocks, iv, at<WsHeader>(ws, L.hdr), ws);
