@@ -82,6 +82,32 @@ def measured_traffic(kernel):
     return fetch + write
 
 
+def measured_valu(kernel, launch_ms):
+    """VALU issue utilisation of `kernel` from the committed counter summary:
+    SQ_INSTS_VALU per dispatch x 4 cycles per wave64 instruction over the
+    SIMD-cycles of a launch (1024 SIMDs at 2.4 GHz); None if there is no
+    summary or the kernel's source has changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                a, b = line.split("=", 1)
+                kv[a.strip()] = b.strip()
+    try:
+        if kv.get("source_sha256_16") != source_digest(kernel):
+            return None
+        insts = float(kv["valu_insts_per_dispatch"])
+    except (KeyError, ValueError):
+        return None
+    lane_ops = insts * 64 / (launch_ms * 1e-3) / 1e12
+    peak = 1024 * 16 * 2.4e9 / 1e12  # lane-operations per second, one per lane per cycle
+    return dict(issue_util=round(insts * 4 / (1024 * 2.4e9 * launch_ms * 1e-3), 3),
+                achieved_Tlane_ops=round(lane_ops, 2), peak_Tlane_ops=round(peak, 1))
+
+
 def copy_calibration(reps):
     """A plain device copy of COPY_BYTES, `reps` times (run under rocprofv3 --pmc
     to read what FETCH_SIZE / WRITE_SIZE report for a known byte count)."""
@@ -243,6 +269,9 @@ def main():
                     traffic=None if traffic is None else round(traffic / (dom_ms * 1e-3) / 1e9, 2), kernel=dom,
                     algo_bytes_per_particle=ALGO_BYTES[dom], launch_ms=round(dom_ms, 4),
                     traffic_bytes_per_launch=None if traffic is None else round(traffic))
+    valu = measured_valu(dom, dom_ms)
+    if valu is not None:
+        roofline["valu"] = valu
     path_bytes = sum(ALGO_BYTES.values())
     out = dict(
         metric="particle-intervals/s (kNN+rates+MC) at 1M; batched vs plain; p50/p99 latency",
