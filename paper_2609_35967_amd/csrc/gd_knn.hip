@@ -47,7 +47,7 @@ constexpr int kNB = 32;   // bins of the per-lane distance histograms
 constexpr int kC1 = 16;   // largest boundary bin ranked in registers
 constexpr int kDMax = 3;  // levels of the nested bin chain
 constexpr int kRescales = 4;  // restarts of pass A on a finer distance scale
-constexpr double kHintSlack = 1.15;  // first radius: previous neighbour distance times this
+constexpr double kHintSlack = 1.08;  // first radius: previous neighbour distance times this
 constexpr int kQBlock = 128;
 
 // ---------------------------------------------------------------------------
