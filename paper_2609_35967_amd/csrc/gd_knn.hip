@@ -180,7 +180,8 @@ __device__ inline float gapf(float x, float lo, float hi)
 }
 
 // Lower bound of the squared distance from q to a (widened) box, minimum
-// image on periodic axes; its own float rounding is covered by r2f below.
+// image on periodic axes; its own float rounding (one product, two fused
+// multiply-adds, each term rounded at most three times) is covered by r2f.
 template <bool PER>
 __device__ inline float box2f(const KnnArgs& A, const QF& f, const FBox& b)
 {
@@ -191,12 +192,11 @@ __device__ inline float box2f(const KnnArgs& A, const QF& f, const FBox& b)
         if (PER && A.per[a]) v = fminf(v, fminf(gapf(f.p[a], b.lo[a], b.hi[a]), gapf(f.m[a], b.lo[a], b.hi[a])));
         g[a] = v;
     }
-    const float s = g[0] * g[0] + g[1] * g[1];
-    return s + g[2] * g[2];
+    return fmaf(g[2], g[2], fmaf(g[1], g[1], g[0] * g[0]));
 }
 
 // Single-precision threshold of the box tests for radius R2: at least
-// R2 (1 + 2^-19), above the three rounded float operations of box2f.
+// R2 (1 + 2^-19), above the three roundings of box2f's sum of squares.
 __device__ inline float r2f(double R2)
 {
     return float(R2 * (1.0 + 0x1p-19)) * (1.0f + 0x1p-22f);
@@ -282,22 +282,22 @@ __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], 
         // a bucket: its particles within R2 go to the visitor together
         ++steps;
         const int j0 = child * kBucket;
+        // the whole bucket (the position buffer is padded to a multiple of 8
+        // slots); slots past the active ones get +inf (or NaN), never within R2
         double px[kBucket], py[kBucket], pz[kBucket];
 #pragma unroll
         for (int t = 0; t < kBucket; ++t) {
-            if (j0 + t < na) {
-                const double* pj = reinterpret_cast<const double*>(A.pos + j0 + t);
-                const double2 xy = *reinterpret_cast<const double2*>(pj);
-                px[t] = xy.x;
-                py[t] = xy.y;
-                pz[t] = pj[2];
-            }
+            const double* pj = reinterpret_cast<const double*>(A.pos + j0 + t);
+            const double2 xy = *reinterpret_cast<const double2*>(pj);
+            px[t] = xy.x;
+            py[t] = xy.y;
+            pz[t] = pj[2];
         }
         double d2[kBucket];
         uint32_t vm = 0;
 #pragma unroll
         for (int t = 0; t < kBucket; ++t) {
-            d2[t] = j0 + t < na ? sep2<PER>(A, qp, px[t], py[t], pz[t]) : INFINITY;
+            d2[t] = sep2<PER>(A, qp, px[t], py[t], pz[t]) + (j0 + t < na ? 0.0 : INFINITY);
             vm |= (d2[t] <= R2 ? 1u : 0u) << t;
         }
         if (vm) f(j0, d2, vm);
@@ -589,6 +589,31 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
             }
             s_list[(len++) * kQBlock + tid] = (uint32_t(b) << 26) | uint32_t(j);
         };
+        // take for the slots of one bucket in mask tm, without a branch per
+        // slot: the list keeps room for a whole bucket (a list that cannot,
+        // after dropping the entries above the cut, is given up), and the
+        // counter add of a slot not taken adds 0
+        auto take_bucket = [&](int j0, const int (&b)[kBucket], uint32_t tm) {
+            if (!ovf && len > cap - kBucket) {
+                int kept = 0;
+                for (int e = 0; e < len; ++e) {
+                    const uint32_t w = s_list[e * kQBlock + tid];
+                    if (int(w >> 26) <= bcut) s_list[(kept++) * kQBlock + tid] = w;
+                }
+                len = kept;
+                ovf = len > cap - kBucket;
+            }
+#pragma unroll
+            for (int t = 0; t < kBucket; ++t) {
+                const bool tk = (tm >> t) & 1u;
+                atomicAdd(s_lds + (b[t] >> 1) * kQBlock + tid, tk ? 1u << (16 * (b[t] & 1)) : 0u);
+                cle += tk ? 1 : 0;
+                hcut += (tk && b[t] == bcut) ? 1 : 0;
+                s_list[(ovf ? 0 : len) * kQBlock + tid] = (uint32_t(b[t]) << 26) | uint32_t(j0 + t);
+                len += (tk && !ovf) ? 1 : 0;
+            }
+            candA += __builtin_popcount(tm);
+        };
         for (int j = wlo; j < whi && !deep; ++j) {
             if (j == q) continue;
             const double d2 = sep2_slot<PER>(A, qp, j);
@@ -601,12 +626,19 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
         if (!deep)
             visA += walk<PER>(A, na, q, qp, qf, R2, [&](int j0, const double (&d2)[kBucket], uint32_t vm) {
                 if (sat || deep) return;
+                int b[kBucket];
+                uint32_t tm = 0;
 #pragma unroll
                 for (int t = 0; t < kBucket; ++t) {
                     const int j = j0 + t;
-                    const int b = log_bin(d2[t] * sA);
-                    if (((vm >> t) & 1u) && j != q && (j < wlo || j >= whi) && b <= bcut) take(j, b);
+                    b[t] = log_bin(d2[t] * sA);
+                    // bitwise, not short-circuit: no branch per slot
+                    const uint32_t ok = ((vm >> t) & 1u) & uint32_t(j != q) & (uint32_t(j < wlo) | uint32_t(j >= whi)) &
+                                        uint32_t(b[t] <= bcut);
+                    tm |= ok << t;
                 }
+                if (!tm) return;
+                take_bucket(j0, b, tm);
                 if (candA > kCandMax) {
                     sat = true;
                     return;
