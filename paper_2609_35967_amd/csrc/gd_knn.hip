@@ -222,11 +222,15 @@ __device__ inline uint32_t child_mask(const KnnArgs& A, int level, int idx, cons
 // visitor filters), a bucket at a time: f(j0, d2[kBucket], mask) gets the
 // bucket's first slot, the d^2 of its slots and the mask of those within R2.
 // A visitor that sets R2 negative ends the walk.
-// Nearest region first: the level-1 ancestor of q's bucket,
-// then the other children of each further ancestor, depth first.  The
-// visitor may lower R2; pruning uses the current value.  One iteration does
-// at most one node expansion and one bucket scan, so the two paths of a
-// diverged wavefront share iterations.  Returns the walk steps.
+// Nearest region first: the level-1 ancestor of q's bucket, then the other
+// children of each further ancestor, depth first.  The visitor may lower R2;
+// pruning uses the current value.  Two units advance in every iteration:
+// the traversal expands one node (a level-1 node yields the mask of its
+// buckets to visit, queued in one of two slots), and the scan visits one
+// bucket of the oldest queued mask.  A lane thus keeps both busy where the
+// walk alternates between them, and the diverged lanes of a wavefront,
+// whose iterations run both paths anyway, finish in fewer iterations.
+// Returns the iterations.
 template <bool PER, class F>
 __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], const QF& qf, double& R2, F&& f)
 {
@@ -234,54 +238,13 @@ __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], 
     int climb = 1, level = 1;
     int idx = (q / kBucket) >> 3;
     uint32_t excl = 0;
-    uint64_t masks = 0;
-    bool pend = true;
-    float R2f = r2f(R2);
-    int steps = 0;
-    for (;;) {
-        if (!(R2 >= 0.0)) break;  // the visitor ended the walk
-        if (pend) {
-            masks |= uint64_t(child_mask<PER>(A, level, idx, qf, R2f) & ~excl) << (8 * (level - 1));
-            excl = 0;
-            pend = false;
-            ++steps;
-        }
-        // next child to visit; climb when the ancestor's subtree is exhausted
-        int c = -1;
-        for (;;) {
-            const int sh = 8 * (level - 1);
-            const uint32_t m = uint32_t(masks >> sh) & 0xFFu;
-            if (m != 0) {
-                c = __ffs(m) - 1;
-                masks &= ~(uint64_t(1) << (sh + c));
-                break;
-            }
-            if (level < climb) {
-                ++level;
-                idx >>= 3;
-                continue;
-            }
-            if (climb < top) {
-                excl = 1u << (idx & 7);
-                ++climb;
-                level = climb;
-                idx >>= 3;
-                pend = true;
-            }
-            break;
-        }
-        if (pend) continue;
-        if (c < 0) break;
-        const int child = idx * kFan + c;
-        if (level > 1) {
-            --level;
-            idx = child;
-            pend = true;
-            continue;
-        }
-        // a bucket: its particles within R2 go to the visitor together
-        ++steps;
-        const int j0 = child * kBucket;
+    uint64_t masks = 0;  // children still to expand, 8 bits per level >= 2
+    bool pend = true;    // node (level, idx) is to be expanded
+    uint32_t bm0 = 0, bm1 = 0;  // queued bucket masks of level-1 nodes base0, base1
+    int base0 = 0, base1 = 0;
+    // a bucket: its particles within R2 go to the visitor together
+    auto scan_bucket = [&](int bucket) {
+        const int j0 = bucket * kBucket;
         // the whole bucket (the position buffer is padded to a multiple of 8
         // slots); slots past the active ones get +inf (or NaN), never within R2
         double px[kBucket], py[kBucket], pz[kBucket];
@@ -301,7 +264,71 @@ __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], 
             vm |= (d2[t] <= R2 ? 1u : 0u) << t;
         }
         if (vm) f(j0, d2, vm);
-        R2f = r2f(R2);
+    };
+    float R2f = r2f(R2);
+    int steps = 0;
+    for (;;) {
+        if (!(R2 >= 0.0)) break;  // the visitor ended the walk
+        ++steps;
+        if (pend && (level > 1 || bm1 == 0)) {
+            const uint32_t m = child_mask<PER>(A, level, idx, qf, R2f) & ~excl;
+            excl = 0;
+            pend = false;
+            if (level > 1) {
+                masks |= uint64_t(m) << (8 * (level - 1));
+            } else if (m != 0) {
+                if (bm0 == 0) {
+                    bm0 = m;
+                    base0 = idx;
+                } else {
+                    bm1 = m;
+                    base1 = idx;
+                }
+            }
+            // next node to expand: a child still to visit, or the next
+            // ancestor's other children once a subtree is exhausted
+            for (;;) {
+                if (level > 1) {
+                    const int sh = 8 * (level - 1);
+                    const uint32_t mm = uint32_t(masks >> sh) & 0xFFu;
+                    if (mm != 0) {
+                        const int c = __ffs(mm) - 1;
+                        masks &= ~(uint64_t(1) << (sh + c));
+                        --level;
+                        idx = idx * kFan + c;
+                        pend = true;
+                        break;
+                    }
+                }
+                if (level < climb) {
+                    ++level;
+                    idx >>= 3;
+                    continue;
+                }
+                if (climb < top) {
+                    excl = 1u << (idx & 7);
+                    ++climb;
+                    level = climb;
+                    idx >>= 3;
+                    pend = true;
+                }
+                break;
+            }
+        }
+        // (no early continue: an iteration that only expands must not become
+        // an inner loop that the scanning lanes of the wavefront wait out)
+        if (bm0 == 0) {
+            if (!pend) break;
+        } else {
+            scan_bucket(base0 * kFan + __ffs(bm0) - 1);
+            bm0 &= bm0 - 1;
+            if (bm0 == 0) {
+                bm0 = bm1;
+                base0 = base1;
+                bm1 = 0;
+            }
+            R2f = r2f(R2);
+        }
     }
     return steps;
 }
