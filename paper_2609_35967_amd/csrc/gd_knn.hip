@@ -49,6 +49,8 @@ constexpr int kDMax = 3;  // levels of the nested bin chain
 constexpr int kRescales = 4;  // restarts of pass A on a finer distance scale
 constexpr double kHintSlack = 1.08;  // first radius: previous neighbour distance times this
 constexpr int kQBlock = 128;
+constexpr int kQueue = 4;  // level-1 bucket masks a walk keeps queued
+static_assert(kQueue >= 1 && kQueue <= 4, "the queue keeps its masks in the bytes of one word");
 
 // ---------------------------------------------------------------------------
 // Tree build
@@ -226,7 +228,7 @@ __device__ inline uint32_t child_mask(const KnnArgs& A, int level, int idx, cons
 // children of each further ancestor, depth first.  The visitor may lower R2;
 // pruning uses the current value.  Two units advance in every iteration:
 // the traversal expands one node (a level-1 node yields the mask of its
-// buckets to visit, queued in one of two slots), and the scan visits one
+// buckets to visit, queued in one of kQueue slots), and the scan visits one
 // bucket of the oldest queued mask.  A lane thus keeps both busy where the
 // walk alternates between them, and the diverged lanes of a wavefront,
 // whose iterations run both paths anyway, finish in fewer iterations.
@@ -240,8 +242,10 @@ __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], 
     uint32_t excl = 0;
     uint64_t masks = 0;  // children still to expand, 8 bits per level >= 2
     bool pend = true;    // node (level, idx) is to be expanded
-    uint32_t bm0 = 0, bm1 = 0;  // queued bucket masks of level-1 nodes base0, base1
-    int base0 = 0, base1 = 0;
+    // queue of the bucket masks of expanded level-1 nodes: slot s is byte s
+    // of qm, for node qb[s]; nq slots in use
+    uint32_t qm = 0;
+    int qb0 = 0, qb1 = 0, qb2 = 0, qb3 = 0, nq = 0;
     // a bucket: its particles within R2 go to the visitor together
     auto scan_bucket = [&](int bucket) {
         const int j0 = bucket * kBucket;
@@ -270,20 +274,19 @@ __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], 
     for (;;) {
         if (!(R2 >= 0.0)) break;  // the visitor ended the walk
         ++steps;
-        if (pend && (level > 1 || bm1 == 0)) {
+        if (pend && (level > 1 || nq < kQueue)) {
             const uint32_t m = child_mask<PER>(A, level, idx, qf, R2f) & ~excl;
             excl = 0;
             pend = false;
             if (level > 1) {
                 masks |= uint64_t(m) << (8 * (level - 1));
             } else if (m != 0) {
-                if (bm0 == 0) {
-                    bm0 = m;
-                    base0 = idx;
-                } else {
-                    bm1 = m;
-                    base1 = idx;
-                }
+                qm |= m << (8 * nq);
+                qb0 = nq == 0 ? idx : qb0;
+                qb1 = nq == 1 ? idx : qb1;
+                qb2 = nq == 2 ? idx : qb2;
+                qb3 = nq == 3 ? idx : qb3;
+                ++nq;
             }
             // next node to expand: a child still to visit, or the next
             // ancestor's other children once a subtree is exhausted
@@ -317,15 +320,17 @@ __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], 
         }
         // (no early continue: an iteration that only expands must not become
         // an inner loop that the scanning lanes of the wavefront wait out)
-        if (bm0 == 0) {
+        if (nq == 0) {
             if (!pend) break;
         } else {
-            scan_bucket(base0 * kFan + __ffs(bm0) - 1);
-            bm0 &= bm0 - 1;
-            if (bm0 == 0) {
-                bm0 = bm1;
-                base0 = base1;
-                bm1 = 0;
+            scan_bucket(qb0 * kFan + __ffs(qm) - 1);
+            qm &= qm - 1;
+            if ((qm & 0xFFu) == 0) {
+                qm >>= 8;
+                qb0 = qb1;
+                qb1 = qb2;
+                qb2 = qb3;
+                --nq;
             }
             R2f = r2f(R2);
         }
