@@ -70,10 +70,13 @@ struct Layout {
     // implicit search tree: level l holds cnt[l] boxes (padded to a multiple
     // of kFan) starting at box index off[l]; level 0 = buckets of kBucket
     // slots, node i of level l >= 1 = children kFan*i .. kFan*i+7 of level l-1;
-    // the root's children are the (<= kFan) boxes of the top level.
+    // the root's children are the (<= kFan) boxes of the top level.  Levels
+    // >= 1 sit at a common stride (the padded size of level 1), so that
+    // off[l] = off1 + (l - 1) * stride1 is computed, not looked up.
     int32_t levels;
     int64_t lvl_cnt[kMaxTreeLevels];
     int64_t lvl_off[kMaxTreeLevels];
+    int64_t off1, stride1;
 };
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -96,19 +99,21 @@ __host__ inline Layout make_layout(int64_t n, int32_t k)
     L.red = take(sizeof(double) * 8 * kRedBlocks);
     L.pos4 = take(32 * nn);
     {
-        int64_t cnt = (int64_t(nn) + kBucket - 1) / kBucket, off = 0;
+        int64_t cnt = (int64_t(nn) + kBucket - 1) / kBucket;
+        const int64_t pad0 = (cnt + kFan - 1) / kFan * kFan;
+        const int64_t cnt1 = (cnt + kFan - 1) / kFan;
+        L.off1 = pad0;
+        L.stride1 = (cnt1 + kFan - 1) / kFan * kFan;  // the largest level >= 1
         int l = 0;
         for (;;) {
-            const int64_t padded = (cnt + kFan - 1) / kFan * kFan;
             L.lvl_cnt[l] = cnt;
-            L.lvl_off[l] = off;
-            off += padded;
+            L.lvl_off[l] = l == 0 ? 0 : L.off1 + (l - 1) * L.stride1;
             ++l;
             if (cnt <= kFan || l == kMaxTreeLevels) break;
             cnt = (cnt + kFan - 1) / kFan;
         }
         L.levels = l;
-        L.boxes = take(sizeof(FBox) * size_t(off));
+        L.boxes = take(sizeof(FBox) * size_t(l == 1 ? pad0 : L.off1 + (l - 1) * L.stride1));
     }
     L.snap = take(32 * nn);
     L.a = take(8 * nn);

@@ -58,7 +58,14 @@ struct TreeLevels {
     int32_t levels;
     int64_t off[kMaxTreeLevels];
     int64_t cap[kMaxTreeLevels];  // padded capacity of each level
+    int32_t off1, stride1;        // off[l] = off1 + (l - 1) stride1 for l >= 1
 };
+
+// first box of level l (arithmetic, no table lookup on the walk's path)
+__device__ inline int32_t level_off(const TreeLevels& T, int l)
+{
+    return l == 0 ? 0 : T.off1 + (l - 1) * T.stride1;
+}
 
 struct Periodicity {
     int32_t per[3];
@@ -204,16 +211,12 @@ __device__ inline float r2f(double R2)
     return float(R2 * (1.0 + 0x1p-19)) * (1.0f + 0x1p-22f);
 }
 
-// mask of the children of node `idx` at `level` (>= 1) whose box may hold a
-// point within the radius; empty boxes (the padding of a level, lo > hi) are
-// never entered, so a walk only reads children of stored nodes
+// mask of the children of a node (boxes b[0..7], already loaded) whose box
+// may hold a point within the radius; empty boxes (the padding of a level,
+// lo > hi) are never entered, so a walk only reads children of stored nodes
 template <bool PER>
-__device__ inline uint32_t child_mask(const KnnArgs& A, int level, int idx, const QF& f, float R2f)
+__device__ inline uint32_t child_mask(const KnnArgs& A, const FBox (&b)[kFan], const QF& f, float R2f)
 {
-    const FBox* ch = A.boxes + A.T.off[level - 1] + int64_t(idx) * kFan;
-    FBox b[kFan];
-#pragma unroll
-    for (int c = 0; c < kFan; ++c) b[c] = ch[c];
     uint32_t m = 0;
 #pragma unroll
     for (int c = 0; c < kFan; ++c) m |= (box2f<PER>(A, f, b[c]) <= R2f && b[c].lo[0] <= b[c].hi[0] ? 1u : 0u) << c;
@@ -229,16 +232,19 @@ __device__ inline uint32_t child_mask(const KnnArgs& A, int level, int idx, cons
 // pruning uses the current value.  Two units advance in every iteration:
 // the traversal expands one node (a level-1 node yields the mask of its
 // buckets to visit, queued in one of kQueue slots), and the scan visits one
-// bucket of the oldest queued mask.  A lane thus keeps both busy where the
-// walk alternates between them, and the diverged lanes of a wavefront,
-// whose iterations run both paths anyway, finish in fewer iterations.
-// Returns the iterations.
+// bucket of the oldest queued mask.  Both read their operands at the top of
+// the iteration (one wait for the 8 child boxes and the 4 positions), and
+// both run in every lane: a lane with no node to expand re-reads a stored
+// node (the walk's current one) and drops the mask, a lane with no bucket
+// queued reads its own bucket and visits nothing.  The lanes of a
+// wavefront, whose iterations run both paths anyway, so share iterations
+// without branching around them.  Returns the iterations.
 template <bool PER, class F>
 __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], const QF& qf, double& R2, F&& f)
 {
     const int top = A.T.levels;  // the root sits one level above the stored ones
     int climb = 1, level = 1;
-    int idx = (q / kBucket) >> 3;
+    int idx = (q / kBucket) >> 3;  // (level, idx) is a stored node (or the root) in every state
     uint32_t excl = 0;
     uint64_t masks = 0;  // children still to expand, 8 bits per level >= 2
     bool pend = true;    // node (level, idx) is to be expanded
@@ -246,9 +252,19 @@ __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], 
     // of qm, for node qb[s]; nq slots in use
     uint32_t qm = 0;
     int qb0 = 0, qb1 = 0, qb2 = 0, qb3 = 0, nq = 0;
-    // a bucket: its particles within R2 go to the visitor together
-    auto scan_bucket = [&](int bucket) {
-        const int j0 = bucket * kBucket;
+    float R2f = r2f(R2);
+    int steps = 0;
+    for (;;) {
+        if (!(R2 >= 0.0)) break;  // the visitor ended the walk
+        ++steps;
+        const bool ex = pend && (level > 1 || nq < kQueue);
+        const bool sc = nq > 0;
+        // operands of both units
+        const FBox* ch = A.boxes + (level_off(A.T, level - 1) + idx * kFan);
+        FBox bx[kFan];
+#pragma unroll
+        for (int c = 0; c < kFan; ++c) bx[c] = ch[c];
+        const int j0 = (sc ? qb0 * kFan + __ffs(qm) - 1 : q / kBucket) * kBucket;
         // the whole bucket (the position buffer is padded to a multiple of 8
         // slots); slots past the active ones get +inf (or NaN), never within R2
         double px[kBucket], py[kBucket], pz[kBucket];
@@ -260,22 +276,9 @@ __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], 
             py[t] = xy.y;
             pz[t] = pj[2];
         }
-        double d2[kBucket];
-        uint32_t vm = 0;
-#pragma unroll
-        for (int t = 0; t < kBucket; ++t) {
-            d2[t] = sep2<PER>(A, qp, px[t], py[t], pz[t]) + (j0 + t < na ? 0.0 : INFINITY);
-            vm |= (d2[t] <= R2 ? 1u : 0u) << t;
-        }
-        if (vm) f(j0, d2, vm);
-    };
-    float R2f = r2f(R2);
-    int steps = 0;
-    for (;;) {
-        if (!(R2 >= 0.0)) break;  // the visitor ended the walk
-        ++steps;
-        if (pend && (level > 1 || nq < kQueue)) {
-            const uint32_t m = child_mask<PER>(A, level, idx, qf, R2f) & ~excl;
+        // traversal unit
+        const uint32_t m = child_mask<PER>(A, bx, qf, R2f) & ~excl;
+        if (ex) {
             excl = 0;
             pend = false;
             if (level > 1) {
@@ -318,22 +321,26 @@ __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], 
                 break;
             }
         }
-        // (no early continue: an iteration that only expands must not become
-        // an inner loop that the scanning lanes of the wavefront wait out)
-        if (nq == 0) {
-            if (!pend) break;
-        } else {
-            scan_bucket(qb0 * kFan + __ffs(qm) - 1);
-            qm &= qm - 1;
-            if ((qm & 0xFFu) == 0) {
-                qm >>= 8;
-                qb0 = qb1;
-                qb1 = qb2;
-                qb2 = qb3;
-                --nq;
-            }
-            R2f = r2f(R2);
+        // scan unit: its particles within R2 go to the visitor together
+        double d2[kBucket];
+        uint32_t vm = 0;
+#pragma unroll
+        for (int t = 0; t < kBucket; ++t) {
+            d2[t] = sep2<PER>(A, qp, px[t], py[t], pz[t]) + (j0 + t < na ? 0.0 : INFINITY);
+            vm |= (d2[t] <= R2 ? 1u : 0u) << t;
         }
+        vm = sc ? vm : 0u;
+        // the scanned bucket leaves the queue (a slot whose mask empties, too)
+        const uint32_t qn = qm & (qm - 1);
+        const bool shift = sc && (qn & 0xFFu) == 0;
+        qm = !sc ? qm : (shift ? qn >> 8 : qn);
+        qb0 = shift ? qb1 : qb0;
+        qb1 = shift ? qb2 : qb1;
+        qb2 = shift ? qb3 : qb2;
+        nq -= shift ? 1 : 0;
+        if (vm) f(j0, d2, vm);
+        R2f = r2f(R2);
+        if (!pend && nq == 0) break;
     }
     return steps;
 }
@@ -943,6 +950,8 @@ int launch_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layo
         T.off[l] = L.lvl_off[l];
         T.cap[l] = (L.lvl_cnt[l] + kFan - 1) / kFan * kFan;
     }
+    T.off1 = int32_t(L.off1);
+    T.stride1 = int32_t(L.stride1);
     Periodicity P{};
     bool per = false;
     for (int a = 0; a < 3; ++a) {
