@@ -212,15 +212,27 @@ __device__ inline float r2f(double R2)
 }
 
 // mask of the children of a node (boxes b[0..7], already loaded) whose box
-// may hold a point within the radius; empty boxes (the padding of a level,
-// lo > hi) are never entered, so a walk only reads children of stored nodes
+// may hold a point within the radius
 template <bool PER>
 __device__ inline uint32_t child_mask(const KnnArgs& A, const FBox (&b)[kFan], const QF& f, float R2f)
 {
     uint32_t m = 0;
 #pragma unroll
-    for (int c = 0; c < kFan; ++c) m |= (box2f<PER>(A, f, b[c]) <= R2f && b[c].lo[0] <= b[c].hi[0] ? 1u : 0u) << c;
+    for (int c = 0; c < kFan; ++c) m |= (box2f<PER>(A, f, b[c]) <= R2f ? 1u : 0u) << c;
     return m;
+}
+
+// mask of the children of node `idx` at `level` (>= 1) that hold active
+// slots: child c covers the 4 8^(level-1) slots from (8 idx + c) 4 8^(level-1)
+// on, and the active slots are [0, na).  Children without any (the padding
+// of a level among them) are never entered, so a walk only reads children
+// of stored nodes.
+__device__ inline uint32_t live_children(int na, int level, int idx)
+{
+    const int sh = 2 + 3 * (level - 1);  // log2 of the slots per child
+    const int64_t left = int64_t(na) - (int64_t(idx) << (sh + 3));
+    const int64_t nv = (left + (int64_t(1) << sh) - 1) >> sh;
+    return nv >= kFan ? 0xFFu : (nv <= 0 ? 0u : (1u << int(nv)) - 1u);
 }
 
 // Visit every active slot j with d^2(q, j) <= R2 (j == q included; the
@@ -277,7 +289,7 @@ __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], 
             pz[t] = pj[2];
         }
         // traversal unit
-        const uint32_t m = child_mask<PER>(A, bx, qf, R2f) & ~excl;
+        const uint32_t m = child_mask<PER>(A, bx, qf, R2f) & live_children(na, level, idx) & ~excl;
         if (ex) {
             excl = 0;
             pend = false;
@@ -291,34 +303,29 @@ __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], 
                 qb3 = nq == 3 ? idx : qb3;
                 ++nq;
             }
-            // next node to expand: a child still to visit, or the next
-            // ancestor's other children once a subtree is exhausted
-            for (;;) {
-                if (level > 1) {
-                    const int sh = 8 * (level - 1);
-                    const uint32_t mm = uint32_t(masks >> sh) & 0xFFu;
-                    if (mm != 0) {
-                        const int c = __ffs(mm) - 1;
-                        masks &= ~(uint64_t(1) << (sh + c));
-                        --level;
-                        idx = idx * kFan + c;
-                        pend = true;
-                        break;
-                    }
-                }
-                if (level < climb) {
-                    ++level;
-                    idx >>= 3;
-                    continue;
-                }
-                if (climb < top) {
-                    excl = 1u << (idx & 7);
-                    ++climb;
-                    level = climb;
-                    idx >>= 3;
-                    pend = true;
-                }
-                break;
+            // next node to expand: the first child still to visit at the
+            // lowest level >= max(level, 2) (masks are empty above climb),
+            // else the other children of the next ancestor
+            const int lo = level > 1 ? level : 2;
+            const uint64_t up = masks >> (8 * (lo - 1));
+            if (up != 0) {
+                const int bit = int(__builtin_ctzll(up));
+                const int lv = lo + (bit >> 3);  // level of the node whose child is taken
+                const int c = bit & 7;
+                masks &= ~(uint64_t(1) << (8 * (lv - 1) + c));
+                idx = ((idx >> (3 * (lv - level))) << 3) + c;
+                level = lv - 1;
+                pend = true;
+            } else if (climb < top) {
+                const int ia = idx >> (3 * (climb - level));  // the ancestor at level climb
+                excl = 1u << (ia & 7);
+                ++climb;
+                level = climb;
+                idx = ia >> 3;
+                pend = true;
+            } else {
+                idx >>= 3 * (climb - level);  // exhausted: rest on the root
+                level = climb;
             }
         }
         // scan unit: its particles within R2 go to the visitor together

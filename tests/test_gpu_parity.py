@@ -131,6 +131,20 @@ def test_build_neighbors_box(case):
     assert int(eng.n_active.item()) == int((st["M"] > 0).sum())
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 31, 32, 33, 129, 257, 2049])
+def test_build_neighbors_sizes(n):
+    # one stored level (n <= 32), two (n <= 256), three, and ragged tails;
+    # n below k keeps every particle
+    params = workloads.const_box_params(4096)
+    st = workloads.const_box(20 + n, n)
+    _say("knn sizes", n)
+    eng = _engine(params, st)
+    eng.build_neighbors()
+    torch.cuda.synchronize()
+    got = _check_permutation(eng, st)
+    _knn_compare(eng, params, got)
+
+
 @pytest.mark.parametrize("hint", ["previous", 0.0, 1e-300, 1e300, 1e17, float("nan"), -1.0, "mixed"])
 def test_build_neighbors_search_hint(hint):
     # the previous distances are read back as a search hint; the result must
