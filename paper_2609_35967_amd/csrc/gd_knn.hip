@@ -278,7 +278,7 @@ __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], 
         for (int c = 0; c < kFan; ++c) bx[c] = ch[c];
         const int j0 = (sc ? qb0 * kFan + __ffs(qm) - 1 : q / kBucket) * kBucket;
         // the whole bucket (the position buffer is padded to a multiple of 8
-        // slots); slots past the active ones get +inf (or NaN), never within R2
+        // slots); slots past the active ones are masked out below
         double px[kBucket], py[kBucket], pz[kBucket];
 #pragma unroll
         for (int t = 0; t < kBucket; ++t) {
@@ -333,10 +333,12 @@ __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], 
         uint32_t vm = 0;
 #pragma unroll
         for (int t = 0; t < kBucket; ++t) {
-            d2[t] = sep2<PER>(A, qp, px[t], py[t], pz[t]) + (j0 + t < na ? 0.0 : INFINITY);
+            d2[t] = sep2<PER>(A, qp, px[t], py[t], pz[t]);
             vm |= (d2[t] <= R2 ? 1u : 0u) << t;
         }
-        vm = sc ? vm : 0u;
+        // only the bucket's active slots, and only a bucket from the queue
+        const int live = na - j0;
+        vm &= !sc ? 0u : (live >= kBucket ? 0xFu : (1u << (live > 0 ? live : 0)) - 1u);
         // the scanned bucket leaves the queue (a slot whose mask empties, too)
         const uint32_t qn = qm & (qm - 1);
         const bool shift = sc && (qn & 0xFFu) == 0;
@@ -361,8 +363,10 @@ constexpr int64_t kLogBase = int64_t(1023) * 8 - kNB;
 
 __device__ inline int log_bin(double x)
 {
-    const int64_t b = (int64_t(__double_as_longlong(x)) >> kLogShift) - kLogBase;
-    return b < 0 ? 0 : (b > kNB - 1 ? kNB - 1 : int(b));
+    // the 64-bit pattern shifted right by kLogShift is the high word shifted
+    // right by kLogShift - 32 (both arithmetic)
+    const int b = (__double2hiint(x) >> (kLogShift - 32)) - int(kLogBase);
+    return min(max(b, 0), kNB - 1);
 }
 
 // lower edge of log bin b (1 <= b <= kNB); log_bin(x) < b exactly when x < edge
