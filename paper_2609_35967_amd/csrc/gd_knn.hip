@@ -14,8 +14,11 @@
 // Query: one lane per particle, stackless walk that keeps, per level, the
 // 8-bit mask of children still to visit (all levels in one 64-bit register).
 // It starts at the level-1 ancestor of the query's bucket and climbs one
-// ancestor at a time, so the space near the query is seen first.  Exact
-// selection of the k-1 nearest others:
+// ancestor at a time, so the space near the query is seen first.  Each
+// iteration expands one node and scans one bucket of a short queue of
+// level-1 bucket masks, with the loads of both issued together and no
+// branch around either (see walk()).  Exact selection of the k-1 nearest
+// others:
 //   1. upper bound R2init of the (k-1)-th d^2: the smallest, over three
 //      windows of k consecutive slots holding the query, of the window's
 //      largest d^2;
