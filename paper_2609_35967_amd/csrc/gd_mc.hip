@@ -211,7 +211,7 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
 }
 
 // ---------------------------------------------------------------------------
-constexpr int kAuditGroups = 4;  // block-partial groups summed in parallel
+constexpr int kAuditGroups = 8;  // block-partial groups summed in parallel
 
 __global__ __launch_bounds__(kAuditGroups * kNBin) void k_audit(DevProblem P, const double* __restrict__ part, int nblk,
                                                                 gd_interval* iv, WsHeader* h)
@@ -221,6 +221,7 @@ __global__ __launch_bounds__(kAuditGroups * kNBin) void k_audit(DevProblem P, co
     const int t = threadIdx.x, b = t % kNBin, gq = t / kNBin;
     {
         dd x{0.0, 0.0};
+#pragma unroll 4
         for (int blk = gq; blk < nblk; blk += kAuditGroups) {
             const double* a = part + (int64_t(blk) * kNBin + b) * 8;
             x = dd_add(x, dd{a[1], a[2]});

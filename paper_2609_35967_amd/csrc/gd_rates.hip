@@ -174,39 +174,57 @@ __global__ __launch_bounds__(256) void k_rates_f32(RatesArgs A)
 // Per-block bin sums.  mode 0 (plan): count, M, M a, M b over bin(m_snap).
 // mode 1 (audit): M |ln(m_new/m_snap)|/3 over bin(m_snap).
 // part[(blk * kNBin + bin) * 8 + f]: f = 0 count, (1,2) (3,4) (5,6) dd values.
-__global__ __launch_bounds__(256) void k_bin_reduce(int mode, const double* __restrict__ msnap,
-                                                    const double* __restrict__ M, const double* __restrict__ va,
-                                                    const double* __restrict__ vb, int64_t n,
-                                                    double* __restrict__ part, void* ws)
+constexpr int kRedWaves = 8;  // wavefronts per bin-reduction block
+
+__global__ __launch_bounds__(kRedWaves * kWave) void k_bin_reduce(int mode, const double* __restrict__ msnap,
+                                                                   const double* __restrict__ M,
+                                                                   const double* __restrict__ va,
+                                                                   const double* __restrict__ vb, int64_t n,
+                                                                   double* __restrict__ part, void* ws)
 {
-    __shared__ double acc[4][kNBin][7];
+    __shared__ double acc[kRedWaves][kNBin][7];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    for (int e = t; e < 4 * kNBin * 7; e += 256) (&acc[0][0][0])[e] = 0.0;
+    for (int e = t; e < kRedWaves * kNBin * 7; e += kRedWaves * kWave) (&acc[0][0][0])[e] = 0.0;
     __syncthreads();
     const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
     const int64_t beg = blockIdx.x * chunk;
     const int64_t end = beg + chunk < n ? beg + chunk : n;
     bool range_bad = false;
-    for (int64_t base = beg; base < end; base += 256) {
-        const int64_t i = base + t;
-        bool valid = i < end;
-        double Mi = 0.0, ms = 1.0, v0 = 0.0, v1 = 0.0, v2 = 0.0;
+    // wavefront w takes the rows of 64 slots w, w + kRedWaves, ... of the
+    // block's range; the next row's operands are loaded before the current
+    // row is reduced
+    struct Row {
+        double Mi, ms, a, b;
+    };
+    auto load = [&](int64_t i, Row& r) {
+        const bool in = i < end;
+        r.Mi = in ? M[i] : 0.0;
+        r.ms = in ? msnap[i] : 1.0;
+        r.a = in ? va[i] : 0.0;
+        r.b = (in && mode == 0) ? vb[i] : 0.0;
+    };
+    const int64_t step = int64_t(kRedWaves) * kWave;
+    int64_t rb = beg + int64_t(w) * kWave;
+    Row cur;
+    load(rb + lane, cur);
+    for (; rb < end; rb += step) {
+        Row nxt;
+        load(rb + step + lane, nxt);
+        const int64_t i = rb + lane;
+        bool valid = i < end && cur.Mi > 0.0;
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0;
         int bin = 0;
         if (valid) {
-            Mi = M[i];
-            valid = Mi > 0.0;
-        }
-        if (valid) {
-            ms = msnap[i];
+            const double ms = cur.ms;
             bin = bin_of(ms);
             const int lb = ilogb(ms);
             range_bad = range_bad || lb < -kBinOff || lb > kNBin - 1 - kBinOff;
             if (mode == 0) {
-                v0 = Mi;
-                v1 = Mi * va[i];
-                v2 = Mi * vb[i];
+                v0 = cur.Mi;
+                v1 = cur.Mi * cur.a;
+                v2 = cur.Mi * cur.b;
             } else {
-                v0 = Mi * (fabs(log(va[i] / ms)) / 3.0);
+                v0 = cur.Mi * (fabs(log(cur.a / ms)) / 3.0);
             }
         }
         uint64_t rem = __ballot(valid);
@@ -236,14 +254,15 @@ __global__ __launch_bounds__(256) void k_bin_reduce(int mode, const double* __re
             }
             rem &= ~match;
         }
+        cur = nxt;
     }
     if (__ballot(range_bad) && lane == 0) set_status(ws, GD_DEV_MASS_RANGE);
     __syncthreads();
-    for (int bin = t; bin < kNBin; bin += 256) {
+    for (int bin = t; bin < kNBin; bin += kRedWaves * kWave) {
         double* out = part + (int64_t(blockIdx.x) * kNBin + bin) * 8;
         double cnt = 0.0;
         dd x0{0.0, 0.0}, x1{0.0, 0.0}, x2{0.0, 0.0};
-        for (int ww = 0; ww < 4; ++ww) {
+        for (int ww = 0; ww < kRedWaves; ++ww) {
             const double* a = acc[ww][bin];
             cnt += a[0];
             x0 = dd_add(x0, dd{a[1], a[2]});
@@ -266,7 +285,7 @@ __global__ __launch_bounds__(256) void k_bin_reduce(int mode, const double* __re
 // A_b = sum M a/sum M, B_b = sum M b/sum M;
 // dt_req = min(dt_remain, dt_fn_max, eps C/A_b, (eps C)^2/B_b);
 // dt_exe = dt_coll 2^-n, the largest aligned dyadic fraction <= dt_req.
-constexpr int kPlanGroups = 4;  // block-partial groups summed in parallel
+constexpr int kPlanGroups = 8;  // block-partial groups summed in parallel
 
 __global__ __launch_bounds__(kPlanGroups * kNBin) void k_plan(DevProblem P, const double* __restrict__ part, int nblk,
                                                               gd_interval* iv, WsHeader* h, void* ws)
@@ -279,6 +298,7 @@ __global__ __launch_bounds__(kPlanGroups * kNBin) void k_plan(DevProblem P, cons
     {
         double c = 0.0;
         dd x0{0.0, 0.0}, x1{0.0, 0.0}, x2{0.0, 0.0};
+#pragma unroll 4
         for (int blk = gq; blk < nblk; blk += kPlanGroups) {
             const double* a = part + (int64_t(blk) * kNBin + b) * 8;
             c += a[0];
@@ -402,7 +422,7 @@ __global__ __launch_bounds__(kPlanGroups * kNBin) void k_plan(DevProblem P, cons
 void launch_bin_reduce(int mode, const double* msnap, const double* M, const double* va, const double* vb, int64_t n,
                        double* part, void* ws, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bin_reduce, dim3(kRedBlocks), dim3(256), 0, st, mode, msnap, M, va, vb, n, part, ws);
+    hipLaunchKernelGGL(k_bin_reduce, dim3(kRedBlocks), dim3(kRedWaves * kWave), 0, st, mode, msnap, M, va, vb, n, part, ws);
 }
 
 int launch_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv, double* lam_i,
