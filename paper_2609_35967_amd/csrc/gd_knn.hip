@@ -479,7 +479,8 @@ struct QueryLds {
     static constexpr int kList = KP2 > 32 ? 80 : 48;
     static constexpr int kWords = kNB / 2 + kList;
 };
-constexpr uint32_t kSlotMask = (1u << 26) - 1;  // list word: mark << 31 | bin << 26 | slot
+constexpr uint32_t kSlotMask = (1u << 26) - 1;  // list word: bin << 26 | slot
+static_assert(QueryLds<32>::kList % 8 == 0 && QueryLds<64>::kList % 8 == 0, "the list is read 8 words at a time");
 static_assert(kC1 <= kNB / 2, "the boundary list reuses the counter words");
 static_assert(kNB <= 32, "list words keep the bin in 5 bits");
 
@@ -714,80 +715,68 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
     //    over-full boundary bin with nested linear bins and walking again.
     //    Either way the retained others end in list words [0, ntot).
     int32_t* s_bnd = reinterpret_cast<int32_t*>(s_lds);  // the counters are no longer needed
-    const bool from_list = !sat && !ovf;
+    bool from_list = !sat && !ovf;
     const bool keep = cle < need;  // fewer than k-1 others within the cap: keep them all
     int c0 = 0, hb = 0, refines = 0, visB = 0, visR = 0, nsel = 0, nb = 0, ntot = 0;
     double maxd2 = 0.0;
     bool fallback = sat;
+    const int b0 = keep ? kNB : bcut;
     if (from_list) {
-        const int b0 = keep ? kNB : bcut;
-        c0 = keep ? cle : cle - hcut;
-        hb = keep ? 0 : hcut;
-        // boundary entries: their list positions
-        for (int e = 0; e < len; ++e)
-            if (int((s_list[e * kQBlock + tid] >> 26) & 31u) == b0) {
-                if (nb < kC1) s_bnd[nb * kQBlock + tid] = e;
-                ++nb;
-            }
-        const int needb = need - c0 < nb ? need - c0 : nb;
-        if (nb <= kC1) {
-            // rank by (d^2, slot) in registers; mark the chosen entries
-            double bd[kC1];
-            int32_t bj[kC1], bp[kC1];
+        // one pass over the list, read 8 words at a time: sure entries (below
+        // the boundary bin) move to the front as slots, boundary entries'
+        // slots go to the boundary words.  A write never passes the read.
+        for (int e0 = 0; e0 < len; e0 += 8) {
+            uint32_t wv[8];
 #pragma unroll
-            for (int e = 0; e < kC1; ++e) {
-                bp[e] = e < nb ? s_bnd[e * kQBlock + tid] : 0;
-                bj[e] = e < nb ? int32_t(s_list[bp[e] * kQBlock + tid] & kSlotMask) : INT32_MAX;
-                bd[e] = e < nb ? sep2_slot<PER>(A, qp, bj[e]) : INFINITY;
-            }
+            for (int u = 0; u < 8; ++u) wv[u] = e0 + u < cap ? s_list[(e0 + u) * kQBlock + tid] : 0u;
 #pragma unroll
-            for (int e = 0; e < kC1; ++e) {
-                int rank = 0;
-#pragma unroll
-                for (int f = 0; f < kC1; ++f) rank += (bd[f] < bd[e]) || (bd[f] == bd[e] && bj[f] < bj[e]);
-                if (e < nb && rank < needb) {
-                    s_list[bp[e] * kQBlock + tid] |= 0x80000000u;
-                    maxd2 = fmax(maxd2, bd[e]);
+            for (int u = 0; u < 8; ++u) {
+                const bool live = e0 + u < len;
+                const int bn = int((wv[u] >> 26) & 31u);
+                const int j = int(wv[u] & kSlotMask);
+                const bool sure = live && bn < b0;
+                s_list[ntot * kQBlock + tid] = uint32_t(j);  // kept only if sure
+                ntot += sure ? 1 : 0;
+                if (keep && sure) maxd2 = fmax(maxd2, sep2_slot<PER>(A, qp, j));
+                if (live && bn == b0) {
+                    if (nb < kC1) s_bnd[nb * kQBlock + tid] = j;
+                    ++nb;
                 }
-            }
-        } else {
-            // many boundary entries (rare): repeated minimum over the list
-            double lastd = -1.0;
-            int lastj = -1;
-            for (int t = 0; t < needb; ++t) {
-                double bestd = INFINITY;
-                int bestj = INT32_MAX, beste = -1;
-                for (int e = 0; e < len; ++e) {
-                    const uint32_t w = s_list[e * kQBlock + tid];
-                    if (int((w >> 26) & 31u) != b0) continue;
-                    const int j = int(w & kSlotMask);
-                    const double d2 = sep2_slot<PER>(A, qp, j);
-                    const bool after = (d2 > lastd) || (d2 == lastd && j > lastj);
-                    const bool better = (d2 < bestd) || (d2 == bestd && j < bestj);
-                    if (after && better) {
-                        bestd = d2;
-                        bestj = j;
-                        beste = e;
-                    }
-                }
-                if (beste >= 0) s_list[beste * kQBlock + tid] |= 0x80000000u;
-                maxd2 = fmax(maxd2, bestd);
-                lastd = bestd;
-                lastj = bestj;
             }
         }
-        // keep the sure and the chosen entries, in place at the front
-        for (int e = 0; e < len; ++e) {
-            const uint32_t w = s_list[e * kQBlock + tid];
-            if (int((w >> 26) & 31u) < b0 || (w >> 31)) {
-                const int j = int(w & kSlotMask);
-                s_list[(ntot++) * kQBlock + tid] = uint32_t(j);
-                if (keep) maxd2 = fmax(maxd2, sep2_slot<PER>(A, qp, j));
+        // more boundary entries than the registers rank: give the list up
+        // (the lane refines the boundary bin and walks again)
+        if (nb > kC1) from_list = false;
+    }
+    if (from_list) {
+        c0 = keep ? cle : cle - hcut;
+        hb = keep ? 0 : hcut;
+        if (ntot != c0) set_status(A.ws, GD_DEV_INTERNAL);
+        const int needb = need - c0 < nb ? need - c0 : nb;
+        // rank the boundary slots by (d^2, slot) in registers; the chosen
+        // ones follow the sure ones
+        double bd[kC1];
+        int32_t bj[kC1];
+#pragma unroll
+        for (int e = 0; e < kC1; ++e) {
+            bj[e] = e < nb ? s_bnd[e * kQBlock + tid] : INT32_MAX;
+            bd[e] = e < nb ? sep2_slot<PER>(A, qp, bj[e]) : INFINITY;
+        }
+#pragma unroll
+        for (int e = 0; e < kC1; ++e) {
+            int rank = 0;
+#pragma unroll
+            for (int f = 0; f < kC1; ++f) rank += (bd[f] < bd[e]) || (bd[f] == bd[e] && bj[f] < bj[e]);
+            if (e < nb && rank < needb) {
+                s_list[(ntot++) * kQBlock + tid] = uint32_t(bj[e]);
+                maxd2 = fmax(maxd2, bd[e]);
             }
         }
         nsel = c0;
         if (ntot != c0 + needb) set_status(A.ws, GD_DEV_INTERNAL);
     } else {
+        nb = ntot = 0;  // (a list given up in the pass above)
+        maxd2 = 0.0;
         if (sat) {
             c.depth = 0;  // every candidate inside R2 is a boundary candidate
         } else if (keep) {
