@@ -199,6 +199,74 @@ def cpu_baseline(params, seed, n, nq):
                         f"for {nq} sampled particles, dt = dt_coll) in {t:.1f} s"))
 
 
+def batch_bench(args):
+    """Batched boxes: the plain per-box loop, then the recorded graph (two
+    intervals of every box per replay) on the same boxes.  A round is one
+    interval of every box."""
+    import torch
+    from paper_2609_35967_amd import load
+    from paper_2609_35967_amd.batch import BoxBatch
+
+    load()
+    torch.cuda.set_device(0)
+    boxes = workloads.box_batch(args.seed, nbox=args.batch)
+    bb = BoxBatch(boxes, streams=args.streams)
+    n = bb.n_particles
+    rounds = max(2, args.steps // 2 * 2)
+
+    def timed(fn, reps, per):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record()
+        for r in range(reps):
+            fn()
+            ev[r + 1].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]) / per
+        return wall, lat
+
+    print(f"[bench] {len(boxes)} boxes, {n} particles: plain loop", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        bb.step_plain()
+    wall_p, lat_p = timed(bb.step_plain, rounds, 1)
+    print(f"[bench] plain {wall_p / rounds * 1e3:.2f} ms per round; recording the graph", file=sys.stderr, flush=True)
+    bb.capture()
+    for _ in range(max(1, args.warmup // 2)):
+        bb.replay()
+    wall_b, lat_b = timed(bb.replay, rounds // 2, 2)
+    print(f"[bench] batched {wall_b / rounds * 1e3:.2f} ms per round", file=sys.stderr, flush=True)
+    status = max(e.status() for e in bb.engines)
+    ev_max = [int(e.events.max().item()) for e in bb.engines]
+    heavy = int(np.argmax(ev_max))
+    print(f"[bench] events of the last interval: most in one particle {ev_max[heavy]} (box {heavy}, "
+          f"n={bb.engines[heavy].n}); total {sum(int(e.events.sum().item()) for e in bb.engines)}",
+          file=sys.stderr, flush=True)
+    value_b = n * rounds / wall_b
+    value_p = n * rounds / wall_p
+    out = dict(
+        metric="particle-intervals/s (kNN+rates+MC) at 1M; batched vs plain; p50/p99 latency",
+        value=round(value_b, 1), unit="particle-intervals/s", n_gpus=1, steps=rounds, warmup=args.warmup,
+        ms_per_step=round(wall_b / rounds * 1e3, 4), higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64", data="synthetic",
+        config=dict(workload=f"box_batch: {len(boxes)} periodic local boxes of the annulus physics, "
+                             f"{n} particles in all (N log-uniform 2^10..2^16), per-box alpha log-uniform "
+                             "1e-4..1e-2 and v_frag uniform 1..10 m/s, k=32, no push",
+                    n_particles=n, n_boxes=len(boxes), k=32,
+                    form=f"batched: one HIP graph per two intervals of every box, {args.streams} streams"),
+        p50_ms=round(float(np.percentile(lat_b, 50)), 4), p99_ms=round(float(np.percentile(lat_b, 99)), 4),
+        plain=dict(value=round(value_p, 1), ms_per_step=round(wall_p / rounds * 1e3, 4),
+                   p50_ms=round(float(np.percentile(lat_p, 50)), 4),
+                   p99_ms=round(float(np.percentile(lat_p, 99)), 4),
+                   form="plain per-box loop, eager launches on one stream"),
+        batched_over_plain=round(value_b / value_p, 3),
+        events_max_per_particle=max(ev_max),
+        status=status,
+    )
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,9 +281,19 @@ def main():
                     help="the single-precision pair-rate form (FP64 positions, distances and push)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="REPS",
                     help="only run a plain 1 GiB device copy REPS times (HBM counter calibration)")
+    ap.add_argument("--batch", type=int, default=0, metavar="NBOX",
+                    help="the batched-boxes configuration instead: NBOX periodic local boxes "
+                         "(N log-uniform 2^10..2^16), the plain per-box loop against the recorded graph")
+    ap.add_argument("--streams", type=int, default=4, help="streams of the batched graph")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.batch:
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        batch_bench(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs the single-GPU path only (asked for --gpus {args.gpus}); the multi-GPU "

@@ -199,7 +199,11 @@ int32_t gd_collision_rates(const gd_problem* p, const gd_particles* st, const gd
  * Random numbers: Philox4x32-10, key = seed, counters (id, interval_index,
  * event, 0 / 1).  Afterwards the safety factor C is audited and the ticks and
  * time advance by the executed interval.  The caller then flips st->cur
- * (the broadcast).  interval_index must be < 2^32. */
+ * (the broadcast).  interval_index must be < 2^32, or GD_INTERVAL_ON_DEVICE:
+ * the kernels then take iv->n_intervals (the intervals completed, read on the
+ * device) as the index, so that a call recorded once in a HIP graph draws
+ * fresh numbers on every replay. */
+#define GD_INTERVAL_ON_DEVICE UINT64_MAX
 int32_t gd_sample_collisions(const gd_problem* p, const gd_particles* st, const gd_neighbors* nb,
                              gd_interval* iv, const double* lam_i, uint64_t seed,
                              uint64_t interval_index, int32_t* n_events, int32_t* log,

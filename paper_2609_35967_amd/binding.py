@@ -61,6 +61,7 @@ class GdInterval(C.Structure):
 EXPORTS = ("gd_workspace_size", "gd_workspace_init", "gd_interval_init", "gd_build_neighbors", "gd_collision_rates",
            "gd_sample_collisions", "gd_push", "gd_profile_events", "gd_status_read", "gd_last_error", "gd_version")
 PROF = {"sort": 0, "tree": 1, "knn_query": 2, "rates": 3, "mc": 4, "audit": 5, "push": 6}
+GD_INTERVAL_ON_DEVICE = (1 << 64) - 1
 
 _lib = None
 
@@ -188,7 +189,8 @@ class Engine:
     """A run of the hot path on one GPU: state (double-buffered for the Morton
     permutation), neighbourhoods, interval state and workspace, all resident in HBM."""
 
-    def __init__(self, params: dict, state: dict, seed: int = 0, device: str = "cuda", stream=None):
+    def __init__(self, params: dict, state: dict, seed: int = 0, device: str = "cuda", stream=None,
+                 device_interval: bool = False):
         import torch
         self.torch = torch
         self.lib = load()
@@ -200,6 +202,9 @@ class Engine:
         self.stream = stream
         self.seed = int(seed)
         self.interval = 0
+        # sampling takes its interval index from the device interval state
+        # (GD_INTERVAL_ON_DEVICE), as a call recorded in a graph must
+        self.device_interval = bool(device_interval)
         k = self.P.k
         self.A = DeviceState(torch, state, n, self.device)
         self.B = DeviceState.like(self.A)
@@ -244,7 +249,8 @@ class Engine:
         s = self.A.struct()
         check(self.lib.gd_sample_collisions(C.byref(self.P), C.byref(s), C.byref(self.nb),
                                             C.c_void_p(self.iv.data_ptr()), _ptr(self.lam), self.seed,
-                                            self.interval, _ptr(self.events), _ptr(log), int(log_cap),
+                                            GD_INTERVAL_ON_DEVICE if self.device_interval else self.interval,
+                                            _ptr(self.events), _ptr(log), int(log_cap),
                                             C.c_void_p(self.ws_ptr), self.ws_bytes, self._s()))
         self.interval += 1
         if flip:

@@ -232,15 +232,17 @@ int32_t gd_sample_collisions(const gd_problem* p, const gd_particles* s, const g
     if (!rc) rc = check_nb(nb);
     if (rc) return rc;
     if (!iv || !lam_i) return fail(GD_E_INVALID_ARG, "interval and lam_i are required");
-    if (interval_index >> 32) return fail(GD_E_INVALID_ARG, "interval_index must be < 2^32");
+    const bool on_device = interval_index == GD_INTERVAL_ON_DEVICE;
+    if (!on_device && (interval_index >> 32))
+        return fail(GD_E_INVALID_ARG, "interval_index must be < 2^32 or GD_INTERVAL_ON_DEVICE");
     if (log_cap < 0 || (log_cap > 0 && !log)) return fail(GD_E_INVALID_ARG, "log_cap > 0 needs a log array");
     if (int64_t(log_cap) * p->n >= (int64_t(1) << 31)) return fail(GD_E_UNSUPPORTED, "n * log_cap must stay below 2^31");
     Layout L;
     rc = check_ws(p, ws, ws_bytes, L);
     if (rc) return rc;
     if (p->n == 0) return GD_OK;
-    launch_sample(p, s, nb, iv, lam_i, seed, uint32_t(interval_index), n_events, log, log_cap, ws, L,
-                  static_cast<hipStream_t>(stream));
+    launch_sample(p, s, nb, iv, lam_i, seed, on_device ? 0u : uint32_t(interval_index), on_device, n_events, log,
+                  log_cap, ws, L, static_cast<hipStream_t>(stream));
     return hip_ok("gd_sample_collisions");
 }
 

@@ -58,12 +58,14 @@ struct alignas(256) WsHeader {
     double gM[kNBin];            // plan: sum of M per merged group
     double scratch[16];
     int32_t xq[4][8];            // per-die work queues of the gather-heavy kernels
+    int32_t heavy_n;             // sampling: particles handed to the wavefront-per-particle pass
+    int32_t heavy_next;          // sampling: next of them to take
 };
 
 // Workspace layout (byte offsets), identical on host and device.
 struct Layout {
     size_t hdr, keys0, keys1, vals0, vals1, hist, red, pos4, boxes,
-        snap, a, b, part, hint, stats, total;
+        snap, a, b, part, hint, heavy, stats, total;
     int64_t n;
     int32_t k;
     int32_t nsort_blocks;
@@ -120,6 +122,7 @@ __host__ inline Layout make_layout(int64_t n, int32_t k)
     L.b = take(8 * nn);
     L.part = take(sizeof(double) * 8 * kNBin * kRedBlocks);
     L.hint = take(8 * nn);
+    L.heavy = take(24 * nn);  // sampling: (slot, events, time, mass) of deferred particles
 #ifdef GD_KNN_STATS
     L.stats = take(32 * nn);
 #endif

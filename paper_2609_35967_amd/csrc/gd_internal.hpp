@@ -29,7 +29,7 @@ int launch_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layo
 int launch_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv, double* lam_i,
                  double* lam_pair, double* ab, void* ws, const Layout& L, hipStream_t st);
 int launch_sample(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
-                  const double* lam_i, uint64_t seed, uint32_t interval, int32_t* n_events, int32_t* log,
+                  const double* lam_i, uint64_t seed, uint32_t interval, bool interval_on_device, int32_t* n_events, int32_t* log,
                   int32_t log_cap, void* ws, const Layout& L, hipStream_t st);
 int launch_push(const gd_problem* p, const gd_particles* s, const gd_interval* iv, double dt, void* ws,
                 const Layout& L, hipStream_t st);

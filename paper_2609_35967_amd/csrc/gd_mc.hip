@@ -40,11 +40,28 @@ struct McArgs {
     int32_t log_cap;
     uint64_t seed;
     uint32_t interval;
+    int32_t interval_on_device;  // take the index from iv->n_intervals
     void* ws;
     unsigned long long* ev_counter;
+    // particles still sampling after `budget` events are handed, at that
+    // event boundary, to a pass that runs one wavefront per particle
+    int32_t budget;
+    struct Deferred* heavy;
+    int32_t* heavy_n;
+    int32_t* heavy_next;
+};
+
+// a particle handed over after e events, at time t of the interval, with mass m
+struct Deferred {
+    int32_t i;
+    int32_t e;
+    double t;
+    double m;
 };
 
 constexpr int kEventCap = 1 << 24;  // safety stop per particle and interval (status-flagged)
+constexpr int kLaneEvents = 16;     // events a lane samples before handing its particle over
+constexpr int kHeavyBlocks = 256;   // blocks (4 wavefronts each) of the wavefront-per-particle pass
 
 template <int KP2>
 __device__ inline double prefix_rates_f32(const McArgs& A, const QCtxF& q, const int32_t* row, int c, double mi,
@@ -107,6 +124,7 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
         double m = A.m[i];
         double li = A.lam_i[i];
         const double dt_exe = A.iv->dt_exe;
+        const uint32_t interval = A.interval_on_device ? uint32_t(A.iv->n_intervals) : A.interval;
         if (c > 1 && li > 0.0) {
             const uint32_t pid = A.id[i];
             const int32_t* row = A.nbr + i * k;
@@ -118,12 +136,20 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
             double t = 0.0;
             for (;;) {
                 if (!(li > 0.0)) break;
+                if (e >= A.budget) {
+                    // many events: the rest of this particle's interval runs
+                    // in the wavefront-per-particle pass (li equals the prefix
+                    // of the current mass, which that pass recomputes)
+                    const int32_t slot = atomicAdd(A.heavy_n, 1);
+                    A.heavy[slot] = Deferred{int32_t(i), e, t, m};
+                    break;
+                }
                 if (e >= kEventCap) {
                     set_status(A.ws, GD_DEV_EVENT_CAP);
                     break;
                 }
                 double u[4];
-                event_uniforms(A.seed, pid, A.interval, uint32_t(e), u);
+                event_uniforms(A.seed, pid, interval, uint32_t(e), u);
                 const double dtw = -log(u[0]) / li;
                 if (dtw > dt_exe - t) break;
                 t = t + dtw;
@@ -211,6 +237,138 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
 }
 
 // ---------------------------------------------------------------------------
+// The rest of the interval of each deferred particle, one wavefront per
+// particle: lane s < c evaluates the pair of neighbour slot s for the
+// particle's current mass, and the prefix is summed in slot order by reading
+// the lanes one after the other, so every rate, prefix and decision is the
+// one the one-lane form computes.  The draw, the selection (first slot whose
+// prefix exceeds the target) and the outcome are uniform over the wavefront.
+// Wavefronts take particles from a counter until the list is exhausted.
+template <bool F32>
+__device__ inline void pair_at(const McArgs& A, const QCtx& q, const QCtxF& qf, double m, double si, double Sti,
+                               const double4& sn, bool phys, Pair& o, double& lam_pre)
+{
+    if (F32) {
+        PairF of;
+        pair_eval_f32(A.P, qf, m, 1.0 / m, float(si), float(Sti), sn.x, phys ? float(sn.y) : 0.0f,
+                      phys ? sn.z : 0.0, of);
+        o.type = of.type;
+        o.r0 = of.r0;
+        o.r1 = of.r1;
+        o.lam_star = double(of.r0) + double(of.r1);
+        o.Ng = of.Ng;
+        lam_pre = double(of.lam_star);  // the prefix adds the float rate
+    } else {
+        pair_eval(A.P, q, m, si, Sti, sn.x, phys ? sn.y : 0.0, phys ? sn.z : 0.0, o);
+        lam_pre = o.lam_star;
+    }
+}
+
+template <int KP2, bool F32>
+__global__ __launch_bounds__(256) void k_mc_heavy(McArgs A)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t nh = *A.heavy_n;
+    const bool phys = A.P.kernel == GD_KERNEL_PHYSICAL;
+    const double dt_exe = A.iv->dt_exe;
+    const uint32_t interval = A.interval_on_device ? uint32_t(A.iv->n_intervals) : A.interval;
+    unsigned long long ev_total = 0;
+    // wavefront w takes entry w first, then entries nw, nw + 1, ... from the
+    // counter (a wavefront with no first entry touches no counter)
+    const int32_t nw = int32_t(gridDim.x * (blockDim.x / kWave));
+    int32_t hidx = int32_t(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+    for (;;) {
+        if (hidx >= nh) break;
+        const Deferred H = A.heavy[hidx];
+        const int64_t i = H.i;
+        int e = H.e;
+        double t = H.t, m = H.m;
+        const int k = A.P.k;
+        const int c = A.cnt[i];
+        const uint32_t pid = A.id[i];
+        QCtx q{};
+        QCtxF qf{};
+        query_ctx(A.P, A.x[i], A.y[i], A.z[i], A.dmax[i], q);
+        if (F32) query_ctx_f32(A.P, q, qf);
+        const bool mine = lane < c && lane < KP2;
+        int j = mine ? A.nbr[i * k + lane] : 0;
+        if (mine && (j < 0 || j >= A.P.n)) set_status(A.ws, GD_DEV_INTERNAL);
+        if (j < 0 || j >= A.P.n) j = 0;
+        const double4 sn = A.snap[j];
+        double si = 0.0, Sti = 0.0;
+        Pair o{};
+        double mypre = 0.0, li = 0.0;
+        auto rates = [&]() {
+            if (phys) {
+                si = grain_size(A.P, m);
+                Sti = F32 ? double(qf.stfac * float(si)) : q.stfac * si;
+            }
+            double lam = 0.0;
+            pair_at<F32>(A, q, qf, m, si, Sti, sn, phys, o, lam);
+            double acc = 0.0;
+#pragma unroll
+            for (int s = 0; s < KP2; ++s) {
+                if (s < c) acc = acc + __shfl(lam, s, 64);
+                if (s == lane) mypre = acc;
+            }
+            li = acc;
+        };
+        rates();
+        for (;;) {
+            if (!(li > 0.0)) break;
+            if (e >= kEventCap) {
+                if (lane == 0) set_status(A.ws, GD_DEV_EVENT_CAP);
+                break;
+            }
+            double u[4];
+            event_uniforms(A.seed, pid, interval, uint32_t(e), u);
+            const double dtw = -log(u[0]) / li;
+            if (dtw > dt_exe - t) break;
+            t = t + dtw;
+            const double target = u[1] * li;
+            const uint64_t hit = __ballot(lane < c - 1 && mypre > target);
+            const int sel = hit ? int(__ffsll((unsigned long long)hit)) - 1 : c - 1;
+            const int type = __shfl(o.type, sel, 64);
+            const double r0 = __shfl(o.r0, sel, 64);
+            const double lam_star = __shfl(o.lam_star, sel, 64);
+            const double Ng = __shfl(o.Ng, sel, 64);
+            const double mj = __shfl(sn.x, sel, 64);
+            int ch = 0;
+            if (type == kErosion) ch = (r0 > u[2] * lam_star) ? 0 : 1;
+            double mnew;
+            if (type == kStick) {
+                mnew = m + Ng * mj;
+            } else if (type == kErosion) {
+                mnew = (ch == 0) ? m - Ng * mj : mj;
+            } else {
+                const double a = sqrt(A.P.s_min);
+                const double w = a + u[3] * (sqrt(si) - a);
+                const double sz = w * w;
+                mnew = kPi * A.P.rho_s * sz * sz * sz / 6.0;
+            }
+            if (A.log && lane == 0) {
+                if (e < A.log_cap) A.log[i * A.log_cap + e] = sel | (ch << 16) | (type << 24);
+                else set_status(A.ws, GD_DEV_LOG_OVERFLOW);
+            }
+            ++e;
+            if (mnew != m) {
+                m = mnew;
+                rates();
+            }
+        }
+        if (lane == 0) {
+            A.m_out[i] = m;
+            if (A.n_events) A.n_events[i] = e;
+            ev_total += (unsigned long long)(e - H.e);
+        }
+        int32_t next = 0;
+        if (lane == 0) next = atomicAdd(A.heavy_next, 1);
+        hidx = nw + __builtin_amdgcn_readfirstlane(next);
+    }
+    if (lane == 0 && ev_total) atomicAdd(A.ev_counter, ev_total);
+}
+
+// ---------------------------------------------------------------------------
 constexpr int kAuditGroups = 8;  // block-partial groups summed in parallel
 
 __global__ __launch_bounds__(kAuditGroups * kNBin) void k_audit(DevProblem P, const double* __restrict__ part, int nblk,
@@ -295,7 +453,7 @@ void launch_interval_init(gd_interval* iv, double dt_coll, hipStream_t st)
 }
 
 int launch_sample(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
-                  const double* lam_i, uint64_t seed, uint32_t interval, int32_t* n_events, int32_t* log,
+                  const double* lam_i, uint64_t seed, uint32_t interval, bool interval_on_device, int32_t* n_events, int32_t* log,
                   int32_t log_cap, void* ws, const Layout& L, hipStream_t st)
 {
     const DevProblem P = to_dev(p);
@@ -320,16 +478,31 @@ int launch_sample(const gd_problem* p, const gd_particles* s, const gd_neighbors
     A.log_cap = log_cap;
     A.seed = seed;
     A.interval = interval;
+    A.interval_on_device = interval_on_device ? 1 : 0;
     A.ws = ws;
     A.ev_counter = reinterpret_cast<unsigned long long*>(&h->scratch[0]);
+    A.budget = kLaneEvents;
+    A.heavy = at<Deferred>(ws, L.heavy);
+    A.heavy_n = &h->heavy_n;
+    A.heavy_next = &h->heavy_next;
     const int g = int((n + 255) / 256);
     prof_mark(GD_PROF_MC, 0, st);
     if (p->rates_fp32) {
-        if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, true>), dim3(g), dim3(256), 0, st, A);
-        else hipLaunchKernelGGL((k_mc<64, true>), dim3(g), dim3(256), 0, st, A);
+        if (p->k <= 32) {
+            hipLaunchKernelGGL((k_mc<32, true>), dim3(g), dim3(256), 0, st, A);
+            hipLaunchKernelGGL((k_mc_heavy<32, true>), dim3(kHeavyBlocks), dim3(256), 0, st, A);
+        } else {
+            hipLaunchKernelGGL((k_mc<64, true>), dim3(g), dim3(256), 0, st, A);
+            hipLaunchKernelGGL((k_mc_heavy<64, true>), dim3(kHeavyBlocks), dim3(256), 0, st, A);
+        }
     } else {
-        if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, false>), dim3(g), dim3(256), 0, st, A);
-        else hipLaunchKernelGGL((k_mc<64, false>), dim3(g), dim3(256), 0, st, A);
+        if (p->k <= 32) {
+            hipLaunchKernelGGL((k_mc<32, false>), dim3(g), dim3(256), 0, st, A);
+            hipLaunchKernelGGL((k_mc_heavy<32, false>), dim3(kHeavyBlocks), dim3(256), 0, st, A);
+        } else {
+            hipLaunchKernelGGL((k_mc<64, false>), dim3(g), dim3(256), 0, st, A);
+            hipLaunchKernelGGL((k_mc_heavy<64, false>), dim3(kHeavyBlocks), dim3(256), 0, st, A);
+        }
     }
     prof_mark(GD_PROF_MC, 1, st);
     double* part = at<double>(ws, L.part);

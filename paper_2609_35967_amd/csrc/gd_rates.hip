@@ -409,6 +409,8 @@ __global__ __launch_bounds__(kPlanGroups * kNBin) void k_plan(DevProblem P, cons
         iv->exe_ticks = size;
         iv->n_groups = ng;
         h->scratch[0] = 0.0;  // event counter of the coming interval
+        h->heavy_n = 0;       // and the sampling's deferred particles
+        h->heavy_next = 0;
         s_ng = ng;
     }
     __syncthreads();

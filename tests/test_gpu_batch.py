@@ -1,0 +1,87 @@
+"""Batched boxes (BoxBatch): every box's state after the recorded graph's
+replays, and after the plain per-box loop, equals the same box stepped alone.
+
+The graph runs two intervals of every box per replay over three streams; the
+replays are separated by eager work and synchronisations, and every replay is
+checked."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2609_35967_amd import Engine, load  # noqa: E402
+from paper_2609_35967_amd.batch import BoxBatch  # noqa: E402
+
+
+def _say(*a):
+    print("[gpu]", *a, flush=True)
+
+
+def _boxes():
+    # six local boxes of uneven size, per-box alpha and v_frag (each interval
+    # has thousands of events at the workload's eps)
+    return workloads.box_batch(5, nbox=6, lo=10.0, hi=12.5)
+
+
+def _snap(e):
+    st = e.state_numpy()
+    return dict(st, nbr=e.nbr.cpu().numpy(), cnt=e.cnt.cpu().numpy(), dmax=e.dmax.cpu().numpy(),
+                events=e.events.cpu().numpy(), iv=e.interval_state())
+
+
+def _same(a, b, where):
+    for key in ("id", "x", "y", "z", "M", "m", "nbr", "cnt", "dmax", "events"):
+        assert np.array_equal(a[key], b[key]), f"{where}: {key} differs"
+    for key in ("time", "ticks", "dt_exe", "n_intervals", "n_events", "C"):
+        assert a["iv"][key] == b["iv"][key], f"{where}: interval {key} differs"
+
+
+def _alone(boxes, rounds):
+    ref = []
+    for p, s, sd in boxes:
+        e = Engine(p, s, seed=sd)
+        snaps = []
+        for _ in range(rounds):
+            e.step()
+            e.step()
+            snaps.append(_snap(e))
+        ref.append(snaps)
+    return ref
+
+
+def test_batch_graph_matches_alone():
+    load()
+    boxes = _boxes()
+    _say("batch", len(boxes), "boxes", [len(s["x"]) for _, s, _ in boxes])
+    ref = _alone(boxes, 3)
+    assert all(r[-1]["iv"]["n_events"] > 0 for r in ref)
+    _say("alone runs done")
+    bb = BoxBatch(boxes, streams=3)
+    bb.capture()
+    _say("graph recorded")
+    for r in range(3):
+        bb.replay()
+        torch.cuda.synchronize()
+        assert float(torch.arange(1000, device="cuda", dtype=torch.float64).sum().item()) == 499500.0
+        for b, e in enumerate(bb.engines):
+            _same(_snap(e), ref[b][r], f"replay {r} box {b}")
+            assert e.status() == 0
+        _say("replay", r, "matches")
+
+
+def test_batch_plain_matches_alone():
+    load()
+    boxes = _boxes()[:3]
+    ref = _alone(boxes, 1)
+    bb = BoxBatch(boxes)
+    bb.step_plain()
+    bb.step_plain()
+    torch.cuda.synchronize()
+    for b, e in enumerate(bb.engines):
+        _same(_snap(e), ref[b][0], f"plain box {b}")

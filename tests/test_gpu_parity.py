@@ -325,6 +325,22 @@ def test_sample_physical(warm):
     assert ntie <= 5
 
 
+@pytest.mark.parametrize("R_au, alpha, v_frag", [(12.0, 1e-2, 100.0), (80.0, 1e-4, 1000.0)])
+def test_local_box(R_au, alpha, v_frag):
+    # a periodic local box of the annulus (the batched-boxes workload): kNN
+    # with minimum images, physical rates, one sampled interval
+    n = 4096
+    params = workloads.local_box_params(n, R_au=R_au, alpha=alpha, v_frag=v_frag)
+    st = workloads.local_box(31, n, params)
+    eng = _engine(params, st)
+    eng.build_neighbors()
+    torch.cuda.synchronize()
+    _knn_compare(eng, params, _check_permutation(eng, st))
+    ntie, nev = _interval_compare(params, st, seed=17, interval_index=2)
+    _say("local box", R_au, alpha, v_frag, "events", nev, "near-ties", ntie)
+    assert nev > 100 and ntie <= 5
+
+
 def test_sample_physical_fragmentation_erosion():
     n = 16384
     params = dict(workloads.disk3d_params(n), eps=10.0, v_frag=1e-3)

@@ -19,6 +19,14 @@ whose own setups and data are not available):
                  k = 32, Keplerian initial velocities.  cgs units.
   disk3d_warm    as disk3d but grain radius log-uniform 1 um .. 1 mm (a builder
                  addition that exercises fragmentation, erosion and grouping).
+  local_box      a periodic cube of side 0.005 R at the midplane of the annulus
+                 at radius R: the annulus physics (gas model, Brownian + OC07,
+                 sticking / erosion / fragmentation), no push, grain radius
+                 log-uniform 1 um .. 1 mm, dust-to-gas 0.01 of the midplane
+                 gas density, per-box alpha and v_frag.
+  box_batch      256 such boxes: N log-uniform 2^10..2^16, R uniform in
+                 [10, 100] au, alpha log-uniform 1e-4..1e-2, v_frag uniform
+                 1..10 m/s (the batched-boxes configuration).
 """
 from __future__ import annotations
 
@@ -114,6 +122,46 @@ def disk3d(seed: int, n: int = 1 << 20, warm: bool = False, params: dict | None 
     lph = np.sqrt(P["GM"] * R)  # Keplerian specific angular momentum
     return dict(id=np.arange(n, dtype=np.uint32), x=x, y=y, z=z, r=r, th=th, ph=ph,
                 vr=np.zeros(n), lth=np.zeros(n), lph=lph, M=np.full(n, Md / n), m=m)
+
+
+def local_box_params(n: int, R_au: float = 30.0, alpha: float = 1e-3, v_frag: float = 100.0, k: int = 32) -> dict:
+    """A periodic cube of side 0.005 R at the midplane of the annulus at R."""
+    P = disk3d_params(n, k=k, alpha=alpha, v_frag=v_frag)
+    R = R_au * AU
+    side = 0.005 * R
+    period = 2.0 * math.pi / math.sqrt(P["GM"] / R ** 3)
+    P.update(name="local_box", periodic=(1, 1, 1), L=(side, side, side), push="none",
+             dt_fn_max=period / 50.0, dt_coll=period / 50.0, R_box=R)
+    return P
+
+
+def local_box(seed: int, n: int, params: dict) -> dict:
+    g = _rng(seed)
+    R, side = params["R_box"], params["L"][0]
+    x = R + side * g.random(n)
+    y = side * (g.random(n) - 0.5)
+    z = side * (g.random(n) - 0.5)
+    a = 10.0 ** g.uniform(-4.0, -1.0, n)  # grain radius 1 um .. 1 mm
+    m = math.pi * params["rho_s"] * (2.0 * a) ** 3 / 6.0
+    # dust-to-gas 0.01 of the midplane gas density Sigma_g / (sqrt(2 pi) H), H = h_g0 R
+    sigma = params["Sigma_g0"] * (R / params["R0"]) ** params["p"]
+    rho_g = sigma / (math.sqrt(2.0 * math.pi) * params["h_g0"] * R)
+    Md = params["dust_to_gas"] * rho_g * side ** 3
+    return dict(id=np.arange(n, dtype=np.uint32), x=x, y=y, z=z, M=np.full(n, Md / n), m=m)
+
+
+def box_batch(seed: int, nbox: int = 256, lo: int = 10, hi: int = 16):
+    """[(params, state, seed)] of nbox independent local boxes."""
+    g = _rng(seed)
+    out = []
+    for b in range(nbox):
+        n = int(round(2.0 ** g.uniform(lo, hi)))
+        R_au = g.uniform(10.0, 100.0)
+        alpha = 10.0 ** g.uniform(-4.0, -2.0)
+        v_frag = 100.0 * g.uniform(1.0, 10.0)  # cm/s
+        P = local_box_params(n, R_au=R_au, alpha=alpha, v_frag=v_frag)
+        out.append((P, local_box(seed * 1000 + b, n, P), seed * 1000 + b))
+    return out
 
 
 def lattice_box(nside: int, jitter: float = 0.0, seed: int = 0) -> dict:
