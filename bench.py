@@ -284,7 +284,7 @@ def main():
     ap.add_argument("--batch", type=int, default=0, metavar="NBOX",
                     help="the batched-boxes configuration instead: NBOX periodic local boxes "
                          "(N log-uniform 2^10..2^16), the plain per-box loop against the recorded graph")
-    ap.add_argument("--streams", type=int, default=4, help="streams of the batched graph")
+    ap.add_argument("--streams", type=int, default=8, help="streams of the batched graph")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)

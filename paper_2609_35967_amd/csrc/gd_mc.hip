@@ -60,7 +60,7 @@ struct Deferred {
 };
 
 constexpr int kEventCap = 1 << 24;  // safety stop per particle and interval (status-flagged)
-constexpr int kLaneEvents = 16;     // events a lane samples before handing its particle over
+constexpr int kLaneEvents = 4;      // events a lane samples before handing its particle over
 constexpr int kHeavyBlocks = 256;   // blocks (4 wavefronts each) of the wavefront-per-particle pass
 
 template <int KP2>
