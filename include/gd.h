@@ -204,6 +204,38 @@ int32_t gd_collision_rates(const gd_problem* p, const gd_particles* st, const gd
  * device) as the index, so that a call recorded once in a HIP graph draws
  * fresh numbers on every replay. */
 #define GD_INTERVAL_ON_DEVICE UINT64_MAX
+
+/* Sampling over many independent runs (boxes) at once.  gd_sample_collisions
+ * is, in order: the per-lane pass (each particle's first events; a particle
+ * with more is recorded in the workspace at that event boundary), the pass
+ * that runs the rest of every recorded particle with one wavefront each, and
+ * the audit.  The three calls below make the same passes with the second
+ * one shared by many runs, so that the recorded particles of every run are
+ * sampled in one launch.  Results are those of gd_sample_collisions, bit for
+ * bit.
+ *
+ * The table is device memory owned by the caller, gd_sample_table_size(nslot)
+ * bytes (1 <= nslot <= 4096).  Per interval, for each run r in [0, nslot):
+ * gd_sample_collisions_deferred(..., table, table_bytes, slot = r, stream_r),
+ * which takes gd_sample_collisions' arguments and writes the run's sampling
+ * arguments into slot r; then, on one stream ordered after all of them,
+ * gd_sample_table_run(table, table_bytes, nslot, k, rates_fp32, stream), where
+ * every run has the same k class (k <= 32, or 32 < k <= 64) and the same
+ * rates_fp32 (a run that differs is skipped and raises GD_DEV_INTERNAL); then
+ * gd_sample_audit for each run, after which the caller flips st->cur.  Every
+ * slot below nslot must have been written in the same interval: a slot left
+ * from an earlier interval would be sampled again.  Calls that overlap on one
+ * table race. */
+int32_t gd_sample_table_size(int32_t nslot, size_t* bytes);
+int32_t gd_sample_collisions_deferred(const gd_problem* p, const gd_particles* st, const gd_neighbors* nb,
+                                      gd_interval* iv, const double* lam_i, uint64_t seed,
+                                      uint64_t interval_index, int32_t* n_events, int32_t* log,
+                                      int32_t log_cap, void* ws, size_t ws_bytes, void* table,
+                                      size_t table_bytes, int32_t slot, void* stream);
+int32_t gd_sample_table_run(void* table, size_t table_bytes, int32_t nslot, int32_t k, int32_t rates_fp32,
+                            void* stream);
+int32_t gd_sample_audit(const gd_problem* p, const gd_particles* st, gd_interval* iv, void* ws,
+                        size_t ws_bytes, void* stream);
 int32_t gd_sample_collisions(const gd_problem* p, const gd_particles* st, const gd_neighbors* nb,
                              gd_interval* iv, const double* lam_i, uint64_t seed,
                              uint64_t interval_index, int32_t* n_events, int32_t* log,

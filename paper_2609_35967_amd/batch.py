@@ -5,13 +5,17 @@ workspace, and its own adaptive interval.  Two forms step every box:
 
 * ``step_plain`` -- the plain per-box loop: one interval of each box after the
   other, launched eagerly on the current stream;
-* ``replay`` -- one HIP graph holding two intervals of every box, the boxes
-  dealt to a few streams (largest first, each to the stream with the least
-  work so far) so that the small launches of different boxes overlap on the
-  device.  Two intervals per graph: the Morton permutation alternates between
-  a box's two state buffers and the sampling between its two mass buffers,
-  so after two intervals every buffer is back in its place and the graph can
-  be replayed.  The sampling calls take their interval index from the device
+* ``replay`` -- one HIP graph holding two intervals of every box.  Per
+  interval: each box's neighbour search, rates and per-lane sampling pass on
+  its stream (boxes dealt to a few streams, largest first, each to the stream
+  with the least work so far, so that the small launches of different boxes
+  overlap), its sampling arguments written to a slot of a shared table; then
+  one launch samples the particles that outlast the per-lane pass in every
+  box (gd_sample_table_run), and each box's audit follows on its stream.
+  Two intervals per graph: the Morton permutation alternates between a box's
+  two state buffers and the sampling between its two mass buffers, so after
+  two intervals every buffer is back in its place and the graph can be
+  replayed.  The sampling calls take their interval index from the device
   interval state, so each replay draws fresh numbers.
 
 A box's result does not depend on the form or on the other boxes: the kernels
@@ -67,6 +71,16 @@ class BoxBatch:
             s = min(range(self.nstreams), key=lambda t: load_of[t])
             assign[i] = s
             load_of[s] += self.engines[i].n
+        ks = {e.P.k <= 32 for e in self.engines}
+        fp = {int(e.P.rates_fp32) for e in self.engines}
+        if len(ks) != 1 or len(fp) != 1:
+            raise ValueError("batched boxes need one k class (k <= 32 or not) and one rates form")
+        nb = len(self.engines)
+        sz = C.c_size_t()
+        check(lib.gd_sample_table_size(nb, C.byref(sz)))
+        self.table = torch.empty(sz.value, dtype=torch.uint8, device=self.device)
+        tp, tb = self.table.data_ptr(), sz.value
+        k, f32 = self.engines[0].P.k, fp.pop()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             cs = torch.cuda.current_stream()
@@ -75,7 +89,18 @@ class BoxBatch:
             for _ in range(2):
                 for i, e in enumerate(self.engines):
                     e.stream = self.streams[assign[i]]
-                    e.step()
+                    e.build_neighbors()
+                    e.collision_rates()
+                    e.sample_deferred(tp, tb, i)
+                for st in self.streams:
+                    cs.wait_stream(st)
+                check(lib.gd_sample_table_run(C.c_void_p(tp), tb, nb, k, f32, C.c_void_p(cs.cuda_stream)))
+                for st in self.streams:
+                    st.wait_stream(cs)
+                for e in self.engines:
+                    e.sample_audit()
+                    if e.P.push != 0:
+                        e.push()
             for st in self.streams:
                 cs.wait_stream(st)
         for e in self.engines:

@@ -59,7 +59,8 @@ class GdInterval(C.Structure):
 
 
 EXPORTS = ("gd_workspace_size", "gd_workspace_init", "gd_interval_init", "gd_build_neighbors", "gd_collision_rates",
-           "gd_sample_collisions", "gd_push", "gd_profile_events", "gd_status_read", "gd_last_error", "gd_version")
+           "gd_sample_collisions", "gd_push", "gd_profile_events", "gd_status_read", "gd_last_error", "gd_version",
+           "gd_sample_table_size", "gd_sample_collisions_deferred", "gd_sample_table_run", "gd_sample_audit")
 PROF = {"sort": 0, "tree": 1, "knn_query": 2, "rates": 3, "mc": 4, "audit": 5, "push": 6}
 GD_INTERVAL_ON_DEVICE = (1 << 64) - 1
 
@@ -91,12 +92,19 @@ def load(path: str | None = None):
     L.gd_sample_collisions.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.POINTER(GdNeighbors), vp, vp,
                                        C.c_uint64, C.c_uint64, vp, vp, C.c_int32, vp, C.c_size_t, vp]
     L.gd_push.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), vp, C.c_double, vp, C.c_size_t, vp]
+    L.gd_sample_table_size.argtypes = [C.c_int32, C.POINTER(C.c_size_t)]
+    L.gd_sample_collisions_deferred.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.POINTER(GdNeighbors),
+                                                vp, vp, C.c_uint64, C.c_uint64, vp, vp, C.c_int32, vp, C.c_size_t,
+                                                vp, C.c_size_t, C.c_int32, vp]
+    L.gd_sample_table_run.argtypes = [vp, C.c_size_t, C.c_int32, C.c_int32, C.c_int32, vp]
+    L.gd_sample_audit.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), vp, vp, C.c_size_t, vp]
     L.gd_status_read.argtypes = [vp, vp, C.POINTER(C.c_int32)]
     L.gd_profile_events.argtypes = [C.c_int32, vp, vp]
     L.gd_last_error.restype = C.c_char_p
     L.gd_version.restype = C.c_char_p
     for name in ("gd_workspace_size", "gd_workspace_init", "gd_interval_init", "gd_build_neighbors", "gd_collision_rates",
-                 "gd_sample_collisions", "gd_push", "gd_status_read", "gd_profile_events"):
+                 "gd_sample_collisions", "gd_push", "gd_status_read", "gd_profile_events", "gd_sample_table_size",
+                 "gd_sample_collisions_deferred", "gd_sample_table_run", "gd_sample_audit"):
         getattr(L, name).restype = C.c_int32
     if path is None:
         _lib = L
@@ -252,6 +260,23 @@ class Engine:
                                             GD_INTERVAL_ON_DEVICE if self.device_interval else self.interval,
                                             _ptr(self.events), _ptr(log), int(log_cap),
                                             C.c_void_p(self.ws_ptr), self.ws_bytes, self._s()))
+        self.interval += 1
+        if flip:
+            self.A.cur ^= 1
+
+    def sample_deferred(self, table, table_bytes: int, slot: int):
+        """The per-lane pass of sampling; the run's arguments go to table slot `slot`
+        (the rest runs in gd_sample_table_run, then sample_audit)."""
+        s = self.A.struct()
+        check(self.lib.gd_sample_collisions_deferred(
+            C.byref(self.P), C.byref(s), C.byref(self.nb), C.c_void_p(self.iv.data_ptr()), _ptr(self.lam),
+            self.seed, GD_INTERVAL_ON_DEVICE if self.device_interval else self.interval, _ptr(self.events), None, 0,
+            C.c_void_p(self.ws_ptr), self.ws_bytes, C.c_void_p(table), int(table_bytes), int(slot), self._s()))
+
+    def sample_audit(self, flip: bool = True):
+        s = self.A.struct()
+        check(self.lib.gd_sample_audit(C.byref(self.P), C.byref(s), C.c_void_p(self.iv.data_ptr()),
+                                       C.c_void_p(self.ws_ptr), self.ws_bytes, self._s()))
         self.interval += 1
         if flip:
             self.A.cur ^= 1

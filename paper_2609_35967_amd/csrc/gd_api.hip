@@ -223,10 +223,13 @@ int32_t gd_collision_rates(const gd_problem* p, const gd_particles* s, const gd_
     return hip_ok("gd_collision_rates");
 }
 
-int32_t gd_sample_collisions(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
-                             const double* lam_i, uint64_t seed, uint64_t interval_index, int32_t* n_events,
-                             int32_t* log, int32_t log_cap, void* ws, size_t ws_bytes, void* stream)
+static int32_t sample_call(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
+                           const double* lam_i, uint64_t seed, uint64_t interval_index, int32_t* n_events,
+                           int32_t* log, int32_t log_cap, void* ws, size_t ws_bytes, void* stream, void* table,
+                           size_t table_bytes, int32_t slot, const char* what)
 {
+    if (table && (slot < 0 || slot >= max_table_slots() || table_bytes < sample_table_bytes(slot + 1)))
+        return fail(GD_E_INVALID_ARG, "%s: slot %d does not fit the table", what, slot);
     int rc = check_problem(p);
     if (!rc) rc = check_state(p, s, true);
     if (!rc) rc = check_nb(nb);
@@ -240,10 +243,64 @@ int32_t gd_sample_collisions(const gd_problem* p, const gd_particles* s, const g
     Layout L;
     rc = check_ws(p, ws, ws_bytes, L);
     if (rc) return rc;
-    if (p->n == 0) return GD_OK;
+    if (p->n == 0 && !table) return GD_OK;  // (a table slot is written even for no particles)
     launch_sample(p, s, nb, iv, lam_i, seed, on_device ? 0u : uint32_t(interval_index), on_device, n_events, log,
-                  log_cap, ws, L, static_cast<hipStream_t>(stream));
-    return hip_ok("gd_sample_collisions");
+                  log_cap, ws, L, static_cast<hipStream_t>(stream), table, slot);
+    return hip_ok(what);
+}
+
+int32_t gd_sample_collisions(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
+                             const double* lam_i, uint64_t seed, uint64_t interval_index, int32_t* n_events,
+                             int32_t* log, int32_t log_cap, void* ws, size_t ws_bytes, void* stream)
+{
+    return sample_call(p, s, nb, iv, lam_i, seed, interval_index, n_events, log, log_cap, ws, ws_bytes, stream,
+                       nullptr, 0, 0, "gd_sample_collisions");
+}
+
+int32_t gd_sample_table_size(int32_t nslot, size_t* bytes)
+{
+    if (!bytes) return fail(GD_E_INVALID_ARG, "bytes is NULL");
+    if (nslot < 1 || nslot > max_table_slots())
+        return fail(GD_E_INVALID_ARG, "nslot must be in [1, %d]", max_table_slots());
+    *bytes = sample_table_bytes(nslot);
+    return GD_OK;
+}
+
+int32_t gd_sample_collisions_deferred(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb,
+                                      gd_interval* iv, const double* lam_i, uint64_t seed, uint64_t interval_index,
+                                      int32_t* n_events, int32_t* log, int32_t log_cap, void* ws, size_t ws_bytes,
+                                      void* table, size_t table_bytes, int32_t slot, void* stream)
+{
+    if (!table) return fail(GD_E_INVALID_ARG, "table is NULL");
+    return sample_call(p, s, nb, iv, lam_i, seed, interval_index, n_events, log, log_cap, ws, ws_bytes, stream,
+                       table, table_bytes, slot, "gd_sample_collisions_deferred");
+}
+
+int32_t gd_sample_table_run(void* table, size_t table_bytes, int32_t nslot, int32_t k, int32_t rates_fp32,
+                            void* stream)
+{
+    if (!table) return fail(GD_E_INVALID_ARG, "table is NULL");
+    if (nslot < 1 || nslot > max_table_slots() || table_bytes < sample_table_bytes(nslot))
+        return fail(GD_E_INVALID_ARG, "nslot does not fit the table");
+    if (k < 1 || k > kMaxK) return fail(GD_E_INVALID_ARG, "k must be in [1, %d]", kMaxK);
+    if (rates_fp32 != 0 && rates_fp32 != 1) return fail(GD_E_INVALID_ARG, "rates_fp32 must be 0 or 1");
+    launch_sample_table(table, nslot, k, rates_fp32, static_cast<hipStream_t>(stream));
+    return hip_ok("gd_sample_table_run");
+}
+
+int32_t gd_sample_audit(const gd_problem* p, const gd_particles* s, gd_interval* iv, void* ws, size_t ws_bytes,
+                        void* stream)
+{
+    int rc = check_problem(p);
+    if (!rc) rc = check_state(p, s, true);
+    if (rc) return rc;
+    if (!iv) return fail(GD_E_INVALID_ARG, "interval is NULL");
+    Layout L;
+    rc = check_ws(p, ws, ws_bytes, L);
+    if (rc) return rc;
+    if (p->n == 0) return GD_OK;
+    launch_audit(p, s, iv, ws, L, static_cast<hipStream_t>(stream));
+    return hip_ok("gd_sample_audit");
 }
 
 int32_t gd_push(const gd_problem* p, const gd_particles* s, const gd_interval* iv, double dt, void* ws,

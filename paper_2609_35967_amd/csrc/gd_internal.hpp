@@ -30,7 +30,11 @@ int launch_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors*
                  double* lam_pair, double* ab, void* ws, const Layout& L, hipStream_t st);
 int launch_sample(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
                   const double* lam_i, uint64_t seed, uint32_t interval, bool interval_on_device, int32_t* n_events, int32_t* log,
-                  int32_t log_cap, void* ws, const Layout& L, hipStream_t st);
+                  int32_t log_cap, void* ws, const Layout& L, hipStream_t st, void* table, int32_t slot);
+int launch_audit(const gd_problem* p, const gd_particles* s, gd_interval* iv, void* ws, const Layout& L, hipStream_t st);
+size_t sample_table_bytes(int32_t nslot);
+int max_table_slots();
+int launch_sample_table(void* table, int32_t nslot, int32_t k, int32_t rates_fp32, hipStream_t st);
 int launch_push(const gd_problem* p, const gd_particles* s, const gd_interval* iv, double dt, void* ws,
                 const Layout& L, hipStream_t st);
 void launch_interval_init(gd_interval* iv, double dt_coll, hipStream_t st);

@@ -264,14 +264,114 @@ __device__ inline void pair_at(const McArgs& A, const QCtx& q, const QCtxF& qf, 
     }
 }
 
+// the rest of deferred particle `hidx` of the run described by A; returns the
+// events it adds
+template <int KP2, bool F32>
+__device__ inline int run_deferred(const McArgs& A, int32_t hidx, int lane)
+{
+    const bool phys = A.P.kernel == GD_KERNEL_PHYSICAL;
+    const double dt_exe = A.iv->dt_exe;
+    const uint32_t interval = A.interval_on_device ? uint32_t(A.iv->n_intervals) : A.interval;
+    const Deferred H = A.heavy[hidx];
+    const int64_t i = H.i;
+    int e = H.e;
+    double t = H.t, m = H.m;
+    const int k = A.P.k;
+    const int c = A.cnt[i];
+    const uint32_t pid = A.id[i];
+    QCtx q{};
+    QCtxF qf{};
+    query_ctx(A.P, A.x[i], A.y[i], A.z[i], A.dmax[i], q);
+    if (F32) query_ctx_f32(A.P, q, qf);
+    const bool mine = lane < c && lane < KP2;
+    int j = mine ? A.nbr[i * k + lane] : 0;
+    if (mine && (j < 0 || j >= A.P.n)) set_status(A.ws, GD_DEV_INTERNAL);
+    if (j < 0 || j >= A.P.n) j = 0;
+    const double4 sn = A.snap[j];
+    double si = 0.0, Sti = 0.0;
+    Pair o{};
+    double mypre = 0.0, li = 0.0;
+    auto rates = [&]() {
+        if (phys) {
+            si = grain_size(A.P, m);
+            Sti = F32 ? double(qf.stfac * float(si)) : q.stfac * si;
+        }
+        double lam = 0.0;
+        pair_at<F32>(A, q, qf, m, si, Sti, sn, phys, o, lam);
+        // lane s's rate read by every lane (a uniform lane index: two scalar reads)
+        const int lam_lo = __double2loint(lam), lam_hi = __double2hiint(lam);
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s < KP2; ++s) {
+            const double v = __hiloint2double(__builtin_amdgcn_readlane(lam_hi, s), __builtin_amdgcn_readlane(lam_lo, s));
+            if (s < c) acc = acc + v;
+            if (s == lane) mypre = acc;
+        }
+        li = acc;
+    };
+    rates();
+    // the draws of the coming event are made before the rates of the mass it
+    // finds are recomputed (they do not depend on them), so both overlap
+    double u[4];
+    event_uniforms(A.seed, pid, interval, uint32_t(e), u);
+    double lw = -log(u[0]);
+    for (;;) {
+        if (!(li > 0.0)) break;
+        if (e >= kEventCap) {
+            if (lane == 0) set_status(A.ws, GD_DEV_EVENT_CAP);
+            break;
+        }
+        const double dtw = lw / li;
+        if (dtw > dt_exe - t) break;
+        t = t + dtw;
+        const double target = u[1] * li;
+        const uint64_t hit = __ballot(lane < c - 1 && mypre > target);
+        const int sel = hit ? int(__ffsll((unsigned long long)hit)) - 1 : c - 1;
+        auto from = [&](double x) {
+            return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), sel),
+                                    __builtin_amdgcn_readlane(__double2loint(x), sel));
+        };
+        const int type = __builtin_amdgcn_readlane(o.type, sel);
+        const double r0 = from(o.r0);
+        const double lam_star = from(o.lam_star);
+        const double Ng = from(o.Ng);
+        const double mj = from(sn.x);
+        int ch = 0;
+        if (type == kErosion) ch = (r0 > u[2] * lam_star) ? 0 : 1;
+        double mnew;
+        if (type == kStick) {
+            mnew = m + Ng * mj;
+        } else if (type == kErosion) {
+            mnew = (ch == 0) ? m - Ng * mj : mj;
+        } else {
+            const double a = sqrt(A.P.s_min);
+            const double w = a + u[3] * (sqrt(si) - a);
+            const double sz = w * w;
+            mnew = kPi * A.P.rho_s * sz * sz * sz / 6.0;
+        }
+        if (A.log && lane == 0) {
+            if (e < A.log_cap) A.log[i * A.log_cap + e] = sel | (ch << 16) | (type << 24);
+            else set_status(A.ws, GD_DEV_LOG_OVERFLOW);
+        }
+        ++e;
+        event_uniforms(A.seed, pid, interval, uint32_t(e), u);
+        lw = -log(u[0]);
+        // (an unchanged mass recomputes the same rates: no branch around them)
+        m = mnew;
+        rates();
+    }
+    if (lane == 0) {
+        A.m_out[i] = m;
+        if (A.n_events) A.n_events[i] = e;
+    }
+    return e - H.e;
+}
+
 template <int KP2, bool F32>
 __global__ __launch_bounds__(256) void k_mc_heavy(McArgs A)
 {
     const int lane = threadIdx.x & 63;
     const int32_t nh = *A.heavy_n;
-    const bool phys = A.P.kernel == GD_KERNEL_PHYSICAL;
-    const double dt_exe = A.iv->dt_exe;
-    const uint32_t interval = A.interval_on_device ? uint32_t(A.iv->n_intervals) : A.interval;
     unsigned long long ev_total = 0;
     // wavefront w takes entry w first, then entries nw, nw + 1, ... from the
     // counter (a wavefront with no first entry touches no counter)
@@ -279,93 +379,77 @@ __global__ __launch_bounds__(256) void k_mc_heavy(McArgs A)
     int32_t hidx = int32_t(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
     for (;;) {
         if (hidx >= nh) break;
-        const Deferred H = A.heavy[hidx];
-        const int64_t i = H.i;
-        int e = H.e;
-        double t = H.t, m = H.m;
-        const int k = A.P.k;
-        const int c = A.cnt[i];
-        const uint32_t pid = A.id[i];
-        QCtx q{};
-        QCtxF qf{};
-        query_ctx(A.P, A.x[i], A.y[i], A.z[i], A.dmax[i], q);
-        if (F32) query_ctx_f32(A.P, q, qf);
-        const bool mine = lane < c && lane < KP2;
-        int j = mine ? A.nbr[i * k + lane] : 0;
-        if (mine && (j < 0 || j >= A.P.n)) set_status(A.ws, GD_DEV_INTERNAL);
-        if (j < 0 || j >= A.P.n) j = 0;
-        const double4 sn = A.snap[j];
-        double si = 0.0, Sti = 0.0;
-        Pair o{};
-        double mypre = 0.0, li = 0.0;
-        auto rates = [&]() {
-            if (phys) {
-                si = grain_size(A.P, m);
-                Sti = F32 ? double(qf.stfac * float(si)) : q.stfac * si;
-            }
-            double lam = 0.0;
-            pair_at<F32>(A, q, qf, m, si, Sti, sn, phys, o, lam);
-            double acc = 0.0;
-#pragma unroll
-            for (int s = 0; s < KP2; ++s) {
-                if (s < c) acc = acc + __shfl(lam, s, 64);
-                if (s == lane) mypre = acc;
-            }
-            li = acc;
-        };
-        rates();
-        for (;;) {
-            if (!(li > 0.0)) break;
-            if (e >= kEventCap) {
-                if (lane == 0) set_status(A.ws, GD_DEV_EVENT_CAP);
-                break;
-            }
-            double u[4];
-            event_uniforms(A.seed, pid, interval, uint32_t(e), u);
-            const double dtw = -log(u[0]) / li;
-            if (dtw > dt_exe - t) break;
-            t = t + dtw;
-            const double target = u[1] * li;
-            const uint64_t hit = __ballot(lane < c - 1 && mypre > target);
-            const int sel = hit ? int(__ffsll((unsigned long long)hit)) - 1 : c - 1;
-            const int type = __shfl(o.type, sel, 64);
-            const double r0 = __shfl(o.r0, sel, 64);
-            const double lam_star = __shfl(o.lam_star, sel, 64);
-            const double Ng = __shfl(o.Ng, sel, 64);
-            const double mj = __shfl(sn.x, sel, 64);
-            int ch = 0;
-            if (type == kErosion) ch = (r0 > u[2] * lam_star) ? 0 : 1;
-            double mnew;
-            if (type == kStick) {
-                mnew = m + Ng * mj;
-            } else if (type == kErosion) {
-                mnew = (ch == 0) ? m - Ng * mj : mj;
-            } else {
-                const double a = sqrt(A.P.s_min);
-                const double w = a + u[3] * (sqrt(si) - a);
-                const double sz = w * w;
-                mnew = kPi * A.P.rho_s * sz * sz * sz / 6.0;
-            }
-            if (A.log && lane == 0) {
-                if (e < A.log_cap) A.log[i * A.log_cap + e] = sel | (ch << 16) | (type << 24);
-                else set_status(A.ws, GD_DEV_LOG_OVERFLOW);
-            }
-            ++e;
-            if (mnew != m) {
-                m = mnew;
-                rates();
-            }
-        }
-        if (lane == 0) {
-            A.m_out[i] = m;
-            if (A.n_events) A.n_events[i] = e;
-            ev_total += (unsigned long long)(e - H.e);
-        }
+        ev_total += (unsigned long long)run_deferred<KP2, F32>(A, hidx, lane);
         int32_t next = 0;
         if (lane == 0) next = atomicAdd(A.heavy_next, 1);
         hidx = nw + __builtin_amdgcn_readfirstlane(next);
     }
     if (lane == 0 && ev_total) atomicAdd(A.ev_counter, ev_total);
+}
+
+// ---------------------------------------------------------------------------
+// Many runs: a table in device memory holds, per slot, the sampling arguments
+// of one run (written by its deferred call), after a 256-byte header whose
+// first word counts the entries taken.  One launch runs the deferred
+// particles of every slot: the global entry g is the slot's own entry
+// g - (deferred particles of the slots before it).
+constexpr size_t kTableHeader = 256;
+constexpr int kMaxTableSlots = 4096;
+
+__global__ void k_table_put(McArgs* dst, McArgs A)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = A;
+}
+
+template <int KP2, bool F32>
+__global__ __launch_bounds__(256) void k_mc_heavy_batch(char* table, int32_t nbox)
+{
+    __shared__ int32_t s_pre[kMaxTableSlots];
+    __shared__ int32_t s_total;
+    const McArgs* T = reinterpret_cast<const McArgs*>(table + kTableHeader);
+    int32_t* counter = reinterpret_cast<int32_t*>(table);
+    const int t = threadIdx.x, lane = t & 63;
+    for (int b = t; b < nbox; b += blockDim.x) s_pre[b] = *T[b].heavy_n;
+    __syncthreads();
+    if (t < kWave) {  // exclusive prefix of the slots' counts, 64 at a time
+        int32_t carry = 0;
+        for (int c0 = 0; c0 < nbox; c0 += kWave) {
+            const int32_t v = c0 + t < nbox ? s_pre[c0 + t] : 0;
+            int32_t x = v;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int32_t y = __shfl_up(x, o, kWave);
+                if (t >= o) x += y;
+            }
+            if (c0 + t < nbox) s_pre[c0 + t] = carry + x - v;
+            carry += __shfl(x, kWave - 1, kWave);
+        }
+        if (t == 0) s_total = carry;
+    }
+    __syncthreads();
+    const int32_t total = s_total;
+    const int32_t nw = int32_t(gridDim.x * (blockDim.x / kWave));
+    int32_t g = int32_t(blockIdx.x * (blockDim.x / kWave) + t / kWave);
+    for (;;) {
+        if (g >= total) break;
+        // the last slot whose prefix is <= g (slots with no entries share a prefix)
+        int lo = 0, hi = nbox - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_pre[mid] <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        const McArgs& A = T[lo];
+        if (A.P.k > KP2 || (A.P.rates_fp32 != 0) != F32) {
+            if (lane == 0) set_status(A.ws, GD_DEV_INTERNAL);
+        } else {
+            const int ev = run_deferred<KP2, F32>(A, g - s_pre[lo], lane);
+            if (lane == 0 && ev) atomicAdd(A.ev_counter, (unsigned long long)ev);
+        }
+        int32_t next = 0;
+        if (lane == 0) next = atomicAdd(counter, 1);
+        g = nw + __builtin_amdgcn_readfirstlane(next);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -452,15 +536,13 @@ void launch_interval_init(gd_interval* iv, double dt_coll, hipStream_t st)
     hipLaunchKernelGGL(k_interval_init, dim3(1), dim3(64), 0, st, iv, dt_coll);
 }
 
-int launch_sample(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
-                  const double* lam_i, uint64_t seed, uint32_t interval, bool interval_on_device, int32_t* n_events, int32_t* log,
-                  int32_t log_cap, void* ws, const Layout& L, hipStream_t st)
+static McArgs mc_args(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
+                      const double* lam_i, uint64_t seed, uint32_t interval, bool interval_on_device,
+                      int32_t* n_events, int32_t* log, int32_t log_cap, void* ws, const Layout& L)
 {
-    const DevProblem P = to_dev(p);
-    const int64_t n = p->n;
     WsHeader* h = at<WsHeader>(ws, L.hdr);
     McArgs A{};
-    A.P = P;
+    A.P = to_dev(p);
     A.id = s->id;
     A.nbr = nb->nbr;
     A.cnt = nb->cnt;
@@ -485,31 +567,80 @@ int launch_sample(const gd_problem* p, const gd_particles* s, const gd_neighbors
     A.heavy = at<Deferred>(ws, L.heavy);
     A.heavy_n = &h->heavy_n;
     A.heavy_next = &h->heavy_next;
-    const int g = int((n + 255) / 256);
-    prof_mark(GD_PROF_MC, 0, st);
+    return A;
+}
+
+static void launch_first(const McArgs& A, const gd_problem* p, hipStream_t st)
+{
+    const int g = int((p->n + 255) / 256);
     if (p->rates_fp32) {
-        if (p->k <= 32) {
-            hipLaunchKernelGGL((k_mc<32, true>), dim3(g), dim3(256), 0, st, A);
-            hipLaunchKernelGGL((k_mc_heavy<32, true>), dim3(kHeavyBlocks), dim3(256), 0, st, A);
-        } else {
-            hipLaunchKernelGGL((k_mc<64, true>), dim3(g), dim3(256), 0, st, A);
-            hipLaunchKernelGGL((k_mc_heavy<64, true>), dim3(kHeavyBlocks), dim3(256), 0, st, A);
-        }
+        if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, true>), dim3(g), dim3(256), 0, st, A);
+        else hipLaunchKernelGGL((k_mc<64, true>), dim3(g), dim3(256), 0, st, A);
     } else {
-        if (p->k <= 32) {
-            hipLaunchKernelGGL((k_mc<32, false>), dim3(g), dim3(256), 0, st, A);
-            hipLaunchKernelGGL((k_mc_heavy<32, false>), dim3(kHeavyBlocks), dim3(256), 0, st, A);
-        } else {
-            hipLaunchKernelGGL((k_mc<64, false>), dim3(g), dim3(256), 0, st, A);
-            hipLaunchKernelGGL((k_mc_heavy<64, false>), dim3(kHeavyBlocks), dim3(256), 0, st, A);
-        }
+        if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, false>), dim3(g), dim3(256), 0, st, A);
+        else hipLaunchKernelGGL((k_mc<64, false>), dim3(g), dim3(256), 0, st, A);
     }
-    prof_mark(GD_PROF_MC, 1, st);
+}
+
+static void launch_deferred(const McArgs& A, const gd_problem* p, hipStream_t st)
+{
+    if (p->rates_fp32) {
+        if (p->k <= 32) hipLaunchKernelGGL((k_mc_heavy<32, true>), dim3(kHeavyBlocks), dim3(256), 0, st, A);
+        else hipLaunchKernelGGL((k_mc_heavy<64, true>), dim3(kHeavyBlocks), dim3(256), 0, st, A);
+    } else {
+        if (p->k <= 32) hipLaunchKernelGGL((k_mc_heavy<32, false>), dim3(kHeavyBlocks), dim3(256), 0, st, A);
+        else hipLaunchKernelGGL((k_mc_heavy<64, false>), dim3(kHeavyBlocks), dim3(256), 0, st, A);
+    }
+}
+
+int launch_audit(const gd_problem* p, const gd_particles* s, gd_interval* iv, void* ws, const Layout& L, hipStream_t st)
+{
+    WsHeader* h = at<WsHeader>(ws, L.hdr);
     double* part = at<double>(ws, L.part);
     prof_mark(GD_PROF_AUDIT, 0, st);
-    launch_bin_reduce(1, A.m, s->M, A.m_out, nullptr, n, part, ws, st);
-    hipLaunchKernelGGL(k_audit, dim3(1), dim3(kAuditGroups * kNBin), 0, st, P, part, kRedBlocks, iv, h);
+    launch_bin_reduce(1, s->m[s->cur], s->M, s->m[s->cur ^ 1], nullptr, p->n, part, ws, st);
+    hipLaunchKernelGGL(k_audit, dim3(1), dim3(kAuditGroups * kNBin), 0, st, to_dev(p), part, kRedBlocks, iv, h);
     prof_mark(GD_PROF_AUDIT, 1, st);
+    return 0;
+}
+
+int launch_sample(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
+                  const double* lam_i, uint64_t seed, uint32_t interval, bool interval_on_device, int32_t* n_events, int32_t* log,
+                  int32_t log_cap, void* ws, const Layout& L, hipStream_t st, void* table, int32_t slot)
+{
+    const McArgs A = mc_args(p, s, nb, iv, lam_i, seed, interval, interval_on_device, n_events, log, log_cap, ws, L);
+    prof_mark(GD_PROF_MC, 0, st);
+    if (p->n > 0) launch_first(A, p, st);
+    if (table) {
+        // deferred particles are left to the launch over the whole table
+        McArgs* dst = reinterpret_cast<McArgs*>(static_cast<char*>(table) + kTableHeader) + slot;
+        hipLaunchKernelGGL(k_table_put, dim3(1), dim3(64), 0, st, dst, A);
+        prof_mark(GD_PROF_MC, 1, st);
+        return 0;
+    }
+    launch_deferred(A, p, st);
+    prof_mark(GD_PROF_MC, 1, st);
+    return launch_audit(p, s, iv, ws, L, st);
+}
+
+size_t sample_table_bytes(int32_t nslot)
+{
+    return kTableHeader + sizeof(McArgs) * size_t(nslot);
+}
+
+int max_table_slots() { return kMaxTableSlots; }
+
+int launch_sample_table(void* table, int32_t nslot, int32_t k, int32_t rates_fp32, hipStream_t st)
+{
+    launch_fill_i32(static_cast<int32_t*>(table), 1, 0, st);
+    char* tb = static_cast<char*>(table);
+    if (rates_fp32) {
+        if (k <= 32) hipLaunchKernelGGL((k_mc_heavy_batch<32, true>), dim3(kHeavyBlocks), dim3(256), 0, st, tb, nslot);
+        else hipLaunchKernelGGL((k_mc_heavy_batch<64, true>), dim3(kHeavyBlocks), dim3(256), 0, st, tb, nslot);
+    } else {
+        if (k <= 32) hipLaunchKernelGGL((k_mc_heavy_batch<32, false>), dim3(kHeavyBlocks), dim3(256), 0, st, tb, nslot);
+        else hipLaunchKernelGGL((k_mc_heavy_batch<64, false>), dim3(kHeavyBlocks), dim3(256), 0, st, tb, nslot);
+    }
     return 0;
 }
 

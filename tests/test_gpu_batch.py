@@ -85,3 +85,30 @@ def test_batch_plain_matches_alone():
     torch.cuda.synchronize()
     for b, e in enumerate(bb.engines):
         _same(_snap(e), ref[b][0], f"plain box {b}")
+
+
+def test_table_sampling_matches_alone():
+    # the three-call form (deferred pass per box, one table run, audits),
+    # eager on one stream, equals gd_sample_collisions per box
+    import ctypes as C
+    from paper_2609_35967_amd.binding import check
+    lib = load()
+    boxes = _boxes()[:4]
+    ref = _alone(boxes, 1)
+    engines = [Engine(p, s, seed=sd, device_interval=True) for p, s, sd in boxes]
+    sz = C.c_size_t()
+    check(lib.gd_sample_table_size(len(engines), C.byref(sz)))
+    table = torch.empty(sz.value, dtype=torch.uint8, device="cuda")
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for _ in range(2):
+        for b, e in enumerate(engines):
+            e.build_neighbors()
+            e.collision_rates()
+            e.sample_deferred(table.data_ptr(), sz.value, b)
+        check(lib.gd_sample_table_run(C.c_void_p(table.data_ptr()), sz.value, len(engines), 32, 0, stream))
+        for e in engines:
+            e.sample_audit()
+    torch.cuda.synchronize()
+    for b, e in enumerate(engines):
+        _same(_snap(e), ref[b][0], f"table box {b}")
+        assert e.status() == 0
