@@ -267,6 +267,106 @@ def batch_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def serve_bench(args):
+    """Served stream: disk-annulus runs (N log-uniform 2^12..2^20, alpha and
+    v_frag as the batched boxes, 50 intervals each) arrive as a Poisson
+    process at 20 runs/s for args.serve seconds and are served under a 200 GB
+    budget; then the same runs one after another in the plain single-run form."""
+    import torch
+    from paper_2609_35967_amd import Engine, load
+    from paper_2609_35967_amd.serve import Run, Server, latency_percentiles
+
+    load()
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(args.seed)
+    rate, intervals = 20.0, 50
+    t, arrivals = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > args.serve:
+            break
+        arrivals.append(t)
+    runs = []
+    for r, ta in enumerate(arrivals):
+        n = int(round(2.0 ** rng.uniform(12, 20)))
+        p = workloads.disk3d_params(n, alpha=10.0 ** rng.uniform(-4, -2), v_frag=100.0 * rng.uniform(1, 10))
+        runs.append(Run(rid=r, params=p, state=workloads.disk3d(args.seed * 1000 + r, n, params=p),
+                        seed=args.seed * 1000 + r, intervals=intervals, arrival=ta))
+    total = sum(len(r.state["x"]) for r in runs) * intervals
+    print(f"[bench] {len(runs)} runs, {total} particle-intervals; serving", file=sys.stderr, flush=True)
+    # warm the kernels outside the measurement
+    w = Engine(runs[0].params, runs[0].state, seed=0)
+    w.step()
+    torch.cuda.synchronize()
+    del w
+    srv = Server(budget_bytes=200e9, streams=args.streams, keep_results=False)
+    pending = list(runs)
+    t0 = time.perf_counter()
+    rounds = 0
+    while pending or not srv.idle():
+        now = time.perf_counter() - t0
+        while pending and pending[0].arrival <= now:
+            srv.submit(pending.pop(0))
+        srv.admit()
+        if srv.active:
+            srv.round()
+            rounds += 1
+        elif pending:
+            time.sleep(max(0.0, pending[0].arrival - (time.perf_counter() - t0)))
+    wall_s = time.perf_counter() - t0
+    p50, p99 = latency_percentiles(srv.finished)
+    print(f"[bench] served in {wall_s:.2f} s, {rounds} rounds; saturated pass", file=sys.stderr, flush=True)
+    # capacity: the same runs all submitted at once
+    sat = Server(budget_bytes=200e9, streams=args.streams, keep_results=False)
+    for r in runs:
+        r.done, r.latencies_ms, r.engine = 0, [], None
+        sat.submit(r)
+    torch.cuda.synchronize()
+    ts0 = time.perf_counter()
+    srounds = 0
+    while not sat.idle():
+        sat.admit()
+        sat.round()
+        srounds += 1
+    sat_s = time.perf_counter() - ts0
+    print(f"[bench] saturated {sat_s:.2f} s, {srounds} rounds; plain form", file=sys.stderr, flush=True)
+    # the same runs in the plain single-run form, one after another
+    plain_lat = []
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for r in runs:
+        e = Engine(r.params, r.state, seed=r.seed)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(intervals + 1)]
+        ev[0].record()
+        for s_ in range(intervals):
+            e.step()
+            ev[s_ + 1].record()
+        torch.cuda.synchronize()
+        plain_lat += [ev[i].elapsed_time(ev[i + 1]) for i in range(intervals)]
+        del e
+    plain_s = time.perf_counter() - tp0
+    out = dict(
+        metric="particle-intervals/s (kNN+rates+MC) at 1M; batched vs plain; p50/p99 latency",
+        value=round(total / wall_s, 1), unit="particle-intervals/s", n_gpus=1, steps=intervals, warmup=0,
+        ms_per_step=None, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload=f"served stream: {len(runs)} disk-annulus runs arriving at 20 runs/s over {args.serve} s "
+                             "(Poisson), N log-uniform 2^12..2^20, alpha log-uniform 1e-4..1e-2, v_frag uniform "
+                             f"1..10 m/s, {intervals} intervals each, 200 GB budget, k=32",
+                    n_runs=len(runs), particle_intervals=total,
+                    form=f"served: continuous batching, {args.streams} streams, one deferred-sampling launch per round"),
+        wall_s=round(wall_s, 3), rounds=rounds,
+        p50_ms=round(p50, 3), p99_ms=round(p99, 3),
+        plain=dict(value=round(total / plain_s, 1), wall_s=round(plain_s, 3),
+                   p50_ms=round(float(np.percentile(plain_lat, 50)), 3),
+                   p99_ms=round(float(np.percentile(plain_lat, 99)), 3),
+                   form="the same runs one after another, plain single-run form"),
+        saturated=dict(value=round(total / sat_s, 1), wall_s=round(sat_s, 3), rounds=srounds,
+                       form="the same runs all submitted at once"),
+        saturated_over_plain=round(plain_s / sat_s, 3),
+    )
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -285,15 +385,21 @@ def main():
                     help="the batched-boxes configuration instead: NBOX periodic local boxes "
                          "(N log-uniform 2^10..2^16), the plain per-box loop against the recorded graph")
     ap.add_argument("--streams", type=int, default=8, help="streams of the batched graph")
+    ap.add_argument("--serve", type=float, default=0.0, metavar="SECONDS",
+                    help="the served-stream configuration instead: Poisson arrivals (20 runs/s) of disk-annulus "
+                         "runs for SECONDS, served under a 200 GB budget, against the same runs one after another")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
-    if args.batch:
+    if args.batch or args.serve:
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        batch_bench(args)
+        if args.serve:
+            serve_bench(args)
+        else:
+            batch_bench(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs the single-GPU path only (asked for --gpus {args.gpus}); the multi-GPU "
