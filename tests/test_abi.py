@@ -89,6 +89,40 @@ def test_host_validation(lib):
     assert rc == -1 and b"interval_index" in lib.gd_last_error()
 
 
+def test_sample_table_validation(lib):
+    # the calls that share the deferred sampling pass between runs reject bad
+    # tables, slots and arguments before any launch
+    from paper_2609_35967_amd import binding
+    P = binding.make_problem(workloads.local_box_params(1000))
+    sz = C.c_size_t()
+    assert lib.gd_sample_table_size(0, C.byref(sz)) == -1
+    assert lib.gd_sample_table_size(4097, C.byref(sz)) == -1
+    assert lib.gd_sample_table_size(1, None) == -1
+    assert lib.gd_sample_table_size(8, C.byref(sz)) == 0
+    one = C.c_size_t()
+    assert lib.gd_sample_table_size(1, C.byref(one)) == 0
+    assert sz.value > one.value > 0
+    # a table run that does not fit its table, or with bad k / rates form
+    assert lib.gd_sample_table_run(None, sz.value, 8, 32, 0, None) == -1
+    assert lib.gd_sample_table_run(C.c_void_p(256), one.value, 8, 32, 0, None) == -1
+    assert lib.gd_sample_table_run(C.c_void_p(256), sz.value, 8, 65, 0, None) == -1
+    assert lib.gd_sample_table_run(C.c_void_p(256), sz.value, 8, 32, 2, None) == -1
+    fake = binding.GdParticles()
+    for k in ("id", "x", "y", "z", "M", "r", "th", "ph", "vr", "lth", "lph"):
+        setattr(fake, k, 256)
+    fake.m[0] = 256
+    fake.m[1] = 512
+    nb = binding.GdNeighbors(4096, 4096, 4096, None)
+    args = (C.byref(P), C.byref(fake), C.byref(nb), C.c_void_p(256), C.c_void_p(256), 1, 0, None, None, 0,
+            C.c_void_p(256), 1 << 40)
+    assert lib.gd_sample_collisions_deferred(*args, None, sz.value, 0, None) == -1
+    assert b"table" in lib.gd_last_error()
+    assert lib.gd_sample_collisions_deferred(*args, C.c_void_p(4096), sz.value, 8, None) == -1
+    assert b"slot" in lib.gd_last_error()
+    assert lib.gd_sample_collisions_deferred(*args, C.c_void_p(4096), sz.value, -1, None) == -1
+    assert lib.gd_sample_audit(C.byref(P), C.byref(fake), None, C.c_void_p(256), 1 << 40, None) == -1
+
+
 def test_problem_rmax_default_is_infinite():
     from paper_2609_35967_amd import binding
     assert math.isinf(binding.make_problem(workloads.const_box_params()).rmax)
