@@ -110,6 +110,9 @@ def lib():
             L.orc_gas_at.argtypes = [vp, d, d, vp]
             L.orc_oc07.argtypes = [d, d, d, d]
             L.orc_oc07.restype = d
+            L.orc_reshuffle_index.argtypes = [i64, C.c_uint64, C.c_uint32, i64]
+            L.orc_reshuffle_index.restype = i64
+            L.orc_reshuffle.argtypes = [i64, C.c_int32, vp, vp, i64, C.c_uint64, C.c_uint32]
             L.orc_fsum.argtypes = [i64, vp]
             L.orc_fsum.restype = d
             L.orc_num_threads.restype = C.c_int
@@ -275,6 +278,19 @@ def gas_at(P: Problem, R, Z):
 
 def oc07(St1, St2, Vg2, tke):
     return lib().orc_oc07(St1, St2, Vg2, tke)
+
+
+def reshuffle_index(N: int, seed: int, refresh: int, j: int) -> int:
+    """pi(j) for the random bijection of [0, N) drawn for `refresh` (product-kernel test)."""
+    return int(lib().orc_reshuffle_index(N, C.c_uint64(seed), refresh, j))
+
+
+def reshuffle(nbr, cnt, N: int, seed: int, refresh: int):
+    """Cached neighbour rows with every index but slot 0 relabelled by pi."""
+    nb = _c(nbr, np.int32).copy()
+    n, k = nb.shape
+    lib().orc_reshuffle(n, k, _p(nb), _p(_c(cnt, np.int32)), N, C.c_uint64(seed), refresh)
+    return nb
 
 
 def fsum(v):

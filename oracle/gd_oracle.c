@@ -26,6 +26,8 @@
  *   orc_push_local      drift-kick-drift vertical settling, local column
  *   orc_push_global     staggered semi-analytic push in spherical coords (Sect. 2.3.3)
  *   orc_fsum            exactly rounded sum (used for all reductions)
+ *   orc_reshuffle       random relabelling of the cached neighbours before a
+ *                       refresh (product-kernel test, Sect. 3.3)
  *
  * Readings of passages the paper leaves open are listed where they are used
  * and collected in the design notes of the repository.
@@ -1026,4 +1028,56 @@ void orc_set_threads(int nt)
 #else
     (void)nt;
 #endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neighbour reshuffling of the product-kernel test (Sect. 3.3): before every */
+/* refresh the cached neighbour indices of all particles are permuted at     */
+/* random, so that the frozen neighbourhoods sample a well-mixed population.  */
+/* Reading: slot 0 (the particle itself) is kept; every other cached index j  */
+/* becomes pi(j) for one random bijection pi of the N active slots drawn per  */
+/* refresh.  pi: a balanced Feistel network (Luby and Rackoff 1988) of four   */
+/* rounds on 2h bits, 4^h >= N, the round function being word 0 of Philox     */
+/* with counter (right half, round, refresh, 0x52534831) and key = seed,      */
+/* restricted to [0, N) by cycle walking (Black and Rogaway 2002): apply the  */
+/* network until the value falls below N.                                     */
+/* ------------------------------------------------------------------------ */
+static uint32_t orc_feistel(uint32_t x, int h, uint64_t seed, uint32_t refresh)
+{
+    const uint32_t mask = (h >= 32) ? 0xFFFFFFFFu : ((1u << h) - 1u);
+    uint32_t L = x >> h, R = x & mask;
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    for (uint32_t t = 0; t < 4; t++) {
+        uint32_t c[4] = { R, t, refresh, 0x52534831u }, o[4];
+        orc_philox4x32_10(c, key, o);
+        uint32_t nL = R;
+        uint32_t nR = L ^ (o[0] & mask);
+        L = nL;
+        R = nR;
+    }
+    return (L << h) | R;
+}
+
+int64_t orc_reshuffle_index(int64_t N, uint64_t seed, uint32_t refresh, int64_t j)
+{
+    if (N <= 1) return j;
+    int bits = 0;
+    while ((1LL << bits) < N) bits++;      /* 2^bits >= N */
+    int h = (bits + 1) / 2;                /* 4^h >= N */
+    uint32_t x = (uint32_t)j;
+    do {
+        x = orc_feistel(x, h, seed, refresh);
+    } while ((int64_t)x >= N);
+    return (int64_t)x;
+}
+
+void orc_reshuffle(int64_t n, int32_t k, int32_t* nbr, const int32_t* cnt, int64_t N, uint64_t seed,
+                   uint32_t refresh)
+{
+    for (int64_t i = 0; i < n; i++) {
+        for (int32_t s = 1; s < cnt[i] && s < k; s++) {
+            int32_t* e = &nbr[i * k + s];
+            if (*e >= 0 && *e < N) *e = (int32_t)orc_reshuffle_index(N, seed, refresh, *e);
+        }
+    }
 }
