@@ -205,6 +205,20 @@ int32_t gd_collision_rates(const gd_problem* p, const gd_particles* st, const gd
  * fresh numbers on every replay. */
 #define GD_INTERVAL_ON_DEVICE UINT64_MAX
 
+/* Neighbour reshuffling of the product-kernel test (Sect. 3.3): before a
+ * refresh of the frozen neighbourhoods, the cached neighbour indices of all
+ * particles are permuted at random so that they sample a well-mixed
+ * population.  Every entry nbr[i*k + s] with 1 <= s < cnt[i] and an index in
+ * [0, N), N = *nb->n_active (read on the device), becomes pi(index); slot 0
+ * (the particle itself), cnt, dmax and the rest of each row are kept.  pi is
+ * one random bijection of [0, N) per (seed, refresh): a four-round balanced
+ * Feistel network on two h-bit halves (4^h >= N) with round function word 0
+ * of Philox4x32-10, counter (right half, round, refresh, 0x52534831), key =
+ * seed, restricted to [0, N) by cycle walking.  In place on the caller's
+ * stream. */
+int32_t gd_reshuffle_neighbors(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh,
+                               void* stream);
+
 /* Sampling over many independent runs (boxes) at once.  gd_sample_collisions
  * is, in order: the per-lane pass (each particle's first events; a particle
  * with more is recorded in the workspace at that event boundary), the pass

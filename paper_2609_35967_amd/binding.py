@@ -60,7 +60,8 @@ class GdInterval(C.Structure):
 
 EXPORTS = ("gd_workspace_size", "gd_workspace_init", "gd_interval_init", "gd_build_neighbors", "gd_collision_rates",
            "gd_sample_collisions", "gd_push", "gd_profile_events", "gd_status_read", "gd_last_error", "gd_version",
-           "gd_sample_table_size", "gd_sample_collisions_deferred", "gd_sample_table_run", "gd_sample_audit")
+           "gd_sample_table_size", "gd_sample_collisions_deferred", "gd_sample_table_run", "gd_sample_audit",
+           "gd_reshuffle_neighbors")
 PROF = {"sort": 0, "tree": 1, "knn_query": 2, "rates": 3, "mc": 4, "audit": 5, "push": 6}
 GD_INTERVAL_ON_DEVICE = (1 << 64) - 1
 
@@ -98,13 +99,15 @@ def load(path: str | None = None):
                                                 vp, C.c_size_t, C.c_int32, vp]
     L.gd_sample_table_run.argtypes = [vp, C.c_size_t, C.c_int32, C.c_int32, C.c_int32, vp]
     L.gd_sample_audit.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), vp, vp, C.c_size_t, vp]
+    L.gd_reshuffle_neighbors.argtypes = [C.POINTER(GdProblem), C.POINTER(GdNeighbors), C.c_uint64, C.c_uint32, vp]
     L.gd_status_read.argtypes = [vp, vp, C.POINTER(C.c_int32)]
     L.gd_profile_events.argtypes = [C.c_int32, vp, vp]
     L.gd_last_error.restype = C.c_char_p
     L.gd_version.restype = C.c_char_p
     for name in ("gd_workspace_size", "gd_workspace_init", "gd_interval_init", "gd_build_neighbors", "gd_collision_rates",
                  "gd_sample_collisions", "gd_push", "gd_status_read", "gd_profile_events", "gd_sample_table_size",
-                 "gd_sample_collisions_deferred", "gd_sample_table_run", "gd_sample_audit"):
+                 "gd_sample_collisions_deferred", "gd_sample_table_run", "gd_sample_audit",
+                 "gd_reshuffle_neighbors"):
         getattr(L, name).restype = C.c_int32
     if path is None:
         _lib = L
@@ -263,6 +266,10 @@ class Engine:
         self.interval += 1
         if flip:
             self.A.cur ^= 1
+
+    def reshuffle_neighbors(self, refresh: int):
+        """Random relabelling of the cached neighbours (product-kernel test), in place."""
+        check(self.lib.gd_reshuffle_neighbors(C.byref(self.P), C.byref(self.nb), self.seed, int(refresh), self._s()))
 
     def sample_deferred(self, table, table_bytes: int, slot: int):
         """The per-lane pass of sampling; the run's arguments go to table slot `slot`

@@ -257,6 +257,17 @@ int32_t gd_sample_collisions(const gd_problem* p, const gd_particles* s, const g
                        nullptr, 0, 0, "gd_sample_collisions");
 }
 
+int32_t gd_reshuffle_neighbors(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh,
+                               void* stream)
+{
+    int rc = check_problem(p);
+    if (!rc) rc = check_nb(nb);
+    if (rc) return rc;
+    if (!nb->n_active) return fail(GD_E_INVALID_ARG, "neighbours: n_active is NULL");
+    launch_reshuffle(p, nb, seed, refresh, static_cast<hipStream_t>(stream));
+    return hip_ok("gd_reshuffle_neighbors");
+}
+
 int32_t gd_sample_table_size(int32_t nslot, size_t* bytes)
 {
     if (!bytes) return fail(GD_E_INVALID_ARG, "bytes is NULL");

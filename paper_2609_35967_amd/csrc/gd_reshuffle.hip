@@ -1,0 +1,68 @@
+// gd_reshuffle.hip -- random relabelling of the cached neighbours before a
+// refresh, as the product-kernel test does (Sect. 3.3): the frozen
+// neighbourhoods then sample a well-mixed population.
+//
+// Slot 0 (the particle itself) is kept.  Every other cached index j becomes
+// pi(j), pi one random bijection of the N active slots per (seed, refresh):
+// a balanced Feistel network (Luby and Rackoff) of four rounds on two h-bit
+// halves, 4^h >= N, whose round function is word 0 of Philox4x32-10 with
+// counter (right half, round, refresh, 0x52534831) and the seed as key,
+// restricted to [0, N) by cycle walking (Black and Rogaway): the network is
+// applied until the value falls below N.  A walk stays on the cycle of the
+// network's permutation through j, so it ends within 4^h <= 4N steps.
+#include "gd_common.hpp"
+#include "gd_internal.hpp"
+
+namespace gd {
+
+__device__ inline uint32_t feistel4(uint32_t x, int h, uint32_t mask, uint32_t k0, uint32_t k1, uint32_t refresh)
+{
+    uint32_t L = x >> h, R = x & mask;
+#pragma unroll
+    for (uint32_t t = 0; t < 4; ++t) {
+        uint32_t c[4] = {R, t, refresh, 0x52534831u};
+        philox4x32_10(c, k0, k1);
+        const uint32_t nR = L ^ (c[0] & mask);
+        L = R;
+        R = nR;
+    }
+    return (L << h) | R;
+}
+
+// one thread per (particle, slot); slots 1 .. cnt-1 of active rows
+__global__ __launch_bounds__(256) void k_reshuffle(int32_t* __restrict__ nbr, const int32_t* __restrict__ cnt,
+                                                   const int32_t* __restrict__ n_active, int64_t n, int32_t k,
+                                                   uint64_t seed, uint32_t refresh)
+{
+    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (e >= n * k) return;
+    const int64_t i = e / k;
+    const int s = int(e - i * k);
+    const int64_t N = *n_active;
+    if (s == 0 || s >= cnt[i] || N <= 1) return;
+    const int32_t j = nbr[e];
+    if (j < 0 || j >= N) return;
+    int bits = 0;
+    while ((int64_t(1) << bits) < N) ++bits;
+    const int h = (bits + 1) >> 1;
+    const uint32_t mask = (1u << h) - 1u;
+    const uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
+    const int64_t cap = int64_t(1) << (2 * h);  // the network's domain: a walk is shorter
+    uint32_t x = uint32_t(j);
+    for (int64_t step = 0; step < cap; ++step) {
+        x = feistel4(x, h, mask, k0, k1, refresh);
+        if (int64_t(x) < N) break;
+    }
+    nbr[e] = int32_t(x);
+}
+
+int launch_reshuffle(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh, hipStream_t st)
+{
+    const int64_t total = p->n * int64_t(p->k);
+    if (total <= 0) return 0;
+    hipLaunchKernelGGL(k_reshuffle, dim3(unsigned((total + 255) / 256)), dim3(256), 0, st, nb->nbr, nb->cnt,
+                       nb->n_active, p->n, p->k, seed, refresh);
+    return 0;
+}
+
+}  // namespace gd

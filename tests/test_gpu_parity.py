@@ -145,6 +145,32 @@ def test_build_neighbors_sizes(n):
     _knn_compare(eng, params, got)
 
 
+@pytest.mark.parametrize("n", [1, 3, 1000, 4099])
+def test_reshuffle_neighbors(n):
+    # the product-kernel test's relabelling of the cached neighbours, then the
+    # product-kernel rates over the relabelled rows
+    params = dict(workloads.const_box_params(4096), kernel="product")
+    st = _perturb_inactive(workloads.const_box(40 + n, n), 9) if n > 10 else workloads.const_box(40 + n, n)
+    _say("reshuffle", n)
+    eng = _engine(params, st, seed=77)
+    eng.build_neighbors()
+    torch.cuda.synchronize()
+    before, cnt = eng.nbr.cpu().numpy(), eng.cnt.cpu().numpy()
+    N = int(eng.n_active.item())
+    eng.reshuffle_neighbors(5)
+    torch.cuda.synchronize()
+    after = eng.nbr.cpu().numpy()
+    assert np.array_equal(after, oracle.reshuffle(before, cnt, N, 77, 5))
+    assert np.array_equal(after[:, 0], before[:, 0])
+    eng.collision_rates()
+    torch.cuda.synchronize()
+    got = eng.state_numpy()
+    P = oracle.make_problem(params)
+    lam_o, _, _, _ = oracle.rates(P, after, cnt, eng.dmax.cpu().numpy(), got["m"], got["M"], got["x"], got["y"],
+                                  got["z"])
+    assert np.array_equal(eng.lam.cpu().numpy(), lam_o)
+
+
 @pytest.mark.parametrize("hint", ["previous", 0.0, 1e-300, 1e300, 1e17, float("nan"), -1.0, "mixed"])
 def test_build_neighbors_search_hint(hint):
     # the previous distances are read back as a search hint; the result must
