@@ -30,6 +30,7 @@ _lock = threading.Lock()
 _lib = None
 
 KERNELS = {"const": 0, "additive": 1, "product": 2, "physical": 3}
+DIFFUSION = {"none": 0, "concentration": 1, "density": 2}
 NBIN = 128
 
 
@@ -56,6 +57,8 @@ class Problem(C.Structure):
         ("sigma_H2", C.c_double), ("s0", C.c_double), ("St0", C.c_double),
         ("r_in", C.c_double), ("r_out", C.c_double),
         ("drag", C.c_int32), ("brownian", C.c_int32), ("turbulence", C.c_int32), ("caps", C.c_int32),
+        ("diffusion", C.c_int32), ("vint", C.c_int32), ("axisym", C.c_int32), ("pad_", C.c_int32),
+        ("Sc", C.c_double * 3), ("St_diff", C.c_double),
     ]
 
 
@@ -76,8 +79,13 @@ def make_problem(cfg: dict) -> Problem:
     for name in ("t0", "m0", "eps", "dt_fn_max", "rho_s", "s_min", "v_frag", "GM", "Sigma_g0", "R0",
                  "p", "q", "h_g0", "alpha", "mu_mH", "sigma_H2", "s0", "St0", "r_in", "r_out"):
         setattr(P, name, float(cfg.get(name, 0.0)))
-    for name in ("drag", "brownian", "turbulence", "caps"):
+    for name in ("drag", "brownian", "turbulence", "caps", "vint", "axisym"):
         setattr(P, name, int(cfg.get(name, 0)))
+    P.diffusion = DIFFUSION[cfg.get("diffusion", "none")]
+    Sc = cfg.get("Sc", (1.0, 1.0, 1.0))
+    for a in range(3):
+        P.Sc[a] = float(Sc[a])
+    P.St_diff = float(cfg.get("St_diff", 0.0))
     return P
 
 
@@ -113,6 +121,10 @@ def lib():
             L.orc_reshuffle_index.argtypes = [i64, C.c_uint64, C.c_uint32, i64]
             L.orc_reshuffle_index.restype = i64
             L.orc_reshuffle.argtypes = [i64, C.c_int32, vp, vp, i64, C.c_uint64, C.c_uint32]
+            L.orc_diff_coeffs.argtypes = [vp, d, d, d, vp]
+            L.orc_diff_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, vp]
+            L.orc_diffuse.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, d, C.c_uint64,
+                                      C.c_uint32]
             L.orc_fsum.argtypes = [i64, vp]
             L.orc_fsum.restype = d
             L.orc_num_threads.restype = C.c_int
@@ -291,6 +303,32 @@ def reshuffle(nbr, cnt, N: int, seed: int, refresh: int):
     n, k = nb.shape
     lib().orc_reshuffle(n, k, _p(nb), _p(_c(cnt, np.int32)), N, C.c_uint64(seed), refresh)
     return nb
+
+
+def diff_coeffs(P: Problem, R, Z, s):
+    """Diffusion coefficients at cylindrical (R, Z) for grain diameter s:
+    D_R, D_Z, D_phi, dD_R/dR, dD_Z/dZ, dln rho_g/dR, dln rho_g/dZ, ln rho_g."""
+    out = np.zeros(8)
+    lib().orc_diff_coeffs(C.byref(P), float(R), float(Z), float(s), _p(out))
+    keys = ("D_R", "D_Z", "D_phi", "dDR_dR", "dDZ_dZ", "dlnrho_dR", "dlnrho_dZ", "lnrho")
+    return dict(zip(keys, out))
+
+
+def diff_normals(seed: int, pid: int, step: int):
+    out = np.zeros(3)
+    lib().orc_diff_normals(C.c_uint64(seed), pid, step, _p(out))
+    return out
+
+
+def diffuse(P: Problem, st: dict, dt: float, seed: int, step: int) -> dict:
+    """One diffusion step (Sect. 2.4) on a copy of the spherical state dict
+    (keys id, r, th, ph, vr, lth, lph, m, M, x, y, z)."""
+    s = {k: np.array(st[k], np.float64) for k in ("r", "th", "ph", "vr", "lth", "lph", "m", "M", "x", "y", "z")}
+    s["id"] = _c(st["id"], np.uint32)
+    lib().orc_diffuse(C.byref(P), len(s["r"]), _p(s["id"]), _p(s["r"]), _p(s["th"]), _p(s["ph"]), _p(s["vr"]),
+                      _p(s["lth"]), _p(s["lph"]), _p(s["m"]), _p(s["M"]), _p(s["x"]), _p(s["y"]), _p(s["z"]),
+                      float(dt), C.c_uint64(seed), step)
+    return s
 
 
 def fsum(v):

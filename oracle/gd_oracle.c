@@ -25,6 +25,7 @@
  *   orc_audit           post-interval audit of the safety factor C
  *   orc_push_local      drift-kick-drift vertical settling, local column
  *   orc_push_global     staggered semi-analytic push in spherical coords (Sect. 2.3.3)
+ *   orc_diffuse         Euler--Maruyama dust diffusion step (Sect. 2.4)
  *   orc_fsum            exactly rounded sum (used for all reductions)
  *   orc_reshuffle       random relabelling of the cached neighbours before a
  *                       refresh (product-kernel test, Sect. 3.3)
@@ -81,6 +82,13 @@ typedef struct {
     int32_t brownian;    /* 1: Brownian term in Delta v */
     int32_t turbulence;  /* 1: turbulent term in Delta v */
     int32_t caps;        /* 1: boundary caps subtracted from V_i */
+    /* dust diffusion (Sect. 2.4) */
+    int32_t diffusion;   /* 0 off, 1 concentration form (chi = 1), 2 density form (chi = 0) */
+    int32_t vint;        /* 1: vertically integrated model (Sigma_g for rho_g, midplane St, no Z step) */
+    int32_t axisym;      /* 1: axisymmetric model (no azimuthal step) */
+    int32_t pad_;
+    double Sc[3];        /* Schmidt numbers of the R, Z and phi directions */
+    double St_diff;      /* > 0: spatially constant Stokes number in D (ring test, Sect. 3.2) */
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -981,6 +989,161 @@ void orc_push_global(const orc_problem* P, int64_t n, double* r, double* th, dou
         y[i] = ri * st * sin(pi_);
         z[i] = ri * cos(ti);
         if (ri < P->r_in || ri > P->r_out) M[i] = 0.0;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dust diffusion (Sect. 2.4).  Diagonal tensor in the cylindrical basis,   */
+/* D_a = nu / (Sc_a (1 + St^2)) with nu = alpha c_s H_g (Sect. 2.2), and    */
+/* one Euler--Maruyama step per call:                                        */
+/*   dR   = sqrt(2 D_R dt) z_R + (D_R/R + dD_R/dR + chi D_R dln rho_g/dR) dt */
+/*   dZ   = sqrt(2 D_Z dt) z_Z + (dD_Z/dZ + chi D_Z dln rho_g/dZ) dt        */
+/*   dphi = sqrt(2 D_phi dt) z_phi / R                                      */
+/* (the azimuthal gradients vanish for the axisymmetric gas disk).  A       */
+/* vertically integrated model takes Sigma_g for rho_g, the midplane Stokes */
+/* number and no vertical step; an axisymmetric one no azimuthal step.      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double D[3];        /* D_R, D_Z, D_phi */
+    double dDR_dR;      /* dD_R/dR */
+    double dDZ_dZ;      /* dD_Z/dZ */
+    double dlnrho[2];   /* d ln rho_g / dR, d ln rho_g / dZ (Sigma_g when vint) */
+    double lnrho;       /* ln rho_g (ln Sigma_g when vint), for the tests */
+} orc_diffco;
+
+/* Coefficients at cylindrical (R, Z) for a grain of diameter s.
+ * With x = R/R0: h_g^2 = h_g0^2 x^(q+1), so nu = alpha h_g^2 R^2 Omega_K is
+ * proportional to R^(q + 3/2) and independent of Z.  With w = 1 - R/r,
+ * St = St0 (s/s0) x^-p exp(w/h_g^2) and rho_g = Sigma_g/(sqrt(2 pi) H_g) exp(-w/h_g^2):
+ *   d(w/h^2)/dR = (-Z^2/r^3 - w (q+1)/R)/h^2,   d(w/h^2)/dZ = R Z/(r^3 h^2),
+ *   dSt/dR = St (-p/R + d(w/h^2)/dR),           dSt/dZ = St d(w/h^2)/dZ,
+ *   dln rho_g/dR = (p - (q+3)/2)/R - d(w/h^2)/dR,  dln rho_g/dZ = -d(w/h^2)/dZ,
+ * and in a vertically integrated model ln Sigma_g has dR-derivative p/R.
+ * D_a derivatives by the quotient rule on nu/(Sc (1 + St^2)). */
+static void diff_coeffs(const orc_problem* P, double R, double Z, double s, orc_diffco* c)
+{
+    double Zg = P->vint ? 0.0 : Z;
+    orc_gas g;
+    gas_at(P, R, Zg, &g);
+    double nu = P->alpha * g.cs * g.Hg;
+    double dnu_dR = nu * (P->q + 1.5) / R;
+    double hg2 = g.hg * g.hg;
+    double r = g.r;
+    double w = 1.0 - R / r;
+    double gR = (-(Zg * Zg) / (r * r * r) - w * (P->q + 1.0) / R) / hg2;
+    double gZ = R * Zg / (r * r * r * hg2);
+    double St, dSt_dR, dSt_dZ;
+    if (P->St_diff > 0.0) {
+        St = P->St_diff;
+        dSt_dR = 0.0;
+        dSt_dZ = 0.0;
+    } else {
+        St = g.stfac * s;
+        dSt_dR = St * (-P->p / R + gR);
+        dSt_dZ = St * gZ;
+    }
+    double den = 1.0 + St * St;
+    for (int a = 0; a < 3; a++) c->D[a] = nu / (P->Sc[a] * den);
+    /* d/dx [nu/(Sc (1 + St^2))] = [nu' (1 + St^2) - nu 2 St St'] / (Sc (1 + St^2)^2) */
+    c->dDR_dR = (dnu_dR * den - nu * 2.0 * St * dSt_dR) / (P->Sc[0] * den * den);
+    c->dDZ_dZ = -(nu * 2.0 * St * dSt_dZ) / (P->Sc[1] * den * den);   /* nu is independent of Z */
+    if (P->vint) {
+        c->dlnrho[0] = P->p / R;
+        c->dlnrho[1] = 0.0;
+        c->lnrho = log(P->Sigma_g0 * pow(R / P->R0, P->p));
+    } else {
+        c->dlnrho[0] = (P->p - 0.5 * (P->q + 3.0)) / R - gR;
+        c->dlnrho[1] = -gZ;
+        c->lnrho = log(g.rhog);
+    }
+}
+
+void orc_diff_coeffs(const orc_problem* P, double R, double Z, double s, double* out)
+{
+    orc_diffco c;
+    diff_coeffs(P, R, Z, s, &c);
+    out[0] = c.D[0]; out[1] = c.D[1]; out[2] = c.D[2];
+    out[3] = c.dDR_dR; out[4] = c.dDZ_dZ;
+    out[5] = c.dlnrho[0]; out[6] = c.dlnrho[1]; out[7] = c.lnrho;
+}
+
+/* Three standard normals of particle `id` in diffusion step `step`: two     */
+/* generator calls with counters (id, step, 0x44494646, w), w = 0, 1, key =  */
+/* the seed words; each call gives u1 = (a + 1) 2^-53 in (0, 1] and          */
+/* u2 = b 2^-53 in [0, 1), and the Box--Muller transform (Box & Muller 1958) */
+/* sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2).  z_R, z_Z are the first pair,  */
+/* z_phi the cosine of the second.                                           */
+void orc_diff_normals(uint64_t seed, uint32_t id, uint32_t step, double zeta[3])
+{
+    const double two53 = 1.0 / 9007199254740992.0;
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    double pair[4];
+    for (uint32_t w = 0; w < 2; w++) {
+        uint32_t c[4] = { id, step, 0x44494646u, w }, o[4];
+        orc_philox4x32_10(c, key, o);
+        uint64_t a = ((((uint64_t)o[1]) << 32) | o[0]) >> 11;
+        uint64_t b = ((((uint64_t)o[3]) << 32) | o[2]) >> 11;
+        double u1 = (double)(a + 1) * two53;
+        double u2 = (double)b * two53;
+        double rad = sqrt(-2.0 * log(u1));
+        pair[2 * w] = rad * cos(2.0 * ORC_PI * u2);
+        pair[2 * w + 1] = rad * sin(2.0 * ORC_PI * u2);
+    }
+    zeta[0] = pair[0];
+    zeta[1] = pair[1];
+    zeta[2] = pair[2];
+}
+
+/* One diffusion step of length dt on the spherical state.  The Cartesian    */
+/* velocity is kept: it is formed at the old position and projected on the   */
+/* spherical basis at the new one (v_r, l_theta = r v_theta,                 */
+/* l_phi = R v_phi).  A radial step past the axis (R' < 0) is the same       */
+/* Cartesian displacement: R' -> -R', phi' -> phi' + pi.  Particles leaving  */
+/* r_in <= r <= r_out are deactivated (M = 0), as in the push.               */
+void orc_diffuse(const orc_problem* P, int64_t n, const uint32_t* id, double* r, double* th, double* ph,
+                 double* vr, double* lth, double* lph, const double* m, double* M,
+                 double* x, double* y, double* z, double dt, uint64_t seed, uint32_t step)
+{
+    double chi = P->diffusion == 1 ? 1.0 : 0.0;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        if (!(M[i] > 0.0)) continue;
+        double r0 = r[i], t0 = th[i], p0 = ph[i];
+        double R = r0 * sin(t0), Z = r0 * cos(t0);
+        double s = P->St_diff > 0.0 ? 0.0 : grain_size(P, m[i]);
+        orc_diffco c;
+        diff_coeffs(P, R, Z, s, &c);
+        double zeta[3];
+        orc_diff_normals(seed, id[i], step, zeta);
+        double dR = sqrt(2.0 * c.D[0] * dt) * zeta[0]
+                  + (c.D[0] / R + c.dDR_dR + chi * c.D[0] * c.dlnrho[0]) * dt;
+        double dZ = 0.0, dphi = 0.0;
+        if (!P->vint)
+            dZ = sqrt(2.0 * c.D[1] * dt) * zeta[1] + (c.dDZ_dZ + chi * c.D[1] * c.dlnrho[1]) * dt;
+        if (!P->axisym)
+            dphi = sqrt(2.0 * c.D[2] * dt) * zeta[2] / R;
+        /* Cartesian velocity at the old position */
+        double st0 = sin(t0), ct0 = cos(t0), sp0 = sin(p0), cp0 = cos(p0);
+        double v_r = vr[i], v_t = lth[i] / r0, v_p = lph[i] / R;
+        double vx = v_r * st0 * cp0 + v_t * ct0 * cp0 - v_p * sp0;
+        double vy = v_r * st0 * sp0 + v_t * ct0 * sp0 + v_p * cp0;
+        double vz = v_r * ct0 - v_t * st0;
+        /* new position */
+        double R1 = R + dR, Z1 = Z + dZ, p1 = p0 + dphi;
+        if (R1 < 0.0) { R1 = -R1; p1 = p1 + ORC_PI; }
+        double r1 = sqrt(R1 * R1 + Z1 * Z1);
+        double t1 = atan2(R1, Z1);
+        double st1 = sin(t1), ct1 = cos(t1), sp1 = sin(p1), cp1 = cos(p1);
+        /* projections on the new basis */
+        double nvr = vx * st1 * cp1 + vy * st1 * sp1 + vz * ct1;
+        double nvt = vx * ct1 * cp1 + vy * ct1 * sp1 - vz * st1;
+        double nvp = -vx * sp1 + vy * cp1;
+        r[i] = r1; th[i] = t1; ph[i] = p1;
+        vr[i] = nvr; lth[i] = r1 * nvt; lph[i] = R1 * nvp;
+        x[i] = R1 * cp1;
+        y[i] = R1 * sp1;
+        z[i] = Z1;
+        if (r1 < P->r_in || r1 > P->r_out) M[i] = 0.0;
     }
 }
 
