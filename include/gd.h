@@ -74,6 +74,12 @@ typedef enum gd_push_kind {
     GD_PUSH_GLOBAL = 2       /* spherical staggered semi-analytic push (Sect. 2.3.3) */
 } gd_push_kind;
 
+typedef enum gd_diffusion_form {
+    GD_DIFFUSION_NONE = 0,
+    GD_DIFFUSION_CONCENTRATION = 1,  /* acts on rho_d/rho_g (chi = 1, eq:diff_conc) */
+    GD_DIFFUSION_DENSITY = 2         /* acts on rho_d (chi = 0, eq:diff_dens) */
+} gd_diffusion_form;
+
 /* Problem description (host struct, read during each call). */
 typedef struct gd_problem {
     int64_t n;            /* length of every particle array */
@@ -106,6 +112,15 @@ typedef struct gd_problem {
     int32_t rates_fp32;   /* 0: FP64 pair rates (the reference form); 1: pair collision speeds,
                              kernels, channel rates and moments in FP32, summed in FP64 (the
                              context per particle, N_j/V_i, psi and grouping stay FP64) */
+    /* dust diffusion (Sect. 2.4), read by gd_diffuse only */
+    int32_t diffusion;    /* gd_diffusion_form */
+    int32_t vint;         /* 1: vertically integrated disk: Sigma_g stands for rho_g, the
+                             midplane Stokes number is used and there is no vertical step */
+    int32_t axisym;       /* 1: axisymmetric model: no azimuthal step */
+    int32_t pad_;
+    double Sc[3];         /* Schmidt numbers of the R, Z and phi directions (> 0; INFINITY: none) */
+    double St_diff;       /* > 0: this spatially constant Stokes number in D for every grain
+                             (the ring test of Sect. 3.2); 0: the local Stokes number */
 } gd_problem;
 
 /* Particle state, structure of arrays, device pointers, length n.
@@ -264,6 +279,32 @@ int32_t gd_sample_collisions(const gd_problem* p, const gd_particles* st, const 
 int32_t gd_push(const gd_problem* p, const gd_particles* st, const gd_interval* iv, double dt,
                 void* ws, size_t ws_bytes, void* stream);
 
+/* Dust diffusion operator D (Sect. 2.4), one Euler--Maruyama step of length
+ * dt >= 0 on every active particle of st (M_i > 0), in place.
+ * D_a = nu/(Sc_a (1 + St^2)) in each cylindrical direction a = R, Z, phi with
+ * nu = alpha c_s H_g of the gas disk (Sect. 2.2) and St the grain's local
+ * Stokes number at (R, Z) (midplane when p->vint; p->St_diff when > 0):
+ *   dR   = sqrt(2 D_R dt) z_R + (D_R/R + dD_R/dR + chi D_R dln rho_g/dR) dt
+ *   dZ   = sqrt(2 D_Z dt) z_Z + (dD_Z/dZ + chi D_Z dln rho_g/dZ) dt     (none if vint)
+ *   dphi = sqrt(2 D_phi dt) z_phi / R                                  (none if axisym)
+ * with chi = 1 for GD_DIFFUSION_CONCENTRATION and 0 for GD_DIFFUSION_DENSITY
+ * (the azimuthal gradients of the axisymmetric gas vanish).  The z are
+ * standard normals by the Box--Muller transform of two Philox4x32-10 calls,
+ * key = seed, counters (id, step, 0x44494646, w) for w = 0, 1: each call gives
+ * u1 = ((hi:lo of words 1:0) >> 11 + 1) 2^-53 and u2 = (words 3:2 >> 11) 2^-53,
+ * sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2); z_R, z_Z are the first pair and
+ * z_phi the cosine of the second.  A step with R + dR < 0 passes the axis:
+ * R' = -(R + dR), phi' += pi.  The Cartesian velocity is kept: v_r, l_theta,
+ * l_phi are recomputed in the basis at the new position; r, th, ph, x, y, z
+ * are rewritten, and a particle leaving r_in <= r <= r_out gets M = 0.
+ * Requires id, x, y, z, M, r, th, ph, vr, lth, lph (and m[cur] unless
+ * St_diff > 0), GM, R0, h_g0, alpha > 0, and Sc_a > 0 for each direction
+ * stepped.  p->diffusion == GD_DIFFUSION_NONE enqueues nothing.  Needs no
+ * workspace and no synchronisation; the paper's cadence calls it twice per
+ * transport step with dt = Delta t / 2 (Sect. 2.6). */
+int32_t gd_diffuse(const gd_problem* p, const gd_particles* st, double dt, uint64_t seed, uint32_t step,
+                   void* stream);
+
 /* Kernels that gd_profile_events can bracket. */
 typedef enum gd_prof_kernel {
     GD_PROF_SORT = 0,       /* bounding box, Morton keys, radix sort, permutation */
@@ -273,7 +314,8 @@ typedef enum gd_prof_kernel {
     GD_PROF_MC = 4,         /* sampling kernel */
     GD_PROF_AUDIT = 5,      /* audit reduction */
     GD_PROF_PUSH = 6,       /* push */
-    GD_PROF_COUNT = 7
+    GD_PROF_DIFFUSE = 7,    /* diffusion step */
+    GD_PROF_COUNT = 8
 } gd_prof_kernel;
 
 /* Diagnostics for measurement: from now on, record the HIP events `before`

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libgd.so")
 GD_OK = 0
 KERNELS = {"const": 0, "additive": 1, "product": 2, "physical": 3}
 PUSH = {"none": 0, "local": 1, "global": 2}
+DIFFUSION = {"none": 0, "concentration": 1, "density": 2}
 DEV_BITS = {"nonfinite": 0x1, "log_overflow": 0x2, "knn_fallback": 0x4, "tick_floor": 0x8, "mass_range": 0x10,
             "internal": 0x20, "event_cap": 0x40}
 T_TICKS = 1 << 30
@@ -33,6 +34,8 @@ class GdProblem(C.Structure):
         ("alpha", C.c_double), ("mu_mH", C.c_double), ("sigma_H2", C.c_double), ("s0", C.c_double),
         ("St0", C.c_double), ("r_in", C.c_double), ("r_out", C.c_double), ("drag", C.c_int32),
         ("brownian", C.c_int32), ("turbulence", C.c_int32), ("caps", C.c_int32), ("rates_fp32", C.c_int32),
+        ("diffusion", C.c_int32), ("vint", C.c_int32), ("axisym", C.c_int32), ("pad_", C.c_int32),
+        ("Sc", C.c_double * 3), ("St_diff", C.c_double),
     ]
 
 
@@ -61,8 +64,8 @@ class GdInterval(C.Structure):
 EXPORTS = ("gd_workspace_size", "gd_workspace_init", "gd_interval_init", "gd_build_neighbors", "gd_collision_rates",
            "gd_sample_collisions", "gd_push", "gd_profile_events", "gd_status_read", "gd_last_error", "gd_version",
            "gd_sample_table_size", "gd_sample_collisions_deferred", "gd_sample_table_run", "gd_sample_audit",
-           "gd_reshuffle_neighbors")
-PROF = {"sort": 0, "tree": 1, "knn_query": 2, "rates": 3, "mc": 4, "audit": 5, "push": 6}
+           "gd_reshuffle_neighbors", "gd_diffuse")
+PROF = {"sort": 0, "tree": 1, "knn_query": 2, "rates": 3, "mc": 4, "audit": 5, "push": 6, "diffuse": 7}
 GD_INTERVAL_ON_DEVICE = (1 << 64) - 1
 
 _lib = None
@@ -100,6 +103,7 @@ def load(path: str | None = None):
     L.gd_sample_table_run.argtypes = [vp, C.c_size_t, C.c_int32, C.c_int32, C.c_int32, vp]
     L.gd_sample_audit.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), vp, vp, C.c_size_t, vp]
     L.gd_reshuffle_neighbors.argtypes = [C.POINTER(GdProblem), C.POINTER(GdNeighbors), C.c_uint64, C.c_uint32, vp]
+    L.gd_diffuse.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.c_double, C.c_uint64, C.c_uint32, vp]
     L.gd_status_read.argtypes = [vp, vp, C.POINTER(C.c_int32)]
     L.gd_profile_events.argtypes = [C.c_int32, vp, vp]
     L.gd_last_error.restype = C.c_char_p
@@ -107,7 +111,7 @@ def load(path: str | None = None):
     for name in ("gd_workspace_size", "gd_workspace_init", "gd_interval_init", "gd_build_neighbors", "gd_collision_rates",
                  "gd_sample_collisions", "gd_push", "gd_status_read", "gd_profile_events", "gd_sample_table_size",
                  "gd_sample_collisions_deferred", "gd_sample_table_run", "gd_sample_audit",
-                 "gd_reshuffle_neighbors"):
+                 "gd_reshuffle_neighbors", "gd_diffuse"):
         getattr(L, name).restype = C.c_int32
     if path is None:
         _lib = L
@@ -139,8 +143,13 @@ def make_problem(cfg: dict, n: int | None = None) -> GdProblem:
     for name in ("t0", "m0", "eps", "dt_fn_max", "rho_s", "s_min", "v_frag", "GM", "Sigma_g0", "R0", "p", "q",
                  "h_g0", "alpha", "mu_mH", "sigma_H2", "s0", "St0", "r_in", "r_out"):
         setattr(P, name, float(cfg.get(name, 0.0)))
-    for name in ("drag", "brownian", "turbulence", "caps", "rates_fp32"):
+    for name in ("drag", "brownian", "turbulence", "caps", "rates_fp32", "vint", "axisym"):
         setattr(P, name, int(cfg.get(name, 0)))
+    P.diffusion = DIFFUSION[cfg.get("diffusion", "none")]
+    Sc = cfg.get("Sc", (1.0, 1.0, 1.0))
+    for a in range(3):
+        P.Sc[a] = float(Sc[a])
+    P.St_diff = float(cfg.get("St_diff", 0.0))
     return P
 
 
@@ -293,6 +302,12 @@ class Engine:
         ivp = None if dt is not None else C.c_void_p(self.iv.data_ptr())
         check(self.lib.gd_push(C.byref(self.P), C.byref(s), ivp, 0.0 if dt is None else float(dt),
                                C.c_void_p(self.ws_ptr), self.ws_bytes, self._s()))
+
+    def diffuse(self, dt: float, step: int):
+        """One diffusion step of length dt (Sect. 2.4) on the current state, in place;
+        `step` numbers the draws (each call of a run needs its own)."""
+        s = self.A.struct()
+        check(self.lib.gd_diffuse(C.byref(self.P), C.byref(s), float(dt), self.seed, int(step), self._s()))
 
     def step(self, rebuild: bool = True):
         """One frozen-neighbour interval: kNN, rates + plan, sampling, push."""

@@ -329,6 +329,29 @@ int32_t gd_push(const gd_problem* p, const gd_particles* s, const gd_interval* i
     return hip_ok("gd_push");
 }
 
+int32_t gd_diffuse(const gd_problem* p, const gd_particles* s, double dt, uint64_t seed, uint32_t step, void* stream)
+{
+    int rc = check_problem(p);
+    if (rc) return rc;
+    if (p->diffusion < 0 || p->diffusion > 2) return fail(GD_E_INVALID_ARG, "diffusion = %d unknown", p->diffusion);
+    if (p->diffusion == GD_DIFFUSION_NONE) return GD_OK;
+    if (!s) return fail(GD_E_INVALID_ARG, "particles is NULL");
+    if (s->cur != 0 && s->cur != 1) return fail(GD_E_INVALID_ARG, "cur must be 0 or 1");
+    if (!s->id || !s->x || !s->y || !s->z || !s->M || !s->r || !s->th || !s->ph || !s->vr || !s->lth || !s->lph)
+        return fail(GD_E_INVALID_ARG, "diffusion needs id, x, y, z, M, r, th, ph, vr, lth, lph");
+    if (!(p->St_diff >= 0.0)) return fail(GD_E_INVALID_ARG, "St_diff must be >= 0");
+    if (p->St_diff == 0.0 && (!s->m[s->cur] || !(p->rho_s > 0.0) || !(p->s0 > 0.0)))
+        return fail(GD_E_INVALID_ARG, "the local Stokes number needs m[cur], rho_s > 0 and s0 > 0");
+    if (!(p->GM > 0.0) || !(p->R0 > 0.0) || !(p->h_g0 > 0.0) || !(p->alpha >= 0.0))
+        return fail(GD_E_INVALID_ARG, "diffusion needs GM, R0, h_g0 > 0 and alpha >= 0");
+    if (!(p->Sc[0] > 0.0) || (!p->vint && !(p->Sc[1] > 0.0)) || (!p->axisym && !(p->Sc[2] > 0.0)))
+        return fail(GD_E_INVALID_ARG, "Schmidt number of a stepped direction must be > 0");
+    if (!(dt >= 0.0) || !isfinite(dt)) return fail(GD_E_INVALID_ARG, "dt must be finite and >= 0");
+    if (p->n == 0) return GD_OK;
+    launch_diffuse(p, s, dt, seed, step, static_cast<hipStream_t>(stream));
+    return hip_ok("gd_diffuse");
+}
+
 int32_t gd_status_read(void* ws, void* stream, int32_t* out)
 {
     if (!ws || !out) return fail(GD_E_INVALID_ARG, "workspace and out are required");

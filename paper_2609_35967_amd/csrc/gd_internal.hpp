@@ -39,6 +39,8 @@ int launch_sample_table(void* table, int32_t nslot, int32_t k, int32_t rates_fp3
 int launch_push(const gd_problem* p, const gd_particles* s, const gd_interval* iv, double dt, void* ws,
                 const Layout& L, hipStream_t st);
 void launch_interval_init(gd_interval* iv, double dt_coll, hipStream_t st);
+int launch_diffuse(const gd_problem* p, const gd_particles* s, double dt, uint64_t seed, uint32_t step,
+                   hipStream_t st);
 void launch_bin_reduce(int mode, const double* msnap, const double* M, const double* va, const double* vb, int64_t n,
                        double* part, void* ws, hipStream_t st);
 

@@ -126,3 +126,43 @@ def test_sample_table_validation(lib):
 def test_problem_rmax_default_is_infinite():
     from paper_2609_35967_amd import binding
     assert math.isinf(binding.make_problem(workloads.const_box_params()).rmax)
+
+
+def test_diffuse_validation(lib):
+    # gd_diffuse checks its form, arrays, Schmidt numbers and step on the host
+    from paper_2609_35967_amd import binding
+    base = workloads.diffusion_ring_params("concentration", n=1000, axisym=0)
+    full = binding.GdParticles()
+    for k in ("id", "x", "y", "z", "M", "r", "th", "ph", "vr", "lth", "lph"):
+        setattr(full, k, 256)
+    full.m[0] = 256
+    P = binding.make_problem(base)
+    assert lib.gd_diffuse(C.byref(P), None, 1.0, 1, 0, None) == -1
+    part = binding.GdParticles()
+    for k in ("id", "x", "y", "z", "M"):
+        setattr(part, k, 256)
+    assert lib.gd_diffuse(C.byref(P), C.byref(part), 1.0, 1, 0, None) == -1
+    assert b"lph" in lib.gd_last_error()
+    assert lib.gd_diffuse(C.byref(P), C.byref(full), -1.0, 1, 0, None) == -1
+    assert lib.gd_diffuse(C.byref(P), C.byref(full), math.inf, 1, 0, None) == -1
+    bad = binding.make_problem(dict(base, Sc=(1.0, 1.0, 0.0)))
+    assert lib.gd_diffuse(C.byref(bad), C.byref(full), 1.0, 1, 0, None) == -1
+    assert b"Schmidt" in lib.gd_last_error()
+    # the vertical Schmidt number is not used by a vertically integrated disk
+    ok = binding.make_problem(dict(base, Sc=(1.0, 0.0, 1.0)))
+    zero = binding.make_problem(dict(base, Sc=(1.0, 0.0, 1.0)), n=0)
+    assert lib.gd_diffuse(C.byref(zero), C.byref(full), 1.0, 1, 0, None) == 0
+    bad = binding.make_problem(dict(base, St_diff=-1.0))
+    assert lib.gd_diffuse(C.byref(bad), C.byref(full), 1.0, 1, 0, None) == -1
+    bad = binding.make_problem(dict(base, St_diff=0.0))
+    nom = binding.GdParticles.from_buffer_copy(full)
+    nom.m[0] = None
+    assert lib.gd_diffuse(C.byref(bad), C.byref(nom), 1.0, 1, 0, None) == -1
+    assert b"m[cur]" in lib.gd_last_error()
+    bad = binding.make_problem(base)
+    bad.diffusion = 3
+    assert lib.gd_diffuse(C.byref(bad), C.byref(full), 1.0, 1, 0, None) == -1
+    # no diffusion: nothing to check, nothing enqueued
+    off = binding.make_problem(dict(base, diffusion="none"))
+    assert lib.gd_diffuse(C.byref(off), None, -1.0, 1, 0, None) == 0
+    assert ok.vint == 1

@@ -23,25 +23,17 @@ import numpy as np
 import pytest
 
 import oracle
+import workloads
 
 
 def ring_params(chi_form="concentration", St=1.0, Sc=(1.0, 1.0, 1.0), axisym=1, p=-1.0):
     # 1D radial disk of the ring test: h_g0 = 0.05, p = -1, q = 0.5, alpha = 0.04,
     # code units GM = R0 = 1 (so nu = 1e-4 (R/R0)^2)
-    return dict(kernel="physical", k=32, GM=1.0, R0=1.0, p=p, q=0.5, h_g0=0.05, alpha=0.04, Sigma_g0=1.0,
-                St0=1.0, s0=1.0, rho_s=1.0, r_in=1e-3, r_out=1e3, diffusion=chi_form, vint=1, axisym=axisym,
-                Sc=Sc, St_diff=St)
+    return workloads.diffusion_ring_params(chi_form, St=St, Sc=Sc, axisym=axisym, p=p)
 
 
 def ring_state(n, seed, sigma0=0.05):
-    rng = np.random.default_rng(seed)
-    lnR = rng.normal(0.0, sigma0, n)
-    R = np.exp(lnR)
-    ph = rng.uniform(0.0, 2.0 * math.pi, n)
-    th = np.full(n, 0.5 * math.pi)
-    z0 = np.zeros(n)
-    return dict(id=np.arange(n, dtype=np.uint32), r=R, th=th, ph=ph, vr=z0.copy(), lth=z0.copy(), lph=z0.copy(),
-                m=np.ones(n), M=np.ones(n), x=R * np.cos(ph), y=R * np.sin(ph), z=z0.copy())
+    return workloads.diffusion_ring(seed, n, sigma0)
 
 
 def run_ring(cfg, n, t_tilde, dtt, seed=11):

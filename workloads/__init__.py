@@ -27,6 +27,11 @@ whose own setups and data are not available):
   box_batch      256 such boxes: N log-uniform 2^10..2^16, R uniform in
                  [10, 100] au, alpha log-uniform 1e-4..1e-2, v_frag uniform
                  1..10 m/s (the batched-boxes configuration).
+  diffusion_ring the dust-ring test of Sect. 3.2: 2^20 particles with
+                 ln(R/R0) ~ N(0, 0.05^2) at zero velocity in a 1D radial disk
+                 (h_g0 = 0.05, p = -1, q = 0.5, alpha = 0.04, GM = R0 = 1),
+                 Sc = 1, one spatially constant St in {0.1, 1, 10},
+                 concentration or density form; uniform azimuth.
 """
 from __future__ import annotations
 
@@ -162,6 +167,26 @@ def box_batch(seed: int, nbox: int = 256, lo: int = 10, hi: int = 16):
         P = local_box_params(n, R_au=R_au, alpha=alpha, v_frag=v_frag)
         out.append((P, local_box(seed * 1000 + b, n, P), seed * 1000 + b))
     return out
+
+
+def diffusion_ring_params(form: str = "concentration", St: float = 1.0, n: int = 1 << 20,
+                          Sc=(1.0, 1.0, 1.0), axisym: int = 1, p: float = -1.0) -> dict:
+    """The 1D radial disk of the ring-spreading test (code units GM = R0 = 1)."""
+    return dict(name="diffusion_ring", kernel="physical", k=32, n=n, GM=1.0, R0=1.0, p=p, q=0.5, h_g0=0.05,
+                alpha=0.04, Sigma_g0=1.0, St0=1.0, s0=1.0, rho_s=1.0, s_min=1.0, r_in=1e-3, r_out=1e3,
+                push="none", diffusion=form, vint=1, axisym=axisym, Sc=tuple(Sc), St_diff=St, dt_coll=1.0,
+                t0=1.0, m0=1.0)
+
+
+def diffusion_ring(seed: int, n: int = 1 << 20, sigma0: float = 0.05) -> dict:
+    g = _rng(seed)
+    R = np.exp(g.normal(0.0, sigma0, n))
+    ph = g.uniform(0.0, 2.0 * math.pi, n)
+    th = np.full(n, 0.5 * math.pi)
+    zero = np.zeros(n)
+    return dict(id=np.arange(n, dtype=np.uint32), r=R, th=th, ph=ph, vr=zero.copy(), lth=zero.copy(),
+                lph=zero.copy(), m=np.ones(n), M=np.full(n, 1.0 / n), x=R * np.cos(ph), y=R * np.sin(ph),
+                z=zero.copy())
 
 
 def lattice_box(nside: int, jitter: float = 0.0, seed: int = 0) -> dict:
