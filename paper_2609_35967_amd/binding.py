@@ -244,6 +244,8 @@ class Engine:
         self.ws_ptr = (base + 255) & ~255
         self.ws_bytes = sz.value
         self.nb = GdNeighbors(self.nbr.data_ptr(), self.cnt.data_ptr(), self.dmax.data_ptr(), self.n_active.data_ptr())
+        self.moved = True       # positions changed since the neighbour lists were built
+        self.diff_step = 0      # draws of the next diffusion step of strang_step
         check(self.lib.gd_workspace_init(C.byref(self.P), C.c_void_p(self.ws_ptr), self.ws_bytes, self._s()))
         check(self.lib.gd_interval_init(C.c_void_p(self.iv.data_ptr()), float(params["dt_coll"]), self._s()))
 
@@ -258,6 +260,7 @@ class Engine:
                                           C.c_void_p(self.ws_ptr), self.ws_bytes, self._s()))
         self.A, self.B = self.B, self.A
         self.A.cur = sb.cur
+        self.moved = False
 
     def collision_rates(self, lam_pair=None, ab=None):
         s = self.A.struct()
@@ -302,12 +305,47 @@ class Engine:
         ivp = None if dt is not None else C.c_void_p(self.iv.data_ptr())
         check(self.lib.gd_push(C.byref(self.P), C.byref(s), ivp, 0.0 if dt is None else float(dt),
                                C.c_void_p(self.ws_ptr), self.ws_bytes, self._s()))
+        if self.P.push != 0:
+            self.moved = True
 
     def diffuse(self, dt: float, step: int):
         """One diffusion step of length dt (Sect. 2.4) on the current state, in place;
         `step` numbers the draws (each call of a run needs its own)."""
         s = self.A.struct()
         check(self.lib.gd_diffuse(C.byref(self.P), C.byref(s), float(dt), self.seed, int(step), self._s()))
+        if self.P.diffusion != 0:
+            self.moved = True
+
+    def collide(self, max_intervals: int = 1 << 24) -> int:
+        """Collision operator C(dt_coll): frozen-neighbour intervals without
+        transport until the collision step is complete (its ticks wrap to 0).
+        The neighbour lists are rebuilt only if the positions changed since they
+        were built.  Reads the interval state after each interval (synchronises).
+        Returns the number of intervals run."""
+        for it in range(1, max_intervals + 1):
+            if self.moved:
+                self.build_neighbors()
+            self.collision_rates()
+            self.sample_collisions()
+            if self.interval_state()["ticks"] == 0:
+                return it
+        raise GdError(f"collision step not complete after {max_intervals} intervals")
+
+    def strang_step(self) -> int:
+        """One transport step dt = 2 dt_coll in the symmetric sequence of Sect. 2.6:
+        C(dt/2) D(dt/2) T(dt) D(dt/2) C(dt/2).  The last collision operator of a
+        step and the first of the next share their neighbour lists.  Returns the
+        number of intervals run."""
+        h = float(self.params["dt_coll"])
+        n = self.collide()
+        if self.P.diffusion != 0:
+            self.diffuse(h, self.diff_step)
+            self.diff_step += 1
+        self.push(dt=2.0 * h)
+        if self.P.diffusion != 0:
+            self.diffuse(h, self.diff_step)
+            self.diff_step += 1
+        return n + self.collide()
 
     def step(self, rebuild: bool = True):
         """One frozen-neighbour interval: kNN, rates + plan, sampling, push."""
@@ -320,6 +358,8 @@ class Engine:
 
     # ---- inspection (synchronising) -----------------------------------------------
     def interval_state(self) -> dict:
+        if self.stream is not None:
+            self.stream.synchronize()
         raw = self.iv.cpu().numpy().tobytes()
         s = GdInterval.from_buffer_copy(raw)
         return {name: getattr(s, name) for name, _ in GdInterval._fields_}
