@@ -47,7 +47,10 @@ ALGO_BYTES = {
 PROF_KERNELS = ("sort", "tree", "knn_query", "rates", "mc", "audit", "push")
 # source file of each profiled stage (the HBM counter summary is tied to it)
 PROF_SOURCE = {"sort": "gd_sort.hip", "tree": "gd_knn.hip", "knn_query": "gd_knn.hip", "rates": "gd_rates.hip",
-               "mc": "gd_mc.hip", "audit": "gd_mc.hip", "push": "gd_push.hip"}
+               "mc": "gd_mc.hip", "audit": "gd_mc.hip", "push": "gd_push.hip", "diffuse": "gd_diffuse.hip"}
+# the diffusion step on the ring: read id, the six spherical components and M
+# (a constant Stokes number needs no m); write the six components and x, y, z
+DIFFUSE_BYTES = 4 + 6 * 8 + 8 + 9 * 8
 COPY_BYTES = 1 << 30  # the plain copy that calibrates the HBM byte counters
 
 
@@ -267,6 +270,117 @@ def batch_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def _timed_loop(fn, steps):
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record()
+    for s in range(steps):
+        fn(s)
+        ev[s + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+
+
+def diffusion_bench(args):
+    """The diffusion operator on the dust-ring test of Sect. 3.2 at 2^20
+    particles (concentration form, St = 1, dimensionless step 2e-4): one step
+    is one gd_diffuse launch over every particle."""
+    import torch
+    from paper_2609_35967_amd import Engine, binding, load
+
+    load()
+    torch.cuda.set_device(0)
+    n = args.n
+    params = workloads.diffusion_ring_params("concentration", St=1.0, n=n, axisym=0)
+    st = workloads.diffusion_ring(args.seed, n)
+    eng = Engine(params, st, seed=args.seed)
+    dt = 2e-4 / (1e-4 / 2.0)
+    hip = HipEvents()
+    for k in range(args.warmup):
+        eng.diffuse(dt, k)
+    pairs = [(hip.create(), hip.create()) for _ in range(args.steps)]
+
+    def one(s):
+        a, b = pairs[s]
+        eng.lib.gd_profile_events(binding.PROF["diffuse"], a, b)
+        eng.diffuse(dt, args.warmup + s)
+
+    wall, lat = _timed_loop(one, args.steps)
+    binding.check(eng.lib.gd_profile_events(binding.PROF["diffuse"], None, None))
+    k_ms = float(np.mean([hip.elapsed_ms(a, b) for a, b in pairs]))
+    value = n * args.steps / wall
+    achieved = DIFFUSE_BYTES * n / (k_ms * 1e-3) / 1e9
+    traffic = measured_traffic("diffuse")
+    out = dict(
+        metric="particle-steps/s of the diffusion operator (Sect. 2.4)", value=round(value, 1),
+        unit="particle-steps/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(wall / args.steps * 1e3, 4), higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64", data="synthetic",
+        config=dict(workload=f"diffusion_ring: the dust-ring test of Sect. 3.2, {n} particles, ln(R/R0) ~ "
+                             "N(0, 0.05^2), 1D radial disk h_g0=0.05, p=-1, q=0.5, alpha=0.04, St=1, Sc=1, "
+                             "concentration form, azimuthal steps on, dimensionless step 2e-4",
+                    n_particles=n),
+        p50_ms=round(float(np.percentile(lat, 50)), 4), p99_ms=round(float(np.percentile(lat, 99)), 4),
+        roofline=dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=round(achieved / HBM_PEAK_GBS, 5),
+                      traffic=None if traffic is None else round(traffic / (k_ms * 1e-3) / 1e9, 2),
+                      kernel="diffuse", algo_bytes_per_particle=DIFFUSE_BYTES, launch_ms=round(k_ms, 4),
+                      traffic_bytes_per_launch=None if traffic is None else round(traffic)),
+    )
+    if not args.no_cpu_baseline:
+        import oracle
+        P = oracle.make_problem(params)
+        ref = {k: np.array(st[k], np.float64) for k in ("r", "th", "ph", "vr", "lth", "lph", "m", "M", "x", "y",
+                                                         "z")}
+        ref["id"] = st["id"]
+        reps = 256
+        t0 = time.perf_counter()
+        for k in range(reps):
+            ref = oracle.diffuse(P, ref, dt, args.seed, k)
+            ref["id"] = st["id"]
+        t = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(value=round(n * reps / t, 1), unit="particle-steps/s",
+                                   cores=oracle.num_threads(), kind="oracle",
+                                   sample=f"{reps} diffusion steps of all {n} particles in {t:.1f} s")
+    print(json.dumps(out), flush=True)
+
+
+def strang_bench(args):
+    """Transport steps in the paper's cadence C(dt/2) D(dt/2) T(dt) D(dt/2)
+    C(dt/2) on the 1M disk with concentration diffusion; dt/2 = dt_coll."""
+    import torch
+    from paper_2609_35967_amd import Engine, load
+
+    load()
+    torch.cuda.set_device(0)
+    params, st = workloads.by_name(args.workload, seed=args.seed, n=args.n)
+    params = dict(params, diffusion="concentration", Sc=(1.0, 1.0, 1.0))
+    eng = Engine(params, st, seed=args.seed)
+    n = eng.n
+    for _ in range(args.warmup):
+        eng.strang_step()
+    counts = []
+    wall, lat = _timed_loop(lambda s: counts.append(eng.strang_step()), args.steps)
+    value = n * args.steps / wall
+    out = dict(
+        metric="particle-steps/s of the paper-cadence transport step (Sect. 2.6)", value=round(value, 1),
+        unit="particle-steps/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(wall / args.steps * 1e3, 4), higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64", data="synthetic",
+        config=dict(workload=f"{args.workload}: 3D disk annulus r in [10,100] au, {n} particles, k=32, "
+                             "alpha=1e-3, v_frag=1 m/s, concentration diffusion Sc=1; one step is "
+                             "C(dt/2) D(dt/2) T(dt) D(dt/2) C(dt/2) with dt/2 = P(10 au)/50",
+                    n_particles=n, k=32),
+        p50_ms=round(float(np.percentile(lat, 50)), 4), p99_ms=round(float(np.percentile(lat, 99)), 4),
+        intervals_per_step=round(float(np.mean(counts)), 3),
+        status=eng.status(),
+    )
+    print(json.dumps(out), flush=True)
+
+
 def serve_bench(args):
     """Served stream: disk-annulus runs (N log-uniform 2^12..2^20, alpha and
     v_frag as the batched boxes, 50 intervals each) arrive as a Poisson
@@ -388,9 +502,22 @@ def main():
     ap.add_argument("--serve", type=float, default=0.0, metavar="SECONDS",
                     help="the served-stream configuration instead: Poisson arrivals (20 runs/s) of disk-annulus "
                          "runs for SECONDS, served under a 200 GB budget, against the same runs one after another")
+    ap.add_argument("--diffusion", action="store_true",
+                    help="the diffusion operator on the 2^20-particle dust-ring test instead")
+    ap.add_argument("--strang", action="store_true",
+                    help="paper-cadence transport steps C D T D C on the disk instead")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.diffusion or args.strang:
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        if args.diffusion:
+            diffusion_bench(args)
+        else:
+            strang_bench(args)
         return
     if args.batch or args.serve:
         if args.gpus != 1:
