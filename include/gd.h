@@ -279,6 +279,49 @@ int32_t gd_sample_collisions(const gd_problem* p, const gd_particles* st, const 
 int32_t gd_push(const gd_problem* p, const gd_particles* st, const gd_interval* iv, double dt,
                 void* ws, size_t ws_bytes, void* stream);
 
+/* Spatial groups (Sect. 2.5.3).  A group is a contiguous range of
+ * Morton-ordered active slots; each keeps its own gd_interval (safety factor
+ * C, ticks), so that groups run frozen-neighbour intervals of different
+ * lengths within one collision step.  During a collision step m[cur] holds the
+ * broadcast masses and m[cur ^ 1] each group's masses at the end of its
+ * current interval; cur is not flipped.
+ *
+ * gd_group_interactions: mask[g] (DEVICE, n_groups uint64 rows) gets bit h set
+ * when a retained neighbour of a particle of group g lies in group h, or one of
+ * h in g (h != g).  group_lo (HOST, n_groups + 1 ascending slots, group_lo[0]
+ * = 0, group_lo[n_groups] <= n) gives the ranges; 1 <= n_groups <= 64.
+ * Reads the lists written by gd_build_neighbors. */
+int32_t gd_group_interactions(const gd_problem* p, const gd_neighbors* nb, const int32_t* group_lo, int32_t n_groups,
+                              uint64_t* mask, void* stream);
+
+/* gd_collision_rates for the slots [lo, hi) of one group: the snapshot of the
+ * neighbourhood covers every particle (from m[cur]); lambda*_i and the
+ * controller moments are computed for the group's slots only; the plan uses
+ * the group's controller bins and its interval state iv; the executed
+ * interval is then held to [z_lo, z_hi] ticks (powers of two,
+ * 1 <= z_lo <= z_hi <= 2^30, the lower bound taking precedence) and halved
+ * until it starts on a multiple of itself and ends within the collision step.
+ * The bounds carry the rule that the intervals of interacting groups differ by
+ * at most a factor 16 while scheduled intervals are kept. */
+int32_t gd_collision_rates_group(const gd_problem* p, const gd_particles* st, const gd_neighbors* nb,
+                                 gd_interval* iv, double* lambda_i, int64_t lo, int64_t hi, int64_t z_lo, int64_t z_hi,
+                                 void* ws, size_t ws_bytes, void* stream);
+
+/* gd_sample_collisions for the slots [lo, hi) of one group over iv->dt_exe,
+ * against the snapshot of the preceding gd_collision_rates_group call, writing
+ * m[cur ^ 1][lo, hi) (and n_events[lo, hi) if non-NULL), then the audit of
+ * the group's C.  interval_index (< 2^32) keys the random numbers as in
+ * gd_sample_collisions; a run numbers its group intervals so that no particle
+ * meets an index twice.  cur is not flipped. */
+int32_t gd_sample_collisions_group(const gd_problem* p, const gd_particles* st, const gd_neighbors* nb,
+                                   gd_interval* iv, const double* lambda_i, uint64_t seed, uint64_t interval_index,
+                                   int64_t lo, int64_t hi, int32_t* n_events, void* ws, size_t ws_bytes,
+                                   void* stream);
+
+/* Broadcast of a group at the end of its interval: m[cur][lo, hi) =
+ * m[cur ^ 1][lo, hi). */
+int32_t gd_publish_group(const gd_problem* p, const gd_particles* st, int64_t lo, int64_t hi, void* stream);
+
 /* Dust diffusion operator D (Sect. 2.4), one Euler--Maruyama step of length
  * dt >= 0 on every active particle of st (M_i > 0), in place.
  * D_a = nu/(Sc_a (1 + St^2)) in each cylindrical direction a = R, Z, phi with

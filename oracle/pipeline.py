@@ -110,3 +110,106 @@ class OracleRun:
         self.transport(2.0 * h)
         self.diffusion(h)
         return out + self.collide(log_cap)
+
+
+class GroupedRun(OracleRun):
+    """Collision steps with spatial groups (Sect. 2.5.3), on the oracle.
+
+    Groups are n_groups contiguous ranges of the active particles in Morton
+    order, g*N//G .. (g+1)*N//G.  Two groups interact when a particle of one
+    keeps a neighbour in the other.  Every group has its own safety factor C
+    and clock.  Within a collision step of 2^30 ticks the groups are processed
+    instant by instant:
+
+      1. at instant tau the groups whose interval ends there broadcast: their
+         particles' masses at the end of the interval become the masses every
+         later snapshot sees;
+      2. the groups starting at tau (all of them at tau = 0) then plan one by
+         one in ascending order.  A group's dyadic request (the plan of
+         Sect. 2.5.3 over its own controller bins) is kept within 1/16 and 16
+         times the interval of every interacting group that already has one
+         scheduled; where the two limits conflict the lower one wins (a
+         scheduled interval is never cut, so the refinement waits); the size is
+         then halved until it starts on a multiple of itself and ends by 2^30;
+      3. the group samples its whole interval at once against the broadcast
+         masses of tau (nothing it does is visible to others before its end),
+         and its C is audited.
+
+    Group intervals are numbered in the order they are planned; that number
+    keys the random numbers of the interval.
+    """
+
+    def __init__(self, params: dict, state: dict, seed: int = 0, n_groups: int = 1):
+        super().__init__(params, state, seed)
+        self.n_groups = int(n_groups)
+        self.gC = [1.0] * self.n_groups
+        self.bounds = None
+        self.links = None
+        self.log = []
+
+    def _layout(self):
+        n_act = int(np.count_nonzero(self.st["M"] > 0))
+        G = self.n_groups
+        self.bounds = [g * n_act // G for g in range(G + 1)]
+        owner = np.full(len(self.st["M"]), -1, np.int64)
+        for g in range(G):
+            owner[self.bounds[g]:self.bounds[g + 1]] = g
+        nbr, cnt, _ = self.nb
+        links = [set() for _ in range(G)]
+        for i in range(n_act):
+            for j in nbr[i, 1:cnt[i]]:
+                if j >= 0 and owner[j] >= 0 and owner[j] != owner[i]:
+                    links[owner[i]].add(int(owner[j]))
+                    links[owner[j]].add(owner[i])
+        self.links = links
+
+    def collide_groups(self):
+        P = self.P
+        T = T_TICKS
+        if self.moved or self.nb is None:
+            self.build_neighbors()
+            self._layout()
+        elif self.bounds is None:
+            self._layout()
+        st = self.st
+        nbr, cnt, dmax = self.nb
+        G = self.n_groups
+        m_pub = st["m"].copy()             # what the snapshots see
+        m_end = st["m"].copy()             # each group's masses at the end of its interval
+        size = [0] * G
+        end = [0] * G
+        start_at = [0] * G
+        tau, starting, done = 0, list(range(G)), []
+        tick = np.ldexp(self.params["dt_coll"], -30)
+        while True:
+            for g in starting:
+                a0, a1 = self.bounds[g], self.bounds[g + 1]
+                q = np.arange(a0, a1)
+                lam, a, b, _ = rates(P, nbr, cnt, dmax, m_pub, st["M"], st["x"], st["y"], st["z"], queries=q)
+                pl = plan(P, m_pub[a0:a1], st["M"][a0:a1], a, b, self.params["dt_coll"], tau, self.gC[g])
+                want = pl["exe_ticks"]
+                others = [size[h] for h in self.links[g] if size[h]]
+                lo_lim = max([1] + [z // 16 for z in others])
+                hi_lim = min([T] + [16 * z for z in others])
+                z = max(min(want, hi_lim), lo_lim)
+                while z > 1 and (tau % z != 0 or tau + z > T):
+                    z //= 2
+                res = mc(P, st["id"], nbr, cnt, dmax, m_pub, st["M"], st["x"], st["y"], st["z"], z * tick,
+                         self.seed, self.interval, queries=q)
+                self.interval += 1
+                au = audit(P, m_pub[a0:a1], res["m"], st["M"][a0:a1], pl["group_of"], pl["gM"], self.gC[g])
+                self.gC[g] = au["C"]
+                m_end[a0:a1] = res["m"]
+                size[g], end[g], start_at[g] = z, tau + z, tau
+                done.append((g, tau, z))
+                self.log.append(dict(group=g, start=tau, ticks=z, requested=want, lo=lo_lim, hi=hi_lim,
+                                     near_tie=bool(res["near_tie"].any())))
+            tau = min(end)
+            starting = [g for g in range(G) if end[g] == tau]
+            for g in starting:
+                a0, a1 = self.bounds[g], self.bounds[g + 1]
+                m_pub[a0:a1] = m_end[a0:a1]
+                size[g] = 0
+            if tau == T:
+                st["m"] = m_pub
+                return done

@@ -64,7 +64,8 @@ class GdInterval(C.Structure):
 EXPORTS = ("gd_workspace_size", "gd_workspace_init", "gd_interval_init", "gd_build_neighbors", "gd_collision_rates",
            "gd_sample_collisions", "gd_push", "gd_profile_events", "gd_status_read", "gd_last_error", "gd_version",
            "gd_sample_table_size", "gd_sample_collisions_deferred", "gd_sample_table_run", "gd_sample_audit",
-           "gd_reshuffle_neighbors", "gd_diffuse")
+           "gd_reshuffle_neighbors", "gd_diffuse", "gd_group_interactions", "gd_collision_rates_group",
+           "gd_sample_collisions_group", "gd_publish_group")
 PROF = {"sort": 0, "tree": 1, "knn_query": 2, "rates": 3, "mc": 4, "audit": 5, "push": 6, "diffuse": 7}
 GD_INTERVAL_ON_DEVICE = (1 << 64) - 1
 
@@ -104,6 +105,13 @@ def load(path: str | None = None):
     L.gd_sample_audit.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), vp, vp, C.c_size_t, vp]
     L.gd_reshuffle_neighbors.argtypes = [C.POINTER(GdProblem), C.POINTER(GdNeighbors), C.c_uint64, C.c_uint32, vp]
     L.gd_diffuse.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.c_double, C.c_uint64, C.c_uint32, vp]
+    L.gd_group_interactions.argtypes = [C.POINTER(GdProblem), C.POINTER(GdNeighbors), vp, C.c_int32, vp, vp]
+    L.gd_collision_rates_group.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.POINTER(GdNeighbors), vp,
+                                           vp, C.c_int64, C.c_int64, C.c_int64, C.c_int64, vp, C.c_size_t, vp]
+    L.gd_sample_collisions_group.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.POINTER(GdNeighbors),
+                                             vp, vp, C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, vp, vp,
+                                             C.c_size_t, vp]
+    L.gd_publish_group.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.c_int64, C.c_int64, vp]
     L.gd_status_read.argtypes = [vp, vp, C.POINTER(C.c_int32)]
     L.gd_profile_events.argtypes = [C.c_int32, vp, vp]
     L.gd_last_error.restype = C.c_char_p
@@ -111,7 +119,8 @@ def load(path: str | None = None):
     for name in ("gd_workspace_size", "gd_workspace_init", "gd_interval_init", "gd_build_neighbors", "gd_collision_rates",
                  "gd_sample_collisions", "gd_push", "gd_status_read", "gd_profile_events", "gd_sample_table_size",
                  "gd_sample_collisions_deferred", "gd_sample_table_run", "gd_sample_audit",
-                 "gd_reshuffle_neighbors", "gd_diffuse"):
+                 "gd_reshuffle_neighbors", "gd_diffuse", "gd_group_interactions", "gd_collision_rates_group",
+                 "gd_sample_collisions_group", "gd_publish_group"):
         getattr(L, name).restype = C.c_int32
     if path is None:
         _lib = L
@@ -330,6 +339,90 @@ class Engine:
             if self.interval_state()["ticks"] == 0:
                 return it
         raise GdError(f"collision step not complete after {max_intervals} intervals")
+
+    # ---- spatial groups (Sect. 2.5.3) ---------------------------------------------
+    def set_groups(self, n_groups: int):
+        """Split the active particles into `n_groups` contiguous Morton ranges, each
+        with its own interval state; collide_groups() then schedules them."""
+        torch = self.torch
+        if not 1 <= n_groups <= 64:
+            raise GdError("n_groups must be 1..64")
+        self.n_groups = int(n_groups)
+        isz = C.sizeof(GdInterval)
+        self.ivg = torch.zeros((self.n_groups, isz), dtype=torch.uint8, device=self.device)
+        for g in range(self.n_groups):
+            check(self.lib.gd_interval_init(C.c_void_p(self.ivg[g].data_ptr()), float(self.params["dt_coll"]),
+                                            self._s()))
+        self.gmask = torch.zeros(self.n_groups, dtype=torch.int64, device=self.device)
+        self.group_lo = None
+
+    def _group_layout(self):
+        """Ranges over the active slots after a build, and the interaction rows (synchronises)."""
+        if self.stream is not None:
+            self.stream.synchronize()
+        na = int(self.n_active.item())
+        G = self.n_groups
+        if na < G:
+            raise GdError(f"{na} active particles cannot fill {G} groups")
+        lo = (C.c_int32 * (G + 1))(*[g * na // G for g in range(G + 1)])
+        check(self.lib.gd_group_interactions(C.byref(self.P), C.byref(self.nb), lo, G,
+                                             C.c_void_p(self.gmask.data_ptr()), self._s()))
+        self.group_lo = [int(v) for v in lo]
+        self.group_rows = [int(v) & ((1 << 64) - 1) for v in self.gmask.cpu().tolist()]
+
+    def group_interval_state(self, g: int) -> dict:
+        if self.stream is not None:
+            self.stream.synchronize()
+        s = GdInterval.from_buffer_copy(self.ivg[g].cpu().numpy().tobytes())
+        return {name: getattr(s, name) for name, _ in GdInterval._fields_}
+
+    def collide_groups(self) -> list:
+        """Collision operator C(dt_coll) with spatial groups: each group runs its
+        own frozen-neighbour intervals; at each instant the groups whose interval
+        ends broadcast their masses, then the groups starting there plan in
+        ascending order, each interval held within 1/16 .. 16 times the intervals
+        already scheduled for the groups it interacts with (the lower bound wins
+        when the two conflict).  A group's interval is sampled when it starts; its
+        masses are broadcast when it ends.  Returns the executed intervals as
+        (group, start tick, ticks).  Synchronises once per group interval."""
+        T = 1 << 30
+        if self.moved or self.group_lo is None:
+            if self.moved:
+                self.build_neighbors()
+            self._group_layout()
+        G, lo = self.n_groups, self.group_lo
+        size = [0] * G
+        end = [0] * G
+        tau, starting, done = 0, list(range(G)), []
+        sa = self.A.struct()
+        while True:
+            for g in starting:
+                z_lo, z_hi = 1, T
+                for h in range(G):
+                    if h != g and size[h] and (self.group_rows[g] >> h) & 1:
+                        z_lo = max(z_lo, size[h] // 16)
+                        z_hi = min(z_hi, 16 * size[h])
+                z_hi = max(z_hi, z_lo)
+                ivp = C.c_void_p(self.ivg[g].data_ptr())
+                check(self.lib.gd_collision_rates_group(C.byref(self.P), C.byref(sa), C.byref(self.nb), ivp,
+                                                        _ptr(self.lam), lo[g], lo[g + 1], z_lo, z_hi,
+                                                        C.c_void_p(self.ws_ptr), self.ws_bytes, self._s()))
+                check(self.lib.gd_sample_collisions_group(C.byref(self.P), C.byref(sa), C.byref(self.nb), ivp,
+                                                          _ptr(self.lam), self.seed, self.interval, lo[g], lo[g + 1],
+                                                          _ptr(self.events), C.c_void_p(self.ws_ptr), self.ws_bytes,
+                                                          self._s()))
+                self.interval += 1
+                z = int(self.group_interval_state(g)["exe_ticks"])
+                size[g] = z
+                end[g] = tau + z
+                done.append((g, tau, z))
+            tau = min(end)
+            starting = [g for g in range(G) if end[g] == tau]
+            for g in starting:
+                check(self.lib.gd_publish_group(C.byref(self.P), C.byref(sa), lo[g], lo[g + 1], self._s()))
+                size[g] = 0
+            if tau == T:
+                return done
 
     def strang_step(self) -> int:
         """One transport step dt = 2 dt_coll in the symmetric sequence of Sect. 2.6:

@@ -352,6 +352,80 @@ int32_t gd_diffuse(const gd_problem* p, const gd_particles* s, double dt, uint64
     return hip_ok("gd_diffuse");
 }
 
+static int check_range(const gd_problem* p, int64_t lo, int64_t hi)
+{
+    if (lo < 0 || hi < lo || hi > p->n) return fail(GD_E_INVALID_ARG, "slot range [%lld, %lld) outside [0, %lld)",
+                                                    (long long)lo, (long long)hi, (long long)p->n);
+    return GD_OK;
+}
+
+int32_t gd_group_interactions(const gd_problem* p, const gd_neighbors* nb, const int32_t* group_lo, int32_t n_groups,
+                              uint64_t* mask, void* stream)
+{
+    int rc = check_problem(p);
+    if (!rc) rc = check_nb(nb);
+    if (rc) return rc;
+    if (n_groups < 1 || n_groups > max_groups())
+        return fail(GD_E_INVALID_ARG, "n_groups = %d outside 1..%d", n_groups, max_groups());
+    if (!group_lo || !mask) return fail(GD_E_INVALID_ARG, "group_lo and mask are required");
+    if (group_lo[0] != 0) return fail(GD_E_INVALID_ARG, "group_lo[0] must be 0");
+    for (int g = 0; g < n_groups; ++g)
+        if (group_lo[g + 1] <= group_lo[g]) return fail(GD_E_INVALID_ARG, "groups must be non-empty and ascending");
+    if (group_lo[n_groups] > p->n) return fail(GD_E_INVALID_ARG, "group_lo[n_groups] exceeds n");
+    launch_group_interactions(p, nb, group_lo, n_groups, mask, static_cast<hipStream_t>(stream));
+    return hip_ok("gd_group_interactions");
+}
+
+int32_t gd_collision_rates_group(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb,
+                                 gd_interval* iv, double* lam_i, int64_t lo, int64_t hi, int64_t z_lo, int64_t z_hi,
+                                 void* ws, size_t ws_bytes, void* stream)
+{
+    int rc = check_problem(p);
+    if (!rc) rc = check_state(p, s, false);
+    if (!rc) rc = check_nb(nb);
+    if (!rc) rc = check_range(p, lo, hi);
+    if (rc) return rc;
+    if (!iv || !lam_i) return fail(GD_E_INVALID_ARG, "interval and lam_i are required");
+    if (z_lo < 1 || z_hi < z_lo || z_hi > (int64_t(1) << 30) || (z_lo & (z_lo - 1)) || (z_hi & (z_hi - 1)))
+        return fail(GD_E_INVALID_ARG, "z_lo, z_hi must be powers of two with 1 <= z_lo <= z_hi <= 2^30");
+    Layout L;
+    rc = check_ws(p, ws, ws_bytes, L);
+    if (rc) return rc;
+    if (p->n == 0) return GD_OK;
+    launch_rates_group(p, s, nb, iv, lam_i, lo, hi, z_lo, z_hi, ws, L, static_cast<hipStream_t>(stream));
+    return hip_ok("gd_collision_rates_group");
+}
+
+int32_t gd_sample_collisions_group(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb,
+                                   gd_interval* iv, const double* lam_i, uint64_t seed, uint64_t interval_index,
+                                   int64_t lo, int64_t hi, int32_t* n_events, void* ws, size_t ws_bytes, void* stream)
+{
+    int rc = check_problem(p);
+    if (!rc) rc = check_state(p, s, true);
+    if (!rc) rc = check_nb(nb);
+    if (!rc) rc = check_range(p, lo, hi);
+    if (rc) return rc;
+    if (!iv || !lam_i) return fail(GD_E_INVALID_ARG, "interval and lam_i are required");
+    if (interval_index > 0xFFFFFFFFull) return fail(GD_E_INVALID_ARG, "interval_index must be below 2^32");
+    Layout L;
+    rc = check_ws(p, ws, ws_bytes, L);
+    if (rc) return rc;
+    if (p->n == 0) return GD_OK;
+    launch_sample_group(p, s, nb, iv, lam_i, seed, uint32_t(interval_index), lo, hi, n_events, ws, L,
+                        static_cast<hipStream_t>(stream));
+    return hip_ok("gd_sample_collisions_group");
+}
+
+int32_t gd_publish_group(const gd_problem* p, const gd_particles* s, int64_t lo, int64_t hi, void* stream)
+{
+    int rc = check_problem(p);
+    if (!rc) rc = check_state(p, s, true);
+    if (!rc) rc = check_range(p, lo, hi);
+    if (rc) return rc;
+    launch_publish_group(s, lo, hi, static_cast<hipStream_t>(stream));
+    return hip_ok("gd_publish_group");
+}
+
 int32_t gd_status_read(void* ws, void* stream, int32_t* out)
 {
     if (!ws || !out) return fail(GD_E_INVALID_ARG, "workspace and out are required");

@@ -1,0 +1,94 @@
+// gd_groups.hip -- spatial groups (Sect. 2.5.3): which groups interact
+// through the neighbour lists, and the broadcast of a group's masses at the
+// end of its interval.
+//
+// A group is a contiguous range of Morton-ordered slots, group_lo[g] ..
+// group_lo[g+1].  Groups g != h interact when a retained neighbour of a
+// particle of one lies in the other; the relation is returned as one 64-bit
+// row per group.
+#include "gd_common.hpp"
+#include "gd_internal.hpp"
+
+namespace gd {
+
+constexpr int kMaxGroups = 64;
+
+__device__ inline int group_of_slot(const int32_t* lo, int G, int32_t s)
+{
+    int a = 0, b = G - 1;  // largest g with lo[g] <= s
+    while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (lo[mid] <= s) a = mid;
+        else b = mid - 1;
+    }
+    return a;
+}
+
+struct GroupBounds {
+    int32_t lo[kMaxGroups + 1];
+};
+
+__global__ __launch_bounds__(256) void k_group_interactions(const int32_t* __restrict__ nbr,
+                                                            const int32_t* __restrict__ cnt, int k,
+                                                            GroupBounds B, int G,
+                                                            unsigned long long* __restrict__ mask)
+{
+    __shared__ int32_t s_lo[kMaxGroups + 1];
+    __shared__ unsigned long long s_mask[kMaxGroups];
+    for (int t = threadIdx.x; t <= G; t += blockDim.x) s_lo[t] = B.lo[t];
+    for (int t = threadIdx.x; t < G; t += blockDim.x) s_mask[t] = 0ull;
+    __syncthreads();
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int32_t n_act = s_lo[G];
+    if (i < n_act) {
+        const int gi = group_of_slot(s_lo, G, int32_t(i));
+        const int c = cnt[i];
+        unsigned long long row = 0ull;
+        for (int t = 1; t < c; ++t) {
+            const int32_t j = nbr[i * k + t];
+            if (j < 0 || j >= n_act) continue;
+            const int gj = group_of_slot(s_lo, G, j);
+            if (gj != gi) {
+                row |= 1ull << gj;
+                atomicOr(&s_mask[gj], 1ull << gi);
+            }
+        }
+        if (row) atomicOr(&s_mask[gi], row);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < G; t += blockDim.x)
+        if (s_mask[t]) atomicOr(&mask[t], s_mask[t]);
+}
+
+__global__ __launch_bounds__(256) void k_copy_range(double* __restrict__ dst, const double* __restrict__ src,
+                                                    int64_t n)
+{
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+int max_groups() { return kMaxGroups; }
+
+int launch_group_interactions(const gd_problem* p, const gd_neighbors* nb, const int32_t* group_lo, int32_t G,
+                              uint64_t* mask, hipStream_t st)
+{
+    launch_fill_i32(reinterpret_cast<int32_t*>(mask), 2 * int64_t(G), 0, st);
+    GroupBounds B{};
+    for (int g = 0; g <= G; ++g) B.lo[g] = group_lo[g];
+    if (B.lo[G] <= 0) return 0;
+    const int grid = int((int64_t(B.lo[G]) + 255) / 256);
+    hipLaunchKernelGGL(k_group_interactions, dim3(grid), dim3(256), 0, st, nb->nbr, nb->cnt, p->k, B, G,
+                       reinterpret_cast<unsigned long long*>(mask));
+    return 0;
+}
+
+int launch_publish_group(const gd_particles* s, int64_t lo, int64_t hi, hipStream_t st)
+{
+    const int64_t n = hi - lo;
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_copy_range, dim3(int((n + 255) / 256)), dim3(256), 0, st, s->m[s->cur] + lo,
+                       s->m[s->cur ^ 1] + lo, n);
+    return 0;
+}
+
+}  // namespace gd

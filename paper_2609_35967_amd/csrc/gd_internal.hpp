@@ -39,6 +39,16 @@ int launch_sample_table(void* table, int32_t nslot, int32_t k, int32_t rates_fp3
 int launch_push(const gd_problem* p, const gd_particles* s, const gd_interval* iv, double dt, void* ws,
                 const Layout& L, hipStream_t st);
 void launch_interval_init(gd_interval* iv, double dt_coll, hipStream_t st);
+int launch_rates_group(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
+                       double* lam_i, int64_t lo, int64_t hi, int64_t z_lo, int64_t z_hi, void* ws, const Layout& L,
+                       hipStream_t st);
+int launch_sample_group(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
+                        const double* lam_i, uint64_t seed, uint32_t interval, int64_t lo, int64_t hi,
+                        int32_t* n_events, void* ws, const Layout& L, hipStream_t st);
+int max_groups();
+int launch_group_interactions(const gd_problem* p, const gd_neighbors* nb, const int32_t* group_lo, int32_t G,
+                              uint64_t* mask, hipStream_t st);
+int launch_publish_group(const gd_particles* s, int64_t lo, int64_t hi, hipStream_t st);
 int launch_diffuse(const gd_problem* p, const gd_particles* s, double dt, uint64_t seed, uint32_t step,
                    hipStream_t st);
 void launch_bin_reduce(int mode, const double* msnap, const double* M, const double* va, const double* vb, int64_t n,

@@ -49,6 +49,7 @@ struct McArgs {
     struct Deferred* heavy;
     int32_t* heavy_n;
     int32_t* heavy_next;
+    int64_t n_all;  // length of the snapshot: neighbour indices lie in [0, n_all)
 };
 
 // a particle handed over after e events, at time t of the interval, with mass m
@@ -73,7 +74,7 @@ __device__ inline double prefix_rates_f32(const McArgs& A, const QCtxF& q, const
     for (int s = 0; s < KP2; ++s) {
         if (s < c) {
             int j = row[s];
-            if (j < 0 || j >= A.P.n) {
+            if (j < 0 || j >= A.n_all) {
                 set_status(A.ws, GD_DEV_INTERNAL);
                 j = 0;
             }
@@ -97,7 +98,7 @@ __device__ inline double prefix_rates(const McArgs& A, const QCtx& q, const int3
     for (int s = 0; s < KP2; ++s) {
         if (s < c) {
             int j = row[s];
-            if (j < 0 || j >= A.P.n) {
+            if (j < 0 || j >= A.n_all) {
                 set_status(A.ws, GD_DEV_INTERNAL);
                 j = 0;
             }
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
                     found = found || hit;
                 }
                 int j = row[sel];
-                if (j < 0 || j >= A.P.n) j = 0;
+                if (j < 0 || j >= A.n_all) j = 0;
                 const double4 sn = A.snap[j];
                 const double mj = sn.x;
                 const double sj = phys ? sn.y : 0.0;
@@ -285,8 +286,8 @@ __device__ inline int run_deferred(const McArgs& A, int32_t hidx, int lane)
     if (F32) query_ctx_f32(A.P, q, qf);
     const bool mine = lane < c && lane < KP2;
     int j = mine ? A.nbr[i * k + lane] : 0;
-    if (mine && (j < 0 || j >= A.P.n)) set_status(A.ws, GD_DEV_INTERNAL);
-    if (j < 0 || j >= A.P.n) j = 0;
+    if (mine && (j < 0 || j >= A.n_all)) set_status(A.ws, GD_DEV_INTERNAL);
+    if (j < 0 || j >= A.n_all) j = 0;
     const double4 sn = A.snap[j];
     double si = 0.0, Sti = 0.0;
     Pair o{};
@@ -567,12 +568,13 @@ static McArgs mc_args(const gd_problem* p, const gd_particles* s, const gd_neigh
     A.heavy = at<Deferred>(ws, L.heavy);
     A.heavy_n = &h->heavy_n;
     A.heavy_next = &h->heavy_next;
+    A.n_all = p->n;
     return A;
 }
 
 static void launch_first(const McArgs& A, const gd_problem* p, hipStream_t st)
 {
-    const int g = int((p->n + 255) / 256);
+    const int g = int((A.P.n + 255) / 256);
     if (p->rates_fp32) {
         if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, true>), dim3(g), dim3(256), 0, st, A);
         else hipLaunchKernelGGL((k_mc<64, true>), dim3(g), dim3(256), 0, st, A);
@@ -621,6 +623,41 @@ int launch_sample(const gd_problem* p, const gd_particles* s, const gd_neighbors
     launch_deferred(A, p, st);
     prof_mark(GD_PROF_MC, 1, st);
     return launch_audit(p, s, iv, ws, L, st);
+}
+
+// Sampling and audit of the slots [lo, hi) only (one spatial group); the
+// group's interval state supplies dt_exe and takes the audit.
+int launch_sample_group(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
+                        const double* lam_i, uint64_t seed, uint32_t interval, int64_t lo, int64_t hi,
+                        int32_t* n_events, void* ws, const Layout& L, hipStream_t st)
+{
+    McArgs A = mc_args(p, s, nb, iv, lam_i, seed, interval, false, n_events, nullptr, 0, ws, L);
+    const int64_t cnt = hi - lo;
+    A.P.n = cnt;
+    A.id = s->id + lo;
+    A.nbr = nb->nbr + lo * int64_t(p->k);
+    A.cnt = nb->cnt + lo;
+    A.dmax = nb->dmax + lo;
+    A.m = s->m[s->cur] + lo;
+    A.x = s->x + lo;
+    A.y = s->y + lo;
+    A.z = s->z + lo;
+    A.lam_i = lam_i + lo;
+    A.m_out = s->m[s->cur ^ 1] + lo;
+    A.n_events = n_events ? n_events + lo : nullptr;
+    prof_mark(GD_PROF_MC, 0, st);
+    if (cnt > 0) launch_first(A, p, st);
+    launch_deferred(A, p, st);
+    prof_mark(GD_PROF_MC, 1, st);
+    WsHeader* h = at<WsHeader>(ws, L.hdr);
+    double* part = at<double>(ws, L.part);
+    DevProblem P = to_dev(p);
+    P.n = cnt;
+    prof_mark(GD_PROF_AUDIT, 0, st);
+    launch_bin_reduce(1, s->m[s->cur] + lo, s->M + lo, s->m[s->cur ^ 1] + lo, nullptr, cnt, part, ws, st);
+    hipLaunchKernelGGL(k_audit, dim3(1), dim3(kAuditGroups * kNBin), 0, st, P, part, kRedBlocks, iv, h);
+    prof_mark(GD_PROF_AUDIT, 1, st);
+    return 0;
 }
 
 size_t sample_table_bytes(int32_t nslot)

@@ -37,11 +37,13 @@ struct RatesArgs {
     const double* y;
     const double* z;
     const double4* snap;
+    const double4* snap_own;  // the particle's own record: snap offset to the first own slot
     double* lam;
     double* lam_pair;
     double* a;
     double* b;
     void* ws;
+    int64_t n_all;  // length of the snapshot: neighbour indices lie in [0, n_all)
 };
 
 constexpr int kGather = 4;  // neighbours whose slot and record loads are in flight together
@@ -69,7 +71,7 @@ __global__ __launch_bounds__(256) void k_rates(RatesArgs A)
         QCtx q;
         query_ctx(A.P, A.x[i], A.y[i], A.z[i], A.dmax[i], q);
         const double mi = A.m[i];
-        const double si = phys ? A.snap[i].y : 0.0;
+        const double si = phys ? A.snap_own[i].y : 0.0;
         const double Sti = phys ? q.stfac * si : 0.0;
         if (!(mi > 0.0) || !isfinite(mi)) set_status(A.ws, GD_DEV_NONFINITE);
         const int cmax = c < k ? c : k;
@@ -78,13 +80,13 @@ __global__ __launch_bounds__(256) void k_rates(RatesArgs A)
         for (int s0 = 0; s0 < cmax; s0 += kGather) {
             int jj[kGather];
             double4 rec[kGather];
-            gather_neighbours(A.nbr + i * k, s0, cmax, A.P.n, A.snap, jj, rec);
+            gather_neighbours(A.nbr + i * k, s0, cmax, A.n_all, A.snap, jj, rec);
 #pragma unroll
             for (int t = 0; t < kGather; ++t) {
             const int s = s0 + t;
             if (s >= cmax) break;
             const int j = jj[t];
-            if (j < 0 || j >= A.P.n) {
+            if (j < 0 || j >= A.n_all) {
                 set_status(A.ws, GD_DEV_INTERNAL);
                 continue;
             }
@@ -126,13 +128,13 @@ __global__ __launch_bounds__(256) void k_rates_f32(RatesArgs A)
         QCtxF qf;
         query_ctx_f32(A.P, q, qf);
         const double mi = A.m[i];
-        const float si = phys ? float(A.snap[i].y) : 0.0f;
+        const float si = phys ? float(A.snap_own[i].y) : 0.0f;
         const float Sti = phys ? qf.stfac * si : 0.0f;
         const double rmi = 1.0 / mi;
         float mJf = 0.0f, mJ2f = 0.0f;
         if (phys) {
             double mJ, mJ2;
-            frag_moments(A.snap[i].y, A.P.s_min, mJ, mJ2);
+            frag_moments(A.snap_own[i].y, A.P.s_min, mJ, mJ2);
             mJf = float(mJ);
             mJ2f = float(mJ2);
         }
@@ -141,13 +143,13 @@ __global__ __launch_bounds__(256) void k_rates_f32(RatesArgs A)
         for (int s0 = 0; s0 < cmax; s0 += kGather) {
             int jj[kGather];
             double4 rec[kGather];
-            gather_neighbours(A.nbr + i * k, s0, cmax, A.P.n, A.snap, jj, rec);
+            gather_neighbours(A.nbr + i * k, s0, cmax, A.n_all, A.snap, jj, rec);
 #pragma unroll
             for (int t = 0; t < kGather; ++t) {
             const int s = s0 + t;
             if (s >= cmax) break;
             const int j = jj[t];
-            if (j < 0 || j >= A.P.n) {
+            if (j < 0 || j >= A.n_all) {
                 set_status(A.ws, GD_DEV_INTERNAL);
                 continue;
             }
@@ -452,11 +454,69 @@ int launch_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors*
     A.a = ab ? ab : at<double>(ws, L.a);
     A.b = ab ? ab + n : at<double>(ws, L.b);
     A.ws = ws;
+    A.n_all = n;
+    A.snap_own = snap;
     if (p->rates_fp32) hipLaunchKernelGGL(k_rates_f32, dim3(g), dim3(256), 0, st, A);
     else hipLaunchKernelGGL(k_rates, dim3(g), dim3(256), 0, st, A);
     double* part = at<double>(ws, L.part);
     launch_bin_reduce(0, m, s->M, A.a, A.b, n, part, ws, st);
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanGroups * kNBin), 0, st, P, part, kRedBlocks, iv, at<WsHeader>(ws, L.hdr), ws);
+    prof_mark(GD_PROF_RATES, 1, st);
+    return 0;
+}
+
+// Rates and plan of the slots [lo, hi) only (one spatial group): the snapshot
+// still covers every particle, the particle's own arrays are addressed from lo,
+// and the executed interval is then held within [z_lo, z_hi] ticks.
+__global__ void k_group_clamp(gd_interval* iv, int64_t z_lo, int64_t z_hi)
+{
+    if (threadIdx.x != 0) return;
+    const int64_t ticks = iv->ticks;
+    int64_t z = iv->exe_ticks;
+    if (z > z_hi) z = z_hi;
+    if (z < z_lo) z = z_lo;
+    while (z > 1 && ((ticks % z) != 0 || ticks + z > kTicks)) z >>= 1;
+    iv->exe_ticks = z;
+    iv->dt_exe = double(z) * ldexp(iv->dt_coll, -30);
+}
+
+int launch_rates_group(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
+                       double* lam_i, int64_t lo, int64_t hi, int64_t z_lo, int64_t z_hi, void* ws, const Layout& L,
+                       hipStream_t st)
+{
+    DevProblem P = to_dev(p);
+    const int64_t n = p->n, cnt = hi - lo;
+    const double* m = s->m[s->cur];
+    double4* snap = at<double4>(ws, L.snap);
+    prof_mark(GD_PROF_RATES, 0, st);
+    hipLaunchKernelGGL(k_snapshot, dim3(int((n + 255) / 256)), dim3(256), 0, st, P, m, s->M, n, snap);
+    P.n = cnt;
+    RatesArgs A{};
+    A.P = P;
+    A.nbr = nb->nbr + lo * int64_t(p->k);
+    A.cnt = nb->cnt + lo;
+    A.dmax = nb->dmax + lo;
+    A.m = m + lo;
+    A.x = s->x + lo;
+    A.y = s->y + lo;
+    A.z = s->z + lo;
+    A.snap = snap;
+    A.snap_own = snap + lo;
+    A.lam = lam_i + lo;
+    A.lam_pair = nullptr;
+    A.a = at<double>(ws, L.a) + lo;
+    A.b = at<double>(ws, L.b) + lo;
+    A.ws = ws;
+    A.n_all = n;
+    const int g = int((cnt + 255) / 256);
+    if (cnt > 0) {
+        if (p->rates_fp32) hipLaunchKernelGGL(k_rates_f32, dim3(g), dim3(256), 0, st, A);
+        else hipLaunchKernelGGL(k_rates, dim3(g), dim3(256), 0, st, A);
+    }
+    double* part = at<double>(ws, L.part);
+    launch_bin_reduce(0, m + lo, s->M + lo, A.a, A.b, cnt, part, ws, st);
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanGroups * kNBin), 0, st, P, part, kRedBlocks, iv, at<WsHeader>(ws, L.hdr), ws);
+    hipLaunchKernelGGL(k_group_clamp, dim3(1), dim3(64), 0, st, iv, z_lo, z_hi);
     prof_mark(GD_PROF_RATES, 1, st);
     return 0;
 }
