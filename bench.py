@@ -381,6 +381,44 @@ def strang_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def groups_bench(args):
+    """Collision steps C(dt_coll) without transport on the disk: the single-group
+    operator against args.groups spatial groups with the ratio-16 rule, on the
+    same particles (neighbour lists built once, as with static positions)."""
+    import torch
+    from paper_2609_35967_amd import Engine, load
+
+    load()
+    torch.cuda.set_device(0)
+    params, st = workloads.by_name(args.workload, seed=args.seed, n=args.n)
+    single = Engine(params, st, seed=args.seed)
+    grouped = Engine(params, st, seed=args.seed)
+    grouped.set_groups(args.groups)
+    n = single.n
+    for _ in range(max(1, args.warmup)):
+        single.collide()
+        grouped.collide_groups()
+    counts = []
+    wall_s, lat_s = _timed_loop(lambda s: counts.append(single.collide()), args.steps)
+    gcounts = []
+    wall_g, lat_g = _timed_loop(lambda s: gcounts.append(len(grouped.collide_groups())), args.steps)
+    out = dict(
+        metric="particle-collision-steps/s of the collision operator with spatial groups (Sect. 2.5.3)",
+        value=round(n * args.steps / wall_g, 1), unit="particle-collision-steps/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(wall_g / args.steps * 1e3, 4), higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload=f"{args.workload}: 3D disk annulus r in [10,100] au, {n} particles, k=32, "
+                             f"alpha=1e-3, v_frag=1 m/s; one collision step of dt_coll = P(10 au)/50 without "
+                             f"transport, {args.groups} Morton-range groups", n_particles=n, groups=args.groups),
+        p50_ms=round(float(np.percentile(lat_g, 50)), 4), p99_ms=round(float(np.percentile(lat_g, 99)), 4),
+        group_intervals_per_step=round(float(np.mean(gcounts)), 2),
+        single=dict(value=round(n * args.steps / wall_s, 1), ms_per_step=round(wall_s / args.steps * 1e3, 4),
+                    intervals_per_step=round(float(np.mean(counts)), 2)),
+        status=grouped.status(),
+    )
+    print(json.dumps(out), flush=True)
+
+
 def serve_bench(args):
     """Served stream: disk-annulus runs (N log-uniform 2^12..2^20, alpha and
     v_frag as the batched boxes, 50 intervals each) arrive as a Poisson
@@ -506,18 +544,22 @@ def main():
                     help="the diffusion operator on the 2^20-particle dust-ring test instead")
     ap.add_argument("--strang", action="store_true",
                     help="paper-cadence transport steps C D T D C on the disk instead")
+    ap.add_argument("--groups", type=int, default=0, metavar="G",
+                    help="collision steps with G spatial groups against the single group instead")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
-    if args.diffusion or args.strang:
+    if args.diffusion or args.strang or args.groups:
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
         if args.diffusion:
             diffusion_bench(args)
-        else:
+        elif args.strang:
             strang_bench(args)
+        else:
+            groups_bench(args)
         return
     if args.batch or args.serve:
         if args.gpus != 1:

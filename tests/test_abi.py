@@ -166,3 +166,36 @@ def test_diffuse_validation(lib):
     off = binding.make_problem(dict(base, diffusion="none"))
     assert lib.gd_diffuse(C.byref(off), None, -1.0, 1, 0, None) == 0
     assert ok.vint == 1
+
+
+def test_group_call_validation(lib):
+    # the spatial-group calls reject bad group tables, ranges and interval limits
+    from paper_2609_35967_amd import binding
+    P = binding.make_problem(workloads.const_box_params(1000))
+    nb = binding.GdNeighbors(4096, 4096, 4096, None)
+    fake = binding.GdParticles()
+    for k in ("id", "x", "y", "z", "M"):
+        setattr(fake, k, 256)
+    fake.m[0] = 256
+    fake.m[1] = 512
+    lo = (C.c_int32 * 3)(0, 500, 1000)
+    assert lib.gd_group_interactions(C.byref(P), C.byref(nb), lo, 0, C.c_void_p(256), None) == -1
+    assert lib.gd_group_interactions(C.byref(P), C.byref(nb), lo, 65, C.c_void_p(256), None) == -1
+    assert lib.gd_group_interactions(C.byref(P), C.byref(nb), lo, 2, None, None) == -1
+    bad = (C.c_int32 * 3)(0, 500, 500)
+    assert lib.gd_group_interactions(C.byref(P), C.byref(nb), bad, 2, C.c_void_p(256), None) == -1
+    assert b"non-empty" in lib.gd_last_error()
+    over = (C.c_int32 * 3)(0, 500, 1001)
+    assert lib.gd_group_interactions(C.byref(P), C.byref(nb), over, 2, C.c_void_p(256), None) == -1
+    ws = (C.c_void_p(256), 1 << 40)
+    args = (C.byref(P), C.byref(fake), C.byref(nb), C.c_void_p(256), C.c_void_p(256))
+    assert lib.gd_collision_rates_group(*args, 10, 5, 1, 1 << 30, *ws, None) == -1
+    assert b"range" in lib.gd_last_error()
+    assert lib.gd_collision_rates_group(*args, 0, 1001, 1, 1 << 30, *ws, None) == -1
+    assert lib.gd_collision_rates_group(*args, 0, 10, 3, 1 << 30, *ws, None) == -1
+    assert lib.gd_collision_rates_group(*args, 0, 10, 64, 32, *ws, None) == -1
+    assert lib.gd_collision_rates_group(*args, 0, 10, 1, 1 << 31, *ws, None) == -1
+    assert b"powers of two" in lib.gd_last_error()
+    assert lib.gd_sample_collisions_group(*args, 1, 1 << 32, 0, 10, None, *ws, None) == -1
+    assert lib.gd_sample_collisions_group(*args, 1, 0, -1, 10, None, *ws, None) == -1
+    assert lib.gd_publish_group(C.byref(P), C.byref(fake), 5, 1001, None) == -1
