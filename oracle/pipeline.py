@@ -147,6 +147,12 @@ class GroupedRun(OracleRun):
         self.links = None
         self.log = []
 
+    def collide(self, log_cap: int = 0):
+        """The collision operator of strang_step: the grouped one."""
+        start = len(self.log)
+        self.collide_groups()
+        return [dict(mc=dict(near_tie=np.array([e["near_tie"]]))) for e in self.log[start:]]
+
     def _layout(self):
         n_act = int(np.count_nonzero(self.st["M"] > 0))
         G = self.n_groups

@@ -427,10 +427,12 @@ class Engine:
     def strang_step(self) -> int:
         """One transport step dt = 2 dt_coll in the symmetric sequence of Sect. 2.6:
         C(dt/2) D(dt/2) T(dt) D(dt/2) C(dt/2).  The last collision operator of a
-        step and the first of the next share their neighbour lists.  Returns the
-        number of intervals run."""
+        step and the first of the next share their neighbour lists.  With groups
+        set (set_groups), the collision operators are the grouped ones.  Returns
+        the number of (group) intervals run."""
         h = float(self.params["dt_coll"])
-        n = self.collide()
+        collide = (lambda: len(self.collide_groups())) if getattr(self, "n_groups", 0) else self.collide
+        n = collide()
         if self.P.diffusion != 0:
             self.diffuse(h, self.diff_step)
             self.diff_step += 1
@@ -438,7 +440,7 @@ class Engine:
         if self.P.diffusion != 0:
             self.diffuse(h, self.diff_step)
             self.diff_step += 1
-        return n + self.collide()
+        return n + collide()
 
     def step(self, rebuild: bool = True):
         """One frozen-neighbour interval: kNN, rates + plan, sampling, push."""

@@ -97,3 +97,16 @@ def test_independent_groups_run_their_requests():
     # clusters of lighter grains (faster rates) take more intervals
     n_int = [sum(1 for e in run.log if e["group"] == g) for g in range(4)]
     assert n_int == sorted(n_int) and n_int[-1] > n_int[0]
+
+
+def test_grouped_strang_steps_regroup_after_motion():
+    params = dict(workloads.diffusion_ring_params("density", n=1024), kernel="const", t0=1e3, m0=1.0, eps=0.08,
+                  dt_fn_max=10.0)
+    st = workloads.diffusion_ring(3, 1024)
+    run = GroupedRun(params, st, seed=2, n_groups=4)
+    out = run.strang_step()
+    first = list(run.bounds)
+    out += run.strang_step()
+    assert len(out) == len(run.log) and run.diff_step == 4
+    assert first == run.bounds == [0, 256, 512, 768, 1024]
+    _tiles([(e["group"], e["start"], e["ticks"]) for e in run.log[-4:]], 4)
