@@ -294,18 +294,23 @@ int32_t gd_push(const gd_problem* p, const gd_particles* st, const gd_interval* 
 int32_t gd_group_interactions(const gd_problem* p, const gd_neighbors* nb, const int32_t* group_lo, int32_t n_groups,
                               uint64_t* mask, void* stream);
 
-/* gd_collision_rates for the slots [lo, hi) of one group: the snapshot of the
- * neighbourhood covers every particle (from m[cur]); lambda*_i and the
- * controller moments are computed for the group's slots only; the plan uses
- * the group's controller bins and its interval state iv; the executed
- * interval is then held to [z_lo, z_hi] ticks (powers of two,
- * 1 <= z_lo <= z_hi <= 2^30, the lower bound taking precedence) and halved
- * until it starts on a multiple of itself and ends within the collision step.
- * The bounds carry the rule that the intervals of interacting groups differ by
- * at most a factor 16 while scheduled intervals are kept. */
+/* gd_collision_rates for the slots [lo, hi) of group `group` (of n_groups):
+ * with snapshot != 0 the snapshot of the neighbourhood of every particle is
+ * first refreshed from m[cur] (groups planned at the same instant share it;
+ * pass 1 for the first of them); lambda*_i and the controller moments are
+ * computed for the group's slots only; the plan uses the group's controller
+ * bins and its interval state iv.  The executed interval is then held within
+ * 1/16 and 16 times the scheduled interval sched[h] of every group h set in
+ * rows[group] (rows from gd_group_interactions; sched: DEVICE int64[n_groups]
+ * of ticks, 0 = nothing scheduled), the lower limit taking precedence where
+ * the two conflict (a scheduled interval is kept; the refinement waits), then
+ * halved until it starts on a multiple of itself and ends within the
+ * collision step, and written to iv and to sched[group].  The caller sets
+ * sched[h] = 0 when group h's interval ends. */
 int32_t gd_collision_rates_group(const gd_problem* p, const gd_particles* st, const gd_neighbors* nb,
-                                 gd_interval* iv, double* lambda_i, int64_t lo, int64_t hi, int64_t z_lo, int64_t z_hi,
-                                 void* ws, size_t ws_bytes, void* stream);
+                                 gd_interval* iv, double* lambda_i, int64_t lo, int64_t hi, int32_t group,
+                                 int32_t n_groups, const uint64_t* rows, int64_t* sched, int32_t snapshot, void* ws,
+                                 size_t ws_bytes, void* stream);
 
 /* gd_sample_collisions for the slots [lo, hi) of one group over iv->dt_exe,
  * against the snapshot of the preceding gd_collision_rates_group call, writing
@@ -318,9 +323,11 @@ int32_t gd_sample_collisions_group(const gd_problem* p, const gd_particles* st, 
                                    int64_t lo, int64_t hi, int32_t* n_events, void* ws, size_t ws_bytes,
                                    void* stream);
 
-/* Broadcast of a group at the end of its interval: m[cur][lo, hi) =
- * m[cur ^ 1][lo, hi). */
-int32_t gd_publish_group(const gd_problem* p, const gd_particles* st, int64_t lo, int64_t hi, void* stream);
+/* Broadcast of group `group` at the end of its interval: m[cur][lo, hi) =
+ * m[cur ^ 1][lo, hi), and sched[group] = 0 when sched (DEVICE, as in
+ * gd_collision_rates_group) is non-NULL. */
+int32_t gd_publish_group(const gd_problem* p, const gd_particles* st, int64_t lo, int64_t hi, int64_t* sched,
+                         int32_t group, void* stream);
 
 /* Dust diffusion operator D (Sect. 2.4), one Euler--Maruyama step of length
  * dt >= 0 on every active particle of st (M_i > 0), in place.

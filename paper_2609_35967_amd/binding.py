@@ -107,11 +107,13 @@ def load(path: str | None = None):
     L.gd_diffuse.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.c_double, C.c_uint64, C.c_uint32, vp]
     L.gd_group_interactions.argtypes = [C.POINTER(GdProblem), C.POINTER(GdNeighbors), vp, C.c_int32, vp, vp]
     L.gd_collision_rates_group.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.POINTER(GdNeighbors), vp,
-                                           vp, C.c_int64, C.c_int64, C.c_int64, C.c_int64, vp, C.c_size_t, vp]
+                                           vp, C.c_int64, C.c_int64, C.c_int32, C.c_int32, vp, vp, C.c_int32, vp,
+                                           C.c_size_t, vp]
     L.gd_sample_collisions_group.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.POINTER(GdNeighbors),
                                              vp, vp, C.c_uint64, C.c_uint64, C.c_int64, C.c_int64, vp, vp,
                                              C.c_size_t, vp]
-    L.gd_publish_group.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.c_int64, C.c_int64, vp]
+    L.gd_publish_group.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.c_int64, C.c_int64, vp, C.c_int32,
+                                   vp]
     L.gd_status_read.argtypes = [vp, vp, C.POINTER(C.c_int32)]
     L.gd_profile_events.argtypes = [C.c_int32, vp, vp]
     L.gd_last_error.restype = C.c_char_p
@@ -354,6 +356,7 @@ class Engine:
             check(self.lib.gd_interval_init(C.c_void_p(self.ivg[g].data_ptr()), float(self.params["dt_coll"]),
                                             self._s()))
         self.gmask = torch.zeros(self.n_groups, dtype=torch.int64, device=self.device)
+        self.gsched = torch.zeros(self.n_groups, dtype=torch.int64, device=self.device)  # scheduled ticks, 0: none
         self.group_lo = None
 
     def _group_layout(self):
@@ -381,46 +384,44 @@ class Engine:
         own frozen-neighbour intervals; at each instant the groups whose interval
         ends broadcast their masses, then the groups starting there plan in
         ascending order, each interval held within 1/16 .. 16 times the intervals
-        already scheduled for the groups it interacts with (the lower bound wins
-        when the two conflict).  A group's interval is sampled when it starts; its
-        masses are broadcast when it ends.  Returns the executed intervals as
-        (group, start tick, ticks).  Synchronises once per group interval."""
+        already scheduled for the groups it interacts with (the lower limit wins
+        when the two conflict; the limits are applied on the device).  A group's
+        interval is sampled when it starts, against one snapshot per instant;
+        its masses are broadcast when it ends.  Returns the executed intervals
+        as (group, start tick, ticks).  Synchronises once per instant."""
         T = 1 << 30
         if self.moved or self.group_lo is None:
             if self.moved:
                 self.build_neighbors()
             self._group_layout()
         G, lo = self.n_groups, self.group_lo
-        size = [0] * G
         end = [0] * G
         tau, starting, done = 0, list(range(G)), []
         sa = self.A.struct()
+        rows = C.c_void_p(self.gmask.data_ptr())
+        sched = C.c_void_p(self.gsched.data_ptr())
         while True:
-            for g in starting:
-                z_lo, z_hi = 1, T
-                for h in range(G):
-                    if h != g and size[h] and (self.group_rows[g] >> h) & 1:
-                        z_lo = max(z_lo, size[h] // 16)
-                        z_hi = min(z_hi, 16 * size[h])
-                z_hi = max(z_hi, z_lo)
+            for idx, g in enumerate(starting):
                 ivp = C.c_void_p(self.ivg[g].data_ptr())
                 check(self.lib.gd_collision_rates_group(C.byref(self.P), C.byref(sa), C.byref(self.nb), ivp,
-                                                        _ptr(self.lam), lo[g], lo[g + 1], z_lo, z_hi,
-                                                        C.c_void_p(self.ws_ptr), self.ws_bytes, self._s()))
+                                                        _ptr(self.lam), lo[g], lo[g + 1], g, G, rows, sched,
+                                                        1 if idx == 0 else 0, C.c_void_p(self.ws_ptr), self.ws_bytes,
+                                                        self._s()))
                 check(self.lib.gd_sample_collisions_group(C.byref(self.P), C.byref(sa), C.byref(self.nb), ivp,
                                                           _ptr(self.lam), self.seed, self.interval, lo[g], lo[g + 1],
                                                           _ptr(self.events), C.c_void_p(self.ws_ptr), self.ws_bytes,
                                                           self._s()))
                 self.interval += 1
-                z = int(self.group_interval_state(g)["exe_ticks"])
-                size[g] = z
-                end[g] = tau + z
-                done.append((g, tau, z))
+            if self.stream is not None:
+                self.stream.synchronize()
+            sizes = self.gsched.cpu().tolist()
+            for g in starting:
+                end[g] = tau + int(sizes[g])
+                done.append((g, tau, int(sizes[g])))
             tau = min(end)
             starting = [g for g in range(G) if end[g] == tau]
             for g in starting:
-                check(self.lib.gd_publish_group(C.byref(self.P), C.byref(sa), lo[g], lo[g + 1], self._s()))
-                size[g] = 0
+                check(self.lib.gd_publish_group(C.byref(self.P), C.byref(sa), lo[g], lo[g + 1], sched, g, self._s()))
             if tau == T:
                 return done
 

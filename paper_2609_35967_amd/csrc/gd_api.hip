@@ -377,8 +377,9 @@ int32_t gd_group_interactions(const gd_problem* p, const gd_neighbors* nb, const
 }
 
 int32_t gd_collision_rates_group(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb,
-                                 gd_interval* iv, double* lam_i, int64_t lo, int64_t hi, int64_t z_lo, int64_t z_hi,
-                                 void* ws, size_t ws_bytes, void* stream)
+                                 gd_interval* iv, double* lam_i, int64_t lo, int64_t hi, int32_t group,
+                                 int32_t n_groups, const uint64_t* rows, int64_t* sched, int32_t snapshot, void* ws,
+                                 size_t ws_bytes, void* stream)
 {
     int rc = check_problem(p);
     if (!rc) rc = check_state(p, s, false);
@@ -386,13 +387,15 @@ int32_t gd_collision_rates_group(const gd_problem* p, const gd_particles* s, con
     if (!rc) rc = check_range(p, lo, hi);
     if (rc) return rc;
     if (!iv || !lam_i) return fail(GD_E_INVALID_ARG, "interval and lam_i are required");
-    if (z_lo < 1 || z_hi < z_lo || z_hi > (int64_t(1) << 30) || (z_lo & (z_lo - 1)) || (z_hi & (z_hi - 1)))
-        return fail(GD_E_INVALID_ARG, "z_lo, z_hi must be powers of two with 1 <= z_lo <= z_hi <= 2^30");
+    if (n_groups < 1 || n_groups > max_groups() || group < 0 || group >= n_groups)
+        return fail(GD_E_INVALID_ARG, "group %d of n_groups %d outside 0..%d", group, n_groups, max_groups() - 1);
+    if (!rows || !sched) return fail(GD_E_INVALID_ARG, "rows and sched are required");
     Layout L;
     rc = check_ws(p, ws, ws_bytes, L);
     if (rc) return rc;
     if (p->n == 0) return GD_OK;
-    launch_rates_group(p, s, nb, iv, lam_i, lo, hi, z_lo, z_hi, ws, L, static_cast<hipStream_t>(stream));
+    launch_rates_group(p, s, nb, iv, lam_i, lo, hi, group, n_groups, rows, sched, snapshot != 0, ws, L,
+                       static_cast<hipStream_t>(stream));
     return hip_ok("gd_collision_rates_group");
 }
 
@@ -416,13 +419,15 @@ int32_t gd_sample_collisions_group(const gd_problem* p, const gd_particles* s, c
     return hip_ok("gd_sample_collisions_group");
 }
 
-int32_t gd_publish_group(const gd_problem* p, const gd_particles* s, int64_t lo, int64_t hi, void* stream)
+int32_t gd_publish_group(const gd_problem* p, const gd_particles* s, int64_t lo, int64_t hi, int64_t* sched,
+                         int32_t group, void* stream)
 {
     int rc = check_problem(p);
     if (!rc) rc = check_state(p, s, true);
     if (!rc) rc = check_range(p, lo, hi);
     if (rc) return rc;
-    launch_publish_group(s, lo, hi, static_cast<hipStream_t>(stream));
+    if (sched && (group < 0 || group >= max_groups())) return fail(GD_E_INVALID_ARG, "group %d out of range", group);
+    launch_publish_group(s, lo, hi, sched, group, static_cast<hipStream_t>(stream));
     return hip_ok("gd_publish_group");
 }
 

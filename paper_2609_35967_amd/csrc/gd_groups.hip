@@ -3,7 +3,8 @@
 // end of its interval.
 //
 // A group is a contiguous range of Morton-ordered slots, group_lo[g] ..
-// group_lo[g+1].  Groups g != h interact when a retained neighbour of a
+// group_lo[g+1].  sched[g] holds the ticks of group g's scheduled interval
+// (0: none); the broadcast at the end of the interval clears it.  Groups g != h interact when a retained neighbour of a
 // particle of one lies in the other; the relation is returned as one 64-bit
 // row per group.
 #include "gd_common.hpp"
@@ -60,11 +61,13 @@ __global__ __launch_bounds__(256) void k_group_interactions(const int32_t* __res
         if (s_mask[t]) atomicOr(&mask[t], s_mask[t]);
 }
 
+// broadcast of a group's masses; its scheduled interval is over
 __global__ __launch_bounds__(256) void k_copy_range(double* __restrict__ dst, const double* __restrict__ src,
-                                                    int64_t n)
+                                                    int64_t n, int64_t* sched, int group)
 {
     const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (i < n) dst[i] = src[i];
+    if (i == 0 && sched) sched[group] = 0;
 }
 
 int max_groups() { return kMaxGroups; }
@@ -82,12 +85,13 @@ int launch_group_interactions(const gd_problem* p, const gd_neighbors* nb, const
     return 0;
 }
 
-int launch_publish_group(const gd_particles* s, int64_t lo, int64_t hi, hipStream_t st)
+int launch_publish_group(const gd_particles* s, int64_t lo, int64_t hi, int64_t* sched, int32_t group,
+                         hipStream_t st)
 {
     const int64_t n = hi - lo;
-    if (n <= 0) return 0;
-    hipLaunchKernelGGL(k_copy_range, dim3(int((n + 255) / 256)), dim3(256), 0, st, s->m[s->cur] + lo,
-                       s->m[s->cur ^ 1] + lo, n);
+    const int64_t blocks = n > 0 ? (n + 255) / 256 : 1;
+    hipLaunchKernelGGL(k_copy_range, dim3(int(blocks)), dim3(256), 0, st, s->m[s->cur] + lo, s->m[s->cur ^ 1] + lo,
+                       n, sched, int(group));
     return 0;
 }
 

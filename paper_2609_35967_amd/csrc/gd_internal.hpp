@@ -40,15 +40,16 @@ int launch_push(const gd_problem* p, const gd_particles* s, const gd_interval* i
                 const Layout& L, hipStream_t st);
 void launch_interval_init(gd_interval* iv, double dt_coll, hipStream_t st);
 int launch_rates_group(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
-                       double* lam_i, int64_t lo, int64_t hi, int64_t z_lo, int64_t z_hi, void* ws, const Layout& L,
-                       hipStream_t st);
+                       double* lam_i, int64_t lo, int64_t hi, int32_t group, int32_t n_groups, const uint64_t* rows,
+                       int64_t* sched, bool snapshot, void* ws, const Layout& L, hipStream_t st);
 int launch_sample_group(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
                         const double* lam_i, uint64_t seed, uint32_t interval, int64_t lo, int64_t hi,
                         int32_t* n_events, void* ws, const Layout& L, hipStream_t st);
 int max_groups();
 int launch_group_interactions(const gd_problem* p, const gd_neighbors* nb, const int32_t* group_lo, int32_t G,
                               uint64_t* mask, hipStream_t st);
-int launch_publish_group(const gd_particles* s, int64_t lo, int64_t hi, hipStream_t st);
+int launch_publish_group(const gd_particles* s, int64_t lo, int64_t hi, int64_t* sched, int32_t group,
+                         hipStream_t st);
 int launch_diffuse(const gd_problem* p, const gd_particles* s, double dt, uint64_t seed, uint32_t step,
                    hipStream_t st);
 void launch_bin_reduce(int mode, const double* msnap, const double* M, const double* va, const double* vb, int64_t n,

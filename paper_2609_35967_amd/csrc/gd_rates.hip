@@ -465,12 +465,24 @@ int launch_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors*
     return 0;
 }
 
-// Rates and plan of the slots [lo, hi) only (one spatial group): the snapshot
-// still covers every particle, the particle's own arrays are addressed from lo,
-// and the executed interval is then held within [z_lo, z_hi] ticks.
-__global__ void k_group_clamp(gd_interval* iv, int64_t z_lo, int64_t z_hi)
+// Rates and plan of the slots [lo, hi) only (one spatial group): the particle's
+// own arrays are addressed from lo, the snapshot (refreshed first when asked)
+// covers every particle.  The executed interval is then held within 1/16 and
+// 16 times the scheduled intervals sched[h] (0: none) of the groups h set in
+// the group's interaction row (the lower limit wins a conflict), halved until
+// aligned, and recorded in sched[g].
+__global__ void k_group_clamp(gd_interval* iv, int g, int G, const unsigned long long* rows, int64_t* sched)
 {
     if (threadIdx.x != 0) return;
+    const unsigned long long row = rows[g];
+    int64_t z_lo = 1, z_hi = kTicks;
+    for (int h = 0; h < G; ++h) {
+        const int64_t zh = sched[h];
+        if (h == g || zh == 0 || !((row >> h) & 1ull)) continue;
+        if (zh / 16 > z_lo) z_lo = zh / 16;
+        if (16 * zh < z_hi) z_hi = 16 * zh;
+    }
+    if (z_hi < z_lo) z_hi = z_lo;
     const int64_t ticks = iv->ticks;
     int64_t z = iv->exe_ticks;
     if (z > z_hi) z = z_hi;
@@ -478,18 +490,19 @@ __global__ void k_group_clamp(gd_interval* iv, int64_t z_lo, int64_t z_hi)
     while (z > 1 && ((ticks % z) != 0 || ticks + z > kTicks)) z >>= 1;
     iv->exe_ticks = z;
     iv->dt_exe = double(z) * ldexp(iv->dt_coll, -30);
+    sched[g] = z;
 }
 
 int launch_rates_group(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
-                       double* lam_i, int64_t lo, int64_t hi, int64_t z_lo, int64_t z_hi, void* ws, const Layout& L,
-                       hipStream_t st)
+                       double* lam_i, int64_t lo, int64_t hi, int32_t group, int32_t n_groups, const uint64_t* rows,
+                       int64_t* sched, bool snapshot, void* ws, const Layout& L, hipStream_t st)
 {
     DevProblem P = to_dev(p);
     const int64_t n = p->n, cnt = hi - lo;
     const double* m = s->m[s->cur];
     double4* snap = at<double4>(ws, L.snap);
     prof_mark(GD_PROF_RATES, 0, st);
-    hipLaunchKernelGGL(k_snapshot, dim3(int((n + 255) / 256)), dim3(256), 0, st, P, m, s->M, n, snap);
+    if (snapshot) hipLaunchKernelGGL(k_snapshot, dim3(int((n + 255) / 256)), dim3(256), 0, st, P, m, s->M, n, snap);
     P.n = cnt;
     RatesArgs A{};
     A.P = P;
@@ -516,7 +529,8 @@ int launch_rates_group(const gd_problem* p, const gd_particles* s, const gd_neig
     double* part = at<double>(ws, L.part);
     launch_bin_reduce(0, m + lo, s->M + lo, A.a, A.b, cnt, part, ws, st);
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanGroups * kNBin), 0, st, P, part, kRedBlocks, iv, at<WsHeader>(ws, L.hdr), ws);
-    hipLaunchKernelGGL(k_group_clamp, dim3(1), dim3(64), 0, st, iv, z_lo, z_hi);
+    hipLaunchKernelGGL(k_group_clamp, dim3(1), dim3(64), 0, st, iv, int(group), int(n_groups),
+                       reinterpret_cast<const unsigned long long*>(rows), sched);
     prof_mark(GD_PROF_RATES, 1, st);
     return 0;
 }

@@ -189,13 +189,15 @@ def test_group_call_validation(lib):
     assert lib.gd_group_interactions(C.byref(P), C.byref(nb), over, 2, C.c_void_p(256), None) == -1
     ws = (C.c_void_p(256), 1 << 40)
     args = (C.byref(P), C.byref(fake), C.byref(nb), C.c_void_p(256), C.c_void_p(256))
-    assert lib.gd_collision_rates_group(*args, 10, 5, 1, 1 << 30, *ws, None) == -1
+    dev = (C.c_void_p(512), C.c_void_p(768))
+    assert lib.gd_collision_rates_group(*args, 10, 5, 0, 2, *dev, 1, *ws, None) == -1
     assert b"range" in lib.gd_last_error()
-    assert lib.gd_collision_rates_group(*args, 0, 1001, 1, 1 << 30, *ws, None) == -1
-    assert lib.gd_collision_rates_group(*args, 0, 10, 3, 1 << 30, *ws, None) == -1
-    assert lib.gd_collision_rates_group(*args, 0, 10, 64, 32, *ws, None) == -1
-    assert lib.gd_collision_rates_group(*args, 0, 10, 1, 1 << 31, *ws, None) == -1
-    assert b"powers of two" in lib.gd_last_error()
+    assert lib.gd_collision_rates_group(*args, 0, 1001, 0, 2, *dev, 1, *ws, None) == -1
+    assert lib.gd_collision_rates_group(*args, 0, 10, 2, 2, *dev, 1, *ws, None) == -1
+    assert lib.gd_collision_rates_group(*args, 0, 10, 0, 65, *dev, 1, *ws, None) == -1
+    assert lib.gd_collision_rates_group(*args, 0, 10, 0, 2, None, dev[1], 1, *ws, None) == -1
+    assert b"sched" in lib.gd_last_error()
     assert lib.gd_sample_collisions_group(*args, 1, 1 << 32, 0, 10, None, *ws, None) == -1
     assert lib.gd_sample_collisions_group(*args, 1, 0, -1, 10, None, *ws, None) == -1
-    assert lib.gd_publish_group(C.byref(P), C.byref(fake), 5, 1001, None) == -1
+    assert lib.gd_publish_group(C.byref(P), C.byref(fake), 5, 1001, None, 0, None) == -1
+    assert lib.gd_publish_group(C.byref(P), C.byref(fake), 0, 10, C.c_void_p(512), 64, None) == -1
