@@ -359,6 +359,8 @@ def strang_bench(args):
     params, st = workloads.by_name(args.workload, seed=args.seed, n=args.n)
     params = dict(params, diffusion="concentration", Sc=(1.0, 1.0, 1.0))
     eng = Engine(params, st, seed=args.seed)
+    if args.groups:
+        eng.set_groups(args.groups)
     n = eng.n
     for _ in range(args.warmup):
         eng.strang_step()
@@ -373,7 +375,7 @@ def strang_bench(args):
         config=dict(workload=f"{args.workload}: 3D disk annulus r in [10,100] au, {n} particles, k=32, "
                              "alpha=1e-3, v_frag=1 m/s, concentration diffusion Sc=1; one step is "
                              "C(dt/2) D(dt/2) T(dt) D(dt/2) C(dt/2) with dt/2 = P(10 au)/50",
-                    n_particles=n, k=32),
+                    n_particles=n, k=32, groups=args.groups or 1),
         p50_ms=round(float(np.percentile(lat, 50)), 4), p99_ms=round(float(np.percentile(lat, 99)), 4),
         intervals_per_step=round(float(np.mean(counts)), 3),
         status=eng.status(),
@@ -556,7 +558,7 @@ def main():
             sys.exit(2)
         if args.diffusion:
             diffusion_bench(args)
-        elif args.strang:
+        elif args.strang:  # with --groups G: grouped collision operators
             strang_bench(args)
         else:
             groups_bench(args)
