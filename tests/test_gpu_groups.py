@@ -141,3 +141,33 @@ def test_grouped_strang_steps_match_oracle():
         for g in range(4):
             assert eng.group_interval_state(g)["C"] == run.gC[g]
         _say("grouped strang step", step, "group intervals", n_gpu)
+
+
+@pytest.mark.parametrize("workload", ["disk3d", "disk3d_warm"])
+def test_grouped_step_full_size_properties(workload):
+    """The 1M disk with 8 groups, as bench.py --groups 8 runs it: every group's
+    intervals tile the collision step with aligned dyadic intervals, overlapping
+    intervals of interacting groups differ by at most 16 (no limit conflict
+    arises on this disk), particle masses M are untouched and the status word
+    is clean."""
+    params, st = workloads.by_name(workload, seed=0, n=1 << 20)
+    load()
+    eng = Engine(params, st, seed=0)
+    eng.set_groups(8)
+    done = eng.collide_groups()
+    _say(workload, "group intervals", len(done))
+    T = 1 << 30
+    for g in range(8):
+        t = 0
+        for s, z in sorted((s, z) for gg, s, z in done if gg == g):
+            assert s == t and z >= 1 and (z & (z - 1)) == 0 and s % z == 0
+            t = s + z
+        assert t == T
+    for g, s, z in done:
+        for h, s2, z2 in done:
+            if (eng.group_rows[g] >> h) & 1 and s < s2 + z2 and s2 < s + z:
+                assert max(z, z2) <= 16 * min(z, z2)
+    got = eng.state_numpy()
+    assert np.array_equal(np.sort(got["M"]), np.sort(st["M"]))
+    assert np.all(np.isfinite(got["m"])) and np.all(got["m"] > 0)
+    assert eng.status() & ~0x4 == 0
