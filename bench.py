@@ -383,6 +383,54 @@ def strang_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def reshuffle_bench(args):
+    """The product-kernel loop of Sect. 3.3 with static particles: before every
+    neighbourhood refresh the cached neighbour indices are relabelled at
+    random, then rates, plan and sampling run over the relabelled rows."""
+    import torch
+    from paper_2609_35967_amd import Engine, load
+
+    load()
+    torch.cuda.set_device(0)
+    n = args.n
+    params = dict(workloads.const_box_params(n), kernel="product")
+    st = workloads.const_box(args.seed, n)
+    eng = Engine(params, st, seed=args.seed)
+    eng.build_neighbors()
+    for s in range(args.warmup):
+        eng.reshuffle_neighbors(s)
+        eng.step(rebuild=False)
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+
+    def one(s):
+        a, b = pairs[s]
+        a.record()
+        eng.reshuffle_neighbors(args.warmup + s)
+        b.record()
+        eng.step(rebuild=False)
+
+    wall, lat = _timed_loop(one, args.steps)
+    r_ms = float(np.mean([a.elapsed_time(b) for a, b in pairs]))
+    k = int(params["k"])
+    bytes_pp = 2 * 4 * k + 4            # read and write the cached row, read cnt
+    achieved = bytes_pp * n / (r_ms * 1e-3) / 1e9
+    out = dict(
+        metric="particle-intervals/s of the product-kernel loop with neighbour reshuffling (Sect. 3.3)",
+        value=round(n * args.steps / wall, 1), unit="particle-intervals/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(wall / args.steps * 1e3, 4), higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload=f"const_box with the product kernel: {n} particles uniform in the periodic unit "
+                             "cube, m = m0 = 1, k=32, neighbour lists built once, relabelled before every "
+                             "interval", n_particles=n, k=k),
+        p50_ms=round(float(np.percentile(lat, 50)), 4), p99_ms=round(float(np.percentile(lat, 99)), 4),
+        roofline=dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=round(achieved / HBM_PEAK_GBS, 5), traffic=None, kernel="reshuffle",
+                      algo_bytes_per_particle=bytes_pp, launch_ms=round(r_ms, 4), traffic_bytes_per_launch=None),
+        status=eng.status(),
+    )
+    print(json.dumps(out), flush=True)
+
+
 def groups_bench(args):
     """Collision steps C(dt_coll) without transport on the disk: the single-group
     operator against args.groups spatial groups with the ratio-16 rule, on the
@@ -546,17 +594,21 @@ def main():
                     help="the diffusion operator on the 2^20-particle dust-ring test instead")
     ap.add_argument("--strang", action="store_true",
                     help="paper-cadence transport steps C D T D C on the disk instead")
+    ap.add_argument("--reshuffle", action="store_true",
+                    help="the product-kernel loop with neighbour reshuffling instead")
     ap.add_argument("--groups", type=int, default=0, metavar="G",
                     help="collision steps with G spatial groups against the single group instead")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
-    if args.diffusion or args.strang or args.groups:
+    if args.diffusion or args.strang or args.groups or args.reshuffle:
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        if args.diffusion:
+        if args.reshuffle:
+            reshuffle_bench(args)
+        elif args.diffusion:
             diffusion_bench(args)
         elif args.strang:  # with --groups G: grouped collision operators
             strang_bench(args)

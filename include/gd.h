@@ -230,9 +230,11 @@ int32_t gd_collision_rates(const gd_problem* p, const gd_particles* st, const gd
  * Feistel network on two h-bit halves (4^h >= N) with round function word 0
  * of Philox4x32-10, counter (right half, round, refresh, 0x52534831), key =
  * seed, restricted to [0, N) by cycle walking.  In place on the caller's
- * stream. */
+ * stream.  pi is tabulated in the workspace (the part the neighbour build
+ * uses for its sort keys), so the call may sit anywhere outside
+ * gd_build_neighbors. */
 int32_t gd_reshuffle_neighbors(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh,
-                               void* stream);
+                               void* ws, size_t ws_bytes, void* stream);
 
 /* Sampling over many independent runs (boxes) at once.  gd_sample_collisions
  * is, in order: the per-lane pass (each particle's first events; a particle

@@ -103,7 +103,8 @@ def load(path: str | None = None):
                                                 vp, C.c_size_t, C.c_int32, vp]
     L.gd_sample_table_run.argtypes = [vp, C.c_size_t, C.c_int32, C.c_int32, C.c_int32, vp]
     L.gd_sample_audit.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), vp, vp, C.c_size_t, vp]
-    L.gd_reshuffle_neighbors.argtypes = [C.POINTER(GdProblem), C.POINTER(GdNeighbors), C.c_uint64, C.c_uint32, vp]
+    L.gd_reshuffle_neighbors.argtypes = [C.POINTER(GdProblem), C.POINTER(GdNeighbors), C.c_uint64, C.c_uint32, vp,
+                                         C.c_size_t, vp]
     L.gd_diffuse.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.c_double, C.c_uint64, C.c_uint32, vp]
     L.gd_group_interactions.argtypes = [C.POINTER(GdProblem), C.POINTER(GdNeighbors), vp, C.c_int32, vp, vp]
     L.gd_collision_rates_group.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.POINTER(GdNeighbors), vp,
@@ -292,7 +293,8 @@ class Engine:
 
     def reshuffle_neighbors(self, refresh: int):
         """Random relabelling of the cached neighbours (product-kernel test), in place."""
-        check(self.lib.gd_reshuffle_neighbors(C.byref(self.P), C.byref(self.nb), self.seed, int(refresh), self._s()))
+        check(self.lib.gd_reshuffle_neighbors(C.byref(self.P), C.byref(self.nb), self.seed, int(refresh),
+                                              C.c_void_p(self.ws_ptr), self.ws_bytes, self._s()))
 
     def sample_deferred(self, table, table_bytes: int, slot: int):
         """The per-lane pass of sampling; the run's arguments go to table slot `slot`

@@ -258,13 +258,16 @@ int32_t gd_sample_collisions(const gd_problem* p, const gd_particles* s, const g
 }
 
 int32_t gd_reshuffle_neighbors(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh,
-                               void* stream)
+                               void* ws, size_t ws_bytes, void* stream)
 {
     int rc = check_problem(p);
     if (!rc) rc = check_nb(nb);
     if (rc) return rc;
     if (!nb->n_active) return fail(GD_E_INVALID_ARG, "neighbours: n_active is NULL");
-    launch_reshuffle(p, nb, seed, refresh, static_cast<hipStream_t>(stream));
+    Layout L;
+    rc = check_ws(p, ws, ws_bytes, L);
+    if (rc) return rc;
+    launch_reshuffle(p, nb, seed, refresh, ws, L, static_cast<hipStream_t>(stream));
     return hip_ok("gd_reshuffle_neighbors");
 }
 

@@ -31,7 +31,8 @@ int launch_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors*
 int launch_sample(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
                   const double* lam_i, uint64_t seed, uint32_t interval, bool interval_on_device, int32_t* n_events, int32_t* log,
                   int32_t log_cap, void* ws, const Layout& L, hipStream_t st, void* table, int32_t slot);
-int launch_reshuffle(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh, hipStream_t st);
+int launch_reshuffle(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh, void* ws,
+                     const Layout& L, hipStream_t st);
 int launch_audit(const gd_problem* p, const gd_particles* s, gd_interval* iv, void* ws, const Layout& L, hipStream_t st);
 size_t sample_table_bytes(int32_t nslot);
 int max_table_slots();

@@ -10,6 +10,9 @@
 // restricted to [0, N) by cycle walking (Black and Rogaway): the network is
 // applied until the value falls below N.  A walk stays on the cycle of the
 // network's permutation through j, so it ends within 4^h <= 4N steps.
+// pi is evaluated once per slot into a table (the workspace's sort keys,
+// free outside the neighbour build), then every cached entry is relabelled
+// by one read of the table.
 #include "gd_common.hpp"
 #include "gd_internal.hpp"
 
@@ -29,39 +32,68 @@ __device__ inline uint32_t feistel4(uint32_t x, int h, uint32_t mask, uint32_t k
     return (L << h) | R;
 }
 
-// one thread per (particle, slot); slots 1 .. cnt-1 of active rows
-__global__ __launch_bounds__(256) void k_reshuffle(int32_t* __restrict__ nbr, const int32_t* __restrict__ cnt,
-                                                   const int32_t* __restrict__ n_active, int64_t n, int32_t k,
-                                                   uint64_t seed, uint32_t refresh)
+__device__ inline uint32_t pi_of(uint32_t j, int64_t N, uint64_t seed, uint32_t refresh)
 {
-    const int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (e >= n * k) return;
-    const int64_t i = e / k;
-    const int s = int(e - i * k);
-    const int64_t N = *n_active;
-    if (s == 0 || s >= cnt[i] || N <= 1) return;
-    const int32_t j = nbr[e];
-    if (j < 0 || j >= N) return;
     int bits = 0;
     while ((int64_t(1) << bits) < N) ++bits;
     const int h = (bits + 1) >> 1;
     const uint32_t mask = (1u << h) - 1u;
     const uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
     const int64_t cap = int64_t(1) << (2 * h);  // the network's domain: a walk is shorter
-    uint32_t x = uint32_t(j);
+    uint32_t x = j;
     for (int64_t step = 0; step < cap; ++step) {
         x = feistel4(x, h, mask, k0, k1, refresh);
         if (int64_t(x) < N) break;
     }
-    nbr[e] = int32_t(x);
+    return x;
 }
 
-int launch_reshuffle(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh, hipStream_t st)
+// pi once per active slot: table[j] = pi(j), j < N
+__global__ __launch_bounds__(256) void k_reshuffle_table(int32_t* __restrict__ table,
+                                                         const int32_t* __restrict__ n_active, int64_t n,
+                                                         uint64_t seed, uint32_t refresh)
+{
+    const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int64_t N = *n_active;
+    if (j >= n || j >= N || N <= 1) return;
+    table[j] = int32_t(pi_of(uint32_t(j), N, seed, refresh));
+}
+
+// one thread per (particle, slot); slots 1 .. cnt-1 of active rows are
+// relabelled.  n * k < 2^31 (checked on the host), so 32-bit index arithmetic
+// holds; KS > 0 is log2(k) for a power-of-two k, 0 for any other k.
+template <int KS>
+__global__ __launch_bounds__(256) void k_reshuffle_apply(int32_t* __restrict__ nbr, const int32_t* __restrict__ cnt,
+                                                         const int32_t* __restrict__ n_active,
+                                                         const int32_t* __restrict__ table, uint32_t total, uint32_t k)
+{
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const uint32_t i = KS > 0 ? (e >> KS) : e / k;
+    const uint32_t s = e - i * k;
+    const int32_t N = *n_active;
+    if (s == 0 || N <= 1 || int32_t(i) >= N || int32_t(s) >= cnt[i]) return;
+    const int32_t j = nbr[e];
+    if (j < 0 || j >= N) return;
+    nbr[e] = table[j];
+}
+
+int launch_reshuffle(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh, void* ws,
+                     const Layout& L, hipStream_t st)
 {
     const int64_t total = p->n * int64_t(p->k);
     if (total <= 0) return 0;
-    hipLaunchKernelGGL(k_reshuffle, dim3(unsigned((total + 255) / 256)), dim3(256), 0, st, nb->nbr, nb->cnt,
-                       nb->n_active, p->n, p->k, seed, refresh);
+    int32_t* table = at<int32_t>(ws, L.keys0);
+    hipLaunchKernelGGL(k_reshuffle_table, dim3(unsigned((p->n + 255) / 256)), dim3(256), 0, st, table, nb->n_active,
+                       p->n, seed, refresh);
+    const dim3 grid(unsigned((total + 255) / 256));
+    const uint32_t t32 = uint32_t(total), k = uint32_t(p->k);
+    if (k == 32)
+        hipLaunchKernelGGL(k_reshuffle_apply<5>, grid, dim3(256), 0, st, nb->nbr, nb->cnt, nb->n_active, table, t32, k);
+    else if (k == 64)
+        hipLaunchKernelGGL(k_reshuffle_apply<6>, grid, dim3(256), 0, st, nb->nbr, nb->cnt, nb->n_active, table, t32, k);
+    else
+        hipLaunchKernelGGL(k_reshuffle_apply<0>, grid, dim3(256), 0, st, nb->nbr, nb->cnt, nb->n_active, table, t32, k);
     return 0;
 }
 

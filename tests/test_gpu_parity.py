@@ -171,6 +171,21 @@ def test_reshuffle_neighbors(n):
     assert np.array_equal(eng.lam.cpu().numpy(), lam_o)
 
 
+@pytest.mark.parametrize("k", [20, 64])
+def test_reshuffle_neighbors_other_k(k):
+    # row lengths other than 32: the generic and the 64-wide relabelling paths
+    params = dict(workloads.const_box_params(1000, k=k), kernel="product")
+    st = workloads.const_box(47, 1000)
+    eng = _engine(params, st, seed=78)
+    eng.build_neighbors()
+    torch.cuda.synchronize()
+    before, cnt = eng.nbr.cpu().numpy(), eng.cnt.cpu().numpy()
+    eng.reshuffle_neighbors(3)
+    torch.cuda.synchronize()
+    after = eng.nbr.cpu().numpy()
+    assert np.array_equal(after, oracle.reshuffle(before, cnt, int(eng.n_active.item()), 78, 3))
+
+
 @pytest.mark.parametrize("hint", ["previous", 0.0, 1e-300, 1e300, 1e17, float("nan"), -1.0, "mixed"])
 def test_build_neighbors_search_hint(hint):
     # the previous distances are read back as a search hint; the result must
