@@ -39,9 +39,11 @@ __global__ __launch_bounds__(256) void k_group_interactions(const int32_t* __res
     for (int t = threadIdx.x; t <= G; t += blockDim.x) s_lo[t] = B.lo[t];
     for (int t = threadIdx.x; t < G; t += blockDim.x) s_mask[t] = 0ull;
     __syncthreads();
-    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     const int32_t n_act = s_lo[G];
-    if (i < n_act) {
+    // a fixed grid strides over the particles, so that few blocks update the
+    // global rows (updates of one word from many blocks serialise)
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n_act;
+         i += int64_t(gridDim.x) * blockDim.x) {
         const int gi = group_of_slot(s_lo, G, int32_t(i));
         const int c = cnt[i];
         unsigned long long row = 0ull;
@@ -49,16 +51,27 @@ __global__ __launch_bounds__(256) void k_group_interactions(const int32_t* __res
             const int32_t j = nbr[i * k + t];
             if (j < 0 || j >= n_act) continue;
             const int gj = group_of_slot(s_lo, G, j);
-            if (gj != gi) {
-                row |= 1ull << gj;
-                atomicOr(&s_mask[gj], 1ull << gi);
-            }
+            if (gj != gi) row |= 1ull << gj;
         }
-        if (row) atomicOr(&s_mask[gi], row);
+        if (row) atomicOr(&s_mask[gi], row);  // one update per particle; k_group_symmetric adds the reverse
     }
     __syncthreads();
     for (int t = threadIdx.x; t < G; t += blockDim.x)
         if (s_mask[t]) atomicOr(&mask[t], s_mask[t]);
+}
+
+// row g |= bit h for every h whose row holds g (the relation is symmetric)
+__global__ void k_group_symmetric(unsigned long long* mask, int G)
+{
+    __shared__ unsigned long long s[kMaxGroups];
+    const int g = threadIdx.x;
+    if (g < G) s[g] = mask[g];
+    __syncthreads();
+    if (g >= G) return;
+    unsigned long long row = s[g];
+    for (int h = 0; h < G; ++h)
+        if ((s[h] >> g) & 1ull) row |= 1ull << h;
+    mask[g] = row;
 }
 
 // broadcast of a group's masses; its scheduled interval is over
@@ -79,9 +92,12 @@ int launch_group_interactions(const gd_problem* p, const gd_neighbors* nb, const
     GroupBounds B{};
     for (int g = 0; g <= G; ++g) B.lo[g] = group_lo[g];
     if (B.lo[G] <= 0) return 0;
-    const int grid = int((int64_t(B.lo[G]) + 255) / 256);
+    const int64_t want = (int64_t(B.lo[G]) + 255) / 256;
+    const int grid = int(want < 256 ? want : 256);
     hipLaunchKernelGGL(k_group_interactions, dim3(grid), dim3(256), 0, st, nb->nbr, nb->cnt, p->k, B, G,
                        reinterpret_cast<unsigned long long*>(mask));
+    hipLaunchKernelGGL(k_group_symmetric, dim3(1), dim3(kMaxGroups), 0, st, reinterpret_cast<unsigned long long*>(mask),
+                       G);
     return 0;
 }
 
