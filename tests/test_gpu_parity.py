@@ -171,6 +171,31 @@ def test_reshuffle_neighbors(n):
     assert np.array_equal(eng.lam.cpu().numpy(), lam_o)
 
 
+def test_reshuffle_neighbors_full_size_sampled():
+    """2^20 particles of the product-kernel box, as bench.py --reshuffle runs
+    them: 256 sampled rows, every entry against the oracle's pi one by one."""
+    n = 1 << 20
+    params = dict(workloads.const_box_params(n), kernel="product")
+    st = workloads.const_box(0, n)
+    eng = _engine(params, st, seed=0)
+    eng.build_neighbors()
+    torch.cuda.synchronize()
+    before, cnt = eng.nbr.cpu().numpy(), eng.cnt.cpu().numpy()
+    N = int(eng.n_active.item())
+    eng.reshuffle_neighbors(7)
+    torch.cuda.synchronize()
+    after = eng.nbr.cpu().numpy()
+    rows = np.random.default_rng(5).choice(n, 256, replace=False)
+    for i in rows:
+        assert after[i, 0] == before[i, 0]
+        for t in range(1, cnt[i]):
+            assert after[i, t] == oracle.reshuffle_index(N, 0, 7, int(before[i, t]))
+        assert np.array_equal(after[i, cnt[i]:], before[i, cnt[i]:])
+    # a bijection: the relabelled entries of all rows still name distinct
+    # particles within each row
+    assert all(len(set(after[i, :cnt[i]])) == cnt[i] for i in rows)
+
+
 @pytest.mark.parametrize("k", [20, 64])
 def test_reshuffle_neighbors_other_k(k):
     # row lengths other than 32: the generic and the 64-wide relabelling paths
