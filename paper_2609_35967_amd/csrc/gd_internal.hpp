@@ -53,6 +53,7 @@ int launch_publish_group(const gd_particles* s, int64_t lo, int64_t hi, int64_t*
                          hipStream_t st);
 int launch_diffuse(const gd_problem* p, const gd_particles* s, double dt, uint64_t seed, uint32_t step,
                    hipStream_t st);
+const double* launch_part_fold(const double* part, void* ws, const Layout& L, hipStream_t st);
 void launch_bin_reduce(int mode, const double* msnap, const double* M, const double* va, const double* vb, int64_t n,
                        double* part, void* ws, hipStream_t st);
 

@@ -601,7 +601,8 @@ int launch_audit(const gd_problem* p, const gd_particles* s, gd_interval* iv, vo
     double* part = at<double>(ws, L.part);
     prof_mark(GD_PROF_AUDIT, 0, st);
     launch_bin_reduce(1, s->m[s->cur], s->M, s->m[s->cur ^ 1], nullptr, p->n, part, ws, st);
-    hipLaunchKernelGGL(k_audit, dim3(1), dim3(kAuditGroups * kNBin), 0, st, to_dev(p), part, kRedBlocks, iv, h);
+    const double* folded = launch_part_fold(part, ws, L, st);
+    hipLaunchKernelGGL(k_audit, dim3(1), dim3(kAuditGroups * kNBin), 0, st, to_dev(p), folded, 1, iv, h);
     prof_mark(GD_PROF_AUDIT, 1, st);
     return 0;
 }
@@ -655,7 +656,8 @@ int launch_sample_group(const gd_problem* p, const gd_particles* s, const gd_nei
     P.n = cnt;
     prof_mark(GD_PROF_AUDIT, 0, st);
     launch_bin_reduce(1, s->m[s->cur] + lo, s->M + lo, s->m[s->cur ^ 1] + lo, nullptr, cnt, part, ws, st);
-    hipLaunchKernelGGL(k_audit, dim3(1), dim3(kAuditGroups * kNBin), 0, st, P, part, kRedBlocks, iv, h);
+    const double* folded = launch_part_fold(part, ws, L, st);
+    hipLaunchKernelGGL(k_audit, dim3(1), dim3(kAuditGroups * kNBin), 0, st, P, folded, 1, iv, h);
     prof_mark(GD_PROF_AUDIT, 1, st);
     return 0;
 }

@@ -422,6 +422,57 @@ __global__ __launch_bounds__(kPlanGroups * kNBin) void k_plan(DevProblem P, cons
     }
 }
 
+// The kRedBlocks block partials of each bin summed as a tree, one block per
+// bin, into one row per bin (same layout as a block's partials): the plan and
+// the audit then read a single row instead of looping over the blocks.
+__global__ __launch_bounds__(kRedBlocks) void k_part_fold(const double* __restrict__ part, double* __restrict__ out)
+{
+    __shared__ double c[kRedBlocks];
+    __shared__ double hi[3][kRedBlocks], lo[3][kRedBlocks];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const double* a = part + (int64_t(t) * kNBin + b) * 8;
+    c[t] = a[0];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        hi[v][t] = a[1 + 2 * v];
+        lo[v][t] = a[2 + 2 * v];
+    }
+    __syncthreads();
+    for (int w = kRedBlocks / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            c[t] += c[t + w];
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const dd x = dd_add(dd{hi[v][t], lo[v][t]}, dd{hi[v][t + w], lo[v][t + w]});
+                hi[v][t] = x.hi;
+                lo[v][t] = x.lo;
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        double* o = out + int64_t(b) * 8;
+        o[0] = c[0];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            o[1 + 2 * v] = hi[v][0];
+            o[2 + 2 * v] = lo[v][0];
+        }
+        o[7] = 0.0;
+    }
+}
+
+static_assert(kNBin * 8 <= 8 * kRedBlocks, "the folded rows fit the reduction scratch");
+
+// fold the block partials `part` into the reduction scratch of the workspace
+// (free outside the neighbour build); returns the folded rows
+const double* launch_part_fold(const double* part, void* ws, const Layout& L, hipStream_t st)
+{
+    double* out = at<double>(ws, L.red);
+    hipLaunchKernelGGL(k_part_fold, dim3(kNBin), dim3(kRedBlocks), 0, st, part, out);
+    return out;
+}
+
 // ---------------------------------------------------------------------------
 void launch_bin_reduce(int mode, const double* msnap, const double* M, const double* va, const double* vb, int64_t n,
                        double* part, void* ws, hipStream_t st)
@@ -460,7 +511,8 @@ int launch_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors*
     else hipLaunchKernelGGL(k_rates, dim3(g), dim3(256), 0, st, A);
     double* part = at<double>(ws, L.part);
     launch_bin_reduce(0, m, s->M, A.a, A.b, n, part, ws, st);
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanGroups * kNBin), 0, st, P, part, kRedBlocks, iv, at<WsHeader>(ws, L.hdr), ws);
+    const double* folded = launch_part_fold(part, ws, L, st);
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanGroups * kNBin), 0, st, P, folded, 1, iv, at<WsHeader>(ws, L.hdr), ws);
     prof_mark(GD_PROF_RATES, 1, st);
     return 0;
 }
@@ -528,7 +580,8 @@ int launch_rates_group(const gd_problem* p, const gd_particles* s, const gd_neig
     }
     double* part = at<double>(ws, L.part);
     launch_bin_reduce(0, m + lo, s->M + lo, A.a, A.b, cnt, part, ws, st);
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanGroups * kNBin), 0, st, P, part, kRedBlocks, iv, at<WsHeader>(ws, L.hdr), ws);
+    const double* folded = launch_part_fold(part, ws, L, st);
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanGroups * kNBin), 0, st, P, folded, 1, iv, at<WsHeader>(ws, L.hdr), ws);
     hipLaunchKernelGGL(k_group_clamp, dim3(1), dim3(64), 0, st, iv, int(group), int(n_groups),
                        reinterpret_cast<const unsigned long long*>(rows), sched);
     prof_mark(GD_PROF_RATES, 1, st);
