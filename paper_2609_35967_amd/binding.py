@@ -258,6 +258,8 @@ class Engine:
         self.nb = GdNeighbors(self.nbr.data_ptr(), self.cnt.data_ptr(), self.dmax.data_ptr(), self.n_active.data_ptr())
         self.moved = True       # positions changed since the neighbour lists were built
         self.diff_step = 0      # draws of the next diffusion step of strang_step
+        if self.stream is not None:  # the uploads ran on torch's stream, the library runs on ours
+            torch.cuda.current_stream(self.device).synchronize()
         check(self.lib.gd_workspace_init(C.byref(self.P), C.c_void_p(self.ws_ptr), self.ws_bytes, self._s()))
         check(self.lib.gd_interval_init(C.c_void_p(self.iv.data_ptr()), float(params["dt_coll"]), self._s()))
 
@@ -360,6 +362,8 @@ class Engine:
         self.gmask = torch.zeros(self.n_groups, dtype=torch.int64, device=self.device)
         self.gsched = torch.zeros(self.n_groups, dtype=torch.int64, device=self.device)  # scheduled ticks, 0: none
         self.group_lo = None
+        if self.stream is not None:  # the fills ran on torch's stream, the library runs on ours
+            torch.cuda.current_stream(self.device).synchronize()
 
     def _group_layout(self):
         """Ranges over the active slots after a build, and the interaction rows (synchronises)."""
