@@ -40,20 +40,33 @@ __global__ __launch_bounds__(256) void k_group_interactions(const int32_t* __res
     for (int t = threadIdx.x; t < G; t += blockDim.x) s_mask[t] = 0ull;
     __syncthreads();
     const int32_t n_act = s_lo[G];
+    const int lane = threadIdx.x & 63;
     // a fixed grid strides over the particles, so that few blocks update the
     // global rows (updates of one word from many blocks serialise)
-    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n_act;
-         i += int64_t(gridDim.x) * blockDim.x) {
-        const int gi = group_of_slot(s_lo, G, int32_t(i));
-        const int c = cnt[i];
+    for (int64_t base = blockIdx.x * int64_t(blockDim.x); base < n_act; base += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const bool in = i < n_act;
+        const int gi = in ? group_of_slot(s_lo, G, int32_t(i)) : -1;
         unsigned long long row = 0ull;
-        for (int t = 1; t < c; ++t) {
-            const int32_t j = nbr[i * k + t];
-            if (j < 0 || j >= n_act) continue;
-            const int gj = group_of_slot(s_lo, G, j);
-            if (gj != gi) row |= 1ull << gj;
+        if (in) {
+            const int c = cnt[i];
+            for (int t = 1; t < c; ++t) {
+                const int32_t j = nbr[i * k + t];
+                if (j < 0 || j >= n_act) continue;
+                const int gj = group_of_slot(s_lo, G, j);
+                if (gj != gi) row |= 1ull << gj;
+            }
         }
-        if (row) atomicOr(&s_mask[gi], row);  // one update per particle; k_group_symmetric adds the reverse
+        // the lanes of a wavefront nearly always share their group: OR their
+        // rows across the wavefront and let one lane update the LDS row
+        const int g0 = __shfl(gi, 0, 64);
+        if (__all(gi == g0 || gi < 0)) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) row |= __shfl_xor(row, o, 64);
+            if (lane == 0 && g0 >= 0 && row) atomicOr(&s_mask[g0], row);
+        } else if (row) {
+            atomicOr(&s_mask[gi], row);  // k_group_symmetric adds the reverse relation
+        }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < G; t += blockDim.x)
@@ -93,7 +106,7 @@ int launch_group_interactions(const gd_problem* p, const gd_neighbors* nb, const
     for (int g = 0; g <= G; ++g) B.lo[g] = group_lo[g];
     if (B.lo[G] <= 0) return 0;
     const int64_t want = (int64_t(B.lo[G]) + 255) / 256;
-    const int grid = int(want < 256 ? want : 256);
+    const int grid = int(want < 1024 ? want : 1024);
     hipLaunchKernelGGL(k_group_interactions, dim3(grid), dim3(256), 0, st, nb->nbr, nb->cnt, p->k, B, G,
                        reinterpret_cast<unsigned long long*>(mask));
     hipLaunchKernelGGL(k_group_symmetric, dim3(1), dim3(kMaxGroups), 0, st, reinterpret_cast<unsigned long long*>(mask),
