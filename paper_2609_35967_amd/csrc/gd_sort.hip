@@ -231,16 +231,19 @@ __global__ __launch_bounds__(256) void k_permute(PermuteArgs A)
     const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (i >= A.n) return;
     const uint32_t s = A.perm[i];
-#pragma unroll 4
-    for (int a = 0; a < A.nd; ++a) A.dst[a][i] = A.src[a][s];
-    A.id_dst[i] = A.id_src[s];
-    double4 p;
-    p.x = A.src[0][s];
-    p.y = A.src[1][s];
-    p.z = A.src[2][s];
-    p.w = 0.0;
-    A.pos4[i] = p;
-    A.hint_dst[i] = A.hint_src ? A.hint_src[s] : 0.0;
+    // every gather is issued before any store (the array count is uniform),
+    // so a lane keeps all of its loads in flight at once
+    double v[16];
+#pragma unroll
+    for (int a = 0; a < 16; ++a) v[a] = a < A.nd ? A.src[a][s] : 0.0;
+    const uint32_t id = A.id_src[s];
+    const double hint = A.hint_src ? A.hint_src[s] : 0.0;
+#pragma unroll
+    for (int a = 0; a < 16; ++a)
+        if (a < A.nd) A.dst[a][i] = v[a];
+    A.id_dst[i] = id;
+    A.pos4[i] = make_double4(v[0], v[1], v[2], 0.0);  // x, y, z are the first three arrays
+    A.hint_dst[i] = hint;
 }
 
 __global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v)
