@@ -347,13 +347,24 @@ class Engine:
         raise GdError(f"collision step not complete after {max_intervals} intervals")
 
     # ---- spatial groups (Sect. 2.5.3) ---------------------------------------------
-    def set_groups(self, n_groups: int):
+    def set_groups(self, n_groups: int, concurrent: bool = False):
         """Split the active particles into `n_groups` contiguous Morton ranges, each
-        with its own interval state; collide_groups() then schedules them."""
+        with its own interval state; collide_groups() then schedules them.  With
+        `concurrent`, every group also gets its own workspace and stream, so that
+        the sampling of the groups starting at one instant overlaps (their plans
+        still run one after another, as the ratio rule orders them)."""
         torch = self.torch
         if not 1 <= n_groups <= 64:
             raise GdError("n_groups must be 1..64")
         self.n_groups = int(n_groups)
+        self.gws = None
+        if concurrent:
+            self.gws, self.gstreams = [], []
+            for _ in range(self.n_groups):
+                buf = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+                ptr = (buf.data_ptr() + 255) & ~255
+                self.gws.append((buf, ptr))
+                self.gstreams.append(torch.cuda.Stream(device=self.device))
         isz = C.sizeof(GdInterval)
         self.ivg = torch.zeros((self.n_groups, isz), dtype=torch.uint8, device=self.device)
         for g in range(self.n_groups):
@@ -362,8 +373,12 @@ class Engine:
         self.gmask = torch.zeros(self.n_groups, dtype=torch.int64, device=self.device)
         self.gsched = torch.zeros(self.n_groups, dtype=torch.int64, device=self.device)  # scheduled ticks, 0: none
         self.group_lo = None
-        if self.stream is not None:  # the fills ran on torch's stream, the library runs on ours
+        if self.stream is not None or concurrent:  # the fills ran on torch's stream
             torch.cuda.current_stream(self.device).synchronize()
+        if concurrent:
+            for _, ptr in self.gws:
+                check(self.lib.gd_workspace_init(C.byref(self.P), C.c_void_p(ptr), self.ws_bytes, self._s()))
+            self._sync_own()
 
     def _group_layout(self):
         """Ranges over the active slots after a build, and the interaction rows (synchronises)."""
@@ -378,6 +393,15 @@ class Engine:
                                              C.c_void_p(self.gmask.data_ptr()), self._s()))
         self.group_lo = [int(v) for v in lo]
         self.group_rows = [int(v) & ((1 << 64) - 1) for v in self.gmask.cpu().tolist()]
+
+    def _sync_own(self):
+        if self.stream is not None:
+            self.stream.synchronize()
+        else:
+            self.torch.cuda.current_stream(self.device).synchronize()
+
+    def _own_stream(self):
+        return self.stream if self.stream is not None else self.torch.cuda.current_stream(self.device)
 
     def group_interval_state(self, g: int) -> dict:
         if self.stream is not None:
@@ -407,17 +431,27 @@ class Engine:
         rows = C.c_void_p(self.gmask.data_ptr())
         sched = C.c_void_p(self.gsched.data_ptr())
         while True:
-            for idx, g in enumerate(starting):
-                ivp = C.c_void_p(self.ivg[g].data_ptr())
-                check(self.lib.gd_collision_rates_group(C.byref(self.P), C.byref(sa), C.byref(self.nb), ivp,
-                                                        _ptr(self.lam), lo[g], lo[g + 1], g, G, rows, sched,
-                                                        1 if idx == 0 else 0, C.c_void_p(self.ws_ptr), self.ws_bytes,
-                                                        self._s()))
-                check(self.lib.gd_sample_collisions_group(C.byref(self.P), C.byref(sa), C.byref(self.nb), ivp,
-                                                          _ptr(self.lam), self.seed, self.interval, lo[g], lo[g + 1],
-                                                          _ptr(self.events), C.c_void_p(self.ws_ptr), self.ws_bytes,
-                                                          self._s()))
-                self.interval += 1
+            if self.gws is None:
+                for idx, g in enumerate(starting):
+                    self._plan_and_sample(g, lo, rows, sched, idx == 0, C.c_void_p(self.ws_ptr), self._s())
+            else:
+                # group g's plan waits for the plan of the group before it (the
+                # ratio limits read its scheduled size); its sampling runs on
+                # its own stream and overlaps the next groups' work
+                torch = self.torch
+                own = self._own_stream()
+                prev = torch.cuda.Event()
+                prev.record(own)
+                for g in starting:
+                    sg = self.gstreams[g]
+                    sg.wait_event(prev)
+                    ws_g = C.c_void_p(self.gws[g][1])
+                    self._rates_group(g, lo, rows, sched, True, ws_g, C.c_void_p(sg.cuda_stream))
+                    prev = torch.cuda.Event()
+                    prev.record(sg)
+                    self._sample_group(g, lo, ws_g, C.c_void_p(sg.cuda_stream))
+                for g in starting:
+                    own.wait_stream(self.gstreams[g])
             if self.stream is not None:
                 self.stream.synchronize()
             sizes = self.gsched.cpu().tolist()
@@ -430,6 +464,25 @@ class Engine:
                 check(self.lib.gd_publish_group(C.byref(self.P), C.byref(sa), lo[g], lo[g + 1], sched, g, self._s()))
             if tau == T:
                 return done
+
+    def _rates_group(self, g, lo, rows, sched, snapshot, ws, stream):
+        sa = self.A.struct()
+        check(self.lib.gd_collision_rates_group(C.byref(self.P), C.byref(sa), C.byref(self.nb),
+                                                C.c_void_p(self.ivg[g].data_ptr()), _ptr(self.lam), lo[g], lo[g + 1],
+                                                g, self.n_groups, rows, sched, 1 if snapshot else 0, ws, self.ws_bytes,
+                                                stream))
+
+    def _sample_group(self, g, lo, ws, stream):
+        sa = self.A.struct()
+        check(self.lib.gd_sample_collisions_group(C.byref(self.P), C.byref(sa), C.byref(self.nb),
+                                                  C.c_void_p(self.ivg[g].data_ptr()), _ptr(self.lam), self.seed,
+                                                  self.interval, lo[g], lo[g + 1], _ptr(self.events), ws,
+                                                  self.ws_bytes, stream))
+        self.interval += 1
+
+    def _plan_and_sample(self, g, lo, rows, sched, snapshot, ws, stream):
+        self._rates_group(g, lo, rows, sched, snapshot, ws, stream)
+        self._sample_group(g, lo, ws, stream)
 
     def strang_step(self) -> int:
         """One transport step dt = 2 dt_coll in the symmetric sequence of Sect. 2.6:

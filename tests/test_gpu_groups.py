@@ -33,13 +33,14 @@ def _by_id(d):
     return {k: np.asarray(v)[o] for k, v in d.items()}
 
 
-@pytest.mark.parametrize("G,n", [(8, 2048), (5, 4099), (64, 8192)])
-def test_grouped_steps_match_oracle(G, n):
+@pytest.mark.parametrize("G,n,concurrent", [(8, 2048, False), (5, 4099, False), (64, 8192, False),
+                                            (8, 2048, True), (5, 4099, True)])
+def test_grouped_steps_match_oracle(G, n, concurrent):
     params = workloads.const_box_params(n)
     st = two_speed_box(n, 11)
     load()
     eng = Engine(params, st, seed=9)
-    eng.set_groups(G)
+    eng.set_groups(G, concurrent=concurrent)
     run = GroupedRun(params, st, seed=9, n_groups=G)
     for step in range(2):
         d_gpu = eng.collide_groups()
@@ -98,13 +99,14 @@ def test_one_group_equals_single_group_step():
     assert a.group_interval_state(0)["C"] == b.interval_state()["C"]
 
 
-def test_grouped_physical_disk():
+@pytest.mark.parametrize("concurrent", [False, True])
+def test_grouped_physical_disk(concurrent):
     n = 4096
     params = workloads.disk3d_params(n)
     st = workloads.disk3d(13, n, warm=True, params=params)
     load()
     eng = Engine(params, st, seed=4)
-    eng.set_groups(4)
+    eng.set_groups(4, concurrent=concurrent)
     run = GroupedRun(params, st, seed=4, n_groups=4)
     d_gpu = eng.collide_groups()
     d_orc = run.collide_groups()
