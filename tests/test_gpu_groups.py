@@ -118,7 +118,8 @@ def test_grouped_physical_disk(concurrent):
     assert np.array_equal(got["m"], ref["m"])
 
 
-def test_grouped_strang_steps_match_oracle():
+@pytest.mark.parametrize("concurrent", [False, True])
+def test_grouped_strang_steps_match_oracle(concurrent):
     """The paper's cadence with grouped collision operators on a warm disk with
     diffusion: groups are re-formed from the new Morton order after motion."""
     n = 4096
@@ -126,7 +127,7 @@ def test_grouped_strang_steps_match_oracle():
     st = workloads.disk3d(15, n, warm=True, params=params)
     load()
     eng = Engine(params, st, seed=6)
-    eng.set_groups(4)
+    eng.set_groups(4, concurrent=concurrent)
     run = GroupedRun(params, st, seed=6, n_groups=4)
     for step in range(2):
         n_gpu = eng.strang_step()
