@@ -35,3 +35,21 @@ def test_local_box_dust_mass():
     sigma = p["Sigma_g0"] * (R / p["R0"]) ** p["p"]
     rho_g = sigma / (math.sqrt(2.0 * math.pi) * p["h_g0"] * R)
     assert math.isclose(s["M"].sum(), 0.01 * rho_g * p["L"][0] ** 3, rel_tol=1e-12)
+
+
+def test_diffusion_ring_recipe():
+    # the dust ring of Sect. 3.2: ln(R/R0) ~ N(0, 0.05^2), midplane, at rest
+    import math
+
+    import numpy as np
+
+    st = workloads.diffusion_ring(3, 1 << 16)
+    lnR = np.log(st["r"])
+    assert abs(lnR.mean()) < 5 * 0.05 / 256 and abs(lnR.std() - 0.05) < 5 * 0.05 / math.sqrt(2 * (1 << 16))
+    assert np.all(st["th"] == 0.5 * math.pi) and not st["vr"].any() and not st["lph"].any()
+    assert len(np.unique(st["id"])) == len(st["id"])
+    np.testing.assert_allclose(np.hypot(st["x"], st["y"]), st["r"], rtol=1e-15)
+    p = workloads.diffusion_ring_params("density", St=10.0)
+    assert (p["h_g0"], p["p"], p["q"], p["alpha"], p["St_diff"], p["vint"]) == (0.05, -1.0, 0.5, 0.04, 10.0, 1)
+    # nu = alpha h_g0^2 sqrt(GM R0) (R/R0)^2 = 1e-4 (R/R0)^2 in code units
+    assert abs(p["alpha"] * p["h_g0"] ** 2 * math.sqrt(p["GM"] * p["R0"]) - 1e-4) < 1e-18
