@@ -35,9 +35,9 @@
  *
  * Parity unpinned (no independent value to check against; GPU parity is
  * against this code only): the five-term composition of eq:dv at a point
- * where all terms are non-zero (its parts are pinned separately), the OC07
- * branch constants away from the tested regimes and limits, and the disk's
- * gas normalisation.
+ * where all terms are non-zero (its parts are pinned separately) and the
+ * OC07 branch constants away from the tested regimes and limits.  The gas
+ * disk is pinned by its vertical integral and hydrostatic balance.
  */
 #include <math.h>
 #include <stdint.h>
