@@ -34,10 +34,10 @@
  * and collected in the design notes of the repository.
  *
  * Parity unpinned (no independent value to check against; GPU parity is
- * against this code only): the five-term composition of eq:dv at a point
- * where all terms are non-zero (its parts are pinned separately) and the
- * OC07 branch constants away from the tested regimes and limits.  The gas
- * disk is pinned by its vertical integral and hydrostatic balance.
+ * against this code only): the OC07 branch constants away from the tested
+ * regimes and limits.  The gas disk is pinned by its vertical integral and
+ * hydrostatic balance, and eq:dv's composition by the quadrature sum of its
+ * parts at points where all of them matter.
  */
 #include <math.h>
 #include <stdint.h>

@@ -288,3 +288,32 @@ def test_fsum_exact():
     for _ in range(20):
         v = rng.standard_normal(1000) * 10.0 ** rng.integers(-30, 30, 1000)
         assert oracle.fsum(v) == _m.fsum(v)
+
+
+@pytest.mark.parametrize("R_au,zr,ai,aj", [(17.43, 0.08536, 9.299e-05, 9.126e-05),
+                                           (76.01, 0.04763, 6.768e-05, 6.548e-05),
+                                           (26.99, 0.04518, 1.816e-04, 1.822e-04),
+                                           (70.74, -0.03901, 6.12e-05, 6.527e-05)])
+def test_dv_five_terms_compose_in_quadrature(R_au, zr, ai, aj):
+    """eq:dv adds the Brownian, radial, vertical, azimuthal and turbulent speeds
+    in quadrature, and the kernel (hence the pair rate with sticking only and no
+    grouping) is linear in dv, so lambda^2 with every term equals lambda^2 with
+    Brownian only plus lambda^2 with turbulence only minus lambda^2 with the
+    drift terms alone -- at points where each part is 15% or more of the total."""
+    import math
+
+    base = dict(workloads.disk3d_params(1000), v_frag=math.inf, grouping=0, erosion=0)
+    R = R_au * workloads.AU
+    x, y, z = R * math.cos(0.3), R * math.sin(0.3), zr * R
+    mi = math.pi * 1.6 * (2 * ai) ** 3 / 6
+    mj = math.pi * 1.6 * (2 * aj) ** 3 / 6
+    lam = {}
+    for b in (0, 1):
+        for t in (0, 1):
+            P = oracle.make_problem(dict(base, brownian=b, turbulence=t))
+            lam[(b, t)] = oracle.pair_rate(P, x, y, z, 1e-3 * R, mi, mj, 1e20)["lam_star"]
+    d2 = lam[(0, 0)] ** 2
+    B, T = lam[(1, 0)] ** 2 - d2, lam[(0, 1)] ** 2 - d2
+    tot = d2 + B + T
+    assert min(d2, B, T) > 0.15 * tot
+    np.testing.assert_allclose(lam[(1, 1)] ** 2, tot, rtol=1e-12)
