@@ -16,9 +16,11 @@ Steps and the passages they follow (section numbers of the paper):
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
+import tempfile
 import threading
 
 import numpy as np
@@ -89,48 +91,81 @@ def make_problem(cfg: dict) -> Problem:
     return P
 
 
+def _declare(L):
+    """Argument and result types of the oracle's exported functions."""
+    vp = C.c_void_p
+    i64 = C.c_int64
+    d = C.c_double
+    L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+    L.orc_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, vp]
+    L.orc_morton3_10.argtypes = [C.c_uint32] * 3
+    L.orc_morton3_10.restype = C.c_uint32
+    L.orc_morton_keys.argtypes = [i64, vp, vp, vp, vp, vp]
+    L.orc_knn.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp]
+    L.orc_frag_moments.argtypes = [d, d, vp, vp]
+    L.orc_rates.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.orc_bin_of.argtypes = [d]
+    L.orc_bin_of.restype = C.c_int32
+    L.orc_plan.argtypes = [vp, i64, vp, vp, vp, vp, d, i64, d, vp, vp, vp, vp]
+    L.orc_mc.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, d, C.c_uint64,
+                         C.c_uint32, vp, vp, vp, C.c_int32, vp, vp, vp]
+    L.orc_audit.argtypes = [vp, i64, vp, vp, vp, vp, vp, d, vp]
+    L.orc_push_local.argtypes = [i64, vp, vp, vp, vp, d]
+    L.orc_push_global.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, d]
+    L.orc_pair_rate.argtypes = [vp, d, d, d, d, d, d, d, vp]
+    L.orc_gas_at.argtypes = [vp, d, d, vp]
+    L.orc_oc07.argtypes = [d, d, d, d]
+    L.orc_oc07.restype = d
+    L.orc_reshuffle_index.argtypes = [i64, C.c_uint64, C.c_uint32, i64]
+    L.orc_reshuffle_index.restype = i64
+    L.orc_reshuffle.argtypes = [i64, C.c_int32, vp, vp, i64, C.c_uint64, C.c_uint32]
+    L.orc_diff_coeffs.argtypes = [vp, d, d, d, vp]
+    L.orc_diff_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, vp]
+    L.orc_diffuse.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, d, C.c_uint64,
+                              C.c_uint32]
+    L.orc_fsum.argtypes = [i64, vp]
+    L.orc_fsum.restype = d
+    L.orc_num_threads.restype = C.c_int
+    L.orc_set_threads.argtypes = [C.c_int]
+    return L
+
+
 def lib():
     global _lib
     with _lock:
         if _lib is None:
             build()
-            L = C.CDLL(_LIB)
-            vp = C.c_void_p
-            i64 = C.c_int64
-            d = C.c_double
-            L.orc_philox4x32_10.argtypes = [vp, vp, vp]
-            L.orc_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, vp]
-            L.orc_morton3_10.argtypes = [C.c_uint32] * 3
-            L.orc_morton3_10.restype = C.c_uint32
-            L.orc_morton_keys.argtypes = [i64, vp, vp, vp, vp, vp]
-            L.orc_knn.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp]
-            L.orc_frag_moments.argtypes = [d, d, vp, vp]
-            L.orc_rates.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
-            L.orc_bin_of.argtypes = [d]
-            L.orc_bin_of.restype = C.c_int32
-            L.orc_plan.argtypes = [vp, i64, vp, vp, vp, vp, d, i64, d, vp, vp, vp, vp]
-            L.orc_mc.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, d, C.c_uint64,
-                                 C.c_uint32, vp, vp, vp, C.c_int32, vp, vp, vp]
-            L.orc_audit.argtypes = [vp, i64, vp, vp, vp, vp, vp, d, vp]
-            L.orc_push_local.argtypes = [i64, vp, vp, vp, vp, d]
-            L.orc_push_global.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, d]
-            L.orc_pair_rate.argtypes = [vp, d, d, d, d, d, d, d, vp]
-            L.orc_gas_at.argtypes = [vp, d, d, vp]
-            L.orc_oc07.argtypes = [d, d, d, d]
-            L.orc_oc07.restype = d
-            L.orc_reshuffle_index.argtypes = [i64, C.c_uint64, C.c_uint32, i64]
-            L.orc_reshuffle_index.restype = i64
-            L.orc_reshuffle.argtypes = [i64, C.c_int32, vp, vp, i64, C.c_uint64, C.c_uint32]
-            L.orc_diff_coeffs.argtypes = [vp, d, d, d, vp]
-            L.orc_diff_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, vp]
-            L.orc_diffuse.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, d, C.c_uint64,
-                                      C.c_uint32]
-            L.orc_fsum.argtypes = [i64, vp]
-            L.orc_fsum.restype = d
-            L.orc_num_threads.restype = C.c_int
-            L.orc_set_threads.argtypes = [C.c_int]
-            _lib = L
+            _lib = _declare(C.CDLL(_LIB))
     return _lib
+
+
+@contextlib.contextmanager
+def planted(*edits):
+    """Swap in a copy of the oracle with each (old, new) text edit applied to
+    gd_oracle.c, built in a temporary folder: a test that plants a mistake in
+    the oracle checks that its pins reject it.  Every `old` must occur in the
+    source exactly once."""
+    global _lib
+    src = open(_SRC).read()
+    for old, new in edits:
+        if src.count(old) != 1:
+            raise ValueError(f"planted edit does not match exactly once: {old!r}")
+        src = src.replace(old, new)
+    with tempfile.TemporaryDirectory() as tmp:
+        c_path = os.path.join(tmp, "gd_oracle_planted.c")
+        so_path = os.path.join(tmp, "liboracle_planted.so")
+        with open(c_path, "w") as f:
+            f.write(src)
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                               "-shared", "-fPIC", "-o", so_path, c_path, "-lm"])
+        saved = lib()
+        with _lock:
+            _lib = _declare(C.CDLL(so_path))
+        try:
+            yield
+        finally:
+            with _lock:
+                _lib = saved
 
 
 def _p(a):

@@ -33,11 +33,15 @@
  * Readings of passages the paper leaves open are listed where they are used
  * and collected in the design notes of the repository.
  *
- * Parity unpinned (no independent value to check against; GPU parity is
- * against this code only): the OC07 branch constants away from the tested
- * regimes and limits.  The gas disk is pinned by its vertical integral and
- * hydrostatic balance, and eq:dv's composition by the quadrature sum of its
- * parts at points where all of them matter.
+ * The physical pair rate (gas disk, Stokes numbers, every term of eq:dv
+ * including the three Ormel & Cuzzi closed forms, the caps of V_i and the
+ * outcome channels) is pinned by an independent 50-digit evaluation of the
+ * printed formulas in each turbulence regime.  The gas disk is also pinned by
+ * its vertical integral and hydrostatic balance, and eq:dv's composition by
+ * the quadrature sum of its parts at points where all of them matter.
+ * What no pin can fix is the reading of the turbulent term: the paper adopts
+ * a six-branch form taken from another code without printing it; this file
+ * uses the three published limiting forms (see oc07_dv2).
  */
 #include <math.h>
 #include <stdint.h>
@@ -384,6 +388,10 @@ static double grain_size(const orc_problem* P, double m)
 /* Turbulent relative velocity squared, Ormel & Cuzzi (2007) closed forms:
  * tightly coupled (St1 < Re^-1/2), intermediate (Re^-1/2 <= St1 < 1) with
  * y_a = 1.6, heavy (St1 >= 1).  St1 >= St2, dSt = St1 - St2 >= 0.
+ * Sect. 2.5.2 names a six-branch piecewise form of these expressions as
+ * implemented in another code, which it does not print; the three published
+ * limits used here are the reading, with hard switches at the thresholds
+ * (equal grains jump from 0 to about 1.97 V_g^2 St at St = Re^-1/2).
  * The tightly coupled form
  *   Vg^2 (St1 - St2)/(St1 + St2) [St1^2/(St1 + t) - St2^2/(St2 + t)]
  * is evaluated as the algebraically equal
