@@ -33,17 +33,31 @@ import workloads  # noqa: E402
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VEC_PEAK_TFLOPS = 78.6    # MI355X FP64 vector (FMA = 2 flops)
 
-# Algorithmic (compulsory) HBM bytes per particle and launch, for the disk
-# workload (k = 32, FP64); see the design notes for the derivation.
+# Algorithmic (compulsory) HBM bytes per particle and launch, k = 32, FP64.
+# The rows follow the fixed per-particle-interval accounting of the method's
+# hot path (keys, sort, permute, cells, query, rates + sampling, push);
+# neighbour gathers are cache hits under Morton order and are not counted.
+# The sort is this build's: 30-bit keys in four 8-bit radix passes of
+# (key, slot) pairs.  Intermediates that one kernel writes and the next reads
+# back (the snapshot record, lambda*_i, a_i, b_i) are not compulsory and are
+# not counted.
 ALGO_BYTES = {
     "sort": 40 + 4 * 16 + 232,     # keys (read pos 24 + M 8, write key+slot 8); 4 radix passes; permute state
-    "tree": 32 + 7,                # read packed positions; write 24-byte boxes of 4-particle buckets and above
+    "tree": 8,                     # cell (bucket) table
     "knn_query": 24 + 128 + 4 + 8,  # own position; write nbr row, cnt, d_i
-    "rates": 128 + 4 + 8 + 24 + 16 + 32 + 24,  # nbr row, cnt, d_i, position, m and M; write snapshot record; write lam, a, b
-    "mc": 4 + 8 + 8 + 4 + 8 + 4,   # cnt, lam, m, id; write m', events
-    "audit": 24,                   # m, m', M
-    "push": 64 + 72,               # read spherical state, m, M; write state and Cartesian cache
+    "rates": 128 + 4 + 8 + 40,     # nbr row, cnt, d_i; own position, M and m
+    "mc": 16 + 8 + 4,              # own snapshot (m, id); write m', events
+    "audit": 24,                   # m, m', M (the fixed accounting folds this into sampling)
+    "push": 128,                   # spherical state and Cartesian cache, read and written
 }
+# The same accounting for the local column (x, y, z, v_z, St_mid, M, m state)
+# and the constant-kernel box (static positions: no keys, sort, query or push
+# per interval).
+ALGO_BYTES_COLUMN = dict(ALGO_BYTES, sort=32 + 64 + 136, tree=4, push=40)
+# Fixed bytes per particle-interval of the whole path, for the fraction of the
+# HBM roofline the path reaches: ~930 B for the 3D disk, ~650 B for the
+# column, and rates + sampling only (208 B) for the static box.
+PATH_BYTES = {"disk3d": 930, "disk3d_warm": 930, "additive_col": 650, "const_box": 208}
 PROF_KERNELS = ("sort", "tree", "knn_query", "rates", "mc", "audit", "push")
 # source file of each profiled stage (the HBM counter summary is tied to it)
 PROF_SOURCE = {"sort": "gd_sort.hip", "tree": "gd_knn.hip", "knn_query": "gd_knn.hip", "rates": "gd_rates.hip",
@@ -154,7 +168,7 @@ class HipEvents:
         self.lib.hipEventDestroy(e)
 
 
-def kernel_times(eng, hip, names, steps):
+def kernel_times(eng, hip, names, steps, step=None):
     """Run `steps` intervals with events around each named kernel; mean ms per launch."""
     import torch
     from paper_2609_35967_amd import binding
@@ -163,7 +177,7 @@ def kernel_times(eng, hip, names, steps):
         for k in names:
             a, b = pairs[k][s]
             binding.check(eng.lib.gd_profile_events(binding.PROF[k], a, b))
-        eng.step()
+        (step or eng.step)()
     torch.cuda.synchronize()
     for k in names:
         binding.check(eng.lib.gd_profile_events(binding.PROF[k], None, None))
@@ -177,17 +191,42 @@ def kernel_times(eng, hip, names, steps):
     return out
 
 
-def cpu_baseline(params, seed, n, nq):
-    """The FP64 oracle, as it stands, on a bounded sample of the same workload:
-    Morton order of all particles, then brute-force kNN, rates and sampling of
-    one interval for `nq` sampled particles."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_interval(wl, params, seed, n, nq):
+    """One interval of the oracle, as it stands, on a bounded sample: the Morton
+    order of all particles, then its brute-force O(N^2) neighbour search, rates
+    and sampling for `nq` sampled particles (all of them on the static box,
+    whose neighbour lists are built once and not timed).  Returns (particles,
+    seconds)."""
     import oracle
-    st = workloads.disk3d(seed, n, params=params)
+    params, st = workloads.by_name(wl, seed=seed, n=n if wl in ("disk3d", "disk3d_warm") else None)
     P = oracle.make_problem(params)
+    if wl == "const_box":
+        perm = oracle.sort_perm(oracle.morton_keys(st["x"], st["y"], st["z"], st["M"]))
+        s = {k: v[perm] for k, v in st.items()}
+        nbr, cnt, dmax = oracle.knn(P, s["x"], s["y"], s["z"], s["M"])
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < 5.0:
+            oracle.rates(P, nbr, cnt, dmax, s["m"], s["M"], s["x"], s["y"], s["z"])
+            oracle.mc(P, s["id"], nbr, cnt, dmax, s["m"], s["M"], s["x"], s["y"], s["z"], params["dt_coll"], seed,
+                      reps)
+            reps += 1
+        return n * reps, time.perf_counter() - t0
     t0 = time.perf_counter()
     perm = oracle.sort_perm(oracle.morton_keys(st["x"], st["y"], st["z"], st["M"]))
     s = {k: v[perm] for k, v in st.items()}
-    q = np.sort(np.random.default_rng(seed).choice(n, nq, replace=False))
+    q = np.sort(np.random.default_rng(seed).choice(n, min(nq, n), replace=False))
     nbr_q, cnt_q, dmax_q = oracle.knn(P, s["x"], s["y"], s["z"], s["M"], queries=q)
     nbr = np.full((n, P.k), -1, np.int32)
     cnt = np.zeros(n, np.int32)
@@ -196,10 +235,28 @@ def cpu_baseline(params, seed, n, nq):
     oracle.rates(P, nbr, cnt, dmax, s["m"], s["M"], s["x"], s["y"], s["z"], queries=q)
     oracle.mc(P, s["id"], nbr, cnt, dmax, s["m"], s["M"], s["x"], s["y"], s["z"], params["dt_coll"], seed, 0,
               queries=q)
-    t = time.perf_counter() - t0
-    return dict(value=nq / t, unit="particle-intervals/s", cores=oracle.num_threads(), kind="oracle",
-                sample=(f"one interval (Morton order of all {n} particles, brute-force kNN + rates + sampling "
-                        f"for {nq} sampled particles, dt = dt_coll) in {t:.1f} s"))
+    return len(q), time.perf_counter() - t0
+
+
+def cpu_baseline(wl, params, seed, n, nq):
+    """The FP64 oracle as it stands, on the host cores: one run on all of them
+    (OpenMP over particles) and one on a single thread, each on a bounded
+    sample of the same workload, scaled to particle-intervals/s."""
+    import oracle
+    cores = oracle.num_threads()
+    np_all, t_all = _oracle_interval(wl, params, seed, n, nq)
+    oracle.set_threads(1)
+    try:
+        np_one, t_one = _oracle_interval(wl, params, seed, n, max(256, nq // max(cores, 1)))
+    finally:
+        oracle.set_threads(cores)
+    what = ("rates and sampling of every particle, neighbour lists built once" if wl == "const_box" else
+            f"Morton order of all {n} particles, then brute-force O(N^2) kNN, rates and sampling of one interval "
+            f"(dt = dt_coll) for the sampled particles")
+    return dict(value=np_all / t_all, unit="particle-intervals/s", cores=cores, kind="oracle",
+                sample=f"{what}: {np_all} particle-intervals in {t_all:.1f} s on {cores} threads, "
+                       f"{np_one} in {t_one:.1f} s on 1 thread",
+                value_1thread=np_one / t_one, cpu_model=_cpu_model(), host_threads=os.cpu_count())
 
 
 def batch_bench(args):
@@ -575,7 +632,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="disk3d", choices=["disk3d", "disk3d_warm"])
+    ap.add_argument("--workload", default="disk3d", choices=["disk3d", "disk3d_warm", "additive_col", "const_box"])
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=98304, help="particles in the oracle's timed sample")
@@ -637,17 +694,32 @@ def main():
 
     load()
     torch.cuda.set_device(0)
-    params, st = workloads.by_name(args.workload, seed=args.seed, n=args.n)
+    wl = args.workload
+    n_arg = args.n if wl in ("disk3d", "disk3d_warm") else None
+    params, st = workloads.by_name(wl, seed=args.seed, n=n_arg)
     if args.rates_fp32:
         params["rates_fp32"] = 1
     eng = Engine(params, st, seed=args.seed)
     n = eng.n
     hip = HipEvents()
+    static = wl == "const_box"  # positions never move: neighbour lists built once (App. A test)
+    knn_once_ms = None
+    if static:
+        a, b = hip.create(), hip.create()
+        from paper_2609_35967_amd import binding as _b
+        torch.cuda.synchronize()
+        _b.check(eng.lib.gd_profile_events(_b.PROF["knn_query"], a, b))
+        eng.build_neighbors()
+        torch.cuda.synchronize()
+        _b.check(eng.lib.gd_profile_events(_b.PROF["knn_query"], None, None))
+        knn_once_ms = hip.elapsed_ms(a, b)
+    step = (lambda: eng.step(rebuild=False)) if static else eng.step
     for _ in range(args.warmup):
-        eng.step()
+        step()
     torch.cuda.synchronize()
     # per-kernel breakdown on a short pass (untimed for the headline)
-    brk = kernel_times(eng, hip, PROF_KERNELS, max(5, min(20, args.steps // 4)))
+    names = ("rates", "mc", "audit") if static else PROF_KERNELS
+    brk = kernel_times(eng, hip, names, max(5, min(20, args.steps // 4)), step)
     dom = max(brk, key=brk.get)
 
     # timed region: the headline loop; events per interval and around the dominant kernel
@@ -657,11 +729,11 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev[0].record()
-    for s in range(args.steps):
-        a, b = dpairs[s]
+    for s_ in range(args.steps):
+        a, b = dpairs[s_]
         eng.lib.gd_profile_events(binding.PROF[dom], a, b)
-        eng.step()
-        ev[s + 1].record()
+        step()
+        ev[s_ + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     binding.check(eng.lib.gd_profile_events(binding.PROF[dom], None, None))
@@ -672,35 +744,50 @@ def main():
     wall = t1 - t0
     value = n * args.steps / wall
 
-    achieved = ALGO_BYTES[dom] * n / (dom_ms * 1e-3) / 1e9
-    traffic = measured_traffic(dom)
+    algo = ALGO_BYTES_COLUMN if wl in ("additive_col", "const_box") else ALGO_BYTES
+    achieved = algo[dom] * n / (dom_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom) if wl == "disk3d" else None
     roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 5),
                     traffic=None if traffic is None else round(traffic / (dom_ms * 1e-3) / 1e9, 2), kernel=dom,
-                    algo_bytes_per_particle=ALGO_BYTES[dom], launch_ms=round(dom_ms, 4),
+                    algo_bytes_per_particle=algo[dom], launch_ms=round(dom_ms, 4),
                     traffic_bytes_per_launch=None if traffic is None else round(traffic))
-    valu = measured_valu(dom, dom_ms)
+    valu = measured_valu(dom, dom_ms) if wl == "disk3d" else None
     if valu is not None:
         roofline["valu"] = valu
-    path_bytes = sum(ALGO_BYTES.values())
     out = dict(
         metric="particle-intervals/s (kNN+rates+MC) at 1M; batched vs plain; p50/p99 latency",
         value=round(value, 1), unit="particle-intervals/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
         ms_per_step=round(wall / args.steps * 1e3, 4), higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype="f64+f32-rates" if args.rates_fp32 else "f64", data="synthetic",
-        config=dict(workload=f"{args.workload}: 3D disk annulus r in [10,100] au, {n} particles, k=32, "
-                             "alpha=1e-3, v_frag=1 m/s, Brownian+OC07, sticking/erosion/fragmentation, "
-                             "one push per interval", n_particles=n, k=32, form="plain (single run)",
-                    rates="fp32 pairs, fp64 sums" if args.rates_fp32 else "fp64"),
+        config=dict(workload=WORKLOAD_TEXT[wl].format(n=n), n_particles=n, k=int(params["k"]),
+                    form="plain (single run)", rates="fp32 pairs, fp64 sums" if args.rates_fp32 else "fp64"),
         p50_ms=round(float(np.percentile(lat, 50)), 4), p99_ms=round(float(np.percentile(lat, 99)), 4),
         breakdown_ms={k: round(v, 4) for k, v in brk.items()},
-        path_fraction_of_hbm=round(path_bytes * value / (HBM_PEAK_GBS * 1e9), 5),
+        path_fraction_of_hbm=round(PATH_BYTES[wl] * value / (HBM_PEAK_GBS * 1e9), 5),
+        path_bytes_per_particle_interval=PATH_BYTES[wl],
         roofline=roofline,
-        interval=dict(dt_exe=ivs["dt_exe"], C=ivs["C"], n_events_last=ivs["n_events"], status=status),
+        interval=dict(dt_exe=ivs["dt_exe"], C=ivs["C"], n_events_last=ivs["n_events"],
+                      n_intervals=ivs["n_intervals"], time=ivs["time"], status=status),
     )
+    if knn_once_ms is not None:
+        out["knn_once_ms"] = round(knn_once_ms, 4)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(params, args.seed, n, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(wl, params, args.seed, n, args.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+WORKLOAD_TEXT = {
+    "disk3d": ("disk3d: 3D disk annulus r in [10,100] au, {n} particles, k=32, alpha=1e-3, v_frag=1 m/s, "
+               "Brownian+OC07, sticking/erosion/fragmentation, one push per interval"),
+    "disk3d_warm": ("disk3d_warm: 3D disk annulus r in [10,100] au, {n} particles, grain radius log-uniform "
+                    "1 um..1 mm, k=32, alpha=1e-3, v_frag=1 m/s, Brownian+OC07, sticking/erosion/fragmentation, "
+                    "one push per interval"),
+    "additive_col": ("additive_col: local column, {n} particles, additive kernel, k=32, z ~ N(0, H=1), "
+                     "St log-uniform 1e-4..1e-1, one local settling push per interval"),
+    "const_box": ("const_box: periodic unit cube, {n} particles, constant kernel, k=32, static positions "
+                  "(neighbour lists built once, timed apart as knn_once_ms)"),
+}
 
 
 if __name__ == "__main__":

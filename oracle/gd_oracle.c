@@ -1248,7 +1248,13 @@ void orc_reshuffle(int64_t n, int32_t k, int32_t* nbr, const int32_t* cnt, int64
     for (int64_t i = 0; i < n; i++) {
         for (int32_t s = 1; s < cnt[i] && s < k; s++) {
             int32_t* e = &nbr[i * k + s];
-            if (*e >= 0 && *e < N) *e = (int32_t)orc_reshuffle_index(N, seed, refresh, *e);
+            if (*e >= 0 && *e < N) {
+                /* the other that pi sends onto i itself takes pi(i) instead, so
+                 * the row stays free of i (slot 0 holds it) and of repeats */
+                int64_t v = orc_reshuffle_index(N, seed, refresh, *e);
+                if (v == i) v = orc_reshuffle_index(N, seed, refresh, i);
+                *e = (int32_t)v;
+            }
         }
     }
 }

@@ -391,6 +391,7 @@ class Engine:
         lo = (C.c_int32 * (G + 1))(*[g * na // G for g in range(G + 1)])
         check(self.lib.gd_group_interactions(C.byref(self.P), C.byref(self.nb), lo, G,
                                              C.c_void_p(self.gmask.data_ptr()), self._s()))
+        self._sync_own()  # the rows are read below on torch's stream
         self.group_lo = [int(v) for v in lo]
         self.group_rows = [int(v) & ((1 << 64) - 1) for v in self.gmask.cpu().tolist()]
 
@@ -520,9 +521,39 @@ class Engine:
         return {name: getattr(s, name) for name, _ in GdInterval._fields_}
 
     def status(self) -> int:
+        """Device status bits of the engine's workspace, ORed with those of the
+        per-group workspaces when groups run concurrently (synchronises)."""
         v = C.c_int32()
         check(self.lib.gd_status_read(C.c_void_p(self.ws_ptr), self._s(), C.byref(v)))
-        return v.value
+        out = v.value
+        for g, (_, ptr) in enumerate(getattr(self, "gws", None) or []):
+            check(self.lib.gd_status_read(C.c_void_p(ptr), C.c_void_p(self.gstreams[g].cuda_stream), C.byref(v)))
+            out |= v.value
+        return out
 
     def state_numpy(self) -> dict:
         return self.A.to_numpy()
+
+    # ---- checkpoint / resume ------------------------------------------------------
+    def checkpoint(self) -> dict:
+        """Host copy of everything the run needs to continue as if uninterrupted:
+        the particle state in its current order, the device interval state (C,
+        clock, counters), the next interval index and diffusion step, and the
+        seed.  The previous search's neighbour distances go along as well; they
+        only seed the next search's radius.  Synchronises."""
+        self._sync_own()
+        return dict(state=self.A.to_numpy(), iv=self.iv.cpu().numpy().copy(), interval=int(self.interval),
+                    diff_step=int(self.diff_step), seed=int(self.seed), dmax=self.dmax.cpu().numpy().copy())
+
+    @classmethod
+    def restore(cls, params: dict, ckpt: dict, **kw) -> "Engine":
+        """A new engine that continues the run saved by checkpoint()."""
+        eng = cls(params, ckpt["state"], seed=int(ckpt["seed"]), **kw)
+        torch = eng.torch
+        eng._sync_own()  # the interval state's initialisation has run
+        eng.iv.copy_(torch.as_tensor(np.asarray(ckpt["iv"], np.uint8)))
+        eng.dmax.copy_(torch.as_tensor(np.asarray(ckpt["dmax"], np.float64)))
+        eng.interval = int(ckpt["interval"])
+        eng.diff_step = int(ckpt["diff_step"])
+        torch.cuda.current_stream(eng.device).synchronize()  # the copies ran on torch's stream
+        return eng

@@ -75,7 +75,10 @@ __global__ __launch_bounds__(256) void k_reshuffle_apply(int32_t* __restrict__ n
     if (s == 0 || N <= 1 || int32_t(i) >= N || int32_t(s) >= cnt[i]) return;
     const int32_t j = nbr[e];
     if (j < 0 || j >= N) return;
-    nbr[e] = table[j];
+    // pi is a bijection and the row's others exclude i, so exactly one other
+    // can be sent onto i; it takes pi(i), which no other slot receives
+    const int32_t v = table[j];
+    nbr[e] = v == int32_t(i) ? table[i] : v;
 }
 
 int launch_reshuffle(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh, void* ws,

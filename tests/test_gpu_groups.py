@@ -46,9 +46,7 @@ def test_grouped_steps_match_oracle(G, n, concurrent):
         d_gpu = eng.collide_groups()
         d_orc = run.collide_groups()
         _say("G", G, "step", step, "group intervals", len(d_gpu))
-        if any(e["near_tie"] for e in run.log):
-            _say("near tie - stopping the comparison there")
-            return
+        assert not any(e["near_tie"] for e in run.log), "near tie: choose another seed"
         assert d_gpu == d_orc
         rows = [sorted(h for h in range(G) if (eng.group_rows[g] >> h) & 1) for g in range(G)]
         assert rows == [sorted(int(h) for h in s) for s in run.links]
@@ -57,6 +55,7 @@ def test_grouped_steps_match_oracle(G, n, concurrent):
         assert np.array_equal(got["m"], ref["m"])
         for g in range(G):
             assert eng.group_interval_state(g)["C"] == run.gC[g]
+    assert eng.status() & ~0x4 == 0  # every group workspace included
 
 
 def test_grouped_steps_with_inactive_particles():
@@ -71,9 +70,7 @@ def test_grouped_steps_with_inactive_particles():
     run = GroupedRun(params, st, seed=8, n_groups=6)
     d_gpu = eng.collide_groups()
     d_orc = run.collide_groups()
-    if any(e["near_tie"] for e in run.log):
-        _say("near tie - stopping the comparison there")
-        return
+    assert not any(e["near_tie"] for e in run.log), "near tie: choose another seed"
     assert d_gpu == d_orc
     assert eng.group_lo == run.bounds and run.bounds[-1] == n - len(range(0, n, 9))
     got, ref = _by_id(eng.state_numpy()), _by_id(run.st)
@@ -110,12 +107,11 @@ def test_grouped_physical_disk(concurrent):
     run = GroupedRun(params, st, seed=4, n_groups=4)
     d_gpu = eng.collide_groups()
     d_orc = run.collide_groups()
-    if any(e["near_tie"] for e in run.log):
-        _say("near tie - stopping the comparison there")
-        return
+    assert not any(e["near_tie"] for e in run.log), "near tie: choose another seed"
     assert d_gpu == d_orc
     got, ref = _by_id(eng.state_numpy()), _by_id(run.st)
     assert np.array_equal(got["m"], ref["m"])
+    assert eng.status() & ~0x4 == 0  # every group workspace included
 
 
 @pytest.mark.parametrize("concurrent", [False, True])
@@ -133,9 +129,7 @@ def test_grouped_strang_steps_match_oracle(concurrent):
         n_gpu = eng.strang_step()
         res = run.strang_step()
         torch.cuda.synchronize()
-        if any(r["mc"]["near_tie"].any() for r in res):
-            _say("near tie in step", step, "- stopping the comparison there")
-            return
+        assert not any(r["mc"]["near_tie"].any() for r in res), f"near tie in step {step}: choose another seed"
         assert n_gpu == len(res)
         got, ref = _by_id(eng.state_numpy()), _by_id(run.st)
         assert np.array_equal(got["m"], ref["m"])

@@ -45,9 +45,37 @@ def test_rows():
         assert out[i, 0] == nbr[i, 0]
         assert np.array_equal(out[i, max(cnt[i], 1):], nbr[i, max(cnt[i], 1):])
         for s in range(1, cnt[i]):
-            assert out[i, s] == oracle.reshuffle_index(N, 9, 1, int(nbr[i, s]))
+            v = oracle.reshuffle_index(N, 9, 1, int(nbr[i, s]))
+            if v == i:
+                v = oracle.reshuffle_index(N, 9, 1, i)
+            assert out[i, s] == v
     # rows stay free of repeats among the relabelled entries (pi is injective)
     row = np.arange(1, 30, dtype=np.int32)
     nb2 = np.concatenate([[0], row]).astype(np.int32)[None, :]
     o2 = oracle.reshuffle(nb2, np.array([30], np.int32), N, 9, 4)
     assert len(set(o2[0, 1:].tolist())) == 29
+
+
+def test_rows_stay_distinct_and_free_of_self():
+    # real neighbour rows (distinct others, none equal to the row's particle):
+    # after relabelling they are still distinct and still exclude the particle,
+    # which pi sends onto itself from exactly one slot; that slot takes pi(i)
+    import workloads
+    N = 2000
+    params, st = workloads.by_name("const_box", seed=4, n=N)
+    P = oracle.make_problem(params)
+    nbr, cnt, _ = oracle.knn(P, st["x"], st["y"], st["z"], st["M"])
+    hit = 0
+    for refresh in range(3):
+        out = oracle.reshuffle(nbr, cnt, N, 17, refresh)
+        for i in range(N):
+            others = out[i, 1:cnt[i]]
+            assert out[i, 0] == i
+            assert i not in others
+            assert len(set(others.tolist())) == cnt[i] - 1
+            pi_row = [oracle.reshuffle_index(N, 17, refresh, int(j)) for j in nbr[i, 1:cnt[i]]]
+            if i in pi_row:
+                hit += 1
+                assert oracle.reshuffle_index(N, 17, refresh, i) in others
+    # rows where pi sends an other onto i occur about (k - 1)/N of the time
+    assert 20 < hit < 200
