@@ -229,12 +229,30 @@ int32_t gd_collision_rates(const gd_problem* p, const gd_particles* st, const gd
  * one random bijection of [0, N) per (seed, refresh): a four-round balanced
  * Feistel network on two h-bit halves (4^h >= N) with round function word 0
  * of Philox4x32-10, counter (right half, round, refresh, 0x52534831), key =
- * seed, restricted to [0, N) by cycle walking.  In place on the caller's
- * stream.  pi is tabulated in the workspace (the part the neighbour build
- * uses for its sort keys), so the call may sit anywhere outside
- * gd_build_neighbors. */
+ * seed, restricted to [0, N) by cycle walking.  The one other of row i
+ * that pi sends onto i itself becomes pi(i) instead, so rows stay free of i
+ * and of repeats.  In place on the caller's stream.  pi is tabulated in the
+ * workspace (the part the neighbour build uses for its sort keys), so the
+ * call may sit anywhere outside gd_build_neighbors. */
 int32_t gd_reshuffle_neighbors(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh,
                                void* ws, size_t ws_bytes, void* stream);
+
+/* Neighbour reshuffling without allocation, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation.  The same operation and the same result as
+ * gd_reshuffle_neighbors, with no workspace: pi's table is kept in a fixed
+ * device array of GD_RESHUFFLE_STATIC_MAX int32 entries (16 MiB) that the
+ * library holds on every GPU it runs on until the process ends.  p->n must be
+ * at most GD_RESHUFFLE_STATIC_MAX (GD_E_INVALID_ARG otherwise, before any
+ * device work).  The first call on a device, with that device current,
+ * resolves the array's address there (GD_E_HIP if that fails).  No call
+ * allocates or frees memory.  All calls on one GPU share its array, so calls
+ * that overlap on one GPU (other streams, other host threads) race and must
+ * be serialised by the caller; each call rewrites the entries it reads, so
+ * no clearing is needed between calls.  In place on the caller's stream. */
+#define GD_RESHUFFLE_STATIC_MAX (1 << 22)
+int32_t gd_reshuffle_neighbors_static(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh,
+                                      void* stream);
 
 /* Sampling over many independent runs (boxes) at once.  gd_sample_collisions
  * is, in order: the per-lane pass (each particle's first events; a particle

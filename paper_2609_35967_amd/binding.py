@@ -65,7 +65,7 @@ EXPORTS = ("gd_workspace_size", "gd_workspace_init", "gd_interval_init", "gd_bui
            "gd_sample_collisions", "gd_push", "gd_profile_events", "gd_status_read", "gd_last_error", "gd_version",
            "gd_sample_table_size", "gd_sample_collisions_deferred", "gd_sample_table_run", "gd_sample_audit",
            "gd_reshuffle_neighbors", "gd_diffuse", "gd_group_interactions", "gd_collision_rates_group",
-           "gd_sample_collisions_group", "gd_publish_group")
+           "gd_sample_collisions_group", "gd_publish_group", "gd_reshuffle_neighbors_static")
 PROF = {"sort": 0, "tree": 1, "knn_query": 2, "rates": 3, "mc": 4, "audit": 5, "push": 6, "diffuse": 7}
 GD_INTERVAL_ON_DEVICE = (1 << 64) - 1
 
@@ -105,6 +105,8 @@ def load(path: str | None = None):
     L.gd_sample_audit.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), vp, vp, C.c_size_t, vp]
     L.gd_reshuffle_neighbors.argtypes = [C.POINTER(GdProblem), C.POINTER(GdNeighbors), C.c_uint64, C.c_uint32, vp,
                                          C.c_size_t, vp]
+    L.gd_reshuffle_neighbors_static.argtypes = [C.POINTER(GdProblem), C.POINTER(GdNeighbors), C.c_uint64,
+                                                C.c_uint32, vp]
     L.gd_diffuse.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.c_double, C.c_uint64, C.c_uint32, vp]
     L.gd_group_interactions.argtypes = [C.POINTER(GdProblem), C.POINTER(GdNeighbors), vp, C.c_int32, vp, vp]
     L.gd_collision_rates_group.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.POINTER(GdNeighbors), vp,
@@ -123,7 +125,7 @@ def load(path: str | None = None):
                  "gd_sample_collisions", "gd_push", "gd_status_read", "gd_profile_events", "gd_sample_table_size",
                  "gd_sample_collisions_deferred", "gd_sample_table_run", "gd_sample_audit",
                  "gd_reshuffle_neighbors", "gd_diffuse", "gd_group_interactions", "gd_collision_rates_group",
-                 "gd_sample_collisions_group", "gd_publish_group"):
+                 "gd_sample_collisions_group", "gd_publish_group", "gd_reshuffle_neighbors_static"):
         getattr(L, name).restype = C.c_int32
     if path is None:
         _lib = L
@@ -297,6 +299,12 @@ class Engine:
         """Random relabelling of the cached neighbours (product-kernel test), in place."""
         check(self.lib.gd_reshuffle_neighbors(C.byref(self.P), C.byref(self.nb), self.seed, int(refresh),
                                               C.c_void_p(self.ws_ptr), self.ws_bytes, self._s()))
+
+    def reshuffle_neighbors_static(self, refresh: int):
+        """The same relabelling through the allocation-free entry point (its
+        table is the library's fixed per-GPU array, not the workspace)."""
+        check(self.lib.gd_reshuffle_neighbors_static(C.byref(self.P), C.byref(self.nb), self.seed, int(refresh),
+                                                     self._s()))
 
     def sample_deferred(self, table, table_bytes: int, slot: int):
         """The per-lane pass of sampling; the run's arguments go to table slot `slot`

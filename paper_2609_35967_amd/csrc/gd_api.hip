@@ -271,6 +271,24 @@ int32_t gd_reshuffle_neighbors(const gd_problem* p, const gd_neighbors* nb, uint
     return hip_ok("gd_reshuffle_neighbors");
 }
 
+int32_t gd_reshuffle_neighbors_static(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh,
+                                      void* stream)
+{
+    int rc = check_problem(p);
+    if (!rc) rc = check_nb(nb);
+    if (rc) return rc;
+    if (!nb->n_active) return fail(GD_E_INVALID_ARG, "neighbours: n_active is NULL");
+    if (p->n > int64_t(GD_RESHUFFLE_STATIC_MAX))
+        return fail(GD_E_INVALID_ARG, "gd_reshuffle_neighbors_static: n = %lld exceeds its fixed table of %d entries",
+                    (long long)p->n, GD_RESHUFFLE_STATIC_MAX);
+    int32_t* table = nullptr;
+    const hipError_t e = reshuffle_static_table(&table);
+    if (e != hipSuccess)
+        return fail(GD_E_HIP, "gd_reshuffle_neighbors_static: device table address: %s", hipGetErrorString(e));
+    launch_reshuffle_static(p, nb, seed, refresh, table, static_cast<hipStream_t>(stream));
+    return hip_ok("gd_reshuffle_neighbors_static");
+}
+
 int32_t gd_sample_table_size(int32_t nslot, size_t* bytes)
 {
     if (!bytes) return fail(GD_E_INVALID_ARG, "bytes is NULL");

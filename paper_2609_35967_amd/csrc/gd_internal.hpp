@@ -33,6 +33,9 @@ int launch_sample(const gd_problem* p, const gd_particles* s, const gd_neighbors
                   int32_t log_cap, void* ws, const Layout& L, hipStream_t st, void* table, int32_t slot);
 int launch_reshuffle(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh, void* ws,
                      const Layout& L, hipStream_t st);
+hipError_t reshuffle_static_table(int32_t** table);
+int launch_reshuffle_static(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh,
+                            int32_t* table, hipStream_t st);
 int launch_audit(const gd_problem* p, const gd_particles* s, gd_interval* iv, void* ws, const Layout& L, hipStream_t st);
 size_t sample_table_bytes(int32_t nslot);
 int max_table_slots();

@@ -11,8 +11,12 @@
 // applied until the value falls below N.  A walk stays on the cycle of the
 // network's permutation through j, so it ends within 4^h <= 4N steps.
 // pi is evaluated once per slot into a table (the workspace's sort keys,
-// free outside the neighbour build), then every cached entry is relabelled
-// by one read of the table.
+// free outside the neighbour build, or a fixed device array in the
+// allocation-free form), then every cached entry is relabelled by one read
+// of the table.  The one other that pi sends onto the row's own particle
+// takes pi of that particle instead, so a row never holds itself twice.
+#include <mutex>
+
 #include "gd_common.hpp"
 #include "gd_internal.hpp"
 
@@ -81,12 +85,12 @@ __global__ __launch_bounds__(256) void k_reshuffle_apply(int32_t* __restrict__ n
     nbr[e] = v == int32_t(i) ? table[i] : v;
 }
 
-int launch_reshuffle(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh, void* ws,
-                     const Layout& L, hipStream_t st)
+// pi of every active slot into `table`, then every cached entry relabelled
+static void launch_with_table(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh,
+                              int32_t* table, hipStream_t st)
 {
     const int64_t total = p->n * int64_t(p->k);
-    if (total <= 0) return 0;
-    int32_t* table = at<int32_t>(ws, L.keys0);
+    if (total <= 0) return;
     hipLaunchKernelGGL(k_reshuffle_table, dim3(unsigned((p->n + 255) / 256)), dim3(256), 0, st, table, nb->n_active,
                        p->n, seed, refresh);
     const dim3 grid(unsigned((total + 255) / 256));
@@ -97,6 +101,53 @@ int launch_reshuffle(const gd_problem* p, const gd_neighbors* nb, uint64_t seed,
         hipLaunchKernelGGL(k_reshuffle_apply<6>, grid, dim3(256), 0, st, nb->nbr, nb->cnt, nb->n_active, table, t32, k);
     else
         hipLaunchKernelGGL(k_reshuffle_apply<0>, grid, dim3(256), 0, st, nb->nbr, nb->cnt, nb->n_active, table, t32, k);
+}
+
+int launch_reshuffle(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh, void* ws,
+                     const Layout& L, hipStream_t st)
+{
+    launch_with_table(p, nb, seed, refresh, at<int32_t>(ws, L.keys0), st);
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// The allocation-free form: pi's table lives in this fixed device array, one
+// copy per GPU, held until the process ends.  In host code the name `scratch`
+// is a host-side stand-in, not a device address; the array's address on a
+// device is resolved once, with that device current, by hipGetSymbolAddress,
+// and only that address is ever passed to kernels.  Calls on one GPU share
+// the array: overlapping calls there race.  Each call writes entries 0 .. N-1
+// before reading them, so nothing needs clearing between calls.
+static __device__ __align__(256) int32_t scratch[GD_RESHUFFLE_STATIC_MAX];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+hipError_t reshuffle_static_table(int32_t** table)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch[dev] = static_cast<int32_t*>(ptr);
+    }
+    *table = g_scratch[dev];
+    return hipSuccess;
+}
+
+int launch_reshuffle_static(const gd_problem* p, const gd_neighbors* nb, uint64_t seed, uint32_t refresh,
+                            int32_t* table, hipStream_t st)
+{
+    launch_with_table(p, nb, seed, refresh, table, st);
     return 0;
 }
 

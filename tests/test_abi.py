@@ -201,3 +201,18 @@ def test_group_call_validation(lib):
     assert lib.gd_sample_collisions_group(*args, 1, 0, -1, 10, None, *ws, None) == -1
     assert lib.gd_publish_group(C.byref(P), C.byref(fake), 5, 1001, None, 0, None) == -1
     assert lib.gd_publish_group(C.byref(P), C.byref(fake), 0, 10, C.c_void_p(512), 64, None) == -1
+
+
+def test_static_reshuffle_rejects_sizes_beyond_its_table(lib):
+    # the allocation-free entry point keeps pi's table in a fixed per-GPU array
+    # of GD_RESHUFFLE_STATIC_MAX entries; a larger n fails on the host, before
+    # any device work, with a message that names the limit
+    from paper_2609_35967_amd import binding
+    limit = 1 << 22
+    src = open(os.path.join(ROOT, "include", "gd.h")).read()
+    assert "#define GD_RESHUFFLE_STATIC_MAX (1 << 22)" in src
+    nb = binding.GdNeighbors(256, 512, 768, 1024)  # never dereferenced: validation fails first
+    P = binding.make_problem(workloads.const_box_params(limit + 1))
+    assert lib.gd_reshuffle_neighbors_static(C.byref(P), C.byref(nb), 1, 0, None) == -1
+    assert b"exceeds its fixed table of 4194304 entries" in lib.gd_last_error()
+    assert lib.gd_reshuffle_neighbors_static(C.byref(P), None, 1, 0, None) == -1
