@@ -83,7 +83,7 @@ typedef enum gd_diffusion_form {
 /* Problem description (host struct, read during each call). */
 typedef struct gd_problem {
     int64_t n;            /* length of every particle array */
-    int32_t k;            /* N_K: neighbours per particle including itself, 2..64 */
+    int32_t k;            /* N_K: neighbours per particle including itself, 2..256 */
     int32_t kernel;       /* gd_kernel */
     int32_t push;         /* gd_push_kind */
     int32_t nbin_min;     /* minimum particles per merged controller bin (0: max(2k, 64)) */
@@ -269,7 +269,8 @@ int32_t gd_reshuffle_neighbors_static(const gd_problem* p, const gd_neighbors* n
  * which takes gd_sample_collisions' arguments and writes the run's sampling
  * arguments into slot r; then, on one stream ordered after all of them,
  * gd_sample_table_run(table, table_bytes, nslot, k, rates_fp32, stream), where
- * every run has the same k class (k <= 32, or 32 < k <= 64) and the same
+ * every run's k is at most the k passed here (the launch is shaped for the
+ * class of that k: <= 32, <= 64, <= 128 or <= 256) and the same
  * rates_fp32 (a run that differs is skipped and raises GD_DEV_INTERNAL); then
  * gd_sample_audit for each run, after which the caller flips st->cur.  Every
  * slot below nslot must have been written in the same interval: a slot left

@@ -17,7 +17,7 @@ constexpr int kBinOff = 64;
 constexpr int64_t kTicks = int64_t(1) << 30;  // ticks per collision step
 constexpr int kSortTile = 4096;     // keys per radix-sort block
 constexpr int kRedBlocks = 256;     // blocks of the bin reductions
-constexpr int kMaxK = 64;
+constexpr int kMaxK = 256;
 constexpr int kBucket = 4;          // particles per leaf bucket of the search tree
 constexpr int kFan = 8;             // children per internal node of the search tree
 constexpr int kMaxTreeLevels = 8;   // stored box levels (n <= 4 * 8^8 = 2^26 particles)

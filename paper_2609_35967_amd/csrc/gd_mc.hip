@@ -112,9 +112,13 @@ __device__ inline double prefix_rates(const McArgs& A, const QCtx& q, const int3
     return li;
 }
 
+// KP2 = 0: a neighbourhood too large for a lane's prefix registers; a lane
+// only decides whether its particle has an event at all, and hands every
+// particle that has one to the wavefront-per-particle pass at its start.
 template <int KP2, bool F32>
 __global__ __launch_bounds__(256) void k_mc(McArgs A)
 {
+    constexpr int KR = KP2 > 0 ? KP2 : 32;  // prefix registers (unused when KP2 = 0)
     const int64_t i = xcd_block() * int64_t(blockDim.x) + threadIdx.x;
     const int lane = threadIdx.x & 63;
     int e = 0;
@@ -133,7 +137,7 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
             QCtxF qf{};
             bool have_ctx = false, have_pre = false;
             double si = 0.0, Sti = 0.0;
-            double pre[KP2];
+            double pre[KR];
             double t = 0.0;
             for (;;) {
                 if (!(li > 0.0)) break;
@@ -153,6 +157,11 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
                 event_uniforms(A.seed, pid, interval, uint32_t(e), u);
                 const double dtw = -log(u[0]) / li;
                 if (dtw > dt_exe - t) break;
+                if (KP2 == 0) {
+                    const int32_t slot = atomicAdd(A.heavy_n, 1);
+                    A.heavy[slot] = Deferred{int32_t(i), e, t, m};
+                    break;
+                }
                 t = t + dtw;
                 if (!have_ctx) {
                     query_ctx(A.P, A.x[i], A.y[i], A.z[i], A.dmax[i], q);
@@ -164,15 +173,15 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
                         si = grain_size(A.P, m);
                         Sti = F32 ? double(qf.stfac * float(si)) : q.stfac * si;
                     }
-                    li = F32 ? prefix_rates_f32<KP2>(A, qf, row, c, m, float(si), float(Sti), pre)
-                             : prefix_rates<KP2>(A, q, row, c, m, si, Sti, pre);
+                    li = F32 ? prefix_rates_f32<KR>(A, qf, row, c, m, float(si), float(Sti), pre)
+                             : prefix_rates<KR>(A, q, row, c, m, si, Sti, pre);
                     have_pre = true;
                 }
                 const double target = u[1] * li;
                 int sel = c - 1;
                 bool found = false;
 #pragma unroll
-                for (int s = 0; s < KP2; ++s) {
+                for (int s = 0; s < KR; ++s) {
                     const bool hit = !found && s < c - 1 && pre[s] > target;
                     sel = hit ? s : sel;
                     found = found || hit;
@@ -219,8 +228,8 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
                         si = grain_size(A.P, m);
                         Sti = F32 ? double(qf.stfac * float(si)) : q.stfac * si;
                     }
-                    li = F32 ? prefix_rates_f32<KP2>(A, qf, row, c, m, float(si), float(Sti), pre)
-                             : prefix_rates<KP2>(A, q, row, c, m, si, Sti, pre);
+                    li = F32 ? prefix_rates_f32<KR>(A, qf, row, c, m, float(si), float(Sti), pre)
+                             : prefix_rates<KR>(A, q, row, c, m, si, Sti, pre);
                     have_pre = true;
                 }
             }
@@ -266,10 +275,13 @@ __device__ inline void pair_at(const McArgs& A, const QCtx& q, const QCtxF& qf, 
 }
 
 // the rest of deferred particle `hidx` of the run described by A; returns the
-// events it adds
+// events it adds.  Lane s holds the pairs of slots s, s + 64, ... (R of
+// them for neighbourhoods beyond 64).
 template <int KP2, bool F32>
 __device__ inline int run_deferred(const McArgs& A, int32_t hidx, int lane)
 {
+    constexpr int R = KP2 > kWave ? KP2 / kWave : 1;
+    constexpr int W = KP2 < kWave ? KP2 : kWave;  // lanes holding slots
     const bool phys = A.P.kernel == GD_KERNEL_PHYSICAL;
     const double dt_exe = A.iv->dt_exe;
     const uint32_t interval = A.interval_on_device ? uint32_t(A.iv->n_intervals) : A.interval;
@@ -284,29 +296,38 @@ __device__ inline int run_deferred(const McArgs& A, int32_t hidx, int lane)
     QCtxF qf{};
     query_ctx(A.P, A.x[i], A.y[i], A.z[i], A.dmax[i], q);
     if (F32) query_ctx_f32(A.P, q, qf);
-    const bool mine = lane < c && lane < KP2;
-    int j = mine ? A.nbr[i * k + lane] : 0;
-    if (mine && (j < 0 || j >= A.n_all)) set_status(A.ws, GD_DEV_INTERNAL);
-    if (j < 0 || j >= A.n_all) j = 0;
-    const double4 sn = A.snap[j];
+    double4 sn[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int s = r * kWave + lane;
+        const bool mine = s < c && lane < W;
+        int j = mine ? A.nbr[i * k + s] : 0;
+        if (mine && (j < 0 || j >= A.n_all)) set_status(A.ws, GD_DEV_INTERNAL);
+        if (j < 0 || j >= A.n_all) j = 0;
+        sn[r] = A.snap[j];
+    }
     double si = 0.0, Sti = 0.0;
-    Pair o{};
-    double mypre = 0.0, li = 0.0;
+    Pair o[R];
+    double mypre[R], li = 0.0;
     auto rates = [&]() {
         if (phys) {
             si = grain_size(A.P, m);
             Sti = F32 ? double(qf.stfac * float(si)) : q.stfac * si;
         }
-        double lam = 0.0;
-        pair_at<F32>(A, q, qf, m, si, Sti, sn, phys, o, lam);
-        // lane s's rate read by every lane (a uniform lane index: two scalar reads)
-        const int lam_lo = __double2loint(lam), lam_hi = __double2hiint(lam);
         double acc = 0.0;
 #pragma unroll
-        for (int s = 0; s < KP2; ++s) {
-            const double v = __hiloint2double(__builtin_amdgcn_readlane(lam_hi, s), __builtin_amdgcn_readlane(lam_lo, s));
-            if (s < c) acc = acc + v;
-            if (s == lane) mypre = acc;
+        for (int r = 0; r < R; ++r) {
+            double lam = 0.0;
+            pair_at<F32>(A, q, qf, m, si, Sti, sn[r], phys, o[r], lam);
+            // lane s's rate read by every lane (a uniform lane index: two scalar reads)
+            const int lam_lo = __double2loint(lam), lam_hi = __double2hiint(lam);
+#pragma unroll 8
+            for (int s = 0; s < W; ++s) {
+                const double v =
+                    __hiloint2double(__builtin_amdgcn_readlane(lam_hi, s), __builtin_amdgcn_readlane(lam_lo, s));
+                if (r * kWave + s < c) acc = acc + v;
+                if (s == lane) mypre[r] = acc;
+            }
         }
         li = acc;
     };
@@ -326,17 +347,30 @@ __device__ inline int run_deferred(const McArgs& A, int32_t hidx, int lane)
         if (dtw > dt_exe - t) break;
         t = t + dtw;
         const double target = u[1] * li;
-        const uint64_t hit = __ballot(lane < c - 1 && mypre > target);
-        const int sel = hit ? int(__ffsll((unsigned long long)hit)) - 1 : c - 1;
+        // the first slot below c - 1 whose prefix exceeds the target, else c - 1
+        int sel = c - 1;
+#pragma unroll
+        for (int r = R - 1; r >= 0; --r) {
+            const uint64_t hit = __ballot(r * kWave + lane < c - 1 && mypre[r] > target);
+            if (hit) sel = r * kWave + int(__ffsll((unsigned long long)hit)) - 1;
+        }
+        const int sl = sel & (kWave - 1), sr = sel / kWave;
         auto from = [&](double x) {
-            return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), sel),
-                                    __builtin_amdgcn_readlane(__double2loint(x), sel));
+            return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), sl),
+                                    __builtin_amdgcn_readlane(__double2loint(x), sl));
         };
-        const int type = __builtin_amdgcn_readlane(o.type, sel);
-        const double r0 = from(o.r0);
-        const double lam_star = from(o.lam_star);
-        const double Ng = from(o.Ng);
-        const double mj = from(sn.x);
+        int type = 0;
+        double r0 = 0.0, lam_star = 0.0, Ng = 0.0, mj = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (r == sr) {  // uniform: sel is the same in every lane
+                type = __builtin_amdgcn_readlane(o[r].type, sl);
+                r0 = from(o[r].r0);
+                lam_star = from(o[r].lam_star);
+                Ng = from(o[r].Ng);
+                mj = from(sn[r].x);
+            }
+        }
         int ch = 0;
         if (type == kErosion) ch = (r0 > u[2] * lam_star) ? 0 : 1;
         double mnew;
@@ -577,22 +611,29 @@ static void launch_first(const McArgs& A, const gd_problem* p, hipStream_t st)
     const int g = int((A.P.n + 255) / 256);
     if (p->rates_fp32) {
         if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, true>), dim3(g), dim3(256), 0, st, A);
-        else hipLaunchKernelGGL((k_mc<64, true>), dim3(g), dim3(256), 0, st, A);
+        else if (p->k <= 64) hipLaunchKernelGGL((k_mc<64, true>), dim3(g), dim3(256), 0, st, A);
+        else hipLaunchKernelGGL((k_mc<0, true>), dim3(g), dim3(256), 0, st, A);
     } else {
         if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, false>), dim3(g), dim3(256), 0, st, A);
-        else hipLaunchKernelGGL((k_mc<64, false>), dim3(g), dim3(256), 0, st, A);
+        else if (p->k <= 64) hipLaunchKernelGGL((k_mc<64, false>), dim3(g), dim3(256), 0, st, A);
+        else hipLaunchKernelGGL((k_mc<0, false>), dim3(g), dim3(256), 0, st, A);
     }
+}
+
+template <bool F32>
+static void launch_heavy(const McArgs& A, int k, hipStream_t st)
+{
+    const dim3 g(kHeavyBlocks), b(256);
+    if (k <= 32) hipLaunchKernelGGL((k_mc_heavy<32, F32>), g, b, 0, st, A);
+    else if (k <= 64) hipLaunchKernelGGL((k_mc_heavy<64, F32>), g, b, 0, st, A);
+    else if (k <= 128) hipLaunchKernelGGL((k_mc_heavy<128, F32>), g, b, 0, st, A);
+    else hipLaunchKernelGGL((k_mc_heavy<256, F32>), g, b, 0, st, A);
 }
 
 static void launch_deferred(const McArgs& A, const gd_problem* p, hipStream_t st)
 {
-    if (p->rates_fp32) {
-        if (p->k <= 32) hipLaunchKernelGGL((k_mc_heavy<32, true>), dim3(kHeavyBlocks), dim3(256), 0, st, A);
-        else hipLaunchKernelGGL((k_mc_heavy<64, true>), dim3(kHeavyBlocks), dim3(256), 0, st, A);
-    } else {
-        if (p->k <= 32) hipLaunchKernelGGL((k_mc_heavy<32, false>), dim3(kHeavyBlocks), dim3(256), 0, st, A);
-        else hipLaunchKernelGGL((k_mc_heavy<64, false>), dim3(kHeavyBlocks), dim3(256), 0, st, A);
-    }
+    if (p->rates_fp32) launch_heavy<true>(A, p->k, st);
+    else launch_heavy<false>(A, p->k, st);
 }
 
 int launch_audit(const gd_problem* p, const gd_particles* s, gd_interval* iv, void* ws, const Layout& L, hipStream_t st)
@@ -673,12 +714,17 @@ int launch_sample_table(void* table, int32_t nslot, int32_t k, int32_t rates_fp3
 {
     launch_fill_i32(static_cast<int32_t*>(table), 1, 0, st);
     char* tb = static_cast<char*>(table);
+    const dim3 g(kHeavyBlocks), b(256);
     if (rates_fp32) {
-        if (k <= 32) hipLaunchKernelGGL((k_mc_heavy_batch<32, true>), dim3(kHeavyBlocks), dim3(256), 0, st, tb, nslot);
-        else hipLaunchKernelGGL((k_mc_heavy_batch<64, true>), dim3(kHeavyBlocks), dim3(256), 0, st, tb, nslot);
+        if (k <= 32) hipLaunchKernelGGL((k_mc_heavy_batch<32, true>), g, b, 0, st, tb, nslot);
+        else if (k <= 64) hipLaunchKernelGGL((k_mc_heavy_batch<64, true>), g, b, 0, st, tb, nslot);
+        else if (k <= 128) hipLaunchKernelGGL((k_mc_heavy_batch<128, true>), g, b, 0, st, tb, nslot);
+        else hipLaunchKernelGGL((k_mc_heavy_batch<256, true>), g, b, 0, st, tb, nslot);
     } else {
-        if (k <= 32) hipLaunchKernelGGL((k_mc_heavy_batch<32, false>), dim3(kHeavyBlocks), dim3(256), 0, st, tb, nslot);
-        else hipLaunchKernelGGL((k_mc_heavy_batch<64, false>), dim3(kHeavyBlocks), dim3(256), 0, st, tb, nslot);
+        if (k <= 32) hipLaunchKernelGGL((k_mc_heavy_batch<32, false>), g, b, 0, st, tb, nslot);
+        else if (k <= 64) hipLaunchKernelGGL((k_mc_heavy_batch<64, false>), g, b, 0, st, tb, nslot);
+        else if (k <= 128) hipLaunchKernelGGL((k_mc_heavy_batch<128, false>), g, b, 0, st, tb, nslot);
+        else hipLaunchKernelGGL((k_mc_heavy_batch<256, false>), g, b, 0, st, tb, nslot);
     }
     return 0;
 }

@@ -56,9 +56,11 @@ def test_host_validation(lib):
     P = binding.make_problem(workloads.disk3d_params(1000))
     sz = C.c_size_t()
     assert lib.gd_workspace_size(C.byref(P), C.byref(sz)) == 0 and sz.value > 0
-    bad = binding.make_problem(dict(workloads.disk3d_params(1000), k=65))
+    bad = binding.make_problem(dict(workloads.disk3d_params(1000), k=257))
     assert lib.gd_workspace_size(C.byref(bad), C.byref(sz)) == -1
-    assert b"k = 65" in lib.gd_last_error()
+    assert b"k = 257" in lib.gd_last_error()
+    ok = binding.make_problem(dict(workloads.disk3d_params(1000), k=256))
+    assert lib.gd_workspace_size(C.byref(ok), C.byref(sz)) == 0
     bad = binding.make_problem(dict(workloads.const_box_params(1000), t0=0.0))
     assert lib.gd_workspace_size(C.byref(bad), C.byref(sz)) == -1
     assert lib.gd_interval_init(None, 1.0, None) == -1
@@ -105,7 +107,7 @@ def test_sample_table_validation(lib):
     # a table run that does not fit its table, or with bad k / rates form
     assert lib.gd_sample_table_run(None, sz.value, 8, 32, 0, None) == -1
     assert lib.gd_sample_table_run(C.c_void_p(256), one.value, 8, 32, 0, None) == -1
-    assert lib.gd_sample_table_run(C.c_void_p(256), sz.value, 8, 65, 0, None) == -1
+    assert lib.gd_sample_table_run(C.c_void_p(256), sz.value, 8, 257, 0, None) == -1
     assert lib.gd_sample_table_run(C.c_void_p(256), sz.value, 8, 32, 2, None) == -1
     fake = binding.GdParticles()
     for k in ("id", "x", "y", "z", "M", "r", "th", "ph", "vr", "lth", "lph"):
