@@ -60,6 +60,7 @@ struct alignas(256) WsHeader {
     int32_t xq[4][8];            // per-die work queues of the gather-heavy kernels
     int32_t heavy_n;             // sampling: particles handed to the wavefront-per-particle pass
     int32_t heavy_next;          // sampling: next of them to take
+    int32_t knn_fb_n[2];         // neighbour search: queries the tile search handed back (two lists)
 };
 
 // Workspace layout (byte offsets), identical on host and device.

@@ -47,11 +47,11 @@
 
 namespace gd {
 
-constexpr int kNB = 32;   // bins of the per-lane distance histograms
-constexpr int kC1 = 16;   // largest boundary bin ranked in registers
 constexpr int kDMax = 3;  // levels of the nested bin chain
 constexpr int kRescales = 4;  // restarts of pass A on a finer distance scale
 constexpr int kQBlock = 128;
+constexpr bool kTileSearch = true;  // shared candidate tiles before the per-lane search (k <= 33)
+constexpr int kFallbackBlocks = 2048;  // one-wavefront workgroups that take the handed-back queries
 constexpr int kQueue = 4;  // level-1 bucket masks a walk keeps queued
 static_assert(kQueue >= 1 && kQueue <= 4, "the queue keeps its masks in the bytes of one word");
 
@@ -230,27 +230,6 @@ __device__ inline int walk(const KnnArgs& A, int na, int q, const double qp[3], 
     return steps;
 }
 
-// First-level bins: logarithmic in x = d^2 / (the pass's first radius), 8 per
-// octave over the kNB / 8 octaves below 1, read off the bits of the double
-// (monotone for x >= 0); bin 0 also takes everything below, the last bin
-// everything from 2^(-1/8).
-constexpr int kLogShift = 49;
-constexpr int64_t kLogBase = int64_t(1023) * 8 - kNB;
-
-__device__ inline int log_bin(double x)
-{
-    // the 64-bit pattern shifted right by kLogShift is the high word shifted
-    // right by kLogShift - 32 (both arithmetic)
-    const int b = (__double2hiint(x) >> (kLogShift - 32)) - int(kLogBase);
-    return min(max(b, 0), kNB - 1);
-}
-
-// lower edge of log bin b (1 <= b <= kNB); log_bin(x) < b exactly when x < edge
-__device__ inline double log_edge(int b)
-{
-    return __longlong_as_double((long long)((int64_t(b) + kLogBase) << kLogShift));
-}
-
 __device__ inline int bin_at(double x, double lo, double s)
 {
     const double t = (x - lo) * s;
@@ -319,27 +298,6 @@ __device__ inline void hist_inc(uint32_t* lds, int tid, int b)
     atomicAdd(lds + (b >> 1) * kQBlock + tid, 1u << (16 * (b & 1)));
 }
 
-template <int N>
-__device__ inline void bitonic_sort(int32_t (&v)[N])
-{
-#pragma unroll
-    for (int size = 2; size <= N; size <<= 1) {
-#pragma unroll
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const int j = i ^ stride;
-                if (j > i) {
-                    const int32_t a = v[i], b = v[j];
-                    const bool up = (i & size) == 0;
-                    v[i] = up ? min(a, b) : max(a, b);
-                    v[j] = up ? max(a, b) : min(a, b);
-                }
-            }
-        }
-    }
-}
-
 // candidates a lane counts before its 16-bit counters are distrusted (a
 // bucket may add kBucket past the check)
 constexpr int kCandMax = 0xFFFF - 2 * kBucket;
@@ -365,8 +323,14 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
     using QL = QueryLds<KP2>;
     __shared__ uint32_t s_lds[QL::kWords * kQBlock];
     const int tid = threadIdx.x;
-    const int32_t item = xcd_take(A.xq, int32_t(gridDim.x * (kQBlock / kWave)));
-    const int64_t q64 = item < 0 ? A.n : int64_t(item) * kWave + (tid & (kWave - 1));
+    int64_t q64;
+    if (A.list) {  // the queries of a list (those the tile search handed back)
+        const int64_t idx = (int64_t(blockIdx.x) * (kQBlock / kWave) + tid / kWave) * kWave + (tid & (kWave - 1));
+        q64 = idx < *A.list_n ? A.list[idx] : A.n;
+    } else {
+        const int32_t item = xcd_take(A.xq, int32_t(gridDim.x * (kQBlock / kWave)));
+        q64 = item < 0 ? A.n : int64_t(item) * kWave + (tid & (kWave - 1));
+    }
     if (q64 >= A.n) return;
     const int q = int(q64);
     const int na = A.h->n_active;
@@ -876,6 +840,21 @@ int launch_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layo
     }
     const dim3 grid(unsigned((n + kQBlock - 1) / kQBlock));
     launch_fill_i32(A.xq, kXcd, 0, st);
+    if (p->k <= 33 && kTileSearch) {
+        // shared candidate tiles first; the queries they cannot complete go
+        // through the per-lane search
+        WsHeader* hw = at<WsHeader>(ws, L.hdr);
+        int32_t* fb0 = at<int32_t>(ws, L.keys1);  // keys1 and vals1 (n entries each): free after the sort
+        int32_t* fb1 = at<int32_t>(ws, L.vals1);
+        launch_fill_i32(hw->knn_fb_n, 2, 0, st);
+        launch_knn_tile(A, per, fb0, fb1, hw->knn_fb_n, st);
+        // handed-back queries with a previous distance (usually well under 1%:
+        // sparse regions with many candidates) take a wavefront each
+        launch_knn_wave(A, per, fb1, hw->knn_fb_n + 1, kFallbackBlocks, st);
+        // those without one (the first search of a run) take the per-lane search
+        A.list = fb0;
+        A.list_n = hw->knn_fb_n;
+    }
     if (p->k <= 33) {
         if (per) hipLaunchKernelGGL((k_knn_query<true, 32>), grid, dim3(kQBlock), 0, st, A);
         else hipLaunchKernelGGL((k_knn_query<false, 32>), grid, dim3(kQBlock), 0, st, A);

@@ -9,6 +9,8 @@
 namespace gd {
 
 constexpr double kHintSlack = 1.08;  // first radius: previous neighbour distance times this
+constexpr int kNB = 32;   // bins of the per-lane distance histograms
+constexpr int kC1 = 16;   // largest boundary bin ranked in registers
 
 // ---------------------------------------------------------------------------
 // Tree
@@ -61,6 +63,8 @@ struct KnnArgs {
     int32_t* xq;      // per-die work queue counters
     const double* hint;  // previous neighbour distance per slot (search hint only)
     void* ws;
+    const int32_t* list;    // when set: the queries are list[0 .. *list_n)
+    const int32_t* list_n;
 };
 
 template <bool PER>
@@ -141,9 +145,55 @@ __device__ inline uint32_t live_children(int na, int level, int idx)
     return nv >= kFan ? 0xFFu : (nv <= 0 ? 0u : (1u << int(nv)) - 1u);
 }
 
+// First-level bins: logarithmic in x = d^2 / (the pass's first radius), 8 per
+// octave over the kNB / 8 octaves below 1, read off the bits of the double
+// (monotone for x >= 0); bin 0 also takes everything below, the last bin
+// everything from 2^(-1/8).
+constexpr int kLogShift = 49;
+constexpr int64_t kLogBase = int64_t(1023) * 8 - kNB;
+
+__device__ inline int log_bin(double x)
+{
+    // the 64-bit pattern shifted right by kLogShift is the high word shifted
+    // right by kLogShift - 32 (both arithmetic)
+    const int b = (__double2hiint(x) >> (kLogShift - 32)) - int(kLogBase);
+    return min(max(b, 0), kNB - 1);
+}
+
+// lower edge of log bin b (1 <= b <= kNB); log_bin(x) < b exactly when x < edge
+__device__ inline double log_edge(int b)
+{
+    return __longlong_as_double((long long)((int64_t(b) + kLogBase) << kLogShift));
+}
+
+template <int N>
+__device__ inline void bitonic_sort(int32_t (&v)[N])
+{
+#pragma unroll
+    for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const int32_t a = v[i], b = v[j];
+                    const bool up = (i & size) == 0;
+                    v[i] = up ? min(a, b) : max(a, b);
+                    v[j] = up ? max(a, b) : min(a, b);
+                }
+            }
+        }
+    }
+}
+
 // one wavefront per query (gd_knn_wave.hip): every slot, or those of `list`
 // [0, *count) when a list is given
 void launch_knn_wave(const KnnArgs& A, bool per, const int32_t* list, const int32_t* count, int64_t nblocks,
                      hipStream_t st);
+// 64 Morton-consecutive queries per wavefront from shared candidate tiles
+// (gd_knn_tile.hip), k <= 33; the queries it cannot complete go to fb0 (no
+// usable previous distance) or fb1 (the rest)
+void launch_knn_tile(const KnnArgs& A, bool per, int32_t* fb0, int32_t* fb1, int32_t* fb_n, hipStream_t st);
 
 }  // namespace gd

@@ -1,0 +1,593 @@
+// gd_knn_tile.hip -- the N_K nearest neighbours (N_K <= 33) of the 64
+// Morton-consecutive queries of a wavefront from shared candidate tiles
+// (Sect. 2.5.1), exact.
+//
+// The per-lane search of gd_knn.hip walks the tree once per query; most of
+// its instructions go to box tests and walk bookkeeping, not to distances.
+// Here the wavefront's queries share the walk and the candidates:
+//   1. each lane's radius is its particle's distance from the previous search
+//      widened by kHintSlack (a lane without a usable one is handed back, see
+//      6); eight groups of eight Morton-consecutive lanes each bound their
+//      spheres by one box, rounded outward to single precision;
+//   2. the box tree is traversed breadth first, eight nodes (64 child boxes)
+//      at a time, testing each child against the boxes of the groups its
+//      parent met; the buckets reached come out as (bucket, group) pairs;
+//   3. each pair's bucket is tested against the spheres of its group's eight
+//      lanes (the conservative single-precision test of gd_knn.hpp); a bucket
+//      one of them may reach joins that group's bucket list;
+//   4. the groups' buckets are staged through LDS two per group at a time,
+//      and every lane evaluates the exact d^2 to the 8 staged positions of its
+//      group.  Others within the radius are counted into the lane's
+//      logarithmic bins and recorded, with their bin, in its LDS list (a full
+//      list drops the entries above the bin that already completes k-1);
+//   5. the bin holding the (k-1)-th other splits the list into sure entries
+//      and a boundary bin ranked by (d^2, slot); the row is written once, in
+//      slot order;
+//   6. lanes without a usable previous distance, whose radius held fewer
+//      than k-1 others, whose list or group list overflowed, or whose
+//      boundary bin is over-full, go to a list that the per-lane search then
+//      completes.  The result never depends on which lanes go there.
+// d^2 is (dx*dx + dy*dy) + dz*dz with every operation rounded on its own, and
+// every bin function is monotone in d^2, so each row is the k-1 smallest
+// (d^2, slot) exactly.
+#include "gd_common.hpp"
+#include "gd_internal.hpp"
+#include "gd_knn.hpp"
+
+namespace gd {
+
+constexpr int kTG = 8;               // lanes (queries) per group
+constexpr int kNGrp = kWave / kTG;   // groups per wavefront
+constexpr int kTList = 64;           // candidate list entries per lane
+constexpr int kFront = 512;          // traversal frontier (nodes of one level)
+constexpr int kPairs = 1024;         // (bucket, group) pairs awaiting their sphere tests
+constexpr int kGList = 128;          // buckets per group after the sphere tests
+constexpr int kTStep = 2 * kTG;      // candidates of a group staged per step (two per lane)
+static_assert(kGList * kBucket <= 512, "a list entry keeps the tile position in 9 bits");
+
+template <bool PER>
+struct TileLds {
+    union {
+        struct {
+            uint32_t front[2][kFront];  // node | group mask << 24
+            uint32_t pairs[kPairs];     // bucket | group << 24
+        } t;
+        // per-lane candidate lists: bin << 11 | position in the group's tiles
+        // (bucket index in the group list * 4 + slot in the bucket)
+        uint16_t list[kTList][kWave];
+    } u;
+    uint32_t glist[kNGrp][kGList];
+    int32_t gcount[kNGrp];
+    int32_t npairs;
+    float gbox[kNGrp][6];            // group boxes: lo[3], hi[3]
+    float4 sc[kWave];                // query (single precision) and its threshold (negative: none)
+    float4 sp[PER ? kWave : 1];      // its +L and -L images on periodic axes
+    float4 sm[PER ? kWave : 1];
+    // staged candidates (x, y, z, slot; slot -1: none), eight per group; each
+    // group's row is padded by 16 bytes so that the eight groups' concurrent
+    // reads fall in different LDS banks
+    double stage[kNGrp][kTStep * 4 + 2];
+};
+
+// 32 per-lane 8-bit bin counters in 8 registers
+struct Hist8 {
+    uint32_t w[kNB / 4];
+    __device__ void clear()
+    {
+#pragma unroll
+        for (int i = 0; i < kNB / 4; ++i) w[i] = 0;
+    }
+    __device__ void add(int b)
+    {
+#pragma unroll
+        for (int i = 0; i < kNB / 4; ++i) w[i] += (b >> 2) == i ? (1u << (8 * (b & 3))) : 0u;
+    }
+    __device__ int get(int b) const { return int((w[b >> 2] >> (8 * (b & 3))) & 0xFFu); }
+};
+
+__device__ inline bool span_meets(float lo, float hi, float blo, float bhi) { return blo <= hi && lo <= bhi; }
+
+// does box b meet group box g (with its periodic images)?
+template <bool PER>
+__device__ inline bool group_meets(const KnnArgs& A, const float (&g)[6], const FBox& b)
+{
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        bool m = span_meets(g[a], g[3 + a], b.lo[a], b.hi[a]);
+        if (PER && A.per[a]) {
+            const double L = A.L[a];
+            m = m || span_meets(__double2float_rd(double(g[a]) + L), __double2float_ru(double(g[3 + a]) + L), b.lo[a],
+                                b.hi[a]);
+            m = m || span_meets(__double2float_rd(double(g[a]) - L), __double2float_ru(double(g[3 + a]) - L), b.lo[a],
+                                b.hi[a]);
+        }
+        ok = ok && m;
+    }
+    return ok;
+}
+
+// exclusive prefix sum over the wavefront
+__device__ inline int wave_excl_scan(int v, int lane)
+{
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    return x - v;
+}
+
+__device__ inline int wave_sum_i(int v)
+{
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) v += __shfl_xor(v, m, kWave);
+    return v;
+}
+
+template <bool PER>
+__global__ __launch_bounds__(kWave) void k_knn_tile(KnnArgs A, int32_t* __restrict__ fb0, int32_t* __restrict__ fb1,
+                                                    int32_t* __restrict__ fb_n)
+{
+    __shared__ TileLds<PER> L;
+    const int lane = threadIdx.x;
+    const int32_t item = xcd_take(A.xq, int32_t((A.n + kWave - 1) / kWave));
+    if (item < 0) return;
+    const int64_t q64 = int64_t(item) * kWave + lane;
+    const int q = int(q64);
+    const int na = A.h->n_active;
+    const int k = A.k;
+    const int need = k - 1;
+    const bool inq = q64 < A.n;
+    const bool act = inq && q < na;
+    int32_t* row = A.nbr + (inq ? int64_t(q) * k : 0);
+    if (inq && !act) {  // an inactive slot
+        for (int s = 0; s < k; ++s) row[s] = -1;
+        A.cnt[q] = 0;
+        A.dmax[q] = 0.0;
+    }
+    double qp[3] = {0.0, 0.0, 0.0};
+    bool ok = false, fb = false;
+    if (act) {
+        const double4 q4 = A.pos[q];
+        qp[0] = q4.x;
+        qp[1] = q4.y;
+        qp[2] = q4.z;
+        if (!(fabs(qp[0]) < INFINITY && fabs(qp[1]) < INFINITY && fabs(qp[2]) < INFINITY)) {
+            set_status(A.ws, GD_DEV_NONFINITE);  // non-finite position: self only
+            row[0] = q;
+            for (int s = 1; s < k; ++s) row[s] = -1;
+            A.cnt[q] = 1;
+            A.dmax[q] = 0.0;
+        } else {
+            fb = true;  // unless the tiles complete it
+            ok = na > k;
+        }
+    }
+    // 1. radius from the previous distance: positive, finite, within the
+    //    diagonal of the active set's box and below the maximum search scale
+    double R2 = 0.0;
+    if (ok) {
+        const double hv = A.hint[q] * kHintSlack;
+        ok = hv > 0.0 && hv < INFINITY;
+        if (ok) {
+            const FBox* tb = A.boxes + A.T.off[A.T.levels - 1];
+            double e2 = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                float lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+                for (int c = 0; c < kFan; ++c) {
+                    lo = fminf(lo, tb[c].lo[a]);
+                    hi = fmaxf(hi, tb[c].hi[a]);
+                }
+                const double ext = double(hi) - double(lo);
+                e2 += ext * ext;
+            }
+            R2 = hv * hv;
+            ok = R2 <= e2 && R2 < A.rmax2;
+        }
+    }
+    const bool tried = ok;  // searched with a usable previous distance
+    QF qf;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        qf.c[a] = float(qp[a]);
+        qf.p[a] = PER ? float(qp[a] + A.L[a]) : 0.0f;
+        qf.m[a] = PER ? float(qp[a] - A.L[a]) : 0.0f;
+    }
+    L.sc[lane] = make_float4(qf.c[0], qf.c[1], qf.c[2], ok ? r2f(R2) : -1.0f);
+    if (PER) {
+        L.sp[lane] = make_float4(qf.p[0], qf.p[1], qf.p[2], 0.0f);
+        L.sm[lane] = make_float4(qf.m[0], qf.m[1], qf.m[2], 0.0f);
+    }
+    // the group boxes: each sphere's box, widened far beyond the rounding of
+    // q +- R in double and rounded outward to single precision
+    {
+        const double Rw = ok ? sqrt(R2) * (1.0 + 0x1p-30) : 0.0;
+        float g[6];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double mg = (fabs(qp[a]) + Rw) * 0x1p-40;
+            g[a] = ok ? __double2float_rd(qp[a] - Rw - mg) : INFINITY;
+            g[3 + a] = ok ? __double2float_ru(qp[a] + Rw + mg) : -INFINITY;
+        }
+#pragma unroll
+        for (int o = 1; o < kTG; o <<= 1) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                g[a] = fminf(g[a], __shfl_xor(g[a], o, kWave));
+                g[3 + a] = fmaxf(g[3 + a], __shfl_xor(g[3 + a], o, kWave));
+            }
+        }
+        if ((lane & (kTG - 1)) == 0) {
+#pragma unroll
+            for (int a = 0; a < 6; ++a) L.gbox[lane / kTG][a] = g[a];
+        }
+    }
+    const uint64_t okmask = __ballot(ok);
+    uint32_t gall = 0;  // groups with at least one searching lane
+#pragma unroll
+    for (int g = 0; g < kNGrp; ++g) gall |= ((okmask >> (kTG * g)) & 0xFFu) ? (1u << g) : 0u;
+    if (lane < kNGrp) L.gcount[lane] = 0;
+    __syncthreads();
+
+    bool wave_ok = gall != 0;
+    if (lane == 0) L.npairs = 0;
+    __syncthreads();
+#ifdef GD_KNN_STATS
+    const long long tc1 = clock64();
+    long long tcull = 0;
+#endif
+    // 3. sphere tests of the pending pairs, 64 at a time: a bucket joins its
+    //    group's list if the sphere of one of the group's searching lanes may
+    //    reach it
+    auto cull = [&]() {
+#ifdef GD_KNN_STATS
+        const long long t0 = clock64();
+#endif
+        const int np = L.npairs;
+        for (int p0 = 0; p0 < np; p0 += kWave) {
+            const int p = p0 + lane;
+            if (p < np) {
+                const uint32_t e = L.u.t.pairs[p];
+                const int g = int(e >> 24);
+                const FBox bx = A.boxes[e & 0xFFFFFFu];
+                bool hit = false;
+#pragma unroll
+                for (int t = 0; t < kTG; ++t) {
+                    const float4 sq = L.sc[g * kTG + t];
+                    QF f;
+                    f.c[0] = sq.x;
+                    f.c[1] = sq.y;
+                    f.c[2] = sq.z;
+                    if (PER) {
+                        const float4 sp = L.sp[g * kTG + t], sm = L.sm[g * kTG + t];
+                        f.p[0] = sp.x;
+                        f.p[1] = sp.y;
+                        f.p[2] = sp.z;
+                        f.m[0] = sm.x;
+                        f.m[1] = sm.y;
+                        f.m[2] = sm.z;
+                    }
+                    hit = hit || (sq.w >= 0.0f && box2f<PER>(A, f, bx) <= sq.w);
+                }
+                if (hit) {
+                    const int at = atomicAdd(&L.gcount[g], 1);
+                    if (at < kGList) L.glist[g][at] = e & 0xFFFFFFu;
+                }
+            }
+        }
+        __syncthreads();
+        if (lane == 0) L.npairs = 0;
+        __syncthreads();
+#ifdef GD_KNN_STATS
+        tcull += clock64() - t0;
+#endif
+    };
+    // 2. breadth-first traversal: frontier nodes of level lv (their boxes met
+    //    the groups of their mask); their children are tested 32 nodes at a
+    //    time (four per lane, loads issued together).  The virtual root (level
+    //    top + 1) has the top level as children.  Buckets come out as
+    //    (bucket, group) pairs, whose sphere tests run whenever enough wait.
+    if (wave_ok) {
+        int lv = A.T.levels;  // the root
+        int cur = 0, nf = 1;
+        if (lane == 0) L.u.t.front[0][0] = gall << 24;
+        __syncthreads();
+        constexpr int kU = 4;
+        while (lv >= 1 && wave_ok) {
+            int nn = 0;  // next frontier written
+            for (int f0 = 0; f0 < nf && wave_ok; f0 += kU * kFan) {
+                FBox bx[kU];
+                uint32_t pm[kU];
+                int child[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int fi = f0 + u * kFan + (lane >> 3), c = lane & 7;
+                    pm[u] = 0;
+                    child[u] = 0;
+                    if (fi < nf) {
+                        const uint32_t e = L.u.t.front[cur][fi];
+                        const int idx = int(e & 0xFFFFFFu);
+                        if ((live_children(na, lv, idx) >> c) & 1u) {
+                            pm[u] = e >> 24;
+                            child[u] = idx * kFan + c;
+                        }
+                    }
+                    if (pm[u]) bx[u] = A.boxes[level_off(A.T, lv - 1) + child[u]];
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    uint32_t cm = 0;
+                    if (pm[u]) {
+#pragma unroll
+                        for (int g = 0; g < kNGrp; ++g) {
+                            float gb[6];
+#pragma unroll
+                            for (int a = 0; a < 6; ++a) gb[a] = L.gbox[g][a];
+                            cm |= (((pm[u] >> g) & 1u) && group_meets<PER>(A, gb, bx[u])) ? (1u << g) : 0u;
+                        }
+                    }
+                    if (lv > 1) {
+                        const uint64_t bal = __ballot(cm != 0);
+                        const int at = nn + int(__popcll(bal & ((uint64_t(1) << lane) - 1)));
+                        const int tot = int(__popcll(bal));
+                        if (nn + tot > kFront) {
+                            wave_ok = false;
+                            break;
+                        }
+                        if (cm) L.u.t.front[cur ^ 1][at] = uint32_t(child[u]) | (cm << 24);
+                        nn += tot;
+                    } else {
+                        const int cnt = __popc(cm);
+                        const int tot = wave_sum_i(cnt);
+                        if (L.npairs + tot > kPairs) cull();  // room for these
+                        const int base = L.npairs;
+                        if (base + tot > kPairs) {
+                            wave_ok = false;
+                            break;
+                        }
+                        int w = base + wave_excl_scan(cnt, lane);
+                        for (uint32_t m = cm; m; m &= m - 1)
+                            L.u.t.pairs[w++] = uint32_t(child[u]) | (uint32_t(__ffs(m) - 1) << 24);
+                        __syncthreads();
+                        if (lane == 0) L.npairs = base + tot;
+                        __syncthreads();
+                    }
+                }
+            }
+            __syncthreads();
+            if (lv > 1) {
+                cur ^= 1;
+                nf = nn;
+            }
+            --lv;
+            if (nf == 0 && lv >= 1) break;
+        }
+        if (wave_ok) cull();
+    }
+    __syncthreads();
+#ifdef GD_KNN_STATS
+    const long long tc2 = clock64();
+#endif
+
+    // 4. candidate tiles: one bucket slot of its group per lane per step
+    const int gg = lane / kTG, sub = lane & (kTG - 1);
+    const int gcnt = wave_ok ? L.gcount[gg] : 0;
+    if (gcnt > kGList) ok = false;  // the group's list overflowed
+    int gmax = 0;
+#pragma unroll
+    for (int g = 0; g < kNGrp; ++g) gmax = max(gmax, wave_ok ? min(L.gcount[g], kGList) : 0);
+    const int gc = min(gcnt, kGList);
+    ok = ok && wave_ok;
+    const double R2s = R2;                                  // bin scale: the first radius
+    const double sA = ok && R2s > 0.0 ? 1.0 / R2s : 0.0;
+    double R2cut = ok ? R2 : -1.0;
+    int bcut = kNB - 1, len = 0;
+    bool ovf = false, cut = false;
+    __syncthreads();  // the traversal's data are dead: the lists take their place
+#ifdef GD_KNN_STATS
+    const long long tc3 = clock64();
+#endif
+    auto entry_bin = [](uint32_t wv) { return int(wv >> 11); };
+    Hist8 hist;
+    auto hist_from_list = [&]() {
+        hist.clear();
+        for (int e = 0; e < len; ++e) hist.add(entry_bin(L.u.list[e][lane]));
+    };
+    // a list without room for a step: the bin completing k-1 others bounds
+    // what stays and what may still come
+    auto cut_list = [&]() {
+        hist_from_list();
+        int cum = 0, bc = kNB - 1;
+        for (int b = 0; b < kNB; ++b) {
+            cum += hist.get(b);
+            if (cum >= need) {
+                bc = b;
+                break;
+            }
+        }
+        if (cum >= need) cut = true;  // at least k-1 others are counted
+        if (bc < bcut) {
+            bcut = bc;
+            R2cut = fmin(R2cut, (log_edge(bcut + 1) * R2s) * (1.0 + 1e-12));
+        }
+        int kept = 0;
+        for (int e = 0; e < len; ++e) {
+            const uint16_t wv = L.u.list[e][lane];
+            if (entry_bin(wv) <= bcut) L.u.list[kept++][lane] = wv;
+        }
+        len = kept;
+        ovf = len > kTList - kTStep;
+    };
+    const int steps = (gmax * kBucket + kTStep - 1) / kTStep;
+    double4 nxt[2];
+    int32_t nj[2];
+    auto fetch = [&](int t) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int pos = kTStep * t + u * kTG + sub;  // this lane's slots of the group's tiles
+            nj[u] = -1;
+            if ((pos >> 2) < gc) {
+                const int j = int(L.glist[gg][pos >> 2]) * kBucket + (pos & (kBucket - 1));
+                if (j < na) nj[u] = j;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) nxt[u] = nj[u] >= 0 ? A.pos[nj[u]] : make_double4(NAN, NAN, NAN, 0.0);
+    };
+    if (steps > 0) fetch(0);
+    for (int t = 0; t < steps; ++t) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            double2* dst = reinterpret_cast<double2*>(&L.stage[gg][4 * (u * kTG + sub)]);
+            dst[0] = make_double2(nxt[u].x, nxt[u].y);
+            dst[1] = make_double2(nxt[u].z, double(nj[u]));
+        }
+        __syncthreads();
+        if (t + 1 < steps) fetch(t + 1);
+        if (len > kTList - kTStep && !ovf) cut_list();  // room for a whole step
+#pragma unroll
+        for (int c = 0; c < kTStep; ++c) {
+            const double2* src = reinterpret_cast<const double2*>(&L.stage[gg][4 * c]);
+            const double2 s0 = src[0], s1 = src[1];
+            const double d2 = sep2<PER>(A, qp, s0.x, s0.y, s1.x);
+            const int j = int(s1.y);
+            if (d2 <= R2cut && j != q && j >= 0 && !ovf) {
+                const int b = log_bin(d2 * sA);
+                if (b <= bcut) L.u.list[len++][lane] = uint16_t((b << 11) | (kTStep * t + c));
+            }
+        }
+        __syncthreads();
+    }
+#ifdef GD_KNN_STATS
+    const long long tc4 = clock64();
+#endif
+    auto slot_of = [&](uint32_t wv) {
+        const int pos = int(wv & 0x7FFu);
+        return int(L.glist[gg][pos >> 2]) * kBucket + (pos & (kBucket - 1));
+    };
+
+    // 5. sure and boundary entries from the list
+    ok = ok && !ovf && (cut || len >= need);
+    int b0 = 0, c0 = 0, hb = 0;
+    if (ok) {
+        hist_from_list();
+        int cum = 0;
+        bool found = false;
+#pragma unroll
+        for (int b = 0; b < kNB; ++b) {
+            const int h = hist.get(b);
+            if (!found && cum + h >= need) {
+                b0 = b;
+                hb = h;
+                found = true;
+            }
+            if (!found) cum += h;
+        }
+        c0 = cum;
+        ok = hb <= kC1;
+    }
+    int ntot = 0, nb = 0;
+    double maxd2 = 0.0;
+    // the staging area is free now: the boundary entries wait there
+    uint16_t(*bnd)[kWave] = reinterpret_cast<uint16_t(*)[kWave]>(&L.stage[0][0]);
+    static_assert(sizeof(L.stage) >= kC1 * kWave * sizeof(uint16_t), "the boundary entries fit the staging area");
+    if (ok) {
+        // sure entries move to the front of the list, boundary entries aside
+        for (int e = 0; e < len; ++e) {
+            const uint16_t wv = L.u.list[e][lane];
+            const int bn = entry_bin(wv);
+            if (bn < b0) L.u.list[ntot++][lane] = wv;
+            else if (bn == b0) bnd[nb++][lane] = wv;
+        }
+        if (ntot != c0 || nb != hb) set_status(A.ws, GD_DEV_INTERNAL);
+        // boundary entries ranked by (d^2, slot); the chosen ones follow
+        const int needb = need - c0 < nb ? need - c0 : nb;
+        double bd[kC1];
+        int32_t bj[kC1];
+        uint16_t bw[kC1];
+#pragma unroll
+        for (int e = 0; e < kC1; ++e) {
+            bw[e] = e < nb ? bnd[e][lane] : uint16_t(0);
+            bj[e] = e < nb ? slot_of(bw[e]) : INT32_MAX;
+            bd[e] = e < nb ? sep2_slot<PER>(A, qp, bj[e]) : INFINITY;
+        }
+#pragma unroll
+        for (int e = 0; e < kC1; ++e) {
+            int rank = 0;
+#pragma unroll
+            for (int f = 0; f < kC1; ++f) rank += (bd[f] < bd[e]) || (bd[f] == bd[e] && bj[f] < bj[e]);
+            if (e < nb && rank < needb) {
+                L.u.list[ntot + rank][lane] = bw[e];
+                maxd2 = fmax(maxd2, bd[e]);
+            }
+        }
+        ntot += needb;
+        if (ntot != need) set_status(A.ws, GD_DEV_INTERNAL);
+    }
+    // the row in slot order
+    int32_t v[32];
+#pragma unroll
+    for (int e = 0; e < 32; ++e) v[e] = (ok && e < ntot) ? int32_t(slot_of(L.u.list[e][lane])) : INT32_MAX;
+    bitonic_sort<32>(v);
+    if (ok) {
+        if (k == 32 && A.row_vec) {
+#pragma unroll
+            for (int c4 = 0; c4 < 8; ++c4) {
+                int32_t o[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int e = 4 * c4 + t;
+                    o[t] = e == 0 ? q : ((e - 1 < ntot) ? v[e - 1] : -1);
+                }
+                reinterpret_cast<int4*>(row)[c4] = make_int4(o[0], o[1], o[2], o[3]);
+            }
+        } else {
+            row[0] = q;
+#pragma unroll
+            for (int e = 0; e < 32; ++e)
+                if (e < k - 1) row[1 + e] = (e < ntot) ? v[e] : -1;
+        }
+        A.cnt[q] = 1 + ntot;
+        A.dmax[q] = ntot > 0 ? sqrt(maxd2) : 0.0;
+    }
+#ifdef GD_KNN_STATS
+    if (lane == 0) {  // per wavefront: cycles of traversal, sphere tests, tiles, finish; pairs, steps
+        int32_t* w = A.stats + int64_t(item) * 8;
+        w[0] = int32_t(tc2 - tc1 - tcull);
+        w[1] = int32_t(tcull);
+        w[2] = int32_t(tc4 - tc3);
+        w[3] = int32_t(clock64() - tc4);
+        w[4] = gmax;
+        w[5] = steps;
+        w[6] = wave_ok ? 1 : 0;
+    }
+#endif
+    // 6. the rest: lanes that had no usable previous distance to the per-lane
+    //    search (list 0), the others (sparse regions, many candidates) to the
+    //    wavefront-per-query search (list 1)
+    fb = fb && !ok;
+#pragma unroll
+    for (int l = 0; l < 2; ++l) {
+        const bool mine = fb && (l == 0 ? !tried : tried);
+        const uint64_t fbm = __ballot(mine);
+        int32_t base = 0;
+        if (lane == 0 && fbm) base = atomicAdd(fb_n + l, int32_t(__popcll(fbm)));
+        base = __builtin_amdgcn_readfirstlane(base);
+        if (mine) (l == 0 ? fb0 : fb1)[base + int(__popcll(fbm & ((uint64_t(1) << lane) - 1)))] = q;
+    }
+}
+
+// fb0 and fb1 receive the handed-back queries (n entries each): those with no
+// usable previous distance, and the rest; fb_n[0], fb_n[1] count them
+void launch_knn_tile(const KnnArgs& A, bool per, int32_t* fb0, int32_t* fb1, int32_t* fb_n, hipStream_t st)
+{
+    const dim3 grid(unsigned((A.n + kWave - 1) / kWave));
+    if (per) hipLaunchKernelGGL(k_knn_tile<true>, grid, dim3(kWave), 0, st, A, fb0, fb1, fb_n);
+    else hipLaunchKernelGGL(k_knn_tile<false>, grid, dim3(kWave), 0, st, A, fb0, fb1, fb_n);
+}
+
+}  // namespace gd
