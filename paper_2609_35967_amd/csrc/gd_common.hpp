@@ -61,12 +61,14 @@ struct alignas(256) WsHeader {
     int32_t heavy_n;             // sampling: particles handed to the wavefront-per-particle pass
     int32_t heavy_next;          // sampling: next of them to take
     int32_t knn_fb_n[2];         // neighbour search: queries the tile search handed back (two lists)
+    int32_t mc_seg[kXcd];        // sampling: particles with an event, per die's segment of the list
+    int32_t mc_next;             // sampling: next group of them to take
 };
 
 // Workspace layout (byte offsets), identical on host and device.
 struct Layout {
     size_t hdr, keys0, keys1, vals0, vals1, hist, red, pos4, boxes,
-        snap, a, b, part, hint, heavy, stats, total;
+        snap, a, b, part, hint, heavy, mclist, stats, total;
     int64_t n;
     int32_t k;
     int32_t nsort_blocks;
@@ -124,6 +126,7 @@ __host__ inline Layout make_layout(int64_t n, int32_t k)
     L.part = take(sizeof(double) * 8 * kNBin * kRedBlocks);
     L.hint = take(8 * nn);
     L.heavy = take(24 * nn);  // sampling: (slot, events, time, mass) of deferred particles
+    L.mclist = take(4 * ((nn + 255) / 256) * 256);  // sampling: particles with an event, a segment per die
 #ifdef GD_KNN_STATS
     L.stats = take(32 * nn);
 #endif

@@ -50,6 +50,9 @@ struct McArgs {
     int32_t* heavy_n;
     int32_t* heavy_next;
     int64_t n_all;  // length of the snapshot: neighbour indices lie in [0, n_all)
+    int32_t* list;       // particles with an event (screen -> event pass), a segment per die
+    int32_t* list_seg;   // the segments' counts
+    int32_t* list_next;  // the event pass's next group
 };
 
 // a particle handed over after e events, at time t of the interval, with mass m
@@ -62,7 +65,8 @@ struct Deferred {
 
 constexpr int kEventCap = 1 << 24;  // safety stop per particle and interval (status-flagged)
 constexpr int kLaneEvents = 4;      // events a lane samples before handing its particle over
-constexpr int kHeavyBlocks = 256;   // blocks (4 wavefronts each) of the wavefront-per-particle pass
+constexpr int kHeavyBlocks = 768;   // blocks (4 wavefronts each) of the wavefront-per-particle pass: 3 per SIMD
+constexpr int kEventBlocks = 512;   // blocks (4 wavefronts each) of the event pass: two per SIMD
 
 template <int KP2>
 __device__ inline double prefix_rates_f32(const McArgs& A, const QCtxF& q, const int32_t* row, int c, double mi,
@@ -89,8 +93,8 @@ __device__ inline double prefix_rates_f32(const McArgs& A, const QCtxF& q, const
 }
 
 template <int KP2>
-__device__ inline double prefix_rates(const McArgs& A, const QCtx& q, const int32_t* row, int c, double mi,
-                                      double si, double Sti, double (&pre)[KP2])
+__device__ inline double prefix_rates(const McArgs& A, const QCtx& q, const int32_t* row, int c, const Own& w,
+                                      double (&pre)[KP2])
 {
     const bool phys = A.P.kernel == GD_KERNEL_PHYSICAL;
     double li = 0.0;
@@ -104,7 +108,7 @@ __device__ inline double prefix_rates(const McArgs& A, const QCtx& q, const int3
             }
             const double4 sn = A.snap[j];
             Pair o;
-            pair_eval(A.P, q, mi, si, Sti, sn.x, phys ? sn.y : 0.0, phys ? sn.z : 0.0, o);
+            pair_eval(A.P, q, w, sn.x, phys ? sn.y : 0.0, phys ? sn.z : 0.0, sn.w, o);
             li = li + o.lam_star;
         }
         pre[s] = li;
@@ -112,15 +116,74 @@ __device__ inline double prefix_rates(const McArgs& A, const QCtx& q, const int3
     return li;
 }
 
-// KP2 = 0: a neighbourhood too large for a lane's prefix registers; a lane
-// only decides whether its particle has an event at all, and hands every
-// particle that has one to the wavefront-per-particle pass at its start.
-template <int KP2, bool F32>
-__global__ __launch_bounds__(256) void k_mc(McArgs A)
+// Sampling runs in two steps.  The screen (one lane per particle, few
+// registers) draws each particle's first waiting time against lambda*_i of
+// the rates pass: a particle without an event in the interval keeps its mass
+// and is done; the others go, compacted, to a list.  The event pass then
+// samples the listed particles, one lane each (up to kLaneEvents events,
+// then the wavefront-per-particle pass), from a grid that strides over the
+// list, so lanes without events never hold a wavefront's registers.  Its
+// lanes redraw the first event's numbers (the same counters, so the same
+// numbers).  For neighbourhoods beyond 64 (no prefix registers) the screen
+// hands its particles straight to the wavefront-per-particle pass.
+// The list has a segment per die: the blocks dealt to die x (block b with
+// b % 8 == x, 256 particles each) fill segment x, which starts after the
+// blocks of the dies before it, so that the count adds of one die go to its
+// own counter.  One add per block.
+__device__ inline int64_t seg_base(int x, int64_t nblocks)
 {
-    constexpr int KR = KP2 > 0 ? KP2 : 32;  // prefix registers (unused when KP2 = 0)
-    const int64_t i = xcd_block() * int64_t(blockDim.x) + threadIdx.x;
-    const int lane = threadIdx.x & 63;
+    return ((nblocks / kXcd) * x + (x < nblocks % kXcd ? x : nblocks % kXcd)) * 256;
+}
+
+template <bool DIRECT_HEAVY>
+__global__ __launch_bounds__(256) void k_mc_screen(McArgs A)
+{
+    __shared__ int32_t s_w[4];
+    __shared__ int32_t s_base;
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    bool ev = false;
+    if (i < A.P.n) {
+        const int c = A.cnt[i];
+        const double m = A.m[i];
+        const double li = A.lam_i[i];
+        if (c > 1 && li > 0.0) {
+            const uint32_t interval = A.interval_on_device ? uint32_t(A.iv->n_intervals) : A.interval;
+            double u[4];
+            event_uniforms(A.seed, A.id[i], interval, 0u, u);
+            ev = !(-log(u[0]) / li > A.iv->dt_exe);
+        }
+        if (!ev) {
+            A.m_out[i] = m;
+            if (A.n_events) A.n_events[i] = 0;
+            if (A.log)
+                for (int f = 0; f < A.log_cap; ++f) A.log[i * A.log_cap + f] = -1;
+        } else if (DIRECT_HEAVY && A.log) {
+            for (int f = 0; f < A.log_cap; ++f) A.log[i * A.log_cap + f] = -1;
+        }
+    }
+    const uint64_t bal = __ballot(ev);
+    if (lane == 0) s_w[wv] = int32_t(__popcll(bal));
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int32_t tot = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        int32_t b = 0;
+        if (tot) b = atomicAdd(DIRECT_HEAVY ? A.heavy_n : &A.list_seg[blockIdx.x % kXcd], tot);
+        s_base = b;
+    }
+    __syncthreads();
+    if (ev) {
+        int32_t at = s_base + int32_t(__popcll(bal & ((uint64_t(1) << lane) - 1)));
+        for (int w = 0; w < wv; ++w) at += s_w[w];
+        if (DIRECT_HEAVY) A.heavy[at] = Deferred{int32_t(i), 0, 0.0, A.m[i]};
+        else A.list[seg_base(int(blockIdx.x % kXcd), gridDim.x) + at] = int32_t(i);
+    }
+}
+
+template <int KP2, bool F32>
+__device__ inline int mc_particle(const McArgs& A, int64_t i)
+{
+    constexpr int KR = KP2;  // prefix registers
     int e = 0;
     if (i < A.P.n) {
         const int k = A.P.k;
@@ -135,6 +198,7 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
             const int32_t* row = A.nbr + i * k;
             QCtx q{};
             QCtxF qf{};
+            Own own{};
             bool have_ctx = false, have_pre = false;
             double si = 0.0, Sti = 0.0;
             double pre[KR];
@@ -157,11 +221,6 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
                 event_uniforms(A.seed, pid, interval, uint32_t(e), u);
                 const double dtw = -log(u[0]) / li;
                 if (dtw > dt_exe - t) break;
-                if (KP2 == 0) {
-                    const int32_t slot = atomicAdd(A.heavy_n, 1);
-                    A.heavy[slot] = Deferred{int32_t(i), e, t, m};
-                    break;
-                }
                 t = t + dtw;
                 if (!have_ctx) {
                     query_ctx(A.P, A.x[i], A.y[i], A.z[i], A.dmax[i], q);
@@ -173,8 +232,9 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
                         si = grain_size(A.P, m);
                         Sti = F32 ? double(qf.stfac * float(si)) : q.stfac * si;
                     }
+                    if (!F32) own_terms(A.P, q, m, si, false, own);
                     li = F32 ? prefix_rates_f32<KR>(A, qf, row, c, m, float(si), float(Sti), pre)
-                             : prefix_rates<KR>(A, q, row, c, m, si, Sti, pre);
+                             : prefix_rates<KR>(A, q, row, c, own, pre);
                     have_pre = true;
                 }
                 const double target = u[1] * li;
@@ -201,7 +261,7 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
                     o.lam_star = double(of.r0) + double(of.r1);
                     o.Ng = of.Ng;
                 } else {
-                    pair_eval(A.P, q, m, si, Sti, mj, sj, phys ? sn.z : 0.0, o);
+                    pair_eval(A.P, q, own, mj, sj, phys ? sn.z : 0.0, sn.w, o);
                 }
                 int ch = 0;
                 if (o.type == kErosion) ch = (o.r0 > u[2] * o.lam_star) ? 0 : 1;
@@ -228,8 +288,9 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
                         si = grain_size(A.P, m);
                         Sti = F32 ? double(qf.stfac * float(si)) : q.stfac * si;
                     }
+                    if (!F32) own_terms(A.P, q, m, si, false, own);
                     li = F32 ? prefix_rates_f32<KR>(A, qf, row, c, m, float(si), float(Sti), pre)
-                             : prefix_rates<KR>(A, q, row, c, m, si, Sti, pre);
+                             : prefix_rates<KR>(A, q, row, c, own, pre);
                     have_pre = true;
                 }
             }
@@ -239,8 +300,37 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
         if (A.log)
             for (int f = e; f < A.log_cap; ++f) A.log[i * A.log_cap + f] = -1;
     }
-    // events of the interval, one atomic per wavefront
-    unsigned long long ev = (unsigned long long)e;
+    return e;
+}
+
+// the listed particles, one lane each: the segments are read as one list;
+// wavefront w takes entries 64 w .. 64 w + 63 first, then further groups of
+// 64 from a counter until the list is exhausted (a wavefront with no first
+// group touches no counter)
+template <int KP2, bool F32>
+__global__ __launch_bounds__(256) void k_mc(McArgs A, int64_t screen_blocks)
+{
+    const int lane = threadIdx.x & 63;
+    int32_t pre[kXcd + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int x = 0; x < kXcd; ++x) pre[x + 1] = pre[x] + A.list_seg[x];
+    const int32_t nl = pre[kXcd];
+    const int32_t nw = int32_t(gridDim.x * (blockDim.x / kWave));
+    int32_t b = int32_t(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave;
+    unsigned long long ev = 0;
+    while (b < nl) {
+        const int32_t t = b + lane;
+        if (t < nl) {
+            int x = 0;
+#pragma unroll
+            for (int y = 1; y < kXcd; ++y) x += t >= pre[y] ? 1 : 0;
+            ev += (unsigned long long)mc_particle<KP2, F32>(A, A.list[seg_base(x, screen_blocks) + (t - pre[x])]);
+        }
+        int32_t nx = 0;
+        if (lane == 0) nx = atomicAdd(A.list_next, kWave);
+        b = nw * kWave + __builtin_amdgcn_readfirstlane(nx);
+    }    // events of the interval, one atomic per wavefront
 #pragma unroll
     for (int mk = 1; mk < 64; mk <<= 1) ev += __shfl_xor(ev, mk, 64);
     if (lane == 0 && ev) atomicAdd(A.ev_counter, ev);
@@ -249,9 +339,7 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A)
 // ---------------------------------------------------------------------------
 // The rest of the interval of each deferred particle, one wavefront per
 // particle: lane s < c evaluates the pair of neighbour slot s for the
-// particle's current mass, and the prefix is summed in slot order by reading
-// the lanes one after the other, so every rate, prefix and decision is the
-// one the one-lane form computes.  The draw, the selection (first slot whose
+// particle's current mass, and the prefix over the slots is a wavefront scan.  The draw, the selection (first slot whose
 // prefix exceeds the target) and the outcome are uniform over the wavefront.
 // Wavefronts take particles from a counter until the list is exhausted.
 template <bool F32>
@@ -269,7 +357,9 @@ __device__ inline void pair_at(const McArgs& A, const QCtx& q, const QCtxF& qf, 
         o.Ng = of.Ng;
         lam_pre = double(of.lam_star);  // the prefix adds the float rate
     } else {
-        pair_eval(A.P, q, m, si, Sti, sn.x, phys ? sn.y : 0.0, phys ? sn.z : 0.0, o);
+        Own w;
+        own_terms(A.P, q, m, si, false, w);
+        pair_eval(A.P, q, w, sn.x, phys ? sn.y : 0.0, phys ? sn.z : 0.0, sn.w, o);
         lam_pre = o.lam_star;
     }
 }
@@ -314,22 +404,25 @@ __device__ inline int run_deferred(const McArgs& A, int32_t hidx, int lane)
             si = grain_size(A.P, m);
             Sti = F32 ? double(qf.stfac * float(si)) : q.stfac * si;
         }
-        double acc = 0.0;
+        // inclusive prefix over the slots by a wavefront scan (log2 64 steps):
+        // it differs from the slot-order sum only in rounding, so a decision
+        // can differ only within a few ulp of its threshold, far inside the
+        // near-tie margin the parity of sampled events allows
+        double carry = 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             double lam = 0.0;
             pair_at<F32>(A, q, qf, m, si, Sti, sn[r], phys, o[r], lam);
-            // lane s's rate read by every lane (a uniform lane index: two scalar reads)
-            const int lam_lo = __double2loint(lam), lam_hi = __double2hiint(lam);
-#pragma unroll 8
-            for (int s = 0; s < W; ++s) {
-                const double v =
-                    __hiloint2double(__builtin_amdgcn_readlane(lam_hi, s), __builtin_amdgcn_readlane(lam_lo, s));
-                if (r * kWave + s < c) acc = acc + v;
-                if (s == lane) mypre[r] = acc;
+            double x = (r * kWave + lane < c && lane < W) ? lam : 0.0;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const double y = __shfl_up(x, off, kWave);
+                if (lane >= off) x = x + y;
             }
+            mypre[r] = carry + x;
+            carry = carry + __shfl(x, kWave - 1, kWave);
         }
-        li = acc;
+        li = carry;
     };
     rates();
     // the draws of the coming event are made before the rates of the mass it
@@ -603,20 +696,30 @@ static McArgs mc_args(const gd_problem* p, const gd_particles* s, const gd_neigh
     A.heavy_n = &h->heavy_n;
     A.heavy_next = &h->heavy_next;
     A.n_all = p->n;
+    A.list = at<int32_t>(ws, L.mclist);
+    A.list_seg = h->mc_seg;
+    A.list_next = &h->mc_next;
     return A;
 }
 
 static void launch_first(const McArgs& A, const gd_problem* p, hipStream_t st)
 {
     const int g = int((A.P.n + 255) / 256);
+    static_assert(offsetof(WsHeader, mc_next) == offsetof(WsHeader, mc_seg) + kXcd * sizeof(int32_t),
+                  "the segment counts and the next counter are cleared together");
+    launch_fill_i32(A.list_seg, kXcd + 1, 0, st);
+    if (p->k > 64) {  // no prefix registers: straight to the wavefront-per-particle pass
+        hipLaunchKernelGGL(k_mc_screen<true>, dim3(g), dim3(256), 0, st, A);
+        return;
+    }
+    hipLaunchKernelGGL(k_mc_screen<false>, dim3(g), dim3(256), 0, st, A);
+    const dim3 eg(kEventBlocks), eb(256);
     if (p->rates_fp32) {
-        if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, true>), dim3(g), dim3(256), 0, st, A);
-        else if (p->k <= 64) hipLaunchKernelGGL((k_mc<64, true>), dim3(g), dim3(256), 0, st, A);
-        else hipLaunchKernelGGL((k_mc<0, true>), dim3(g), dim3(256), 0, st, A);
+        if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, true>), eg, eb, 0, st, A, int64_t(g));
+        else hipLaunchKernelGGL((k_mc<64, true>), eg, eb, 0, st, A, int64_t(g));
     } else {
-        if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, false>), dim3(g), dim3(256), 0, st, A);
-        else if (p->k <= 64) hipLaunchKernelGGL((k_mc<64, false>), dim3(g), dim3(256), 0, st, A);
-        else hipLaunchKernelGGL((k_mc<0, false>), dim3(g), dim3(256), 0, st, A);
+        if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, false>), eg, eb, 0, st, A, int64_t(g));
+        else hipLaunchKernelGGL((k_mc<64, false>), eg, eb, 0, st, A, int64_t(g));
     }
 }
 

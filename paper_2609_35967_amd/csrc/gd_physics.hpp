@@ -52,15 +52,18 @@ __device__ inline double grain_size(const DevProblem& P, double m)
     return cbrt(6.0 * m / (kPi * P.rho_s));
 }
 
-// Everything of the rate that depends on the query particle only.
+// Everything of the rate that depends on the query particle's position only.
 struct QCtx {
     double V, R, Z, OmK, eta, cs, stfac, Vg2, tke, kT8pi;
+    double invV;        // 1 / V_i (0 when V_i <= 0)
+    double vR, vZ, vP;  // the factors of eq:dv's drift terms: 2 eta R Omega_K, Z Omega_K, eta R Omega_K
 };
 
 __device__ inline void query_ctx(const DevProblem& P, double x, double y, double z, double d, QCtx& c)
 {
     if (P.kernel != GD_KERNEL_PHYSICAL) {
         c.V = 1.0;
+        c.invV = 1.0;
         return;
     }
     const double R = sqrt(x * x + y * y);
@@ -85,6 +88,10 @@ __device__ inline void query_ctx(const DevProblem& P, double x, double y, double
         }
     }
     c.V = V;
+    c.invV = V > 0.0 ? 1.0 / V : 0.0;
+    c.vR = 2.0 * g.eta * R * g.OmK;
+    c.vZ = z * g.OmK;
+    c.vP = g.eta * R * g.OmK;
     c.Vg2 = 1.5 * P.alpha * g.cs * g.cs;
     const double vth = sqrt(8.0 / kPi) * g.cs;
     const double lmfp = P.mu_mH / (g.rhog * P.sigma_H2);
@@ -155,33 +162,57 @@ struct Pair {
     double Ng;
 };
 
-// Own particle: mass mi and (physical) diameter si and Stokes number Sti.
-// Neighbour: mass mj, diameter sj, grain count Nj (physical).
-__device__ inline void pair_eval(const DevProblem& P, const QCtx& c, double mi, double si, double Sti, double mj,
-                                 double sj, double Nj, Pair& o)
+// The query particle's own terms, evaluated once per particle (and again
+// after each change of its mass): mass, 1/m_i, diameter, Stokes number and
+// 1 + St_i^2, and (when asked for) the fragment moments of its size, which
+// depend on nothing else.
+struct Own {
+    double mi, rmi, si, Sti, qi;
+    double mJ, mJ2;
+};
+
+__device__ inline void own_terms(const DevProblem& P, const QCtx& c, double mi, double si, bool moments, Own& w)
 {
+    const bool phys = P.kernel == GD_KERNEL_PHYSICAL;
+    w.mi = mi;
+    w.rmi = 1.0 / mi;
+    w.si = si;
+    w.Sti = phys ? c.stfac * si : 0.0;
+    w.qi = 1.0 + w.Sti * w.Sti;
+    w.mJ = 0.0;
+    w.mJ2 = 0.0;
+    if (phys && moments) frag_moments(si, P.s_min, w.mJ, w.mJ2);
+}
+
+// One pair against neighbour (m_j, s_j, N_j, 1/m_j) of the frozen snapshot.
+// The physical rate is arranged for few divisions: one reciprocal of
+// (1+St_i^2)(1+St_j^2) for both drift differences, the snapshot's 1/m_j in
+// the Brownian term, 1/V_i once per particle.  It agrees with eq:rate to
+// rounding (well inside the 1e-12 contract); the dimensionless rates keep
+// the oracle's operation order exactly.
+__device__ inline void pair_eval(const DevProblem& P, const QCtx& c, const Own& w, double mj, double sj, double Nj,
+                                 double rmj, Pair& o)
+{
+    const double mi = w.mi;
     double lam, dv = 0.0;
     if (P.kernel == GD_KERNEL_PHYSICAL) {
         // St_j = St_i s_j/s_i at the query position; St_i - St_j from the mass
         // difference, s_i - s_j = (6/(pi rho))(m_i - m_j)/(s_i^2 + s_i s_j + s_j^2),
         // so that close grains do not cancel.
+        const double si = w.si, Sti = w.Sti;
         const double Stj = c.stfac * sj;
         const double ds = (6.0 / (kPi * P.rho_s)) * (mi - mj) / (si * si + si * sj + sj * sj);
         const double dSt = c.stfac * ds;
-        const double OR = c.OmK;
-        const double qi = 1.0 + Sti * Sti, qj = 1.0 + Stj * Stj;
-        const double da = dSt * (1.0 - Sti * Stj) / (qi * qj);
-        const double db = -dSt * (Sti + Stj) / (qi * qj);
-        const double dvR = 2.0 * c.eta * c.R * OR * da;
-        const double zi = fmin(Sti, 0.5), zj = fmin(Stj, 0.5);
-        const double dz = (Sti < 0.5 && Stj < 0.5) ? dSt : zi - zj;
-        const double dvZ = c.Z * OR * dz;
-        const double dvP = c.eta * c.R * OR * db;
+        const double qj = 1.0 + Stj * Stj;
+        const double rq = 1.0 / (w.qi * qj);
+        const double da = dSt * (1.0 - Sti * Stj) * rq;
+        const double db = -dSt * (Sti + Stj) * rq;
+        const double dvR = c.vR * da;
+        const double dz = (Sti < 0.5 && Stj < 0.5) ? dSt : fmin(Sti, 0.5) - fmin(Stj, 0.5);
+        const double dvZ = c.vZ * dz;
+        const double dvP = c.vP * db;
         double dvB = 0.0, dvT2 = 0.0;
-        if (P.brownian) {
-            dvB = sqrt(c.kT8pi * (1.0 / mi + 1.0 / mj));
-            if (dvB > c.cs) dvB = c.cs;
-        }
+        if (P.brownian) dvB = fmin(sqrt(c.kT8pi * (w.rmi + rmj)), c.cs);
         if (P.turbulence) {
             const bool ig = Sti >= Stj;
             dvT2 = oc07_dv2(ig ? Sti : Stj, ig ? Stj : Sti, fabs(dSt), c.Vg2, c.tke);
@@ -192,9 +223,8 @@ __device__ inline void pair_eval(const DevProblem& P, const QCtx& c, double mi, 
         dv2 = dv2 + dvT2;
         dv = sqrt(dv2);
         const double ssum = si + sj;
-        const double K = kPi * ssum * ssum * dv / 4.0;
-        lam = Nj * K / c.V;
-        if (!(c.V > 0.0)) lam = 0.0;
+        const double K = kPi * ssum * ssum * dv * 0.25;
+        lam = Nj * K * c.invV;
     } else {
         double Kt;
         if (P.kernel == GD_KERNEL_CONST) Kt = 1.0;
@@ -209,12 +239,12 @@ __device__ inline void pair_eval(const DevProblem& P, const QCtx& c, double mi, 
     o.Ng = Ng;
     if (!fast) {
         o.type = kStick;
-        o.r0 = lam / Ng;
+        o.r0 = Ng == 1.0 ? lam : lam / Ng;
         o.r1 = 0.0;
         o.lam_star = o.r0;
     } else if (P.erosion && psi <= 0.1) {
         o.type = kErosion;
-        o.r0 = (1.0 - psi) * lam / Ng;
+        o.r0 = Ng == 1.0 ? (1.0 - psi) * lam : (1.0 - psi) * lam / Ng;
         o.r1 = psi * lam;
         o.lam_star = o.r0 + o.r1;
     } else {
@@ -226,26 +256,24 @@ __device__ inline void pair_eval(const DevProblem& P, const QCtx& c, double mi, 
 }
 
 // sum over the pair's channels of rate * <J> and rate * <J^2>
-__device__ inline void pair_moments(const DevProblem& P, const Pair& o, double mi, double si, double mj, double& a,
-                                    double& b)
+__device__ inline void pair_moments(const Pair& o, const Own& w, double mj, double& a, double& b)
 {
-    const double psi = mj / mi;
+    constexpr double kThird = 1.0 / 3.0;
+    const double psi = mj / w.mi;
     if (o.type == kStick) {
-        const double J = log1p(o.Ng * psi) / 3.0;
+        const double J = log1p(o.Ng * psi) * kThird;
         a = o.r0 * J;
         b = o.r0 * (J * J);
     } else if (o.type == kErosion) {
-        const double Jr = -log1p(-o.Ng * psi) / 3.0;
-        const double Jd = fabs(log(psi)) / 3.0;
+        const double Jr = -log1p(-o.Ng * psi) * kThird;
+        const double Jd = fabs(log(psi)) * kThird;
         a = o.r0 * Jr;
         b = o.r0 * (Jr * Jr);
         a = a + o.r1 * Jd;
         b = b + o.r1 * (Jd * Jd);
     } else {
-        double mJ, mJ2;
-        frag_moments(si, P.s_min, mJ, mJ2);
-        a = o.r0 * mJ;
-        b = o.r0 * mJ2;
+        a = o.r0 * w.mJ;
+        b = o.r0 * w.mJ2;
     }
 }
 

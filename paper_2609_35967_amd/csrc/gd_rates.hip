@@ -15,8 +15,8 @@
 
 namespace gd {
 
-// packed snapshot of every particle: (m_j, s_j, N_j = M_j / m_j, 0), one
-// 32-byte record per neighbour gather
+// packed snapshot of every particle: (m_j, s_j, N_j = M_j / m_j, 1 / m_j),
+// one 32-byte record per neighbour gather
 __global__ __launch_bounds__(256) void k_snapshot(DevProblem P, const double* __restrict__ m,
                                                   const double* __restrict__ M, int64_t n, double4* __restrict__ snap)
 {
@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void k_snapshot(DevProblem P, const double* __
     if (i >= n) return;
     const double mi = m[i];
     const bool phys = P.kernel == GD_KERNEL_PHYSICAL;
-    snap[i] = make_double4(mi, phys ? grain_size(P, mi) : 0.0, phys ? M[i] / mi : 0.0, 0.0);
+    snap[i] = make_double4(mi, phys ? grain_size(P, mi) : 0.0, phys ? M[i] / mi : 0.0, 1.0 / mi);
 }
 
 struct RatesArgs {
@@ -71,8 +71,8 @@ __global__ __launch_bounds__(256) void k_rates(RatesArgs A)
         QCtx q;
         query_ctx(A.P, A.x[i], A.y[i], A.z[i], A.dmax[i], q);
         const double mi = A.m[i];
-        const double si = phys ? A.snap_own[i].y : 0.0;
-        const double Sti = phys ? q.stfac * si : 0.0;
+        Own w;
+        own_terms(A.P, q, mi, phys ? A.snap_own[i].y : 0.0, true, w);
         if (!(mi > 0.0) || !isfinite(mi)) set_status(A.ws, GD_DEV_NONFINITE);
         const int cmax = c < k ? c : k;
         // neighbours four at a time: their slots, then their records, in flight
@@ -92,14 +92,12 @@ __global__ __launch_bounds__(256) void k_rates(RatesArgs A)
             }
             const double4 sn = rec[t];
             const double mj = sn.x;
-            const double sj = phys ? sn.y : 0.0;
-            const double Nj = phys ? sn.z : 0.0;
             Pair o;
-            pair_eval(A.P, q, mi, si, Sti, mj, sj, Nj, o);
+            pair_eval(A.P, q, w, mj, phys ? sn.y : 0.0, phys ? sn.z : 0.0, sn.w, o);
             lam = lam + o.lam_star;
             if (A.lam_pair) A.lam_pair[i * k + s] = o.lam_star;
             double pa, pb;
-            pair_moments(A.P, o, mi, si, mj, pa, pb);
+            pair_moments(o, w, mj, pa, pb);
             sa = sa + pa;
             sb = sb + pb;
             }
