@@ -67,6 +67,7 @@ constexpr int kEventCap = 1 << 24;  // safety stop per particle and interval (st
 constexpr int kLaneEvents = 4;      // events a lane samples before handing its particle over
 constexpr int kHeavyBlocks = 768;   // blocks (4 wavefronts each) of the wavefront-per-particle pass: 3 per SIMD
 constexpr int kEventBlocks = 512;   // blocks (4 wavefronts each) of the event pass: two per SIMD
+constexpr int kSmallList = 4 * kHeavyBlocks;  // at most this many particles with events: all to the wavefront pass
 
 template <int KP2>
 __device__ inline double prefix_rates_f32(const McArgs& A, const QCtxF& q, const int32_t* row, int c, double mi,
@@ -318,6 +319,22 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A, int64_t screen_blocks)
     const int32_t nl = pre[kXcd];
     const int32_t nw = int32_t(gridDim.x * (blockDim.x / kWave));
     int32_t b = int32_t(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave;
+    if (nl <= kSmallList) {
+        // few particles with events (a cold disk): each takes a wavefront of
+        // the wavefront-per-particle pass at once, where its pairs are
+        // evaluated side by side instead of one after another in a lane
+        const int32_t t = b + lane;
+        if (t < nl) {
+            int x = 0;
+#pragma unroll
+            for (int y = 1; y < kXcd; ++y) x += t >= pre[y] ? 1 : 0;
+            const int32_t i = A.list[seg_base(x, screen_blocks) + (t - pre[x])];
+            if (A.log)
+                for (int f = 0; f < A.log_cap; ++f) A.log[i * A.log_cap + f] = -1;
+            A.heavy[atomicAdd(A.heavy_n, 1)] = Deferred{i, 0, 0.0, A.m[i]};
+        }
+        return;
+    }
     unsigned long long ev = 0;
     while (b < nl) {
         const int32_t t = b + lane;
