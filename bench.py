@@ -60,8 +60,10 @@ ALGO_BYTES_COLUMN = dict(ALGO_BYTES, sort=32 + 64 + 136, tree=4, push=40)
 PATH_BYTES = {"disk3d": 930, "disk3d_warm": 930, "additive_col": 650, "const_box": 208}
 PROF_KERNELS = ("sort", "tree", "knn_query", "rates", "mc", "audit", "push")
 # source file of each profiled stage (the HBM counter summary is tied to it)
-PROF_SOURCE = {"sort": "gd_sort.hip", "tree": "gd_knn.hip", "knn_query": "gd_knn.hip", "rates": "gd_rates.hip",
-               "mc": "gd_mc.hip", "audit": "gd_mc.hip", "push": "gd_push.hip", "diffuse": "gd_diffuse.hip"}
+PROF_SOURCE = {"sort": ("gd_sort.hip",), "tree": ("gd_knn.hip",),
+               "knn_query": ("gd_knn.hip", "gd_knn_tile.hip", "gd_knn_wave.hip", "gd_knn.hpp"),
+               "rates": ("gd_rates.hip", "gd_physics.hpp"), "mc": ("gd_mc.hip", "gd_physics.hpp"),
+               "audit": ("gd_mc.hip",), "push": ("gd_push.hip",), "diffuse": ("gd_diffuse.hip",)}
 # the diffusion step on the ring: read id, the six spherical components and M
 # (a constant Stokes number needs no m); write the six components and x, y, z
 DIFFUSE_BYTES = 4 + 6 * 8 + 8 + 9 * 8
@@ -69,10 +71,14 @@ COPY_BYTES = 1 << 30  # the plain copy that calibrates the HBM byte counters
 
 
 def source_digest(kernel):
+    """Digest of the sources of a stage's kernels (a counter summary is valid
+    only for the sources it was taken on)."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2609_35967_amd", "csrc", PROF_SOURCE[kernel])
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in PROF_SOURCE[kernel]:
+        with open(os.path.join(ROOT, "paper_2609_35967_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel):

@@ -51,7 +51,7 @@ constexpr int kDMax = 3;  // levels of the nested bin chain
 constexpr int kRescales = 4;  // restarts of pass A on a finer distance scale
 constexpr int kQBlock = 128;
 constexpr bool kTileSearch = true;  // shared candidate tiles before the per-lane search (k <= 33)
-constexpr int kFallbackBlocks = 2048;  // one-wavefront workgroups that take the handed-back queries
+constexpr int kFallbackBlocks = 8192;  // one-wavefront workgroups that take the handed-back queries (about one each)
 constexpr int kQueue = 4;  // level-1 bucket masks a walk keeps queued
 static_assert(kQueue >= 1 && kQueue <= 4, "the queue keeps its masks in the bytes of one word");
 
