@@ -279,6 +279,35 @@ __device__ inline double wave_max_d(double v)
     return v;
 }
 
+// Inclusive prefix sum over the 64 lanes by data-parallel-primitive moves
+// (no LDS): shifts by 1, 2, 4, 8 within each row of 16 lanes, then lane 15 of
+// each row added to the next row, then lane 31 to rows 2 and 3.  Lanes whose
+// source lies outside the row (or that a row mask leaves out) add +0.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_take(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROWS, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline double wave_scan_incl(double x)
+{
+    x = x + dpp_take<0x111, 0xf>(x);  // row_shr:1
+    x = x + dpp_take<0x112, 0xf>(x);  // row_shr:2
+    x = x + dpp_take<0x114, 0xf>(x);  // row_shr:4
+    x = x + dpp_take<0x118, 0xf>(x);  // row_shr:8
+    x = x + dpp_take<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+    x = x + dpp_take<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
+__device__ inline double readlane_d(double x, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                            __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+
 __device__ inline void set_status(void* ws, int bits)
 {
     atomicOr(&at<WsHeader>(ws, 0)->status, bits);

@@ -355,30 +355,29 @@ __global__ __launch_bounds__(256) void k_mc(McArgs A, int64_t screen_blocks)
 
 // ---------------------------------------------------------------------------
 // The rest of the interval of each deferred particle, one wavefront per
-// particle: lane s < c evaluates the pair of neighbour slot s for the
-// particle's current mass, and the prefix over the slots is a wavefront scan.  The draw, the selection (first slot whose
-// prefix exceeds the target) and the outcome are uniform over the wavefront.
+// particle.  Lane s < c holds neighbour slot s: the neighbour's terms that
+// the frozen snapshot fixes for the whole interval are computed once, and
+// per event the lane evaluates its pair for the particle's current mass and
+// the outcome the event would have with that partner.  The prefix over the
+// slots is a wavefront scan; the selection (first slot whose prefix exceeds
+// the target) is a ballot, and the chosen lane's outcome is read across.
+// The draws do not depend on the mass: lane L draws the numbers of event
+// e0 + L, 64 events at a time, and each event reads its own from that lane.
 // Wavefronts take particles from a counter until the list is exhausted.
-template <bool F32>
-__device__ inline void pair_at(const McArgs& A, const QCtx& q, const QCtxF& qf, double m, double si, double Sti,
-                               const double4& sn, bool phys, Pair& o, double& lam_pre)
+
+// the numbers of events e0 .. e0 + 63 (lane L: event e0 + L): -ln U_w, U_p, U_c, U_f
+struct Draws {
+    double lw, up, uc, uf;
+};
+
+__device__ inline void draw64(const McArgs& A, uint32_t pid, uint32_t interval, uint32_t e0, int lane, Draws& d)
 {
-    if (F32) {
-        PairF of;
-        pair_eval_f32(A.P, qf, m, 1.0 / m, float(si), float(Sti), sn.x, phys ? float(sn.y) : 0.0f,
-                      phys ? sn.z : 0.0, of);
-        o.type = of.type;
-        o.r0 = of.r0;
-        o.r1 = of.r1;
-        o.lam_star = double(of.r0) + double(of.r1);
-        o.Ng = of.Ng;
-        lam_pre = double(of.lam_star);  // the prefix adds the float rate
-    } else {
-        Own w;
-        own_terms(A.P, q, m, si, false, w);
-        pair_eval(A.P, q, w, sn.x, phys ? sn.y : 0.0, phys ? sn.z : 0.0, sn.w, o);
-        lam_pre = o.lam_star;
-    }
+    double u[4];
+    event_uniforms(A.seed, pid, interval, e0 + uint32_t(lane), u);
+    d.lw = -log(u[0]);
+    d.up = u[1];
+    d.uc = u[2];
+    d.uf = u[3];
 }
 
 // the rest of deferred particle `hidx` of the run described by A; returns the
@@ -403,7 +402,7 @@ __device__ inline int run_deferred(const McArgs& A, int32_t hidx, int lane)
     QCtxF qf{};
     query_ctx(A.P, A.x[i], A.y[i], A.z[i], A.dmax[i], q);
     if (F32) query_ctx_f32(A.P, q, qf);
-    double4 sn[R];
+    Nb nb[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int s = r * kWave + lane;
@@ -411,43 +410,65 @@ __device__ inline int run_deferred(const McArgs& A, int32_t hidx, int lane)
         int j = mine ? A.nbr[i * k + s] : 0;
         if (mine && (j < 0 || j >= A.n_all)) set_status(A.ws, GD_DEV_INTERNAL);
         if (j < 0 || j >= A.n_all) j = 0;
-        sn[r] = A.snap[j];
-    }
-    double si = 0.0, Sti = 0.0;
-    Pair o[R];
-    double mypre[R], li = 0.0;
-    auto rates = [&]() {
-        if (phys) {
-            si = grain_size(A.P, m);
-            Sti = F32 ? double(qf.stfac * float(si)) : q.stfac * si;
+        const double4 sn = A.snap[j];
+        if (F32) {
+            nb[r].mj = sn.x;
+            nb[r].sj = phys ? sn.y : 0.0;
+            nb[r].Nj = phys ? sn.z : 0.0;
+        } else {
+            nb_terms<true>(A.P, q, sn.x, phys ? sn.y : 0.0, phys ? sn.z : 0.0, sn.w, nb[r]);
         }
-        // inclusive prefix over the slots by a wavefront scan (log2 64 steps):
-        // it differs from the slot-order sum only in rounding, so a decision
-        // can differ only within a few ulp of its threshold, far inside the
-        // near-tie margin the parity of sampled events allows
+    }
+    uint32_t e0 = uint32_t(e);
+    Draws d;
+    draw64(A, pid, interval, e0, lane, d);
+    for (;;) {
+        if (uint32_t(e) - e0 >= uint32_t(kWave)) {
+            e0 = uint32_t(e);
+            draw64(A, pid, interval, e0, lane, d);
+        }
+        const int L = int(uint32_t(e) - e0);
+        const double lw = readlane_d(d.lw, L), up = readlane_d(d.up, L), uc = readlane_d(d.uc, L);
+        // the pairs at the current mass, each with its outcome (a fragmentation
+        // outcome does not depend on the partner and is made after the selection)
+        double si = 0.0;
+        Own w{};
+        if (phys) si = grain_size(A.P, m);
+        if (!F32) own_terms(A.P, q, m, si, false, w);
+        const float Stf = F32 && phys ? qf.stfac * float(si) : 0.0f;
+        double pre[R], mnew[R];
+        int code[R];
         double carry = 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            double lam = 0.0;
-            pair_at<F32>(A, q, qf, m, si, Sti, sn[r], phys, o[r], lam);
-            double x = (r * kWave + lane < c && lane < W) ? lam : 0.0;
-#pragma unroll
-            for (int off = 1; off < kWave; off <<= 1) {
-                const double y = __shfl_up(x, off, kWave);
-                if (lane >= off) x = x + y;
+            int type;
+            double r0, lam, Ng;
+            if (F32) {
+                PairF of;
+                pair_eval_f32(A.P, qf, m, 1.0 / m, float(si), Stf, nb[r].mj, float(nb[r].sj), nb[r].Nj, of);
+                type = of.type;
+                r0 = of.r0;
+                lam = double(of.r0) + double(of.r1);  // the channel choice's total
+                Ng = of.Ng;
+                pre[r] = double(of.lam_star);         // the prefix adds the float rate
+            } else {
+                Pair o;
+                pair_core<true>(A.P, q, w, nb[r], o);
+                type = o.type;
+                r0 = o.r0;
+                lam = o.lam_star;
+                Ng = o.Ng;
+                pre[r] = o.lam_star;
             }
-            mypre[r] = carry + x;
-            carry = carry + __shfl(x, kWave - 1, kWave);
+            const int ch = (type == kErosion && !(r0 > uc * lam)) ? 1 : 0;
+            const double mj = nb[r].mj;
+            mnew[r] = type == kStick ? m + Ng * mj : (ch == 0 ? m - Ng * mj : mj);
+            code[r] = (ch << 16) | (type << 24);
+            const double x = wave_scan_incl((r * kWave + lane < c && lane < W) ? pre[r] : 0.0);
+            pre[r] = carry + x;
+            carry = carry + readlane_d(x, kWave - 1);
         }
-        li = carry;
-    };
-    rates();
-    // the draws of the coming event are made before the rates of the mass it
-    // finds are recomputed (they do not depend on them), so both overlap
-    double u[4];
-    event_uniforms(A.seed, pid, interval, uint32_t(e), u);
-    double lw = -log(u[0]);
-    for (;;) {
+        const double li = carry;
         if (!(li > 0.0)) break;
         if (e >= kEventCap) {
             if (lane == 0) set_status(A.ws, GD_DEV_EVENT_CAP);
@@ -456,54 +477,38 @@ __device__ inline int run_deferred(const McArgs& A, int32_t hidx, int lane)
         const double dtw = lw / li;
         if (dtw > dt_exe - t) break;
         t = t + dtw;
-        const double target = u[1] * li;
+        const double target = up * li;
         // the first slot below c - 1 whose prefix exceeds the target, else c - 1
         int sel = c - 1;
 #pragma unroll
         for (int r = R - 1; r >= 0; --r) {
-            const uint64_t hit = __ballot(r * kWave + lane < c - 1 && mypre[r] > target);
+            const uint64_t hit = __ballot(r * kWave + lane < c - 1 && pre[r] > target);
             if (hit) sel = r * kWave + int(__ffsll((unsigned long long)hit)) - 1;
         }
         const int sl = sel & (kWave - 1), sr = sel / kWave;
-        auto from = [&](double x) {
-            return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), sl),
-                                    __builtin_amdgcn_readlane(__double2loint(x), sl));
-        };
-        int type = 0;
-        double r0 = 0.0, lam_star = 0.0, Ng = 0.0, mj = 0.0;
+        int cd = 0;
+        double mn = 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (r == sr) {  // uniform: sel is the same in every lane
-                type = __builtin_amdgcn_readlane(o[r].type, sl);
-                r0 = from(o[r].r0);
-                lam_star = from(o[r].lam_star);
-                Ng = from(o[r].Ng);
-                mj = from(sn[r].x);
+                cd = __builtin_amdgcn_readlane(code[r], sl);
+                mn = readlane_d(mnew[r], sl);
             }
         }
-        int ch = 0;
-        if (type == kErosion) ch = (r0 > u[2] * lam_star) ? 0 : 1;
-        double mnew;
-        if (type == kStick) {
-            mnew = m + Ng * mj;
-        } else if (type == kErosion) {
-            mnew = (ch == 0) ? m - Ng * mj : mj;
-        } else {
+        if ((cd >> 24) == kFrag) {
+            const double uf = readlane_d(d.uf, L);
             const double a = sqrt(A.P.s_min);
-            const double w = a + u[3] * (sqrt(si) - a);
-            const double sz = w * w;
-            mnew = kPi * A.P.rho_s * sz * sz * sz / 6.0;
+            const double wf = a + uf * (sqrt(si) - a);
+            const double sz = wf * wf;
+            mn = kPi * A.P.rho_s * sz * sz * sz / 6.0;
         }
         if (A.log && lane == 0) {
-            if (e < A.log_cap) A.log[i * A.log_cap + e] = sel | (ch << 16) | (type << 24);
+            if (e < A.log_cap) A.log[i * A.log_cap + e] = sel | cd;
             else set_status(A.ws, GD_DEV_LOG_OVERFLOW);
         }
         ++e;
-        event_uniforms(A.seed, pid, interval, uint32_t(e), u);
-        lw = -log(u[0]);
         // (an unchanged mass recomputes the same rates: no branch around them)
-        m = mnew;
-        rates();
+        m = mn;
     }
     if (lane == 0) {
         A.m_out[i] = m;

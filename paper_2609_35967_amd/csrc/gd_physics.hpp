@@ -101,27 +101,6 @@ __device__ inline void query_ctx(const DevProblem& P, double x, double y, double
     c.kT8pi = 8.0 * (P.mu_mH * g.cs * g.cs) / kPi;
 }
 
-// Ormel & Cuzzi (2007) turbulent relative speed squared, St1 >= St2,
-// dSt = St1 - St2: tightly coupled St1 < Re^-1/2 (written as
-// Vg^2 dSt^2 [St1 St2 + t(St1+St2)]/[(St1+St2)(St1+t)(St2+t)], equal to the
-// published form but free of cancellation for close St), intermediate up to
-// St1 = 1 (y_a = 1.6), heavy.
-__device__ inline double oc07_dv2(double St1, double St2, double dSt, double Vg2, double tke)
-{
-    if (St1 < tke) {
-        const double num = St1 * St2 + tke * (St1 + St2);
-        const double den = (St1 + St2) * (St1 + tke) * (St2 + tke);
-        return Vg2 * (dSt * dSt) * num / den;
-    }
-    if (St1 < 1.0) {
-        const double ya = 1.6;
-        const double e = St2 / St1;
-        const double br = 2.0 * ya - (1.0 + e) + 2.0 / (1.0 + e) * (1.0 / (1.0 + ya) + e * e * e / (ya + e));
-        return Vg2 * br * St1;
-    }
-    return Vg2 * (1.0 / (1.0 + St1) + 1.0 / (1.0 + St2));
-}
-
 // <J>, <J^2> of a fragment of a grain of diameter s_i: with x = sqrt(s_i/s_min),
 // d = x - 1: <J> = 2[1 - ln x/d], <J^2> = 4[2x - ln^2 x - 2 ln x - 2]/d, and for
 // d < 0.1 the power series <J> = 2 sum_n (-1)^(n+1) d^n/(n+1),
@@ -163,11 +142,11 @@ struct Pair {
 };
 
 // The query particle's own terms, evaluated once per particle (and again
-// after each change of its mass): mass, 1/m_i, diameter, Stokes number and
-// 1 + St_i^2, and (when asked for) the fragment moments of its size, which
-// depend on nothing else.
+// after each change of its mass): mass, 1/m_i, diameter, Stokes number,
+// 1/(1 + St_i^2) and 1/(1 + St_i), and (when asked for) the fragment moments
+// of its size, which depend on nothing else.
 struct Own {
-    double mi, rmi, si, Sti, qi;
+    double mi, rmi, si, Sti, rqi, rhi;
     double mJ, mJ2;
 };
 
@@ -178,33 +157,80 @@ __device__ inline void own_terms(const DevProblem& P, const QCtx& c, double mi, 
     w.rmi = 1.0 / mi;
     w.si = si;
     w.Sti = phys ? c.stfac * si : 0.0;
-    w.qi = 1.0 + w.Sti * w.Sti;
+    w.rqi = 1.0 / (1.0 + w.Sti * w.Sti);
+    w.rhi = 1.0 / (1.0 + w.Sti);
     w.mJ = 0.0;
     w.mJ2 = 0.0;
     if (phys && moments) frag_moments(si, P.s_min, w.mJ, w.mJ2);
 }
 
-// One pair against neighbour (m_j, s_j, N_j, 1/m_j) of the frozen snapshot.
-// The physical rate is arranged for few divisions: one reciprocal of
-// (1+St_i^2)(1+St_j^2) for both drift differences, the snapshot's 1/m_j in
-// the Brownian term, 1/V_i once per particle.  It agrees with eq:rate to
-// rounding (well inside the 1e-12 contract); the dimensionless rates keep
-// the oracle's operation order exactly.
-__device__ inline void pair_eval(const DevProblem& P, const QCtx& c, const Own& w, double mj, double sj, double Nj,
-                                 double rmj, Pair& o)
+// The terms of neighbour j that do not involve the query particle's mass:
+// the snapshot record (m_j, s_j, N_j, 1/m_j), St_j at the query position,
+// 1/(1 + St_j^2), and (HOIST) 1/(1 + St_j) of OC07's heavy regime and
+// m0/m_j of the dimensionless kernels.  Against the frozen neighbourhood
+// they hold for a whole interval, so a particle with many events computes
+// them once; a single evaluation computes what it needs in place.
+struct Nb {
+    double mj, sj, Nj, rmj;
+    double Stj, rqj, rhj, cj;
+};
+
+template <bool HOIST>
+__device__ inline void nb_terms(const DevProblem& P, const QCtx& c, double mj, double sj, double Nj, double rmj,
+                                Nb& b)
 {
-    const double mi = w.mi;
+    b.mj = mj;
+    b.sj = sj;
+    b.Nj = Nj;
+    b.rmj = rmj;
+    b.Stj = c.stfac * sj;
+    b.rqj = 1.0 / (1.0 + b.Stj * b.Stj);
+    b.rhj = HOIST ? 1.0 / (1.0 + b.Stj) : 0.0;
+    b.cj = HOIST ? P.m0 / mj : 0.0;
+}
+
+// Ormel & Cuzzi (2007) turbulent relative speed squared, St1 >= St2,
+// dSt = St1 - St2: tightly coupled St1 < Re^-1/2 (written as
+// Vg^2 dSt^2 [St1 St2 + t(St1+St2)]/[(St1+St2)(St1+t)(St2+t)], equal to the
+// published form but free of cancellation for close St), intermediate up to
+// St1 = 1 (y_a = 1.6), heavy Vg^2 [1/(1+St1) + 1/(1+St2)] with the two
+// reciprocals rh1, rh2 given.
+__device__ inline double oc07_dv2_r(double St1, double St2, double dSt, double Vg2, double tke, double rh1,
+                                    double rh2)
+{
+    if (St1 < tke) {
+        const double num = St1 * St2 + tke * (St1 + St2);
+        const double den = (St1 + St2) * (St1 + tke) * (St2 + tke);
+        return Vg2 * (dSt * dSt) * num / den;
+    }
+    if (St1 < 1.0) {
+        const double ya = 1.6;
+        const double e = St2 / St1;
+        const double br = 2.0 * ya - (1.0 + e) + 2.0 / (1.0 + e) * (1.0 / (1.0 + ya) + e * e * e / (ya + e));
+        return Vg2 * br * St1;
+    }
+    return Vg2 * (rh1 + rh2);
+}
+
+// One pair: the query particle's terms against neighbour j's.
+// The physical rate is arranged for few divisions: 1/(1+St^2) of each grain
+// for both drift differences, the snapshot's 1/m_j in the Brownian term,
+// 1/V_i once per particle.  It agrees with eq:rate to rounding (well inside
+// the 1e-12 contract); the dimensionless rates keep the oracle's operation
+// order exactly (m0/m_j hoisted or not is the same rounded quotient).
+template <bool HOIST>
+__device__ inline void pair_core(const DevProblem& P, const QCtx& c, const Own& w, const Nb& b, Pair& o)
+{
+    const double mi = w.mi, mj = b.mj;
     double lam, dv = 0.0;
     if (P.kernel == GD_KERNEL_PHYSICAL) {
-        // St_j = St_i s_j/s_i at the query position; St_i - St_j from the mass
-        // difference, s_i - s_j = (6/(pi rho))(m_i - m_j)/(s_i^2 + s_i s_j + s_j^2),
+        // St_i - St_j from the mass difference,
+        // s_i - s_j = (6/(pi rho))(m_i - m_j)/(s_i^2 + s_i s_j + s_j^2),
         // so that close grains do not cancel.
-        const double si = w.si, Sti = w.Sti;
-        const double Stj = c.stfac * sj;
+        const double si = w.si, Sti = w.Sti, sj = b.sj, Stj = b.Stj;
         const double ds = (6.0 / (kPi * P.rho_s)) * (mi - mj) / (si * si + si * sj + sj * sj);
         const double dSt = c.stfac * ds;
-        const double qj = 1.0 + Stj * Stj;
-        const double rq = 1.0 / (w.qi * qj);
+        const double rq = w.rqi * b.rqj;
         const double da = dSt * (1.0 - Sti * Stj) * rq;
         const double db = -dSt * (Sti + Stj) * rq;
         const double dvR = c.vR * da;
@@ -212,10 +238,12 @@ __device__ inline void pair_eval(const DevProblem& P, const QCtx& c, const Own& 
         const double dvZ = c.vZ * dz;
         const double dvP = c.vP * db;
         double dvB = 0.0, dvT2 = 0.0;
-        if (P.brownian) dvB = fmin(sqrt(c.kT8pi * (w.rmi + rmj)), c.cs);
+        if (P.brownian) dvB = fmin(sqrt(c.kT8pi * (w.rmi + b.rmj)), c.cs);
         if (P.turbulence) {
             const bool ig = Sti >= Stj;
-            dvT2 = oc07_dv2(ig ? Sti : Stj, ig ? Stj : Sti, fabs(dSt), c.Vg2, c.tke);
+            const double rhj = HOIST ? b.rhj : 1.0 / (1.0 + Stj);
+            dvT2 = oc07_dv2_r(ig ? Sti : Stj, ig ? Stj : Sti, fabs(dSt), c.Vg2, c.tke, ig ? w.rhi : rhj,
+                              ig ? rhj : w.rhi);
         }
         double dv2 = dvR * dvR + dvZ * dvZ;
         dv2 = dv2 + dvP * dvP;
@@ -224,13 +252,13 @@ __device__ inline void pair_eval(const DevProblem& P, const QCtx& c, const Own& 
         dv = sqrt(dv2);
         const double ssum = si + sj;
         const double K = kPi * ssum * ssum * dv * 0.25;
-        lam = Nj * K * c.invV;
+        lam = b.Nj * K * c.invV;
     } else {
         double Kt;
         if (P.kernel == GD_KERNEL_CONST) Kt = 1.0;
         else if (P.kernel == GD_KERNEL_ADDITIVE) Kt = (mi + mj) / P.m0;
         else Kt = (mi * mj) / (P.m0 * P.m0);
-        lam = ((P.m0 / mj) * Kt) / (P.t0 * double(P.k));
+        lam = ((HOIST ? b.cj : P.m0 / mj) * Kt) / (P.t0 * double(P.k));
     }
     const double psi = mj / mi;
     const bool fast = (P.kernel == GD_KERNEL_PHYSICAL) && (dv >= P.v_frag);
@@ -253,6 +281,15 @@ __device__ inline void pair_eval(const DevProblem& P, const QCtx& c, const Own& 
         o.r1 = 0.0;
         o.lam_star = lam;
     }
+}
+
+// One pair against neighbour (m_j, s_j, N_j, 1/m_j) of the frozen snapshot.
+__device__ inline void pair_eval(const DevProblem& P, const QCtx& c, const Own& w, double mj, double sj, double Nj,
+                                 double rmj, Pair& o)
+{
+    Nb b;
+    nb_terms<false>(P, c, mj, sj, Nj, rmj, b);
+    pair_core<false>(P, c, w, b, o);
 }
 
 // sum over the pair's channels of rate * <J> and rate * <J^2>
