@@ -266,9 +266,10 @@ def cpu_baseline(wl, params, seed, n, nq):
 
 
 def batch_bench(args):
-    """Batched boxes: the plain per-box loop, then the recorded graph (two
-    intervals of every box per replay) on the same boxes.  A round is one
-    interval of every box."""
+    """Batched boxes: the plain per-box loop, the one-launch-per-stage form
+    (launch shapes picked by the autotuner first) and the recorded graph of
+    per-box launches, each over the same intervals from the same saved
+    device state.  A round is one interval of every box."""
     import torch
     from paper_2609_35967_amd import load
     from paper_2609_35967_amd.batch import BoxBatch
@@ -278,7 +279,7 @@ def batch_bench(args):
     boxes = workloads.box_batch(args.seed, nbox=args.batch)
     bb = BoxBatch(boxes, streams=args.streams)
     n = bb.n_particles
-    rounds = max(2, args.steps // 2 * 2)
+    rounds = max(2, min(args.steps, 20) // 2 * 2)
 
     def timed(fn, reps, per):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
@@ -293,40 +294,55 @@ def batch_bench(args):
         lat = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]) / per
         return wall, lat
 
-    print(f"[bench] {len(boxes)} boxes, {n} particles: plain loop", file=sys.stderr, flush=True)
+    print(f"[bench] {len(boxes)} boxes, {n} particles: warmup", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         bb.step_plain()
+    rec = bb.tune()
+    print(f"[bench] tuned {rec['choice']} ({len(rec['trials'])} trials, {rec['ms_per_interval']} ms)",
+          file=sys.stderr, flush=True)
+    saved = bb._save()
     wall_p, lat_p = timed(bb.step_plain, rounds, 1)
-    print(f"[bench] plain {wall_p / rounds * 1e3:.2f} ms per round; recording the graph", file=sys.stderr, flush=True)
-    bb.capture()
-    for _ in range(max(1, args.warmup // 2)):
-        bb.replay()
-    wall_b, lat_b = timed(bb.replay, rounds // 2, 2)
-    print(f"[bench] batched {wall_b / rounds * 1e3:.2f} ms per round", file=sys.stderr, flush=True)
+    print(f"[bench] plain {wall_p / rounds * 1e3:.2f} ms per round", file=sys.stderr, flush=True)
+    bb._load(saved)
+    bb.many(bb.tuned)
+    wall_m, lat_m = timed(bb.step_many, rounds, 1)
+    print(f"[bench] one launch per stage {wall_m / rounds * 1e3:.2f} ms per round", file=sys.stderr, flush=True)
     status = max(e.status() for e in bb.engines)
     ev_max = [int(e.events.max().item()) for e in bb.engines]
     heavy = int(np.argmax(ev_max))
+    ev_total = sum(int(e.events.sum().item()) for e in bb.engines)
+    bb._load(saved)
+    bb.capture()
+    wall_g, lat_g = timed(bb.replay, rounds // 2, 2)
+    print(f"[bench] graph of per-box launches {wall_g / rounds * 1e3:.2f} ms per round", file=sys.stderr, flush=True)
     print(f"[bench] events of the last interval: most in one particle {ev_max[heavy]} (box {heavy}, "
-          f"n={bb.engines[heavy].n}); total {sum(int(e.events.sum().item()) for e in bb.engines)}",
-          file=sys.stderr, flush=True)
-    value_b = n * rounds / wall_b
+          f"n={bb.engines[heavy].n}); total {ev_total}", file=sys.stderr, flush=True)
+    value_m = n * rounds / wall_m
     value_p = n * rounds / wall_p
+    value_g = n * rounds / wall_g
+
+    def pct(lat, q):
+        return round(float(np.percentile(lat, q)), 4)
+
     out = dict(
         metric="particle-intervals/s (kNN+rates+MC) at 1M; batched vs plain; p50/p99 latency",
-        value=round(value_b, 1), unit="particle-intervals/s", n_gpus=1, steps=rounds, warmup=args.warmup,
-        ms_per_step=round(wall_b / rounds * 1e3, 4), higher_is_better=True, scaling="weak", vs_baseline=None,
+        value=round(value_m, 1), unit="particle-intervals/s", n_gpus=1, steps=rounds, warmup=args.warmup,
+        ms_per_step=round(wall_m / rounds * 1e3, 4), higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype="f64", data="synthetic",
         config=dict(workload=f"box_batch: {len(boxes)} periodic local boxes of the annulus physics, "
                              f"{n} particles in all (N log-uniform 2^10..2^16), per-box alpha log-uniform "
                              "1e-4..1e-2 and v_frag uniform 1..10 m/s, k=32, no push",
                     n_particles=n, n_boxes=len(boxes), k=32,
-                    form=f"batched: one HIP graph per two intervals of every box, {args.streams} streams"),
-        p50_ms=round(float(np.percentile(lat_b, 50)), 4), p99_ms=round(float(np.percentile(lat_b, 99)), 4),
-        plain=dict(value=round(value_p, 1), ms_per_step=round(wall_p / rounds * 1e3, 4),
-                   p50_ms=round(float(np.percentile(lat_p, 50)), 4),
-                   p99_ms=round(float(np.percentile(lat_p, 99)), 4),
-                   form="plain per-box loop, eager launches on one stream"),
-        batched_over_plain=round(value_b / value_p, 3),
+                    form="one launch per stage over every box (gd_many_interval), launch shapes from the autotuner",
+                    intervals=[args.warmup, args.warmup + rounds]),
+        p50_ms=pct(lat_m, 50), p99_ms=pct(lat_m, 99),
+        tuning=rec,
+        plain=dict(value=round(value_p, 1), ms_per_step=round(wall_p / rounds * 1e3, 4), p50_ms=pct(lat_p, 50),
+                   p99_ms=pct(lat_p, 99), form="plain per-box loop, eager launches on one stream"),
+        graph=dict(value=round(value_g, 1), ms_per_step=round(wall_g / rounds * 1e3, 4), p50_ms=pct(lat_g, 50),
+                   p99_ms=pct(lat_g, 99),
+                   form=f"one HIP graph per two intervals of per-box launches, {args.streams} streams"),
+        batched_over_plain=round(value_m / value_p, 3),
         events_max_per_particle=max(ev_max),
         status=status,
     )

@@ -291,6 +291,76 @@ int32_t gd_sample_collisions(const gd_problem* p, const gd_particles* st, const 
                              uint64_t interval_index, int32_t* n_events, int32_t* log,
                              int32_t log_cap, void* ws, size_t ws_bytes, void* stream);
 
+/* Many independent runs stepped as one (Sect. 2.5: the interval of each run
+ * is the one gd_build_neighbors, gd_collision_rates, gd_sample_collisions and
+ * gd_push make; Sect. 4.3.1: many small independent domains on one device).
+ * Every stage of the interval -- bounding box, Morton keys and radix sort,
+ * permutation, search tree, neighbour search, snapshot and rates, bin sums and
+ * plan, sampling (the per-lane pass, then one pass over the deferred
+ * particles of all runs), audit, push -- is one launch over all runs: the
+ * runs' blocks follow one another in one grid, and a block finds its run and
+ * that run's arguments through tables the library keeps in device memory.
+ * A run's results are those of its own calls, bit for bit, except that the
+ * bin sums of the plan and the audit are split over a number of blocks that
+ * depends on the run's size (their double-double totals round the same in
+ * all but contrived cases).
+ *
+ * gd_run describes one run: its problem, its two state buffers (a holds the
+ * current state, b receives the first interval's permutation; the buffers
+ * then alternate, so that after an even number of intervals the state is in
+ * a again with the same cur), its neighbour arrays, interval state (set up by
+ * gd_interval_init), lam_i (n doubles), optional n_events (n int32) and a
+ * workspace of gd_workspace_size bytes (initialised).  Sampling draws with
+ * the interval index on the device (GD_INTERVAL_ON_DEVICE).  All runs need
+ * the same rates_fp32, and k at most 256; runs with push enabled are pushed
+ * over their own dt_exe.  Everything is caller-owned and must stay allocated
+ * until gd_many_destroy; the library owns only its tables
+ * (gd_many_create allocates them with hipMalloc on the current device).
+ *
+ * gd_many_tuning holds launch shapes only; no choice changes a result:
+ *   knn_tile      1: the shared-candidate-tile search first (k <= 33), 0: the
+ *                 per-lane search for every query;
+ *   fallback_div  wavefronts of the tile search's fallback pass: n / fallback_div per run;
+ *   event_div     workgroups of the per-lane sampling pass: n / event_div per run (<= 512);
+ *   red_div       workgroups of each bin sum: n / red_div per run (<= 256);
+ *   heavy_blocks  workgroups (4 wavefronts each) of the pass over the deferred particles.
+ * Zero fields take the defaults (1, 256, 512, 2048, 768).
+ *
+ * gd_many_interval enqueues one interval of every run on `stream`; the host
+ * keeps the parity of the buffers and flips it at each call (two calls can
+ * be recorded into a graph and replayed).  gd_many_parity returns it: 0 when
+ * each run's state is in a.  Errors: GD_E_INVALID_ARG for a NULL or
+ * inconsistent description (message names the run), GD_E_HIP for a failed
+ * allocation or launch. */
+typedef struct gd_run {
+    const gd_problem* p;
+    gd_particles* a;
+    gd_particles* b;
+    const gd_neighbors* nb;
+    gd_interval* iv;
+    double* lam_i;
+    int32_t* n_events;
+    void* ws;
+    size_t ws_bytes;
+    uint64_t seed;
+} gd_run;
+
+typedef struct gd_many_tuning {
+    int32_t knn_tile;
+    int32_t fallback_div;
+    int32_t event_div;
+    int32_t red_div;
+    int32_t heavy_blocks;
+} gd_many_tuning;
+
+typedef struct gd_many gd_many;
+
+#define GD_MANY_MAX_RUNS 4096
+int32_t gd_many_create(const gd_run* runs, int32_t nrun, const gd_many_tuning* tune, gd_many** out);
+int32_t gd_many_interval(gd_many* m, void* stream);
+int32_t gd_many_parity(const gd_many* m, int32_t* parity);
+int32_t gd_many_destroy(gd_many* m);
+
 /* Push (Sect. 2.3.3) of every active particle over iv->dt_exe (iv non-NULL,
  * read on the device) or over dt (iv NULL).  GD_PUSH_LOCAL: z, vz by
  * drift-kick-drift with exact drag for the force at the drifted position,

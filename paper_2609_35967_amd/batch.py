@@ -1,10 +1,16 @@
 """Many independent runs ("boxes") stepped together on one GPU.
 
 Each box is an Engine with its own state, neighbourhoods, interval state and
-workspace, and its own adaptive interval.  Two forms step every box:
+workspace, and its own adaptive interval.  Three forms step every box:
 
 * ``step_plain`` -- the plain per-box loop: one interval of each box after the
   other, launched eagerly on the current stream;
+* ``step_many`` -- one launch per stage over every box (gd_many_interval):
+  the boxes' blocks follow one another in each grid and find their box's
+  arguments through tables in device memory, so an interval is about forty
+  launches whatever the number of boxes.  ``tune`` picks its launch shapes
+  by timing candidates on the batch itself (from a saved device state, so
+  every candidate runs the same intervals) and records what it measured;
 * ``replay`` -- one HIP graph holding two intervals of every box.  Per
   interval: each box's neighbour search, rates and per-lane sampling pass on
   its stream (boxes dealt to a few streams, largest first, each to the stream
@@ -23,9 +29,10 @@ and their inputs are the same, and nothing is shared between boxes.
 """
 from __future__ import annotations
 
-from .binding import PROF, Engine, check, load
+from .binding import MANY_DEFAULTS, PROF, Engine, ManyRuns, check, load
 
 import ctypes as C
+import time
 
 
 class BoxBatch:
@@ -43,6 +50,91 @@ class BoxBatch:
     @property
     def n_particles(self) -> int:
         return sum(e.n for e in self.engines)
+
+    def many(self, tuning: dict | None = None) -> ManyRuns:
+        """The one-launch-per-stage form over every box (built on first use,
+        or again when `tuning` is given)."""
+        if tuning is not None or getattr(self, "_many", None) is None:
+            if getattr(self, "_many", None) is not None:
+                self._many.close()
+            self._many = ManyRuns(self.engines, tuning if tuning is not None else getattr(self, "tuned", None))
+        return self._many
+
+    def step_many(self):
+        """One interval of every box, one launch per stage."""
+        self.many().interval()
+
+    # ---- the project's autotuner for the launch shapes of step_many ---------------
+    def _save(self):
+        torch = self.torch
+        torch.cuda.synchronize()
+        out = []
+        for e in self.engines:
+            out.append(dict(A={k: v.clone() for k, v in e.A.t.items()}, B={k: v.clone() for k, v in e.B.t.items()},
+                            Acur=e.A.cur, Bcur=e.B.cur, Aobj=e.A, Bobj=e.B,
+                            t={k: getattr(e, k).clone() for k in ("nbr", "cnt", "dmax", "n_active", "lam", "events", "iv")},
+                            interval=e.interval, moved=e.moved))
+        return out
+
+    def _load(self, saved):
+        torch = self.torch
+        torch.cuda.synchronize()
+        for e, s in zip(self.engines, saved):
+            e.A, e.B = s["Aobj"], s["Bobj"]
+            for k, v in s["A"].items():
+                e.A.t[k].copy_(v)
+            for k, v in s["B"].items():
+                e.B.t[k].copy_(v)
+            e.A.cur, e.B.cur = s["Acur"], s["Bcur"]
+            for k, v in s["t"].items():
+                getattr(e, k).copy_(v)
+            e.interval, e.moved = s["interval"], s["moved"]
+        torch.cuda.synchronize()
+
+    SPACE = dict(knn_tile=(1, 0), heavy_blocks=(256, 512, 768, 1024, 1536), event_div=(256, 512, 1024, 2048),
+                 fallback_div=(64, 256, 1024), red_div=(512, 2048, 8192))
+
+    def tune(self, intervals: int = 2, space: dict | None = None) -> dict:
+        """Coordinate search over the launch shapes of step_many: each knob in
+        turn takes every value of `space` with the others at their best so far;
+        every trial runs the same `intervals` intervals from the same saved
+        state (results do not depend on the shapes, only times do).  Keeps the
+        fastest and returns {"choice", "trials": [(setting, ms per interval)]}."""
+        torch = self.torch
+        space = space or self.SPACE
+        saved = self._save()
+        best = dict(MANY_DEFAULTS)
+        trials = []
+        cache = {}
+
+        def trial(setting):
+            key = tuple(sorted(setting.items()))
+            if key in cache:
+                return cache[key]
+            self._load(saved)
+            m = self.many(dict(setting))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(intervals):
+                m.interval()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / intervals
+            cache[key] = ms
+            trials.append((dict(setting), round(ms, 3)))
+            return ms
+
+        best_ms = trial(best)
+        for knob, values in space.items():
+            for v in values:
+                cand = dict(best, **{knob: v})
+                ms = trial(cand)
+                if ms < best_ms:
+                    best, best_ms = cand, ms
+        self._load(saved)
+        self.tuned = best
+        self.many(best)
+        self.tuning_record = dict(choice=best, ms_per_interval=round(best_ms, 3), trials=trials)
+        return self.tuning_record
 
     def step_plain(self):
         """One interval of every box, one box after the other on the current stream."""

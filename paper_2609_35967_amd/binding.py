@@ -61,11 +61,27 @@ class GdInterval(C.Structure):
     ]
 
 
+class GdRun(C.Structure):
+    _fields_ = [
+        ("p", C.POINTER(GdProblem)), ("a", C.POINTER(GdParticles)), ("b", C.POINTER(GdParticles)),
+        ("nb", C.POINTER(GdNeighbors)), ("iv", C.c_void_p), ("lam_i", C.c_void_p), ("n_events", C.c_void_p),
+        ("ws", C.c_void_p), ("ws_bytes", C.c_size_t), ("seed", C.c_uint64),
+    ]
+
+
+class GdManyTuning(C.Structure):
+    _fields_ = [("knn_tile", C.c_int32), ("fallback_div", C.c_int32), ("event_div", C.c_int32),
+                ("red_div", C.c_int32), ("heavy_blocks", C.c_int32)]
+
+
+MANY_DEFAULTS = dict(knn_tile=1, fallback_div=256, event_div=512, red_div=2048, heavy_blocks=768)
+
 EXPORTS = ("gd_workspace_size", "gd_workspace_init", "gd_interval_init", "gd_build_neighbors", "gd_collision_rates",
            "gd_sample_collisions", "gd_push", "gd_profile_events", "gd_status_read", "gd_last_error", "gd_version",
            "gd_sample_table_size", "gd_sample_collisions_deferred", "gd_sample_table_run", "gd_sample_audit",
            "gd_reshuffle_neighbors", "gd_diffuse", "gd_group_interactions", "gd_collision_rates_group",
-           "gd_sample_collisions_group", "gd_publish_group", "gd_reshuffle_neighbors_static")
+           "gd_sample_collisions_group", "gd_publish_group", "gd_reshuffle_neighbors_static",
+           "gd_many_create", "gd_many_interval", "gd_many_parity", "gd_many_destroy")
 PROF = {"sort": 0, "tree": 1, "knn_query": 2, "rates": 3, "mc": 4, "audit": 5, "push": 6, "diffuse": 7}
 GD_INTERVAL_ON_DEVICE = (1 << 64) - 1
 
@@ -117,6 +133,10 @@ def load(path: str | None = None):
                                              C.c_size_t, vp]
     L.gd_publish_group.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.c_int64, C.c_int64, vp, C.c_int32,
                                    vp]
+    L.gd_many_create.argtypes = [C.POINTER(GdRun), C.c_int32, C.POINTER(GdManyTuning), C.POINTER(vp)]
+    L.gd_many_interval.argtypes = [vp, vp]
+    L.gd_many_parity.argtypes = [vp, C.POINTER(C.c_int32)]
+    L.gd_many_destroy.argtypes = [vp]
     L.gd_status_read.argtypes = [vp, vp, C.POINTER(C.c_int32)]
     L.gd_profile_events.argtypes = [C.c_int32, vp, vp]
     L.gd_last_error.restype = C.c_char_p
@@ -125,7 +145,8 @@ def load(path: str | None = None):
                  "gd_sample_collisions", "gd_push", "gd_status_read", "gd_profile_events", "gd_sample_table_size",
                  "gd_sample_collisions_deferred", "gd_sample_table_run", "gd_sample_audit",
                  "gd_reshuffle_neighbors", "gd_diffuse", "gd_group_interactions", "gd_collision_rates_group",
-                 "gd_sample_collisions_group", "gd_publish_group", "gd_reshuffle_neighbors_static"):
+                 "gd_sample_collisions_group", "gd_publish_group", "gd_reshuffle_neighbors_static",
+                 "gd_many_create", "gd_many_interval", "gd_many_parity", "gd_many_destroy"):
         getattr(L, name).restype = C.c_int32
     if path is None:
         _lib = L
@@ -565,3 +586,62 @@ class Engine:
         eng.diff_step = int(ckpt["diff_step"])
         torch.cuda.current_stream(eng.device).synchronize()  # the copies ran on torch's stream
         return eng
+
+
+class ManyRuns:
+    """Engines stepped as one (gd_many_*): every stage of an interval is one
+    launch over all of them.  The engines keep their own buffers; after each
+    interval their bookkeeping (state buffers, cur, interval count) is
+    updated as their own step() would.  `tuning` takes the keys of
+    MANY_DEFAULTS (launch shapes only; results do not depend on them)."""
+
+    def __init__(self, engines, tuning: dict | None = None):
+        self.lib = load()
+        self.engines = list(engines)
+        self.tuning = dict(MANY_DEFAULTS, **(tuning or {}))
+        n = len(self.engines)
+        runs = (GdRun * n)()
+        keep = []
+        for i, e in enumerate(self.engines):
+            e._sync_own()
+            sa, sb = e.A.struct(), e.B.struct()
+            sb.cur = sa.cur
+            keep += [sa, sb]
+            r = runs[i]
+            r.p = C.pointer(e.P)
+            r.a = C.pointer(sa)
+            r.b = C.pointer(sb)
+            r.nb = C.pointer(e.nb)
+            r.iv = e.iv.data_ptr()
+            r.lam_i = e.lam.data_ptr()
+            r.n_events = e.events.data_ptr()
+            r.ws = e.ws_ptr
+            r.ws_bytes = e.ws_bytes
+            r.seed = e.seed
+        t = GdManyTuning(**{k: int(v) for k, v in self.tuning.items()})
+        self.handle = C.c_void_p()
+        check(self.lib.gd_many_create(runs, n, C.byref(t), C.byref(self.handle)))
+
+    def interval(self, stream=None):
+        """One interval of every run, enqueued on `stream` (torch's current one by default)."""
+        torch = self.engines[0].torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        check(self.lib.gd_many_interval(self.handle, C.c_void_p(st.cuda_stream)))
+        for e in self.engines:
+            cur = e.A.cur
+            e.A, e.B = e.B, e.A
+            e.A.cur = cur ^ 1
+            e.interval += 1
+            if e.P.push != 0:
+                e.moved = True
+
+    def close(self):
+        if self.handle:
+            check(self.lib.gd_many_destroy(self.handle))
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -117,6 +117,23 @@ static int check_state(const gd_problem* p, const gd_particles* s, bool need_oth
     return GD_OK;
 }
 
+// `out` can receive the permutation of `in`: every array `in` provides, distinct
+static int check_out(const gd_particles* in, const gd_particles* o)
+{
+    if (!o->id || !o->x || !o->y || !o->z || !o->M || !o->m[in->cur])
+        return fail(GD_E_INVALID_ARG, "out needs id, x, y, z, M and m[cur]");
+    const double* pairs[][2] = {{in->x, o->x}, {in->y, o->y}, {in->z, o->z}, {in->M, o->M},
+                                {in->m[in->cur], o->m[in->cur]}, {in->r, o->r}, {in->th, o->th}, {in->ph, o->ph},
+                                {in->vr, o->vr}, {in->lth, o->lth}, {in->lph, o->lph}, {in->vz, o->vz},
+                                {in->st_mid, o->st_mid}};
+    for (auto& pr : pairs) {
+        if (pr[0] && !pr[1]) return fail(GD_E_INVALID_ARG, "out is missing an array that in provides");
+        if (pr[0] && pr[0] == pr[1]) return fail(GD_E_INVALID_ARG, "in and out must not alias");
+    }
+    if (in->id == o->id) return fail(GD_E_INVALID_ARG, "in and out must not alias");
+    return GD_OK;
+}
+
 static int check_nb(const gd_neighbors* nb)
 {
     if (!nb || !nb->nbr || !nb->cnt || !nb->dmax) return fail(GD_E_INVALID_ARG, "neighbors nbr, cnt, dmax required");
@@ -184,16 +201,8 @@ int32_t gd_build_neighbors(const gd_problem* p, const gd_particles* in, gd_parti
     if (!out) return fail(GD_E_INVALID_ARG, "out is NULL");
     gd_particles o = *out;
     o.cur = in->cur;
-    if (!o.id || !o.x || !o.y || !o.z || !o.M || !o.m[in->cur])
-        return fail(GD_E_INVALID_ARG, "out needs id, x, y, z, M and m[cur]");
-    const double* pairs[][2] = {{in->x, o.x}, {in->y, o.y}, {in->z, o.z}, {in->M, o.M}, {in->m[in->cur], o.m[in->cur]},
-                                {in->r, o.r}, {in->th, o.th}, {in->ph, o.ph}, {in->vr, o.vr}, {in->lth, o.lth},
-                                {in->lph, o.lph}, {in->vz, o.vz}, {in->st_mid, o.st_mid}};
-    for (auto& pr : pairs) {
-        if (pr[0] && !pr[1]) return fail(GD_E_INVALID_ARG, "out is missing an array that in provides");
-        if (pr[0] && pr[0] == pr[1]) return fail(GD_E_INVALID_ARG, "in and out must not alias");
-    }
-    if (in->id == o.id) return fail(GD_E_INVALID_ARG, "in and out must not alias");
+    rc = check_out(in, &o);
+    if (rc) return rc;
     Layout L;
     rc = check_ws(p, ws, ws_bytes, L);
     if (rc) return rc;
@@ -450,6 +459,140 @@ int32_t gd_publish_group(const gd_problem* p, const gd_particles* s, int64_t lo,
     if (sched && (group < 0 || group >= max_groups())) return fail(GD_E_INVALID_ARG, "group %d out of range", group);
     launch_publish_group(s, lo, hi, sched, group, static_cast<hipStream_t>(stream));
     return hip_ok("gd_publish_group");
+}
+
+}  // extern "C"
+
+struct gd_many {
+    int device;
+    int32_t nrun;
+    int parity;
+    char* dev;
+    size_t bytes;
+    std::vector<ManyStep> steps[2];
+};
+
+extern "C" {
+
+int32_t gd_many_create(const gd_run* runs, int32_t nrun, const gd_many_tuning* tune, gd_many** out)
+{
+    if (!out) return fail(GD_E_INVALID_ARG, "gd_many_create: out is NULL");
+    *out = nullptr;
+    if (!runs || nrun < 1 || nrun > GD_MANY_MAX_RUNS)
+        return fail(GD_E_INVALID_ARG, "gd_many_create: nrun = %d outside 1..%d", nrun, GD_MANY_MAX_RUNS);
+    gd_many_tuning T{1, 256, 512, 2048, 768};
+    if (tune) {
+        if (tune->knn_tile < 0 || tune->knn_tile > 1 || tune->fallback_div < 0 || tune->event_div < 0 ||
+            tune->red_div < 0 || tune->heavy_blocks < 0 || tune->heavy_blocks > 65536)
+            return fail(GD_E_INVALID_ARG, "gd_many_create: tuning field out of range");
+        T.knn_tile = tune->knn_tile;
+        if (tune->fallback_div) T.fallback_div = tune->fallback_div;
+        if (tune->event_div) T.event_div = tune->event_div;
+        if (tune->red_div) T.red_div = tune->red_div;
+        if (tune->heavy_blocks) T.heavy_blocks = tune->heavy_blocks;
+    }
+    std::vector<ManyRun> R[2];
+    for (int32_t r = 0; r < nrun; ++r) {
+        const gd_run& x = runs[r];
+        int rc = check_problem(x.p);
+        if (!rc && x.p->n < 1) rc = fail(GD_E_INVALID_ARG, "n must be >= 1");
+        if (!rc) rc = check_state(x.p, x.a, true);
+        if (!rc) rc = check_state(x.p, x.b, false);
+        if (!rc) rc = check_nb(x.nb);
+        if (!rc && (!x.iv || !x.lam_i)) rc = fail(GD_E_INVALID_ARG, "interval and lam_i are required");
+        if (!rc && x.p->rates_fp32 != runs[0].p->rates_fp32) rc = fail(GD_E_INVALID_ARG, "runs differ in rates_fp32");
+        Layout L;
+        if (!rc) rc = check_ws(x.p, x.ws, x.ws_bytes, L);
+        gd_particles a = *x.a, b = *x.b;
+        b.cur = a.cur;
+        if (!rc) rc = check_out(&a, &b);
+        b.cur = a.cur ^ 1;
+        a.cur = b.cur;
+        if (!rc) rc = check_out(&b, &a);
+        if (rc) {
+            char msg[sizeof(g_err)];
+            snprintf(msg, sizeof(msg), "%s", g_err);
+            return fail(rc, "gd_many_create: run %d: %s", r, msg);
+        }
+        for (int par = 0; par < 2; ++par) {
+            ManyRun m{};
+            m.p = *x.p;
+            m.in = par ? *x.b : *x.a;
+            m.out = par ? *x.a : *x.b;
+            m.in.cur = x.a->cur ^ par;
+            m.out.cur = m.in.cur;
+            m.nb = *x.nb;
+            m.iv = x.iv;
+            m.lam_i = x.lam_i;
+            m.n_events = x.n_events;
+            m.ws = x.ws;
+            m.L = L;
+            m.seed = x.seed;
+            R[par].push_back(m);
+        }
+    }
+    ManyBuilder B;
+    B.tune = T;
+    std::vector<ManyStep> steps[2];
+    for (int par = 0; par < 2; ++par) {
+        B.steps.clear();
+        many_sort(B, R[par]);
+        many_knn(B, R[par]);
+        many_rates(B, R[par]);
+        many_sample(B, R[par]);
+        many_push(B, R[par]);
+        steps[par] = B.steps;
+    }
+    gd_many* m = new gd_many{};
+    if (hipGetDevice(&m->device) != hipSuccess) {
+        delete m;
+        return fail(GD_E_HIP, "gd_many_create: no current device");
+    }
+    m->nrun = nrun;
+    m->parity = 0;
+    m->bytes = B.arena.size();
+    if (hipMalloc(reinterpret_cast<void**>(&m->dev), m->bytes) != hipSuccess) {
+        delete m;
+        return fail(GD_E_HIP, "gd_many_create: hipMalloc of %zu bytes failed", B.arena.size());
+    }
+    if (hipMemcpy(m->dev, B.arena.data(), m->bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(m->dev);
+        delete m;
+        return fail(GD_E_HIP, "gd_many_create: upload of the tables failed");
+    }
+    m->steps[0] = steps[0];
+    m->steps[1] = steps[1];
+    *out = m;
+    return GD_OK;
+}
+
+int32_t gd_many_interval(gd_many* m, void* stream)
+{
+    if (!m) return fail(GD_E_INVALID_ARG, "gd_many_interval: NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (const ManyStep& s : m->steps[m->parity]) s.fn(m->dev, s, st);
+    m->parity ^= 1;
+    return hip_ok("gd_many_interval");
+}
+
+int32_t gd_many_parity(const gd_many* m, int32_t* parity)
+{
+    if (!m || !parity) return fail(GD_E_INVALID_ARG, "gd_many_parity: NULL");
+    *parity = m->parity;
+    return GD_OK;
+}
+
+int32_t gd_many_destroy(gd_many* m)
+{
+    if (!m) return GD_OK;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(m->device);
+    const hipError_t e = hipFree(m->dev);
+    (void)hipSetDevice(cur);
+    delete m;
+    if (e != hipSuccess) return fail(GD_E_HIP, "gd_many_destroy: %s", hipGetErrorString(e));
+    return GD_OK;
 }
 
 int32_t gd_status_read(void* ws, void* stream, int32_t* out)

@@ -177,6 +177,54 @@ __device__ inline int64_t xcd_block()
     return (nb / kXcd) * x + (x < nb % kXcd ? x : nb % kXcd) + r;
 }
 
+// ---------------------------------------------------------------------------
+// Launches over many runs.  A kernel body takes its block as (index, count)
+// within its own run's blocks: a one-run launch passes (blockIdx.x, gridDim.x)
+// or the die-aware order; a many-run launch (one grid for every run) finds its
+// run in a block map, run[g] for block g and b0[r] the first block of run r
+// (runs with no blocks in a stage have b0[r] = b0[r + 1]), and reads that
+// run's arguments from a table in device memory.  K is a struct with the
+// argument type Args, the block size kThreads and the static device function
+// body(const Args&, Blk).
+struct Blk {
+    int64_t id, n;
+};
+
+struct RunMap {
+    const int32_t* run;
+    const int32_t* b0;
+};
+
+template <class K>
+__global__ __launch_bounds__(K::kThreads) void k_many(const typename K::Args* __restrict__ T, RunMap M)
+{
+    const int32_t r = M.run[blockIdx.x];
+    const int32_t s = M.b0[r];
+    const typename K::Args A = T[r];
+    K::body(A, Blk{int64_t(blockIdx.x) - s, int64_t(M.b0[r + 1] - s)});
+}
+
+// the counters a many-run interval clears before a stage (one block per run):
+// the die queues and the two fallback counts of the search, or the list
+// segment counts of sampling
+struct ClearArgs {
+    int32_t* a;
+    int32_t na;
+    int32_t* b;
+    int32_t nb;
+};
+
+struct ClearCounters {
+    using Args = ClearArgs;
+    static constexpr int kThreads = 64;
+    static __device__ void body(const Args& A, Blk)
+    {
+        const int t = threadIdx.x;
+        if (t < A.na) A.a[t] = 0;
+        if (A.b && t < A.nb) A.b[t] = 0;
+    }
+};
+
 template <typename T>
 __host__ __device__ inline T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + off); }
 

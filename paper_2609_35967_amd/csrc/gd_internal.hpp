@@ -1,6 +1,9 @@
 // gd_internal.hpp -- launch functions of the library's kernels (host side).
 #pragma once
 
+#include <cstring>
+#include <vector>
+
 #include "gd_common.hpp"
 
 namespace gd {
@@ -39,7 +42,8 @@ int launch_reshuffle_static(const gd_problem* p, const gd_neighbors* nb, uint64_
 int launch_audit(const gd_problem* p, const gd_particles* s, gd_interval* iv, void* ws, const Layout& L, hipStream_t st);
 size_t sample_table_bytes(int32_t nslot);
 int max_table_slots();
-int launch_sample_table(void* table, int32_t nslot, int32_t k, int32_t rates_fp32, hipStream_t st);
+int launch_sample_table(void* table, int32_t nslot, int32_t k, int32_t rates_fp32, hipStream_t st,
+                        int32_t nblocks = 0);
 int launch_push(const gd_problem* p, const gd_particles* s, const gd_interval* iv, double dt, void* ws,
                 const Layout& L, hipStream_t st);
 void launch_interval_init(gd_interval* iv, double dt_coll, hipStream_t st);
@@ -59,5 +63,95 @@ int launch_diffuse(const gd_problem* p, const gd_particles* s, double dt, uint64
 const double* launch_part_fold(const double* part, void* ws, const Layout& L, hipStream_t st);
 void launch_bin_reduce(int mode, const double* msnap, const double* M, const double* va, const double* vb, int64_t n,
                        double* part, void* ws, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Many runs stepped as one (gd_many_*): each stage of an interval is one
+// launch over every run.  The recorders of each source append their stages'
+// launches, for one parity of the state buffers, to a builder that collects
+// the argument tables and block maps in one host arena, uploaded once.
+struct ManyRun {
+    gd_problem p;
+    gd_particles in, out;  // the interval permutes `in` into `out`, then works on `out`
+    gd_neighbors nb;
+    gd_interval* iv;
+    double* lam_i;
+    int32_t* n_events;
+    void* ws;
+    Layout L;
+    uint64_t seed;
+};
+
+struct ManyStep;
+using ManyFn = void (*)(char* base, const ManyStep& s, hipStream_t st);
+struct ManyStep {
+    ManyFn fn;
+    size_t tab, run, b0;  // arena offsets of the argument table and the block map
+    int64_t nblocks;
+    int64_t a0, a1;       // step-specific values
+};
+
+struct ManyBuilder {
+    std::vector<char> arena;
+    std::vector<ManyStep> steps;
+    gd_many_tuning tune;
+
+    size_t put(const void* p, size_t bytes)
+    {
+        const size_t at = (arena.size() + 255) & ~size_t(255);
+        arena.resize(at + (bytes ? bytes : 1));
+        if (bytes) memcpy(arena.data() + at, p, bytes);
+        return at;
+    }
+    template <class A>
+    size_t put_vec(const std::vector<A>& v)
+    {
+        return put(v.data(), v.size() * sizeof(A));
+    }
+    // block map of per-run block counts nb[r]
+    int64_t map(const std::vector<int64_t>& nb, size_t& run_off, size_t& b0_off)
+    {
+        std::vector<int32_t> b0(nb.size() + 1, 0), run;
+        for (size_t r = 0; r < nb.size(); ++r) {
+            b0[r + 1] = b0[r] + int32_t(nb[r]);
+            for (int64_t b = 0; b < nb[r]; ++b) run.push_back(int32_t(r));
+        }
+        run_off = put_vec(run);
+        b0_off = put_vec(b0);
+        return b0.back();
+    }
+    template <class K>
+    void add(const std::vector<typename K::Args>& tab, const std::vector<int64_t>& nb);
+    void add_raw(ManyFn fn, size_t tab, int64_t a0, int64_t a1)
+    {
+        steps.push_back(ManyStep{fn, tab, 0, 0, 0, a0, a1});
+    }
+};
+
+template <class K>
+void many_launch(char* base, const ManyStep& s, hipStream_t st)
+{
+    if (s.nblocks <= 0) return;
+    const RunMap M{reinterpret_cast<const int32_t*>(base + s.run), reinterpret_cast<const int32_t*>(base + s.b0)};
+    hipLaunchKernelGGL(k_many<K>, dim3(unsigned(s.nblocks)), dim3(K::kThreads), 0, st,
+                       reinterpret_cast<const typename K::Args*>(base + s.tab), M);
+}
+
+// (instantiated in the source that defines K's body)
+template <class K>
+void ManyBuilder::add(const std::vector<typename K::Args>& tab, const std::vector<int64_t>& nb)
+{
+    ManyStep s{&many_launch<K>, put_vec(tab), 0, 0, 0, 0, 0};
+    s.nblocks = map(nb, s.run, s.b0);
+    steps.push_back(s);
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+void many_sort(ManyBuilder& B, const std::vector<ManyRun>& R);
+void many_knn(ManyBuilder& B, const std::vector<ManyRun>& R);
+void many_rates(ManyBuilder& B, const std::vector<ManyRun>& R);
+void many_sample(ManyBuilder& B, const std::vector<ManyRun>& R);
+void many_audit_sums(ManyBuilder& B, const std::vector<ManyRun>& R);
+void many_push(ManyBuilder& B, const std::vector<ManyRun>& R);
 
 }  // namespace gd

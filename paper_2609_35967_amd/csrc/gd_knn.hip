@@ -45,6 +45,8 @@
 #include "gd_internal.hpp"
 #include "gd_knn.hpp"
 
+#include <algorithm>
+
 namespace gd {
 
 constexpr int kDMax = 3;  // levels of the nested bin chain
@@ -58,11 +60,33 @@ static_assert(kQueue >= 1 && kQueue <= 4, "the queue keeps its masks in the byte
 // ---------------------------------------------------------------------------
 // Tree build
 // level 0: widened box of every bucket of kBucket active slots (empty beyond)
-__global__ __launch_bounds__(256) void k_bucket_boxes(const double4* __restrict__ pos, const WsHeader* __restrict__ h,
-                                                      FBox* __restrict__ box0, int64_t cap0, Periodicity P)
+struct BucketArgs {
+    const double4* pos;
+    const WsHeader* h;
+    FBox* box0;
+    int64_t cap0;
+    Periodicity P;
+};
+
+struct BucketBoxes {
+    using Args = BucketArgs;
+    static constexpr int kThreads = 256;
+    static __device__ void body(const Args& A, Blk B);
+};
+
+__global__ __launch_bounds__(256) void k_bucket_boxes(BucketArgs A)
 {
+    BucketBoxes::body(A, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
+}
+
+__device__ void BucketBoxes::body(const Args& A, Blk B)
+{
+    const double4* __restrict__ pos = A.pos;
+    const WsHeader* __restrict__ h = A.h;
+    const int64_t cap0 = A.cap0;
+    const Periodicity P = A.P;
     const int na = h->n_active;
-    const int64_t b = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int64_t b = B.id * int64_t(blockDim.x) + threadIdx.x;
     if (b >= cap0) return;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int t = 0; t < kBucket; ++t) {
@@ -83,15 +107,35 @@ __global__ __launch_bounds__(256) void k_bucket_boxes(const double4* __restrict_
         x.lo[a] = __double2float_rd(lo[a] - del);
         x.hi[a] = __double2float_ru(hi[a] + del);
     }
-    box0[b] = x;
+    A.box0[b] = x;
 }
 
 // level l >= 1: union of the 8 children; children past the stored capacity
 // of level l-1 (the padding of the levels above) are empty
-__global__ __launch_bounds__(256) void k_level_boxes(const FBox* __restrict__ child, int64_t child_cap,
-                                                     FBox* __restrict__ cur, int64_t cap)
+struct LevelArgs {
+    const FBox* child;
+    int64_t child_cap;
+    FBox* cur;
+    int64_t cap;
+};
+
+struct LevelBoxes {
+    using Args = LevelArgs;
+    static constexpr int kThreads = 256;
+    static __device__ void body(const Args& A, Blk B);
+};
+
+__global__ __launch_bounds__(256) void k_level_boxes(LevelArgs A)
 {
-    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    LevelBoxes::body(A, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
+}
+
+__device__ void LevelBoxes::body(const Args& A, Blk B)
+{
+    const FBox* __restrict__ child = A.child;
+    const int64_t child_cap = A.child_cap, cap = A.cap;
+    FBox* __restrict__ cur = A.cur;
+    const int64_t i = B.id * int64_t(blockDim.x) + threadIdx.x;
     if (i >= cap) return;
     FBox x;
     for (int a = 0; a < 3; ++a) {
@@ -318,17 +362,30 @@ static_assert(kC1 <= kNB / 2, "the boundary list reuses the counter words");
 static_assert(kNB <= 32, "list words keep the bin in 5 bits");
 
 template <bool PER, int KP2>
+struct KnnQuery {
+    using Args = KnnArgs;
+    static constexpr int kThreads = kQBlock;
+    static __device__ void body(const Args& A, Blk B);
+};
+
+template <bool PER, int KP2>
 __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
+{
+    KnnQuery<PER, KP2>::body(A, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
+}
+
+template <bool PER, int KP2>
+__device__ void KnnQuery<PER, KP2>::body(const Args& A, Blk B)
 {
     using QL = QueryLds<KP2>;
     __shared__ uint32_t s_lds[QL::kWords * kQBlock];
     const int tid = threadIdx.x;
     int64_t q64;
     if (A.list) {  // the queries of a list (those the tile search handed back)
-        const int64_t idx = (int64_t(blockIdx.x) * (kQBlock / kWave) + tid / kWave) * kWave + (tid & (kWave - 1));
+        const int64_t idx = (B.id * (kQBlock / kWave) + tid / kWave) * kWave + (tid & (kWave - 1));
         q64 = idx < *A.list_n ? A.list[idx] : A.n;
     } else {
-        const int32_t item = xcd_take(A.xq, int32_t(gridDim.x * (kQBlock / kWave)));
+        const int32_t item = xcd_take(A.xq, int32_t(B.n * (kQBlock / kWave)));
         q64 = item < 0 ? A.n : int64_t(item) * kWave + (tid & (kWave - 1));
     }
     if (q64 >= A.n) return;
@@ -780,13 +837,37 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
 }
 
 // ---------------------------------------------------------------------------
-int launch_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layout& L, hipStream_t st)
+struct CopyNaArgs {
+    const WsHeader* h;
+    int32_t* out;
+};
+
+struct CopyNa {
+    using Args = CopyNaArgs;
+    static constexpr int kThreads = 64;
+    static __device__ void body(const Args& A, Blk)
+    {
+        if (threadIdx.x == 0) *A.out = A.h->n_active;
+    }
+};
+
+struct KnnSetup {
+    TreeLevels T;
+    Periodicity P;
+    bool per;
+    BucketArgs bucket;
+    LevelArgs level[kMaxTreeLevels];
+    KnnArgs A;
+};
+
+static KnnSetup knn_setup(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layout& L)
 {
+    KnnSetup S{};
     const int64_t n = p->n;
     const WsHeader* h = at<WsHeader>(ws, L.hdr);
     FBox* boxes = at<FBox>(ws, L.boxes);
     const double4* pos = at<double4>(ws, L.pos4);
-    TreeLevels T{};
+    TreeLevels& T = S.T;
     T.levels = L.levels;
     for (int l = 0; l < L.levels; ++l) {
         T.off[l] = L.lvl_off[l];
@@ -794,25 +875,16 @@ int launch_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layo
     }
     T.off1 = int32_t(L.off1);
     T.stride1 = int32_t(L.stride1);
-    Periodicity P{};
-    bool per = false;
+    S.per = false;
     for (int a = 0; a < 3; ++a) {
-        P.per[a] = p->periodic[a] ? 1 : 0;
-        P.L[a] = p->L[a];
-        per = per || P.per[a];
+        S.P.per[a] = p->periodic[a] ? 1 : 0;
+        S.P.L[a] = p->L[a];
+        S.per = S.per || S.P.per[a];
     }
-    prof_mark(GD_PROF_TREE, 0, st);
-    hipLaunchKernelGGL(k_bucket_boxes, dim3(unsigned((T.cap[0] + 255) / 256)), dim3(256), 0, st, pos, h,
-                       boxes + T.off[0], T.cap[0], P);
+    S.bucket = BucketArgs{pos, h, boxes + T.off[0], T.cap[0], S.P};
     for (int l = 1; l < L.levels; ++l)
-        hipLaunchKernelGGL(k_level_boxes, dim3(unsigned((T.cap[l] + 255) / 256)), dim3(256), 0, st,
-                           boxes + T.off[l - 1], T.cap[l - 1], boxes + T.off[l], T.cap[l]);
-    prof_mark(GD_PROF_TREE, 1, st);
-    KnnArgs A{};
-#ifdef GD_KNN_STATS
-    A.stats = at<int32_t>(ws, L.stats);
-    launch_fill_i32(A.stats, 8 * n, 0, st);
-#endif
+        S.level[l] = LevelArgs{boxes + T.off[l - 1], T.cap[l - 1], boxes + T.off[l], T.cap[l]};
+    KnnArgs& A = S.A;
     A.pos = pos;
     A.boxes = boxes;
     A.T = T;
@@ -821,7 +893,7 @@ int launch_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layo
     A.k = p->k;
     A.rmax2 = p->rmax * p->rmax;
     for (int a = 0; a < 3; ++a) {
-        A.per[a] = P.per[a];
+        A.per[a] = S.P.per[a];
         A.L[a] = p->L[a];
         A.hL[a] = 0.5 * p->L[a];
     }
@@ -832,6 +904,25 @@ int launch_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layo
     A.hint = at<double>(ws, L.hint);
     A.ws = ws;
     A.xq = at<WsHeader>(ws, L.hdr)->xq[kQueueKnn];
+    return S;
+}
+
+int launch_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layout& L, hipStream_t st)
+{
+    const int64_t n = p->n;
+    KnnSetup S = knn_setup(p, nb, ws, L);
+    const TreeLevels& T = S.T;
+    const bool per = S.per;
+    prof_mark(GD_PROF_TREE, 0, st);
+    hipLaunchKernelGGL(k_bucket_boxes, dim3(unsigned((T.cap[0] + 255) / 256)), dim3(256), 0, st, S.bucket);
+    for (int l = 1; l < L.levels; ++l)
+        hipLaunchKernelGGL(k_level_boxes, dim3(unsigned((T.cap[l] + 255) / 256)), dim3(256), 0, st, S.level[l]);
+    prof_mark(GD_PROF_TREE, 1, st);
+    KnnArgs& A = S.A;
+#ifdef GD_KNN_STATS
+    A.stats = at<int32_t>(ws, L.stats);
+    launch_fill_i32(A.stats, 8 * n, 0, st);
+#endif
     prof_mark(GD_PROF_KNN_QUERY, 0, st);
     if (p->k > 64) {  // one wavefront per query: the per-lane search's lists hold at most 64
         launch_knn_wave(A, per, nullptr, nullptr, n, st);
@@ -864,6 +955,107 @@ int launch_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layo
     }
     prof_mark(GD_PROF_KNN_QUERY, 1, st);
     return 0;
+}
+
+// The search of every run as stages of one interval: the bucket boxes, each
+// tree level over the runs that have it, then the queries: k > 64 one
+// wavefront per query; k <= 33 (with tiles) the tile search, its fallback
+// wavefronts and the per-lane search of the first list; otherwise the
+// per-lane search over every query.  Runs are grouped by periodicity and
+// k class, a launch per group and stage.
+void many_knn(ManyBuilder& B, const std::vector<ManyRun>& R)
+{
+    const size_t nr = R.size();
+    std::vector<KnnSetup> S(nr);
+    int maxl = 0;
+    for (size_t r = 0; r < nr; ++r) {
+        S[r] = knn_setup(&R[r].p, &R[r].nb, R[r].ws, R[r].L);
+        maxl = std::max(maxl, R[r].L.levels);
+    }
+    std::vector<int64_t> nb(nr);
+    {
+        std::vector<BucketArgs> tab(nr);
+        for (size_t r = 0; r < nr; ++r) {
+            tab[r] = S[r].bucket;
+            nb[r] = cdiv(S[r].T.cap[0], 256);
+        }
+        B.add<BucketBoxes>(tab, nb);
+    }
+    for (int l = 1; l < maxl; ++l) {
+        std::vector<LevelArgs> tab(nr);
+        for (size_t r = 0; r < nr; ++r) {
+            const bool has = l < R[r].L.levels;
+            tab[r] = has ? S[r].level[l] : LevelArgs{};
+            nb[r] = has ? cdiv(S[r].T.cap[l], 256) : 0;
+        }
+        B.add<LevelBoxes>(tab, nb);
+    }
+    // query groups: (periodic, class) with class 0: k <= 33, 1: 34..64, 2: > 64
+    for (int per = 0; per < 2; ++per) {
+        for (int cls = 0; cls < 3; ++cls) {
+            std::vector<int64_t> mine(nr, 0);
+            bool any = false;
+            for (size_t r = 0; r < nr; ++r) {
+                const int k = R[r].p.k;
+                const int c = k <= 33 ? 0 : (k <= 64 ? 1 : 2);
+                mine[r] = (int(S[r].per) == per && c == cls) ? 1 : 0;
+                any = any || mine[r];
+            }
+            if (!any) continue;
+            if (cls == 2) {
+                std::vector<WaveArgs> tab(nr);
+                for (size_t r = 0; r < nr; ++r) {
+                    tab[r] = WaveArgs{S[r].A, nullptr, nullptr};
+                    nb[r] = mine[r] ? R[r].p.n : 0;
+                }
+                many_add_wave(B, tab, nb, per);
+                continue;
+            }
+            const bool tile = cls == 0 && B.tune.knn_tile;
+            std::vector<ClearArgs> clr(nr);
+            for (size_t r = 0; r < nr; ++r) {
+                WsHeader* hw = at<WsHeader>(R[r].ws, R[r].L.hdr);
+                clr[r] = ClearArgs{S[r].A.xq, kXcd, tile ? hw->knn_fb_n : nullptr, 2};
+                nb[r] = mine[r];
+            }
+            B.add<ClearCounters>(clr, nb);
+            std::vector<KnnArgs> qa(nr);
+            for (size_t r = 0; r < nr; ++r) qa[r] = S[r].A;
+            if (tile) {
+                std::vector<TileArgs> tt(nr);
+                std::vector<WaveArgs> wt(nr);
+                std::vector<int64_t> fnb(nr);
+                for (size_t r = 0; r < nr; ++r) {
+                    WsHeader* hw = at<WsHeader>(R[r].ws, R[r].L.hdr);
+                    int32_t* fb0 = at<int32_t>(R[r].ws, R[r].L.keys1);
+                    int32_t* fb1 = at<int32_t>(R[r].ws, R[r].L.vals1);
+                    tt[r] = TileArgs{S[r].A, fb0, fb1, hw->knn_fb_n};
+                    wt[r] = WaveArgs{S[r].A, fb1, hw->knn_fb_n + 1};
+                    qa[r].list = fb0;
+                    qa[r].list_n = hw->knn_fb_n;
+                    nb[r] = mine[r] ? cdiv(R[r].p.n, kWave) : 0;
+                    fnb[r] = mine[r] ? std::max<int64_t>(1, cdiv(R[r].p.n, B.tune.fallback_div)) : 0;
+                }
+                many_add_tile(B, tt, nb, per);
+                many_add_wave(B, wt, fnb, per);
+            }
+            for (size_t r = 0; r < nr; ++r) nb[r] = mine[r] ? cdiv(R[r].p.n, kQBlock) : 0;
+            if (cls == 0) {
+                if (per) B.add<KnnQuery<true, 32>>(qa, nb);
+                else B.add<KnnQuery<false, 32>>(qa, nb);
+            } else {
+                if (per) B.add<KnnQuery<true, 64>>(qa, nb);
+                else B.add<KnnQuery<false, 64>>(qa, nb);
+            }
+        }
+    }
+    // the active counts, for the runs that ask for them
+    std::vector<CopyNaArgs> na(nr);
+    for (size_t r = 0; r < nr; ++r) {
+        na[r] = CopyNaArgs{S[r].A.h, R[r].nb.n_active};
+        nb[r] = R[r].nb.n_active ? 1 : 0;
+    }
+    B.add<CopyNa>(na, nb);
 }
 
 }  // namespace gd

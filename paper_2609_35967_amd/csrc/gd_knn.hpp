@@ -67,6 +67,23 @@ struct KnnArgs {
     const int32_t* list_n;
 };
 
+// the tile search's arguments: the search's, and its two lists of handed-back
+// queries with their counts
+struct TileArgs {
+    KnnArgs A;
+    int32_t* fb0;
+    int32_t* fb1;
+    int32_t* fb_n;
+};
+
+// the wavefront-per-query search's: the queries list[0 .. *count), or every
+// slot when list is null
+struct WaveArgs {
+    KnnArgs A;
+    const int32_t* list;
+    const int32_t* count;
+};
+
 template <bool PER>
 __device__ inline double sep2(const KnnArgs& A, const double q[3], double px, double py, double pz)
 {
@@ -195,5 +212,8 @@ void launch_knn_wave(const KnnArgs& A, bool per, const int32_t* list, const int3
 // (gd_knn_tile.hip), k <= 33; the queries it cannot complete go to fb0 (no
 // usable previous distance) or fb1 (the rest)
 void launch_knn_tile(const KnnArgs& A, bool per, int32_t* fb0, int32_t* fb1, int32_t* fb_n, hipStream_t st);
+// the same two searches as stages of a many-run interval
+void many_add_tile(ManyBuilder& B, const std::vector<TileArgs>& tab, const std::vector<int64_t>& nb, bool per);
+void many_add_wave(ManyBuilder& B, const std::vector<WaveArgs>& tab, const std::vector<int64_t>& nb, bool per);
 
 }  // namespace gd

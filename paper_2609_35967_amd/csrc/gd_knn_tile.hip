@@ -127,9 +127,27 @@ __device__ inline int wave_sum_i(int v)
 }
 
 template <bool PER>
-__global__ __launch_bounds__(kWave) void k_knn_tile(KnnArgs A, int32_t* __restrict__ fb0, int32_t* __restrict__ fb1,
-                                                    int32_t* __restrict__ fb_n)
+struct KnnTile {
+    using Args = TileArgs;
+    static constexpr int kThreads = kWave;
+    static __device__ void body(const Args& TA, Blk B);
+};
+
+template <bool PER>
+__global__ __launch_bounds__(kWave) void k_knn_tile(TileArgs TA)
 {
+    KnnTile<PER>::body(TA, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
+}
+
+// (each wavefront takes its item from the die queue, so a grid of exactly the
+// run's items is all the body needs of its block)
+template <bool PER>
+__device__ void KnnTile<PER>::body(const Args& TA, Blk)
+{
+    const KnnArgs& A = TA.A;
+    int32_t* __restrict__ fb0 = TA.fb0;
+    int32_t* __restrict__ fb1 = TA.fb1;
+    int32_t* __restrict__ fb_n = TA.fb_n;
     __shared__ TileLds<PER> L;
     const int lane = threadIdx.x;
     const int32_t item = xcd_take(A.xq, int32_t((A.n + kWave - 1) / kWave));
@@ -586,8 +604,15 @@ __global__ __launch_bounds__(kWave) void k_knn_tile(KnnArgs A, int32_t* __restri
 void launch_knn_tile(const KnnArgs& A, bool per, int32_t* fb0, int32_t* fb1, int32_t* fb_n, hipStream_t st)
 {
     const dim3 grid(unsigned((A.n + kWave - 1) / kWave));
-    if (per) hipLaunchKernelGGL(k_knn_tile<true>, grid, dim3(kWave), 0, st, A, fb0, fb1, fb_n);
-    else hipLaunchKernelGGL(k_knn_tile<false>, grid, dim3(kWave), 0, st, A, fb0, fb1, fb_n);
+    const TileArgs TA{A, fb0, fb1, fb_n};
+    if (per) hipLaunchKernelGGL(k_knn_tile<true>, grid, dim3(kWave), 0, st, TA);
+    else hipLaunchKernelGGL(k_knn_tile<false>, grid, dim3(kWave), 0, st, TA);
+}
+
+void many_add_tile(ManyBuilder& B, const std::vector<TileArgs>& tab, const std::vector<int64_t>& nb, bool per)
+{
+    if (per) B.add<KnnTile<true>>(tab, nb);
+    else B.add<KnnTile<false>>(tab, nb);
 }
 
 }  // namespace gd

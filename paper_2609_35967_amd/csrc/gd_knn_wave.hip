@@ -323,26 +323,42 @@ __device__ void knn_wave_query(const KnnArgs& A, int q, WaveLds& L, int lane)
 // One query per 64-thread workgroup: every slot [0, n), or the slots of
 // `list` [0, *count) when a list is given.
 template <bool PER>
-__global__ __launch_bounds__(kWave) void k_knn_wave(KnnArgs A, const int32_t* __restrict__ list,
-                                                    const int32_t* __restrict__ count)
-{
-    __shared__ WaveLds L;
-    const int lane = threadIdx.x;
-    if (list) {
-        const int32_t nl = *count;
-        for (int64_t t = blockIdx.x; t < nl; t += gridDim.x) knn_wave_query<PER>(A, list[t], L, lane);
-    } else {
-        const int64_t q = xcd_block();
-        if (q < A.n) knn_wave_query<PER>(A, int(q), L, lane);
+struct KnnWave {
+    using Args = WaveArgs;
+    static constexpr int kThreads = kWave;
+    static __device__ void body(const Args& W, Blk B)
+    {
+        __shared__ WaveLds L;
+        const int lane = threadIdx.x;
+        if (W.list) {
+            const int32_t nl = *W.count;
+            for (int64_t t = B.id; t < nl; t += B.n) knn_wave_query<PER>(W.A, W.list[t], L, lane);
+        } else {
+            const int64_t q = B.id;
+            if (q < W.A.n) knn_wave_query<PER>(W.A, int(q), L, lane);
+        }
     }
+};
+
+template <bool PER>
+__global__ __launch_bounds__(kWave) void k_knn_wave(WaveArgs W)
+{
+    KnnWave<PER>::body(W, Blk{W.list ? int64_t(blockIdx.x) : xcd_block(), int64_t(gridDim.x)});
 }
 
 void launch_knn_wave(const KnnArgs& A, bool per, const int32_t* list, const int32_t* count, int64_t nblocks,
                      hipStream_t st)
 {
     const dim3 grid(unsigned(nblocks > 0 ? nblocks : 1));
-    if (per) hipLaunchKernelGGL(k_knn_wave<true>, grid, dim3(kWave), 0, st, A, list, count);
-    else hipLaunchKernelGGL(k_knn_wave<false>, grid, dim3(kWave), 0, st, A, list, count);
+    const WaveArgs W{A, list, count};
+    if (per) hipLaunchKernelGGL(k_knn_wave<true>, grid, dim3(kWave), 0, st, W);
+    else hipLaunchKernelGGL(k_knn_wave<false>, grid, dim3(kWave), 0, st, W);
+}
+
+void many_add_wave(ManyBuilder& B, const std::vector<WaveArgs>& tab, const std::vector<int64_t>& nb, bool per)
+{
+    if (per) B.add<KnnWave<true>>(tab, nb);
+    else B.add<KnnWave<false>>(tab, nb);
 }
 
 }  // namespace gd

@@ -19,6 +19,8 @@
 #include "gd_internal.hpp"
 #include "gd_physics.hpp"
 
+#include <algorithm>
+
 namespace gd {
 
 struct McArgs {
@@ -67,7 +69,7 @@ constexpr int kEventCap = 1 << 24;  // safety stop per particle and interval (st
 constexpr int kLaneEvents = 4;      // events a lane samples before handing its particle over
 constexpr int kHeavyBlocks = 768;   // blocks (4 wavefronts each) of the wavefront-per-particle pass: 3 per SIMD
 constexpr int kEventBlocks = 512;   // blocks (4 wavefronts each) of the event pass: two per SIMD
-constexpr int kSmallList = 4 * kHeavyBlocks;  // at most this many particles with events: all to the wavefront pass
+constexpr int kSmallList = 3072;    // at most this many particles with events: all to the wavefront pass
 
 template <int KP2>
 __device__ inline double prefix_rates_f32(const McArgs& A, const QCtxF& q, const int32_t* row, int c, double mi,
@@ -137,11 +139,24 @@ __device__ inline int64_t seg_base(int x, int64_t nblocks)
 }
 
 template <bool DIRECT_HEAVY>
+struct McScreen {
+    using Args = McArgs;
+    static constexpr int kThreads = 256;
+    static __device__ void body(const Args& A, Blk B);
+};
+
+template <bool DIRECT_HEAVY>
 __global__ __launch_bounds__(256) void k_mc_screen(McArgs A)
+{
+    McScreen<DIRECT_HEAVY>::body(A, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
+}
+
+template <bool DIRECT_HEAVY>
+__device__ void McScreen<DIRECT_HEAVY>::body(const Args& A, Blk B)
 {
     __shared__ int32_t s_w[4];
     __shared__ int32_t s_base;
-    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int64_t i = B.id * int64_t(blockDim.x) + threadIdx.x;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     bool ev = false;
     if (i < A.P.n) {
@@ -169,7 +184,7 @@ __global__ __launch_bounds__(256) void k_mc_screen(McArgs A)
     if (threadIdx.x == 0) {
         const int32_t tot = s_w[0] + s_w[1] + s_w[2] + s_w[3];
         int32_t b = 0;
-        if (tot) b = atomicAdd(DIRECT_HEAVY ? A.heavy_n : &A.list_seg[blockIdx.x % kXcd], tot);
+        if (tot) b = atomicAdd(DIRECT_HEAVY ? A.heavy_n : &A.list_seg[B.id % kXcd], tot);
         s_base = b;
     }
     __syncthreads();
@@ -177,7 +192,7 @@ __global__ __launch_bounds__(256) void k_mc_screen(McArgs A)
         int32_t at = s_base + int32_t(__popcll(bal & ((uint64_t(1) << lane) - 1)));
         for (int w = 0; w < wv; ++w) at += s_w[w];
         if (DIRECT_HEAVY) A.heavy[at] = Deferred{int32_t(i), 0, 0.0, A.m[i]};
-        else A.list[seg_base(int(blockIdx.x % kXcd), gridDim.x) + at] = int32_t(i);
+        else A.list[seg_base(int(B.id % kXcd), B.n) + at] = int32_t(i);
     }
 }
 
@@ -308,23 +323,45 @@ __device__ inline int mc_particle(const McArgs& A, int64_t i)
 // wavefront w takes entries 64 w .. 64 w + 63 first, then further groups of
 // 64 from a counter until the list is exhausted (a wavefront with no first
 // group touches no counter)
+// the event pass's arguments: the sampling's and the screen's block count
+// (the list's segments are laid out by it)
+struct EventArgs {
+    McArgs A;
+    int64_t screen_blocks;
+};
+
 template <int KP2, bool F32>
-__global__ __launch_bounds__(256) void k_mc(McArgs A, int64_t screen_blocks)
+struct McEvents {
+    using Args = EventArgs;
+    static constexpr int kThreads = 256;
+    static __device__ void body(const Args& E, Blk B);
+};
+
+template <int KP2, bool F32>
+__global__ __launch_bounds__(256) void k_mc(EventArgs E)
 {
+    McEvents<KP2, F32>::body(E, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
+}
+
+template <int KP2, bool F32>
+__device__ void McEvents<KP2, F32>::body(const Args& E, Blk B)
+{
+    const McArgs& A = E.A;
+    const int64_t screen_blocks = E.screen_blocks;
     const int lane = threadIdx.x & 63;
     int32_t pre[kXcd + 1];
     pre[0] = 0;
 #pragma unroll
     for (int x = 0; x < kXcd; ++x) pre[x + 1] = pre[x] + A.list_seg[x];
     const int32_t nl = pre[kXcd];
-    const int32_t nw = int32_t(gridDim.x * (blockDim.x / kWave));
-    int32_t b = int32_t(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave;
+    const int32_t nw = int32_t(B.n * (blockDim.x / kWave));
+    int32_t b = int32_t(B.id * (blockDim.x / kWave) + threadIdx.x / kWave) * kWave;
     if (nl <= kSmallList) {
         // few particles with events (a cold disk): each takes a wavefront of
         // the wavefront-per-particle pass at once, where its pairs are
-        // evaluated side by side instead of one after another in a lane
-        const int32_t t = b + lane;
-        if (t < nl) {
+        // evaluated side by side instead of one after another in a lane.
+        // The grid strides over the list (a small grid covers less than it).
+        for (int32_t t = b + lane; t < nl; t += nw * kWave) {
             int x = 0;
 #pragma unroll
             for (int y = 1; y < kXcd; ++y) x += t >= pre[y] ? 1 : 0;
@@ -605,9 +642,32 @@ __global__ __launch_bounds__(256) void k_mc_heavy_batch(char* table, int32_t nbo
 // ---------------------------------------------------------------------------
 constexpr int kAuditGroups = 8;  // block-partial groups summed in parallel
 
-__global__ __launch_bounds__(kAuditGroups * kNBin) void k_audit(DevProblem P, const double* __restrict__ part, int nblk,
-                                                                gd_interval* iv, WsHeader* h)
+struct AuditArgs {
+    DevProblem P;
+    const double* part;
+    int nblk;
+    gd_interval* iv;
+    WsHeader* h;
+};
+
+struct Audit {
+    using Args = AuditArgs;
+    static constexpr int kThreads = kAuditGroups * kNBin;
+    static __device__ void body(const Args& A, Blk B);
+};
+
+__global__ __launch_bounds__(kAuditGroups * kNBin) void k_audit(AuditArgs A)
 {
+    Audit::body(A, Blk{0, 1});
+}
+
+__device__ void Audit::body(const Args& A, Blk)
+{
+    const DevProblem& P = A.P;
+    const double* __restrict__ part = A.part;
+    const int nblk = A.nblk;
+    gd_interval* iv = A.iv;
+    WsHeader* h = A.h;
     __shared__ double sh[kAuditGroups][kNBin], sl[kAuditGroups][kNBin];
     __shared__ int32_t s_grp[kNBin];
     const int t = threadIdx.x, b = t % kNBin, gq = t / kNBin;
@@ -736,12 +796,13 @@ static void launch_first(const McArgs& A, const gd_problem* p, hipStream_t st)
     }
     hipLaunchKernelGGL(k_mc_screen<false>, dim3(g), dim3(256), 0, st, A);
     const dim3 eg(kEventBlocks), eb(256);
+    const EventArgs E{A, int64_t(g)};
     if (p->rates_fp32) {
-        if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, true>), eg, eb, 0, st, A, int64_t(g));
-        else hipLaunchKernelGGL((k_mc<64, true>), eg, eb, 0, st, A, int64_t(g));
+        if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, true>), eg, eb, 0, st, E);
+        else hipLaunchKernelGGL((k_mc<64, true>), eg, eb, 0, st, E);
     } else {
-        if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, false>), eg, eb, 0, st, A, int64_t(g));
-        else hipLaunchKernelGGL((k_mc<64, false>), eg, eb, 0, st, A, int64_t(g));
+        if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, false>), eg, eb, 0, st, E);
+        else hipLaunchKernelGGL((k_mc<64, false>), eg, eb, 0, st, E);
     }
 }
 
@@ -768,7 +829,7 @@ int launch_audit(const gd_problem* p, const gd_particles* s, gd_interval* iv, vo
     prof_mark(GD_PROF_AUDIT, 0, st);
     launch_bin_reduce(1, s->m[s->cur], s->M, s->m[s->cur ^ 1], nullptr, p->n, part, ws, st);
     const double* folded = launch_part_fold(part, ws, L, st);
-    hipLaunchKernelGGL(k_audit, dim3(1), dim3(kAuditGroups * kNBin), 0, st, to_dev(p), folded, 1, iv, h);
+    hipLaunchKernelGGL(k_audit, dim3(1), dim3(kAuditGroups * kNBin), 0, st, AuditArgs{to_dev(p), folded, 1, iv, h});
     prof_mark(GD_PROF_AUDIT, 1, st);
     return 0;
 }
@@ -823,7 +884,7 @@ int launch_sample_group(const gd_problem* p, const gd_particles* s, const gd_nei
     prof_mark(GD_PROF_AUDIT, 0, st);
     launch_bin_reduce(1, s->m[s->cur] + lo, s->M + lo, s->m[s->cur ^ 1] + lo, nullptr, cnt, part, ws, st);
     const double* folded = launch_part_fold(part, ws, L, st);
-    hipLaunchKernelGGL(k_audit, dim3(1), dim3(kAuditGroups * kNBin), 0, st, P, folded, 1, iv, h);
+    hipLaunchKernelGGL(k_audit, dim3(1), dim3(kAuditGroups * kNBin), 0, st, AuditArgs{P, folded, 1, iv, h});
     prof_mark(GD_PROF_AUDIT, 1, st);
     return 0;
 }
@@ -835,11 +896,11 @@ size_t sample_table_bytes(int32_t nslot)
 
 int max_table_slots() { return kMaxTableSlots; }
 
-int launch_sample_table(void* table, int32_t nslot, int32_t k, int32_t rates_fp32, hipStream_t st)
+int launch_sample_table(void* table, int32_t nslot, int32_t k, int32_t rates_fp32, hipStream_t st, int32_t nblocks)
 {
     launch_fill_i32(static_cast<int32_t*>(table), 1, 0, st);
     char* tb = static_cast<char*>(table);
-    const dim3 g(kHeavyBlocks), b(256);
+    const dim3 g(nblocks > 0 ? nblocks : kHeavyBlocks), b(256);
     if (rates_fp32) {
         if (k <= 32) hipLaunchKernelGGL((k_mc_heavy_batch<32, true>), g, b, 0, st, tb, nslot);
         else if (k <= 64) hipLaunchKernelGGL((k_mc_heavy_batch<64, true>), g, b, 0, st, tb, nslot);
@@ -852,6 +913,73 @@ int launch_sample_table(void* table, int32_t nslot, int32_t k, int32_t rates_fp3
         else hipLaunchKernelGGL((k_mc_heavy_batch<256, false>), g, b, 0, st, tb, nslot);
     }
     return 0;
+}
+
+// Sampling and audit of every run as stages of one interval: clear the list
+// counters, the screen, the per-lane event pass (k <= 64), the pass over the
+// deferred particles of every run (one launch through a table of the runs'
+// arguments, shaped for the largest k), then the audit's bin sums, fold and
+// rule.  Draws take the interval index from each run's interval state.
+static void many_table_step(char* base, const ManyStep& s, hipStream_t st)
+{
+    launch_sample_table(base + s.tab, int32_t(s.a0), int32_t(s.a1 >> 1), int32_t(s.a1 & 1), st, int32_t(s.nblocks));
+}
+
+void many_sample(ManyBuilder& B, const std::vector<ManyRun>& R)
+{
+    const size_t nr = R.size();
+    std::vector<McArgs> ma(nr);
+    std::vector<ClearArgs> clr(nr);
+    std::vector<int64_t> one(nr, 1), nb(nr), scr_d(nr), scr_l(nr);
+    int kmax = 1, f32 = 0;
+    for (size_t r = 0; r < nr; ++r) {
+        const ManyRun& x = R[r];
+        ma[r] = mc_args(&x.p, &x.out, &x.nb, x.iv, x.lam_i, x.seed, 0u, true, x.n_events, nullptr, 0, x.ws, x.L);
+        clr[r] = ClearArgs{ma[r].list_seg, kXcd + 1, nullptr, 0};
+        nb[r] = cdiv(x.p.n, 256);
+        scr_d[r] = x.p.k > 64 ? nb[r] : 0;
+        scr_l[r] = x.p.k > 64 ? 0 : nb[r];
+        kmax = std::max(kmax, int(x.p.k));
+        f32 = x.p.rates_fp32 ? 1 : 0;
+    }
+    B.add<ClearCounters>(clr, one);
+    B.add<McScreen<true>>(ma, scr_d);
+    B.add<McScreen<false>>(ma, scr_l);
+    for (int cls = 0; cls < 2; ++cls) {
+        std::vector<EventArgs> ev(nr);
+        std::vector<int64_t> eb(nr, 0);
+        bool any = false;
+        for (size_t r = 0; r < nr; ++r) {
+            const int k = R[r].p.k;
+            ev[r] = EventArgs{ma[r], nb[r]};
+            if (k <= 64 && (k <= 32) == (cls == 0)) {
+                eb[r] = std::min<int64_t>(kEventBlocks, std::max<int64_t>(1, cdiv(R[r].p.n, B.tune.event_div)));
+                any = true;
+            }
+        }
+        if (!any) continue;
+        if (cls == 0) {
+            if (f32) B.add<McEvents<32, true>>(ev, eb);
+            else B.add<McEvents<32, false>>(ev, eb);
+        } else {
+            if (f32) B.add<McEvents<64, true>>(ev, eb);
+            else B.add<McEvents<64, false>>(ev, eb);
+        }
+    }
+    // the deferred particles of every run: a table (256-byte header, then
+    // the runs' arguments) in the arena
+    std::vector<char> table(kTableHeader + sizeof(McArgs) * nr, 0);
+    memcpy(table.data() + kTableHeader, ma.data(), sizeof(McArgs) * nr);
+    const size_t tab = B.put_vec(table);
+    ManyStep st{&many_table_step, tab, 0, 0, B.tune.heavy_blocks, int64_t(nr), int64_t(kmax) * 2 + f32};
+    B.steps.push_back(st);
+    many_audit_sums(B, R);
+    std::vector<AuditArgs> au(nr);
+    for (size_t r = 0; r < nr; ++r) {
+        const ManyRun& x = R[r];
+        au[r] = AuditArgs{to_dev(&x.p), at<double>(x.ws, x.L.red), 1, x.iv, at<WsHeader>(x.ws, x.L.hdr)};
+    }
+    B.add<Audit>(au, one);
 }
 
 }  // namespace gd

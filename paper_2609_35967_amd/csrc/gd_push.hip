@@ -22,14 +22,36 @@
 
 namespace gd {
 
-__global__ __launch_bounds__(256) void k_push_local(int64_t n, double* __restrict__ z, double* __restrict__ vz,
-                                                    const double* __restrict__ st, const double* __restrict__ M,
-                                                    const gd_interval* __restrict__ iv, double dt_host)
+struct LocalPushArgs {
+    int64_t n;
+    double* z;
+    double* vz;
+    const double* st;
+    const double* M;
+    const gd_interval* iv;
+    double dt_host;
+};
+
+struct PushLocal {
+    using Args = LocalPushArgs;
+    static constexpr int kThreads = 256;
+    static __device__ void body(const Args& A, Blk B);
+};
+
+__global__ __launch_bounds__(256) void k_push_local(LocalPushArgs A)
 {
-    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (i >= n) return;
-    if (!(M[i] > 0.0)) return;
-    const double dt = iv ? iv->dt_exe : dt_host;
+    PushLocal::body(A, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
+}
+
+__device__ void PushLocal::body(const Args& A, Blk B)
+{
+    double* __restrict__ z = A.z;
+    double* __restrict__ vz = A.vz;
+    const double* __restrict__ st = A.st;
+    const int64_t i = B.id * int64_t(blockDim.x) + threadIdx.x;
+    if (i >= A.n) return;
+    if (!(A.M[i] > 0.0)) return;
+    const double dt = A.iv ? A.iv->dt_exe : A.dt_host;
     const double h = 0.5 * dt;
     const double v0 = vz[i];
     const double zs = z[i] + v0 * h;
@@ -76,9 +98,20 @@ struct PushArgs {
     double dt_host;
 };
 
+struct PushGlobal {
+    using Args = PushArgs;
+    static constexpr int kThreads = 256;
+    static __device__ void body(const Args& A, Blk B);
+};
+
 __global__ __launch_bounds__(256) void k_push_global(PushArgs A)
 {
-    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    PushGlobal::body(A, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
+}
+
+__device__ void PushGlobal::body(const Args& A, Blk B)
+{
+    const int64_t i = B.id * int64_t(blockDim.x) + threadIdx.x;
     if (i >= A.P.n) return;
     if (!(A.M[i] > 0.0)) return;
     const DevProblem& P = A.P;
@@ -129,6 +162,26 @@ __global__ __launch_bounds__(256) void k_push_global(PushArgs A)
     if (ri < P.r_in || ri > P.r_out) A.M[i] = 0.0;
 }
 
+static PushArgs push_args(const gd_problem* p, const gd_particles* s, const double* m, const gd_interval* iv, double dt)
+{
+    PushArgs A{};
+    A.P = to_dev(p);
+    A.r = s->r;
+    A.th = s->th;
+    A.ph = s->ph;
+    A.vr = s->vr;
+    A.lth = s->lth;
+    A.lph = s->lph;
+    A.x = s->x;
+    A.y = s->y;
+    A.z = s->z;
+    A.M = s->M;
+    A.m = m;
+    A.iv = iv;
+    A.dt_host = dt;
+    return A;
+}
+
 int launch_push(const gd_problem* p, const gd_particles* s, const gd_interval* iv, double dt, void* ws,
                 const Layout& L, hipStream_t st)
 {
@@ -138,27 +191,40 @@ int launch_push(const gd_problem* p, const gd_particles* s, const gd_interval* i
     const int g = int((n + 255) / 256);
     prof_mark(GD_PROF_PUSH, 0, st);
     if (p->push == GD_PUSH_LOCAL) {
-        hipLaunchKernelGGL(k_push_local, dim3(g), dim3(256), 0, st, n, s->z, s->vz, s->st_mid, s->M, iv, dt);
+        hipLaunchKernelGGL(k_push_local, dim3(g), dim3(256), 0, st,
+                           LocalPushArgs{n, s->z, s->vz, s->st_mid, s->M, iv, dt});
     } else if (p->push == GD_PUSH_GLOBAL) {
-        PushArgs A{};
-        A.P = to_dev(p);
-        A.r = s->r;
-        A.th = s->th;
-        A.ph = s->ph;
-        A.vr = s->vr;
-        A.lth = s->lth;
-        A.lph = s->lph;
-        A.x = s->x;
-        A.y = s->y;
-        A.z = s->z;
-        A.M = s->M;
-        A.m = s->m[s->cur];
-        A.iv = iv;
-        A.dt_host = dt;
-        hipLaunchKernelGGL(k_push_global, dim3(g), dim3(256), 0, st, A);
+        hipLaunchKernelGGL(k_push_global, dim3(g), dim3(256), 0, st, push_args(p, s, s->m[s->cur], iv, dt));
     }
     prof_mark(GD_PROF_PUSH, 1, st);
     return 0;
+}
+
+// The push of every run that has one, over its own dt_exe, after sampling:
+// the new masses are in m[cur ^ 1] of the interval's state.
+void many_push(ManyBuilder& B, const std::vector<ManyRun>& R)
+{
+    const size_t nr = R.size();
+    std::vector<LocalPushArgs> lo(nr);
+    std::vector<PushArgs> gl(nr);
+    std::vector<int64_t> nl(nr, 0), ng(nr, 0);
+    bool any_l = false, any_g = false;
+    for (size_t r = 0; r < nr; ++r) {
+        const ManyRun& x = R[r];
+        const gd_particles* s = &x.out;
+        const int64_t nb = cdiv(x.p.n, 256);
+        lo[r] = LocalPushArgs{x.p.n, s->z, s->vz, s->st_mid, s->M, x.iv, 0.0};
+        gl[r] = push_args(&x.p, s, s->m[s->cur ^ 1], x.iv, 0.0);
+        if (x.p.push == GD_PUSH_LOCAL) {
+            nl[r] = nb;
+            any_l = true;
+        } else if (x.p.push == GD_PUSH_GLOBAL) {
+            ng[r] = nb;
+            any_g = true;
+        }
+    }
+    if (any_l) B.add<PushLocal>(lo, nl);
+    if (any_g) B.add<PushGlobal>(gl, ng);
 }
 
 }  // namespace gd

@@ -13,18 +13,36 @@
 #include "gd_internal.hpp"
 #include "gd_physics.hpp"
 
+#include <algorithm>
+
 namespace gd {
 
 // packed snapshot of every particle: (m_j, s_j, N_j = M_j / m_j, 1 / m_j),
 // one 32-byte record per neighbour gather
-__global__ __launch_bounds__(256) void k_snapshot(DevProblem P, const double* __restrict__ m,
-                                                  const double* __restrict__ M, int64_t n, double4* __restrict__ snap)
+struct SnapArgs {
+    DevProblem P;
+    const double* m;
+    const double* M;
+    int64_t n;
+    double4* snap;
+};
+
+struct Snapshot {
+    using Args = SnapArgs;
+    static constexpr int kThreads = 256;
+    static __device__ void body(const Args& A, Blk B)
+    {
+        const int64_t i = B.id * int64_t(blockDim.x) + threadIdx.x;
+        if (i >= A.n) return;
+        const double mi = A.m[i];
+        const bool phys = A.P.kernel == GD_KERNEL_PHYSICAL;
+        A.snap[i] = make_double4(mi, phys ? grain_size(A.P, mi) : 0.0, phys ? A.M[i] / mi : 0.0, 1.0 / mi);
+    }
+};
+
+__global__ __launch_bounds__(256) void k_snapshot(SnapArgs A)
 {
-    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (i >= n) return;
-    const double mi = m[i];
-    const bool phys = P.kernel == GD_KERNEL_PHYSICAL;
-    snap[i] = make_double4(mi, phys ? grain_size(P, mi) : 0.0, phys ? M[i] / mi : 0.0, 1.0 / mi);
+    Snapshot::body(A, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
 }
 
 struct RatesArgs {
@@ -59,9 +77,20 @@ __device__ inline void gather_neighbours(const int32_t* row, int s0, int cmax, i
     for (int t = 0; t < kGather; ++t) rec[t] = (jj[t] >= 0 && jj[t] < n) ? snap[jj[t]] : make_double4(0.0, 0.0, 0.0, 0.0);
 }
 
+struct Rates {
+    using Args = RatesArgs;
+    static constexpr int kThreads = 256;
+    static __device__ void body(const Args& A, Blk B);
+};
+
 __global__ __launch_bounds__(256) void k_rates(RatesArgs A)
 {
-    const int64_t i = xcd_block() * int64_t(blockDim.x) + threadIdx.x;
+    Rates::body(A, Blk{xcd_block(), int64_t(gridDim.x)});
+}
+
+__device__ void Rates::body(const Args& A, Blk B)
+{
+    const int64_t i = B.id * int64_t(blockDim.x) + threadIdx.x;
     if (i >= A.P.n) return;
     const int k = A.P.k;
     const bool phys = A.P.kernel == GD_KERNEL_PHYSICAL;
@@ -112,9 +141,20 @@ __global__ __launch_bounds__(256) void k_rates(RatesArgs A)
 
 // The same pass with the single-precision pair form (gd_problem.rates_fp32):
 // float pair terms, summed in FP64 in slot order.
+struct RatesF32 {
+    using Args = RatesArgs;
+    static constexpr int kThreads = 256;
+    static __device__ void body(const Args& A, Blk B);
+};
+
 __global__ __launch_bounds__(256) void k_rates_f32(RatesArgs A)
 {
-    const int64_t i = xcd_block() * int64_t(blockDim.x) + threadIdx.x;
+    RatesF32::body(A, Blk{xcd_block(), int64_t(gridDim.x)});
+}
+
+__device__ void RatesF32::body(const Args& A, Blk B)
+{
+    const int64_t i = B.id * int64_t(blockDim.x) + threadIdx.x;
     if (i >= A.P.n) return;
     const int k = A.P.k;
     const bool phys = A.P.kernel == GD_KERNEL_PHYSICAL;
@@ -176,18 +216,44 @@ __global__ __launch_bounds__(256) void k_rates_f32(RatesArgs A)
 // part[(blk * kNBin + bin) * 8 + f]: f = 0 count, (1,2) (3,4) (5,6) dd values.
 constexpr int kRedWaves = 8;  // wavefronts per bin-reduction block
 
-__global__ __launch_bounds__(kRedWaves * kWave) void k_bin_reduce(int mode, const double* __restrict__ msnap,
-                                                                   const double* __restrict__ M,
-                                                                   const double* __restrict__ va,
-                                                                   const double* __restrict__ vb, int64_t n,
-                                                                   double* __restrict__ part, void* ws)
+struct BinArgs {
+    int mode;
+    const double* msnap;
+    const double* M;
+    const double* va;
+    const double* vb;
+    int64_t n;
+    double* part;
+    void* ws;
+};
+
+struct BinReduce {
+    using Args = BinArgs;
+    static constexpr int kThreads = kRedWaves * kWave;
+    static __device__ void body(const Args& A, Blk B);
+};
+
+__global__ __launch_bounds__(kRedWaves * kWave) void k_bin_reduce(BinArgs A)
 {
+    BinReduce::body(A, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
+}
+
+__device__ void BinReduce::body(const Args& A, Blk B)
+{
+    const int mode = A.mode;
+    const double* __restrict__ msnap = A.msnap;
+    const double* __restrict__ M = A.M;
+    const double* __restrict__ va = A.va;
+    const double* __restrict__ vb = A.vb;
+    const int64_t n = A.n;
+    double* __restrict__ part = A.part;
+    void* ws = A.ws;
     __shared__ double acc[kRedWaves][kNBin][7];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     for (int e = t; e < kRedWaves * kNBin * 7; e += kRedWaves * kWave) (&acc[0][0][0])[e] = 0.0;
     __syncthreads();
-    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-    const int64_t beg = blockIdx.x * chunk;
+    const int64_t chunk = (n + B.n - 1) / B.n;
+    const int64_t beg = B.id * chunk;
     const int64_t end = beg + chunk < n ? beg + chunk : n;
     bool range_bad = false;
     // wavefront w takes the rows of 64 slots w, w + kRedWaves, ... of the
@@ -259,7 +325,7 @@ __global__ __launch_bounds__(kRedWaves * kWave) void k_bin_reduce(int mode, cons
     if (__ballot(range_bad) && lane == 0) set_status(ws, GD_DEV_MASS_RANGE);
     __syncthreads();
     for (int bin = t; bin < kNBin; bin += kRedWaves * kWave) {
-        double* out = part + (int64_t(blockIdx.x) * kNBin + bin) * 8;
+        double* out = part + (B.id * kNBin + bin) * 8;
         double cnt = 0.0;
         dd x0{0.0, 0.0}, x1{0.0, 0.0}, x2{0.0, 0.0};
         for (int ww = 0; ww < kRedWaves; ++ww) {
@@ -287,9 +353,33 @@ __global__ __launch_bounds__(kRedWaves * kWave) void k_bin_reduce(int mode, cons
 // dt_exe = dt_coll 2^-n, the largest aligned dyadic fraction <= dt_req.
 constexpr int kPlanGroups = 8;  // block-partial groups summed in parallel
 
-__global__ __launch_bounds__(kPlanGroups * kNBin) void k_plan(DevProblem P, const double* __restrict__ part, int nblk,
-                                                              gd_interval* iv, WsHeader* h, void* ws)
+struct PlanArgs {
+    DevProblem P;
+    const double* part;
+    int nblk;
+    gd_interval* iv;
+    WsHeader* h;
+    void* ws;
+};
+
+struct Plan {
+    using Args = PlanArgs;
+    static constexpr int kThreads = kPlanGroups * kNBin;
+    static __device__ void body(const Args& A, Blk B);
+};
+
+__global__ __launch_bounds__(kPlanGroups * kNBin) void k_plan(PlanArgs A)
 {
+    Plan::body(A, Blk{0, 1});
+}
+
+__device__ void Plan::body(const Args& A, Blk)
+{
+    const DevProblem& P = A.P;
+    const double* __restrict__ part = A.part;
+    const int nblk = A.nblk;
+    gd_interval* iv = A.iv;
+    WsHeader* h = A.h;
     __shared__ double pc[kPlanGroups][kNBin];
     __shared__ double ph[kPlanGroups][3][kNBin], pl[kPlanGroups][3][kNBin];
     __shared__ int32_t s_grp[kNBin];
@@ -423,17 +513,36 @@ __global__ __launch_bounds__(kPlanGroups * kNBin) void k_plan(DevProblem P, cons
 // The kRedBlocks block partials of each bin summed as a tree, one block per
 // bin, into one row per bin (same layout as a block's partials): the plan and
 // the audit then read a single row instead of looping over the blocks.
-__global__ __launch_bounds__(kRedBlocks) void k_part_fold(const double* __restrict__ part, double* __restrict__ out)
+struct FoldArgs {
+    const double* part;
+    double* out;
+    int nblk;  // partial rows written (the rest count as zero)
+};
+
+struct PartFold {
+    using Args = FoldArgs;
+    static constexpr int kThreads = kRedBlocks;
+    static __device__ void body(const Args& A, Blk B);
+};
+
+__global__ __launch_bounds__(kRedBlocks) void k_part_fold(FoldArgs A)
+{
+    PartFold::body(A, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
+}
+
+__device__ void PartFold::body(const Args& A, Blk B)
 {
     __shared__ double c[kRedBlocks];
     __shared__ double hi[3][kRedBlocks], lo[3][kRedBlocks];
-    const int b = blockIdx.x, t = threadIdx.x;
-    const double* a = part + (int64_t(t) * kNBin + b) * 8;
-    c[t] = a[0];
+    const int b = int(B.id), t = threadIdx.x;
+    double* __restrict__ out = A.out;
+    const bool have = t < A.nblk;
+    const double* a = A.part + (int64_t(have ? t : 0) * kNBin + b) * 8;
+    c[t] = have ? a[0] : 0.0;
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
-        hi[v][t] = a[1 + 2 * v];
-        lo[v][t] = a[2 + 2 * v];
+        hi[v][t] = have ? a[1 + 2 * v] : 0.0;
+        lo[v][t] = have ? a[2 + 2 * v] : 0.0;
     }
     __syncthreads();
     for (int w = kRedBlocks / 2; w > 0; w >>= 1) {
@@ -467,7 +576,7 @@ static_assert(kNBin * 8 <= 8 * kRedBlocks, "the folded rows fit the reduction sc
 const double* launch_part_fold(const double* part, void* ws, const Layout& L, hipStream_t st)
 {
     double* out = at<double>(ws, L.red);
-    hipLaunchKernelGGL(k_part_fold, dim3(kNBin), dim3(kRedBlocks), 0, st, part, out);
+    hipLaunchKernelGGL(k_part_fold, dim3(kNBin), dim3(kRedBlocks), 0, st, FoldArgs{part, out, kRedBlocks});
     return out;
 }
 
@@ -475,7 +584,8 @@ const double* launch_part_fold(const double* part, void* ws, const Layout& L, hi
 void launch_bin_reduce(int mode, const double* msnap, const double* M, const double* va, const double* vb, int64_t n,
                        double* part, void* ws, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bin_reduce, dim3(kRedBlocks), dim3(kRedWaves * kWave), 0, st, mode, msnap, M, va, vb, n, part, ws);
+    hipLaunchKernelGGL(k_bin_reduce, dim3(kRedBlocks), dim3(kRedWaves * kWave), 0, st,
+                       BinArgs{mode, msnap, M, va, vb, n, part, ws});
 }
 
 int launch_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv, double* lam_i,
@@ -487,7 +597,7 @@ int launch_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors*
     const double* m = s->m[s->cur];
     double4* snap = at<double4>(ws, L.snap);
     prof_mark(GD_PROF_RATES, 0, st);
-    hipLaunchKernelGGL(k_snapshot, dim3(g), dim3(256), 0, st, P, m, s->M, n, snap);
+    hipLaunchKernelGGL(k_snapshot, dim3(g), dim3(256), 0, st, SnapArgs{P, m, s->M, n, snap});
     RatesArgs A{};
     A.P = P;
     A.nbr = nb->nbr;
@@ -510,7 +620,8 @@ int launch_rates(const gd_problem* p, const gd_particles* s, const gd_neighbors*
     double* part = at<double>(ws, L.part);
     launch_bin_reduce(0, m, s->M, A.a, A.b, n, part, ws, st);
     const double* folded = launch_part_fold(part, ws, L, st);
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanGroups * kNBin), 0, st, P, folded, 1, iv, at<WsHeader>(ws, L.hdr), ws);
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanGroups * kNBin), 0, st,
+                       PlanArgs{P, folded, 1, iv, at<WsHeader>(ws, L.hdr), ws});
     prof_mark(GD_PROF_RATES, 1, st);
     return 0;
 }
@@ -552,7 +663,8 @@ int launch_rates_group(const gd_problem* p, const gd_particles* s, const gd_neig
     const double* m = s->m[s->cur];
     double4* snap = at<double4>(ws, L.snap);
     prof_mark(GD_PROF_RATES, 0, st);
-    if (snapshot) hipLaunchKernelGGL(k_snapshot, dim3(int((n + 255) / 256)), dim3(256), 0, st, P, m, s->M, n, snap);
+    if (snapshot)
+        hipLaunchKernelGGL(k_snapshot, dim3(int((n + 255) / 256)), dim3(256), 0, st, SnapArgs{P, m, s->M, n, snap});
     P.n = cnt;
     RatesArgs A{};
     A.P = P;
@@ -579,11 +691,90 @@ int launch_rates_group(const gd_problem* p, const gd_particles* s, const gd_neig
     double* part = at<double>(ws, L.part);
     launch_bin_reduce(0, m + lo, s->M + lo, A.a, A.b, cnt, part, ws, st);
     const double* folded = launch_part_fold(part, ws, L, st);
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanGroups * kNBin), 0, st, P, folded, 1, iv, at<WsHeader>(ws, L.hdr), ws);
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanGroups * kNBin), 0, st,
+                       PlanArgs{P, folded, 1, iv, at<WsHeader>(ws, L.hdr), ws});
     hipLaunchKernelGGL(k_group_clamp, dim3(1), dim3(64), 0, st, iv, int(group), int(n_groups),
                        reinterpret_cast<const unsigned long long*>(rows), sched);
     prof_mark(GD_PROF_RATES, 1, st);
     return 0;
+}
+
+// Rates and plan of every run as stages of one interval: snapshot, rates,
+// the bin sums over n / red_div blocks per run (at most kRedBlocks), their
+// fold and the plan.
+void many_rates(ManyBuilder& B, const std::vector<ManyRun>& R)
+{
+    const size_t nr = R.size();
+    std::vector<SnapArgs> sn(nr);
+    std::vector<RatesArgs> ra(nr);
+    std::vector<BinArgs> bi(nr);
+    std::vector<FoldArgs> fo(nr);
+    std::vector<PlanArgs> pl(nr);
+    std::vector<int64_t> nb(nr), nred(nr), nbin(nr, kNBin), one(nr, 1), f64(nr), f32(nr);
+    for (size_t r = 0; r < nr; ++r) {
+        const ManyRun& x = R[r];
+        const gd_problem* p = &x.p;
+        const gd_particles* s = &x.out;
+        const DevProblem P = to_dev(p);
+        const int64_t n = p->n;
+        const double* m = s->m[s->cur];
+        double4* snap = at<double4>(x.ws, x.L.snap);
+        sn[r] = SnapArgs{P, m, s->M, n, snap};
+        RatesArgs& A = ra[r];
+        A = RatesArgs{};
+        A.P = P;
+        A.nbr = x.nb.nbr;
+        A.cnt = x.nb.cnt;
+        A.dmax = x.nb.dmax;
+        A.m = m;
+        A.x = s->x;
+        A.y = s->y;
+        A.z = s->z;
+        A.snap = snap;
+        A.snap_own = snap;
+        A.lam = x.lam_i;
+        A.lam_pair = nullptr;
+        A.a = at<double>(x.ws, x.L.a);
+        A.b = at<double>(x.ws, x.L.b);
+        A.ws = x.ws;
+        A.n_all = n;
+        nb[r] = cdiv(n, 256);
+        f64[r] = p->rates_fp32 ? 0 : nb[r];
+        f32[r] = p->rates_fp32 ? nb[r] : 0;
+        nred[r] = std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, cdiv(n, B.tune.red_div)));
+        double* part = at<double>(x.ws, x.L.part);
+        double* folded = at<double>(x.ws, x.L.red);
+        bi[r] = BinArgs{0, m, s->M, A.a, A.b, n, part, x.ws};
+        fo[r] = FoldArgs{part, folded, int(nred[r])};
+        pl[r] = PlanArgs{P, folded, 1, x.iv, at<WsHeader>(x.ws, x.L.hdr), x.ws};
+    }
+    B.add<Snapshot>(sn, nb);
+    B.add<Rates>(ra, f64);
+    B.add<RatesF32>(ra, f32);
+    B.add<BinReduce>(bi, nred);
+    B.add<PartFold>(fo, nbin);
+    B.add<Plan>(pl, one);
+}
+
+// the audit's bin sums and their fold (mode 1 over m_snap, M, m_new), for
+// the sampling stage's audit
+void many_audit_sums(ManyBuilder& B, const std::vector<ManyRun>& R)
+{
+    const size_t nr = R.size();
+    std::vector<BinArgs> bi(nr);
+    std::vector<FoldArgs> fo(nr);
+    std::vector<int64_t> nred(nr), nbin(nr, kNBin);
+    for (size_t r = 0; r < nr; ++r) {
+        const ManyRun& x = R[r];
+        const gd_particles* s = &x.out;
+        const int64_t n = x.p.n;
+        nred[r] = std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, cdiv(n, B.tune.red_div)));
+        double* part = at<double>(x.ws, x.L.part);
+        bi[r] = BinArgs{1, s->m[s->cur], s->M, s->m[s->cur ^ 1], nullptr, n, part, x.ws};
+        fo[r] = FoldArgs{part, at<double>(x.ws, x.L.red), int(nred[r])};
+    }
+    B.add<BinReduce>(bi, nred);
+    B.add<PartFold>(fo, nbin);
 }
 
 }  // namespace gd

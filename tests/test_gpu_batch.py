@@ -112,3 +112,79 @@ def test_table_sampling_matches_alone():
     for b, e in enumerate(engines):
         _same(_snap(e), ref[b][0], f"table box {b}")
         assert e.status() == 0
+
+
+def test_batch_many_matches_alone():
+    # one launch per stage over every box (gd_many_interval), default shapes:
+    # every box equals the same box stepped alone, after every pair of intervals
+    load()
+    boxes = _boxes()
+    ref = _alone(boxes, 3)
+    bb = BoxBatch(boxes)
+    for r in range(3):
+        bb.step_many()
+        bb.step_many()
+        torch.cuda.synchronize()
+        for b, e in enumerate(bb.engines):
+            _same(_snap(e), ref[b][r], f"many round {r} box {b}")
+            assert e.status() == 0
+        _say("many round", r, "matches")
+
+
+def _mixed():
+    # runs of different kinds in one many-run form: dimensionless constant
+    # kernel (periodic), additive column with the local push, a small disk
+    # annulus with the global push (not periodic), and k = 48 and k = 96 boxes
+    out = []
+    p = workloads.const_box_params(3000)
+    out.append((p, workloads.const_box(31, 3000), 31))
+    p = workloads.additive_col_params(2500)
+    out.append((p, workloads.additive_col(32, 2500), 32))
+    p = workloads.disk3d_params(4000)
+    out.append((p, workloads.disk3d(33, 4000, warm=True, params=p), 33))
+    for k, sd in ((48, 34), (96, 35)):
+        p = workloads.local_box_params(2000, alpha=3e-3, v_frag=300.0, k=k)
+        out.append((p, workloads.local_box(sd, 2000, p), sd))
+    return out
+
+
+def test_many_mixed_runs_match_alone():
+    load()
+    runs = _mixed()
+    ref = _alone(runs, 2)
+    bb = BoxBatch(runs)
+    for r in range(2):
+        bb.step_many()
+        bb.step_many()
+        torch.cuda.synchronize()
+        for b, e in enumerate(bb.engines):
+            got = _snap(e)
+            _same(got, ref[b][r], f"mixed round {r} run {b}")
+            for key in ("r", "th", "ph", "vr", "lth", "lph", "vz"):
+                if key in got:
+                    assert np.array_equal(got[key], ref[b][r][key]), f"mixed round {r} run {b}: {key} differs"
+            assert e.status() & ~0x4 == 0
+        _say("mixed round", r, "matches")
+
+
+def test_many_tuned_shapes_do_not_change_results():
+    # the autotuner's trials run from a saved state; whatever it picks, the
+    # next intervals equal those of the default shapes
+    load()
+    boxes = _boxes()[:4]
+    ref = _alone(boxes, 2)
+    bb = BoxBatch(boxes)
+    bb.step_many()
+    bb.step_many()
+    torch.cuda.synchronize()
+    rec = bb.tune(intervals=1, space=dict(knn_tile=(1, 0), heavy_blocks=(64, 768), event_div=(128, 4096),
+                                          red_div=(256, 1 << 20)))
+    assert len(rec["trials"]) >= 5 and set(rec["choice"]) >= {"knn_tile", "heavy_blocks"}
+    for b, e in enumerate(bb.engines):  # tuning left the state where it was
+        _same(_snap(e), ref[b][0], f"after tuning box {b}")
+    bb.step_many()
+    bb.step_many()
+    torch.cuda.synchronize()
+    for b, e in enumerate(bb.engines):
+        _same(_snap(e), ref[b][1], f"tuned box {b}")
+    _say("tuning", rec["choice"], rec["ms_per_interval"])
