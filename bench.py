@@ -556,7 +556,7 @@ def serve_bench(args):
     budget; then the same runs one after another in the plain single-run form."""
     import torch
     from paper_2609_35967_amd import Engine, load
-    from paper_2609_35967_amd.serve import Run, Server, latency_percentiles
+    from paper_2609_35967_amd.serve import Run, Server, drive, gap_percentiles, latency_percentiles
 
     load()
     torch.cuda.set_device(0)
@@ -577,41 +577,35 @@ def serve_bench(args):
     total = sum(len(r.state["x"]) for r in runs) * intervals
     print(f"[bench] {len(runs)} runs, {total} particle-intervals; serving", file=sys.stderr, flush=True)
     # warm the kernels outside the measurement
-    w = Engine(runs[0].params, runs[0].state, seed=0)
+    from paper_2609_35967_amd.binding import ManyRuns
+    w = Engine(runs[0].params, runs[0].state, seed=0, device_interval=True)
     w.step()
+    m = ManyRuns([w])
+    m.interval()
     torch.cuda.synchronize()
-    del w
-    srv = Server(budget_bytes=200e9, streams=args.streams, keep_results=False)
-    pending = list(runs)
+    m.close()
+    del w, m
+    srv = Server(budget_bytes=200e9, keep_results=False)
     t0 = time.perf_counter()
-    rounds = 0
-    while pending or not srv.idle():
-        now = time.perf_counter() - t0
-        while pending and pending[0].arrival <= now:
-            srv.submit(pending.pop(0))
-        srv.admit()
-        if srv.active:
-            srv.round()
-            rounds += 1
-        elif pending:
-            time.sleep(max(0.0, pending[0].arrival - (time.perf_counter() - t0)))
+    drive(srv, [(r.arrival, r) for r in runs], lambda: time.perf_counter() - t0)
     wall_s = time.perf_counter() - t0
+    rounds = srv.rounds
+    srv.close()
     p50, p99 = latency_percentiles(srv.finished)
-    print(f"[bench] served in {wall_s:.2f} s, {rounds} rounds; saturated pass", file=sys.stderr, flush=True)
+    g50, g99 = gap_percentiles(srv.finished)
+    print(f"[bench] served in {wall_s:.2f} s, {rounds} tier rounds, p50/p99 {p50:.3f}/{p99:.3f} ms, "
+          f"gap p50/p99 {g50:.3f}/{g99:.3f} ms; saturated pass", file=sys.stderr, flush=True)
     # capacity: the same runs all submitted at once
-    sat = Server(budget_bytes=200e9, streams=args.streams, keep_results=False)
+    sat = Server(budget_bytes=200e9, keep_results=False)
     for r in runs:
-        r.done, r.latencies_ms, r.engine = 0, [], None
-        sat.submit(r)
+        r.done, r.finished, r.latencies_ms, r.ends_ms, r.engine = 0, 0, [], [], None
     torch.cuda.synchronize()
     ts0 = time.perf_counter()
-    srounds = 0
-    while not sat.idle():
-        sat.admit()
-        sat.round()
-        srounds += 1
+    drive(sat, [(0.0, r) for r in runs], lambda: 1.0)
     sat_s = time.perf_counter() - ts0
-    print(f"[bench] saturated {sat_s:.2f} s, {srounds} rounds; plain form", file=sys.stderr, flush=True)
+    srounds = sat.rounds
+    sat.close()
+    print(f"[bench] saturated {sat_s:.2f} s, {srounds} tier rounds; plain form", file=sys.stderr, flush=True)
     # the same runs in the plain single-run form, one after another
     plain_lat = []
     torch.cuda.synchronize()
@@ -635,14 +629,18 @@ def serve_bench(args):
                              "(Poisson), N log-uniform 2^12..2^20, alpha log-uniform 1e-4..1e-2, v_frag uniform "
                              f"1..10 m/s, {intervals} intervals each, 200 GB budget, k=32",
                     n_runs=len(runs), particle_intervals=total,
-                    form=f"served: continuous batching, {args.streams} streams, one deferred-sampling launch per round"),
-        wall_s=round(wall_s, 3), rounds=rounds,
+                    form="served: size tiers (N <= 2^14, <= 2^17, larger) on a stream each, not in lock-step; "
+                         "a tier round is one launch per stage over a group of its runs (at most 2^20 particles, "
+                         "gd_many_interval), two rounds queued"),
+        wall_s=round(wall_s, 3), tier_rounds=rounds,
         p50_ms=round(p50, 3), p99_ms=round(p99, 3),
+        latency="GPU time of the round that holds the interval",
+        gap_p50_ms=round(g50, 3), gap_p99_ms=round(g99, 3),
         plain=dict(value=round(total / plain_s, 1), wall_s=round(plain_s, 3),
                    p50_ms=round(float(np.percentile(plain_lat, 50)), 3),
                    p99_ms=round(float(np.percentile(plain_lat, 99)), 3),
                    form="the same runs one after another, plain single-run form"),
-        saturated=dict(value=round(total / sat_s, 1), wall_s=round(sat_s, 3), rounds=srounds,
+        saturated=dict(value=round(total / sat_s, 1), wall_s=round(sat_s, 3), tier_rounds=srounds,
                        form="the same runs all submitted at once"),
         saturated_over_plain=round(plain_s / sat_s, 3),
     )

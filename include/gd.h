@@ -466,6 +466,16 @@ typedef enum gd_prof_kernel {
  * events stay owned by the caller. */
 int32_t gd_profile_events(int32_t which, void* before, void* after);
 
+/* A stream restricted to a subset of the current device's compute units
+ * (hipExtStreamCreateWithCUMask), default priority: bit i of mask[i / 32]
+ * selects CU i; words beyond the device's CU count are ignored.  For callers
+ * that keep latency-bound launches apart from large ones (the serving tiers:
+ * a small run's launches then never wait for CU slots behind a large run's
+ * workgroups).  GD_E_INVALID_ARG for a NULL or empty mask, GD_E_HIP when the
+ * runtime refuses it.  gd_stream_destroy releases it. */
+int32_t gd_stream_create_cu_mask(const uint32_t* mask, int32_t mask_words, void** stream);
+int32_t gd_stream_destroy(void* stream);
+
 /* Copy the device status word of the workspace to *out (bits GD_DEV_*), then
  * clear it.  Synchronises `stream`. */
 int32_t gd_status_read(void* ws, void* stream, int32_t* out);

@@ -81,7 +81,8 @@ EXPORTS = ("gd_workspace_size", "gd_workspace_init", "gd_interval_init", "gd_bui
            "gd_sample_table_size", "gd_sample_collisions_deferred", "gd_sample_table_run", "gd_sample_audit",
            "gd_reshuffle_neighbors", "gd_diffuse", "gd_group_interactions", "gd_collision_rates_group",
            "gd_sample_collisions_group", "gd_publish_group", "gd_reshuffle_neighbors_static",
-           "gd_many_create", "gd_many_interval", "gd_many_parity", "gd_many_destroy")
+           "gd_many_create", "gd_many_interval", "gd_many_parity", "gd_many_destroy", "gd_stream_create_cu_mask",
+           "gd_stream_destroy")
 PROF = {"sort": 0, "tree": 1, "knn_query": 2, "rates": 3, "mc": 4, "audit": 5, "push": 6, "diffuse": 7}
 GD_INTERVAL_ON_DEVICE = (1 << 64) - 1
 
@@ -137,6 +138,8 @@ def load(path: str | None = None):
     L.gd_many_interval.argtypes = [vp, vp]
     L.gd_many_parity.argtypes = [vp, C.POINTER(C.c_int32)]
     L.gd_many_destroy.argtypes = [vp]
+    L.gd_stream_create_cu_mask.argtypes = [C.POINTER(C.c_uint32), C.c_int32, C.POINTER(vp)]
+    L.gd_stream_destroy.argtypes = [vp]
     L.gd_status_read.argtypes = [vp, vp, C.POINTER(C.c_int32)]
     L.gd_profile_events.argtypes = [C.c_int32, vp, vp]
     L.gd_last_error.restype = C.c_char_p
@@ -146,7 +149,8 @@ def load(path: str | None = None):
                  "gd_sample_collisions_deferred", "gd_sample_table_run", "gd_sample_audit",
                  "gd_reshuffle_neighbors", "gd_diffuse", "gd_group_interactions", "gd_collision_rates_group",
                  "gd_sample_collisions_group", "gd_publish_group", "gd_reshuffle_neighbors_static",
-                 "gd_many_create", "gd_many_interval", "gd_many_parity", "gd_many_destroy"):
+                 "gd_many_create", "gd_many_interval", "gd_many_parity", "gd_many_destroy",
+                 "gd_stream_create_cu_mask", "gd_stream_destroy"):
         getattr(L, name).restype = C.c_int32
     if path is None:
         _lib = L
@@ -645,3 +649,26 @@ class ManyRuns:
             self.close()
         except Exception:
             pass
+
+
+class CuStream:
+    """A torch stream over a library stream restricted to the compute units
+    [first, first + count) (gd_stream_create_cu_mask); `stream` is the torch
+    object to launch and record events on.  close() releases it."""
+
+    def __init__(self, first: int, count: int, device=None):
+        import torch
+        self.lib = load()
+        words = (int(first) + int(count) + 31) // 32
+        mask = (C.c_uint32 * max(1, words))()
+        for cu in range(int(first), int(first) + int(count)):
+            mask[cu // 32] |= 1 << (cu % 32)
+        self.handle = C.c_void_p()
+        check(self.lib.gd_stream_create_cu_mask(mask, len(mask), C.byref(self.handle)))
+        self.stream = torch.cuda.ExternalStream(self.handle.value, device=device)
+
+    def close(self):
+        if self.handle:
+            self.stream.synchronize()
+            check(self.lib.gd_stream_destroy(self.handle))
+            self.handle = C.c_void_p()

@@ -503,12 +503,14 @@ int32_t gd_many_create(const gd_run* runs, int32_t nrun, const gd_many_tuning* t
         if (!rc && x.p->rates_fp32 != runs[0].p->rates_fp32) rc = fail(GD_E_INVALID_ARG, "runs differ in rates_fp32");
         Layout L;
         if (!rc) rc = check_ws(x.p, x.ws, x.ws_bytes, L);
-        gd_particles a = *x.a, b = *x.b;
-        b.cur = a.cur;
-        if (!rc) rc = check_out(&a, &b);
-        b.cur = a.cur ^ 1;
-        a.cur = b.cur;
-        if (!rc) rc = check_out(&b, &a);
+        if (!rc) {  // each buffer can receive the other's permutation
+            gd_particles a = *x.a, b = *x.b;
+            b.cur = a.cur;
+            rc = check_out(&a, &b);
+            b.cur = a.cur ^ 1;
+            a.cur = b.cur;
+            if (!rc) rc = check_out(&b, &a);
+        }
         if (rc) {
             char msg[sizeof(g_err)];
             snprintf(msg, sizeof(msg), "%s", g_err);
@@ -592,6 +594,29 @@ int32_t gd_many_destroy(gd_many* m)
     (void)hipSetDevice(cur);
     delete m;
     if (e != hipSuccess) return fail(GD_E_HIP, "gd_many_destroy: %s", hipGetErrorString(e));
+    return GD_OK;
+}
+
+int32_t gd_stream_create_cu_mask(const uint32_t* mask, int32_t mask_words, void** stream)
+{
+    if (!stream) return fail(GD_E_INVALID_ARG, "gd_stream_create_cu_mask: stream is NULL");
+    *stream = nullptr;
+    if (!mask || mask_words < 1) return fail(GD_E_INVALID_ARG, "gd_stream_create_cu_mask: empty mask");
+    bool any = false;
+    for (int32_t w = 0; w < mask_words; ++w) any = any || mask[w] != 0;
+    if (!any) return fail(GD_E_INVALID_ARG, "gd_stream_create_cu_mask: no CU selected");
+    hipStream_t st = nullptr;
+    const hipError_t e = hipExtStreamCreateWithCUMask(&st, uint32_t(mask_words), mask);
+    if (e != hipSuccess) return fail(GD_E_HIP, "gd_stream_create_cu_mask: %s", hipGetErrorString(e));
+    *stream = st;
+    return GD_OK;
+}
+
+int32_t gd_stream_destroy(void* stream)
+{
+    if (!stream) return GD_OK;
+    const hipError_t e = hipStreamDestroy(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(GD_E_HIP, "gd_stream_destroy: %s", hipGetErrorString(e));
     return GD_OK;
 }
 

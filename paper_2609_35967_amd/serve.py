@@ -2,25 +2,36 @@
 
 A run is (params, state, seed, intervals).  Runs wait in arrival order until
 the HBM budget has room for them (their state, neighbourhoods and workspace,
-sized from the library's own workspace size); then each round advances every
-admitted run by one interval:
+sized from the library's own workspace size).  An admitted run joins the
+tier of its size (by particle count); each tier has its own stream and
+advances on its own:
 
-    per run, on one of a few streams: neighbour search, rates, the per-lane
-    sampling pass (its arguments into slot r of a shared table);
-    one launch: the deferred particles of every run (gd_sample_table_run);
-    per run: the audit, the push.
+    a tier round = one interval of every run of the tier, as one launch per
+    stage over all of them (gd_many_interval: sort, tree, search, rates and
+    plan, sampling with one pass over the deferred particles of the tier,
+    audit, push).
 
-A run that has done its intervals retires and frees its budget, and runs
-waiting for memory are admitted at the next round.  Runs share nothing, and
-each run's kernels and their inputs are those of the run stepped alone, so
-its result does not depend on what else is served.
+Tiers are not in lock-step: a tier whose round has finished starts its next
+one at once, so small runs do not wait for the intervals of large ones, and
+the host keeps up to `depth` rounds of a tier queued so that the GPU does
+not idle between them.  A tier whose live runs hold more than `round_cap`
+particles splits them into groups under the cap and steps the groups in
+turn, so that one round never holds the intervals of every large run.  A
+tier's launch tables are built again only when its set of live runs changes
+(a run joins or queues its last interval); tables a tier no longer uses are
+released once the rounds that read them have finished.
+
+A run that has done its intervals retires and frees its budget; runs waiting
+for memory are admitted at the next poll.  Runs share nothing, and each
+run's kernels and their inputs are those of the run stepped alone, so its
+result does not depend on what else is served.
 """
 from __future__ import annotations
 
 import ctypes as C
 from dataclasses import dataclass, field
 
-from .binding import Engine, check, load
+from .binding import CuStream, Engine, ManyRuns, check, load
 
 import numpy as np
 
@@ -34,14 +45,100 @@ class Run:
     intervals: int
     arrival: float = 0.0
     engine: Engine | None = None
-    done: int = 0
+    done: int = 0       # intervals enqueued
+    finished: int = 0   # intervals completed
     bytes: int = 0
-    latencies_ms: list = field(default_factory=list)
+    latencies_ms: list = field(default_factory=list)   # GPU time of each interval's round
+    ends_ms: list = field(default_factory=list)        # completion of each interval (server clock)
+
+
+class _Tier:
+    def __init__(self, torch, device, cap: int, cus=None):
+        self.torch = torch
+        self.cu = CuStream(cus[0], cus[1], device=device) if cus else None
+        self.stream = self.cu.stream if cus else torch.cuda.Stream(device=device)
+        self.cap = int(cap)
+        self.runs: list[Run] = []
+        self.groups: list[tuple[list[Run], ManyRuns]] = []
+        self.plan: list[int] = []  # rids the current groups step
+        self.next = 0        # group of the next round
+        self.inflight = []   # (start event, end event, runs of the round)
+        self.stale = []      # (tables, event after which they are unused)
+
+    def live(self) -> list[Run]:
+        """The runs the next rounds step: those with intervals left to queue."""
+        return [r for r in self.runs if r.done < r.intervals]
+
+    def _regroup(self, live):
+        """Largest first, each run into the first group with room for it under
+        the particle cap (a run above the cap has a group of its own)."""
+        if self.groups:
+            done = self.torch.cuda.Event()
+            done.record(self.stream)
+            self.stale += [(many, done) for _, many in self.groups]
+        bins: list[list[Run]] = []
+        load: list[int] = []
+        for r in sorted(live, key=lambda x: -x.engine.n):
+            for g in range(len(bins)):
+                if load[g] + r.engine.n <= self.cap:
+                    bins[g].append(r)
+                    load[g] += r.engine.n
+                    break
+            else:
+                bins.append([r])
+                load.append(r.engine.n)
+        self.groups = [(b, ManyRuns([r.engine for r in b])) for b in bins]
+        self.next = 0
+
+    def launch(self) -> bool:
+        torch = self.torch
+        live = self.live()
+        if not live:
+            return False
+        ids = sorted(r.rid for r in live)
+        if ids != self.plan:
+            self._regroup(live)
+            self.plan = ids
+        runs, many = self.groups[self.next % len(self.groups)]
+        self.next += 1
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(self.stream)
+        many.interval(self.stream)
+        t1.record(self.stream)
+        for r in runs:
+            r.done += 1
+        self.inflight.append((t0, t1, runs))
+        return True
+
+    def reap(self, ref, block: bool = False):
+        """Completed rounds: (ms, end on the server clock, runs) for each, oldest first."""
+        out = []
+        while self.inflight and (block or self.inflight[0][1].query()):
+            t0, t1, runs = self.inflight.pop(0)
+            t1.synchronize()
+            out.append((t0.elapsed_time(t1), ref.elapsed_time(t1), runs))
+            block = False
+        keep = []
+        for many, ev in self.stale:
+            if ev.query():
+                many.close()
+            else:
+                keep.append((many, ev))
+        self.stale = keep
+        return out
 
 
 class Server:
-    def __init__(self, budget_bytes: float, streams: int = 8, max_runs: int = 1024, device: str = "cuda",
-                 keep_results: bool = True):
+    def __init__(self, budget_bytes: float, tiers=(1 << 14, 1 << 17), depth: int = 2, max_runs: int = 1024,
+                 device: str = "cuda", keep_results: bool = True, round_cap: int = 1 << 20, cus=None):
+        """tiers: particle-count limits of the tiers but the last (a run goes
+        to the first tier whose limit it does not exceed); depth: rounds a
+        tier keeps queued; round_cap: particles one round of a tier steps at
+        most (a tier with more live runs takes them in groups, round after
+        round, so that a long round does not hold every run's interval);
+        cus: None, or per tier (first CU, CU count) of the compute units its
+        stream may use (a stream per tier restricted to them)."""
         import torch
         self.keep_results = bool(keep_results)
         self.torch = torch
@@ -49,15 +146,18 @@ class Server:
         self.budget = float(budget_bytes)
         self.used = 0.0
         self.device = device
-        self.streams = [torch.cuda.Stream() for _ in range(max(1, int(streams)))]
+        self.limits = list(tiers)
+        nt = len(self.limits) + 1
+        if cus is not None and len(cus) != nt:
+            raise ValueError(f"cus needs one (first, count) per tier ({nt})")
+        self.tiers = [_Tier(torch, device, round_cap, cus[i] if cus else None) for i in range(nt)]
+        self.ref = torch.cuda.Event(enable_timing=True)  # the server clock's origin
+        self.ref.record(torch.cuda.current_stream())
+        self.depth = max(1, int(depth))
         self.max_runs = int(max_runs)
-        sz = C.c_size_t()
-        check(self.lib.gd_sample_table_size(self.max_runs, C.byref(sz)))
-        self.table = torch.empty(sz.value, dtype=torch.uint8, device=device)
-        self.table_bytes = sz.value
         self.waiting: list[Run] = []
-        self.active: list[Run] = []
         self.finished: list[Run] = []
+        self.rounds = 0  # tier rounds queued
 
     @staticmethod
     def run_bytes(lib, params: dict, n: int) -> int:
@@ -71,70 +171,44 @@ class Server:
         rows = n * P.k * 4 + n * (4 + 8 + 8 + 4)
         return int(sz.value + state + rows)
 
+    @property
+    def active(self) -> list[Run]:
+        return [r for t in self.tiers for r in t.runs]
+
     def submit(self, run: Run):
         run.bytes = self.run_bytes(self.lib, run.params, len(run.state["x"]))
         if run.bytes > self.budget:
             raise ValueError(f"run {run.rid} needs {run.bytes} B, above the budget")
         self.waiting.append(run)
 
-    def admit(self):
-        while self.waiting and len(self.active) < self.max_runs and self.used + self.waiting[0].bytes <= self.budget:
-            r = self.waiting.pop(0)
-            r.engine = Engine(r.params, r.state, seed=r.seed, device=self.device)
-            self.used += r.bytes
-            self.active.append(r)
+    def _tier_of(self, n: int) -> _Tier:
+        for lim, t in zip(self.limits, self.tiers):
+            if n <= lim:
+                return t
+        return self.tiers[-1]
 
-    def round(self):
-        """One interval of every active run; returns the runs that finished."""
-        torch = self.torch
-        lib = self.lib
-        if not self.active:
-            return []
-        act = self.active
-        ks = {r.engine.P.k <= 32 for r in act}
-        fp = {int(r.engine.P.rates_fp32) for r in act}
-        if len(ks) != 1 or len(fp) != 1:
-            raise ValueError("served runs need one k class and one rates form")
-        cs = torch.cuda.current_stream()
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        t0.record(cs)
-        for st in self.streams:
-            st.wait_stream(cs)
-        order = sorted(range(len(act)), key=lambda i: -act[i].engine.n)
-        load_of = [0] * len(self.streams)
-        tp = self.table.data_ptr()
-        for slot, i in enumerate(order):
-            s = min(range(len(self.streams)), key=lambda t: load_of[t])
-            load_of[s] += act[i].engine.n
-            e = act[i].engine
-            e.stream = self.streams[s]
-            e.build_neighbors()
-            e.collision_rates()
-            e.sample_deferred(tp, self.table_bytes, slot)
-        for st in self.streams:
-            cs.wait_stream(st)
-        check(lib.gd_sample_table_run(C.c_void_p(tp), self.table_bytes, len(act), act[0].engine.P.k, fp.pop(),
-                                      C.c_void_p(cs.cuda_stream)))
-        for st in self.streams:
-            st.wait_stream(cs)
-        for r in act:
-            r.engine.sample_audit()
-            if r.engine.P.push != 0:
-                r.engine.push()
-        for st in self.streams:
-            cs.wait_stream(st)
-        t1.record(cs)
-        t1.synchronize()
-        ms = t0.elapsed_time(t1)
+    def admit(self):
+        admitted = False
+        while (self.waiting and len(self.active) < self.max_runs
+               and self.used + self.waiting[0].bytes <= self.budget):
+            r = self.waiting.pop(0)
+            r.engine = Engine(r.params, r.state, seed=r.seed, device=self.device, device_interval=True)
+            self.used += r.bytes
+            self._tier_of(r.engine.n).runs.append(r)
+            admitted = True
+        if admitted:  # the new engines' uploads ran on torch's stream
+            self.torch.cuda.current_stream().synchronize()
+
+    def _collect(self, tier: _Tier, block: bool = False) -> list[Run]:
         out = []
-        for r in act:
-            r.engine.stream = None
-            r.done += 1
-            r.latencies_ms.append(ms)
-        for r in list(act):
-            if r.done >= r.intervals:
-                act.remove(r)
+        for ms, end, runs in tier.reap(self.ref, block):
+            for r in runs:
+                r.finished += 1
+                r.latencies_ms.append(ms)
+                r.ends_ms.append(end)
+        for r in list(tier.runs):
+            if r.finished >= r.intervals:
+                tier.runs.remove(r)
                 self.used -= r.bytes
                 if not self.keep_results:
                     r.engine = None  # its memory goes back to the allocator
@@ -142,10 +216,88 @@ class Server:
                 out.append(r)
         return out
 
+    def poll(self) -> tuple[list[Run], bool]:
+        """Collect finished rounds, retire finished runs, and queue the next
+        round of every tier that has room.  Returns (runs retired, whether a
+        round was queued).  Never waits for the GPU."""
+        out, launched = [], False
+        for t in self.tiers:
+            out += self._collect(t)
+            if len(t.inflight) < self.depth and t.launch():
+                self.rounds += 1
+                launched = True
+        return out, launched
+
+    def wait(self) -> list[Run]:
+        """Block until the oldest queued round of any tier finishes."""
+        busy = [t for t in self.tiers if t.inflight]
+        if not busy:
+            return []
+        t = min(busy, key=lambda x: len(x.inflight))
+        return self._collect(t, block=True)
+
+    def round(self) -> list[Run]:
+        """One round of every tier with runs, then wait for all of them (the
+        blocking form, for tests and simple drivers)."""
+        for t in self.tiers:
+            if t.launch():
+                self.rounds += 1
+        out = []
+        for t in self.tiers:
+            while t.inflight:
+                out += self._collect(t, block=True)
+            out += self._collect(t)
+        return out
+
     def idle(self) -> bool:
         return not self.active and not self.waiting
 
+    def close(self):
+        for t in self.tiers:
+            while t.inflight:
+                self._collect(t, block=True)
+            for many, ev in t.stale:
+                ev.synchronize()
+                many.close()
+            t.stale = []
+            for _, many in t.groups:
+                many.close()
+            t.groups = []
+            t.plan = []
+            if t.cu is not None:
+                t.cu.close()
+                t.cu = None
+
+
+def drive(server: Server, arrivals, clock) -> None:
+    """Serve `arrivals` [(time, Run)] (ascending) to completion: submit each
+    run at its time on `clock()`, admit, queue rounds, and wait for the GPU
+    only when nothing can be queued."""
+    import time
+    pending = list(arrivals)
+    while pending or not server.idle():
+        now = clock()
+        while pending and pending[0][0] <= now:
+            server.submit(pending.pop(0)[1])
+        server.admit()
+        _, launched = server.poll()
+        if launched:
+            continue
+        if any(t.inflight for t in server.tiers):
+            server.wait()
+        elif pending:
+            time.sleep(max(0.0, pending[0][0] - clock()))
+
 
 def latency_percentiles(runs, q=(50, 99)):
+    """Percentiles of the GPU time of the rounds that held each run's intervals."""
     lat = np.concatenate([np.asarray(r.latencies_ms) for r in runs]) if runs else np.zeros(1)
     return [float(np.percentile(lat, x)) for x in q]
+
+
+def gap_percentiles(runs, q=(50, 99)):
+    """Percentiles of the time between successive interval completions of a
+    run (what its owner waits per interval once it is running)."""
+    gaps = [np.diff(np.asarray(r.ends_ms)) for r in runs if len(r.ends_ms) > 1]
+    g = np.concatenate(gaps) if gaps else np.zeros(1)
+    return [float(np.percentile(g, x)) for x in q]

@@ -218,3 +218,29 @@ def test_static_reshuffle_rejects_sizes_beyond_its_table(lib):
     assert lib.gd_reshuffle_neighbors_static(C.byref(P), C.byref(nb), 1, 0, None) == -1
     assert b"exceeds its fixed table of 4194304 entries" in lib.gd_last_error()
     assert lib.gd_reshuffle_neighbors_static(C.byref(P), None, 1, 0, None) == -1
+
+
+def test_many_and_stream_validation(lib):
+    from paper_2609_35967_amd.binding import GdManyTuning, GdRun
+    out = C.c_void_p(123)
+    runs = (GdRun * 1)()
+    assert lib.gd_many_create(runs, 0, None, C.byref(out)) == -1 and not out.value
+    assert b"nrun" in lib.gd_last_error()
+    assert lib.gd_many_create(runs, 4097, None, C.byref(out)) == -1
+    assert lib.gd_many_create(runs, 1, None, None) == -1
+    bad = GdManyTuning(knn_tile=2)
+    assert lib.gd_many_create(runs, 1, C.byref(bad), C.byref(out)) == -1
+    assert b"tuning" in lib.gd_last_error()
+    # a run with no problem is rejected, named by its index
+    assert lib.gd_many_create(runs, 1, None, C.byref(out)) == -1
+    assert b"run 0" in lib.gd_last_error()
+    assert lib.gd_many_interval(None, None) == -1
+    assert lib.gd_many_destroy(None) == 0
+    par = C.c_int32()
+    assert lib.gd_many_parity(None, C.byref(par)) == -1
+    st = C.c_void_p(5)
+    mask = (C.c_uint32 * 8)()
+    assert lib.gd_stream_create_cu_mask(mask, 8, C.byref(st)) == -1 and not st.value
+    assert b"no CU" in lib.gd_last_error()
+    assert lib.gd_stream_create_cu_mask(None, 8, C.byref(st)) == -1
+    assert lib.gd_stream_destroy(None) == 0

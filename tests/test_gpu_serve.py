@@ -1,6 +1,7 @@
 """Serving (Server): runs that arrive at different rounds, admitted under an
 HBM budget that makes some of them wait, each end in the state of the same
-run stepped alone."""
+run stepped alone; the non-blocking driver gives the same; a served run
+matches the oracle."""
 import numpy as np
 import pytest
 
@@ -13,7 +14,8 @@ if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("needs a GPU", allow_module_level=True)
 
 from paper_2609_35967_amd import Engine, load  # noqa: E402
-from paper_2609_35967_amd.serve import Run, Server  # noqa: E402
+from oracle.pipeline import OracleRun  # noqa: E402
+from paper_2609_35967_amd.serve import Run, Server, drive  # noqa: E402
 
 
 def _say(*a):
@@ -48,7 +50,7 @@ def test_served_runs_match_alone():
         ref[run.rid] = _state(e)
     lib = load()
     sizes = sorted(Server.run_bytes(lib, r.params, len(r.state["x"])) for r, _ in runs)
-    srv = Server(budget_bytes=sizes[-1] + sizes[-2] + 1, streams=3)
+    srv = Server(budget_bytes=sizes[-1] + sizes[-2] + 1, tiers=(5000,))
     rnd = 0
     waited = 0
     while True:
@@ -72,3 +74,71 @@ def test_served_runs_match_alone():
         for key in ("time", "ticks", "n_intervals", "n_events", "C"):
             assert got["iv"][key] == want["iv"][key], f"run {run.rid}: interval {key} differs"
         assert run.engine.status() == 0
+
+
+def test_driven_runs_match_alone():
+    # every run submitted at its own time into the non-blocking driver: tiers
+    # advance on their own streams with two rounds queued
+    import time
+    load()
+    runs = _runs()
+    ref = {}
+    for run, _ in runs:
+        e = Engine(run.params, run.state, seed=run.seed)
+        for _ in range(run.intervals):
+            e.step()
+        ref[run.rid] = _state(e)
+    # the middle tier's stream may use only a share of the compute units
+    srv = Server(budget_bytes=1e12, tiers=(4500, 7000), cus=[(0, 256), (0, 32), (32, 224)])
+    t0 = time.perf_counter()
+    drive(srv, [(0.002 * a, r) for r, a in runs], lambda: time.perf_counter() - t0)
+    torch.cuda.synchronize()
+    assert len(srv.finished) == len(runs)
+    for run in srv.finished:
+        assert len(run.latencies_ms) == run.intervals
+        got = _state(run.engine)
+        want = ref[run.rid]
+        for key in ("id", "x", "y", "z", "M", "m", "nbr"):
+            assert np.array_equal(got[key], want[key]), f"run {run.rid}: {key} differs"
+        for key in ("time", "ticks", "n_intervals", "n_events", "C"):
+            assert got["iv"][key] == want["iv"][key], f"run {run.rid}: interval {key} differs"
+    srv.close()
+    _say("driven", len(srv.finished), "runs in", srv.rounds, "tier rounds")
+
+
+def _by_id(d):
+    o = np.argsort(np.asarray(d["id"]).astype(np.int64))
+    return {k: np.asarray(v)[o] for k, v in d.items()}
+
+
+def test_served_run_matches_oracle():
+    # three runs in two tiers, served together; the first one against the
+    # oracle's run of the same intervals (global push over each dt_exe)
+    load()
+    runs = _runs()[:3]
+    srv = Server(budget_bytes=1e12, tiers=(4000,))
+    for run, _ in runs:
+        srv.submit(run)
+    srv.admit()
+    while not srv.idle():
+        srv.round()
+    run = runs[0][0]
+    ref = OracleRun(run.params, run.state, seed=run.seed)
+    near = False
+    for _ in range(run.intervals):
+        r = ref.step(push=True)
+        near = near or bool(r["mc"]["near_tie"].any())
+    assert not near, "a near tie: choose another seed"
+    got, want = _by_id(run.engine.state_numpy()), _by_id(ref.st)
+    iv = run.engine.interval_state()
+    assert iv["C"] == ref.C and iv["ticks"] == ref.ticks and iv["n_intervals"] == ref.interval
+    assert np.array_equal(got["id"], want["id"]) and np.array_equal(got["M"], want["M"])
+    np.testing.assert_allclose(got["m"], want["m"], rtol=1e-12, atol=0)
+    for k in ("r", "th", "x", "y", "z"):
+        np.testing.assert_allclose(got[k], want[k], rtol=1e-12, atol=0, err_msg=k)
+    np.testing.assert_allclose(got["ph"], want["ph"], rtol=1e-12, atol=1e-12, err_msg="ph")
+    for k in ("vr", "lth", "lph"):
+        scale = np.abs(want[k]).max()
+        np.testing.assert_allclose(got[k], want[k], rtol=1e-10, atol=1e-12 * scale, err_msg=k)
+    assert iv["n_events"] > 0
+    srv.close()
