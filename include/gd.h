@@ -291,6 +291,35 @@ int32_t gd_sample_collisions(const gd_problem* p, const gd_particles* st, const 
                              uint64_t interval_index, int32_t* n_events, int32_t* log,
                              int32_t log_cap, void* ws, size_t ws_bytes, void* stream);
 
+/* The common transport step of Sect. 2.6: dt = min(dt_max, dt_out, min_i dt_i)
+ * over the active particles.  The paper names dt_i's constraints (orbital
+ * motion, deterministic and diffusive displacement against the local
+ * spacing) without their forms; the reading taken, with d_i = nb->dmax[i]
+ * the particle's neighbourhood radius from the last search:
+ *   orbital        c_orb / Omega_K(R) for GD_PUSH_GLOBAL (R = sqrt(x^2 + y^2)),
+ *                  c_orb for GD_PUSH_LOCAL (Omega = 1);
+ *   deterministic  c_adv d_i / u_i, u_i the speed relative to the local
+ *                  circular orbit (v_r, l_th / r, l_ph / R - sqrt(GM / R)), or
+ *                  |v_z| in the local column;
+ *   diffusive      c_diff d_i^2 / D_i when diffusion is on, D_i the largest
+ *                  coefficient nu / (Sc (1 + St^2)) of the directions stepped.
+ * A term that does not apply (no push, no diffusion, d_i = 0, u_i = 0) is left
+ * out.  The result goes to *dt (one device double).  With iv non-NULL the
+ * interval state takes dt_coll = dt / 2 for the step's two collision
+ * operators; that is valid only at a collision-step boundary (iv->ticks ==
+ * 0), and elsewhere iv is left alone and GD_DEV_INTERNAL is raised.  Uses
+ * the workspace's reduction scratch.  Errors: GD_E_INVALID_ARG for NULL
+ * arguments, arrays a term needs, or limits that are not positive. */
+typedef struct gd_step_limits {
+    double dt_max;  /* prescribed maximum step */
+    double dt_out;  /* time left to the next output (INFINITY: none) */
+    double c_orb, c_adv, c_diff;
+} gd_step_limits;
+
+int32_t gd_transport_dt(const gd_problem* p, const gd_particles* st, const gd_neighbors* nb,
+                        const gd_step_limits* lim, gd_interval* iv, double* dt, void* ws, size_t ws_bytes,
+                        void* stream);
+
 /* Many independent runs stepped as one (Sect. 2.5: the interval of each run
  * is the one gd_build_neighbors, gd_collision_rates, gd_sample_collisions and
  * gd_push make; Sect. 4.3.1: many small independent domains on one device).

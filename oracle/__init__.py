@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import contextlib
 import ctypes as C
+import math
 import os
 import subprocess
 import tempfile
@@ -123,6 +124,8 @@ def _declare(L):
     L.orc_diff_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, vp]
     L.orc_diffuse.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, d, C.c_uint64,
                               C.c_uint32]
+    L.orc_transport_dt.argtypes = [vp, C.c_int, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, d, d, d, d, d]
+    L.orc_transport_dt.restype = d
     L.orc_fsum.argtypes = [i64, vp]
     L.orc_fsum.restype = d
     L.orc_num_threads.restype = C.c_int
@@ -364,6 +367,27 @@ def diffuse(P: Problem, st: dict, dt: float, seed: int, step: int) -> dict:
                       _p(s["lth"]), _p(s["lph"]), _p(s["m"]), _p(s["M"]), _p(s["x"]), _p(s["y"]), _p(s["z"]),
                       float(dt), C.c_uint64(seed), step)
     return s
+
+
+PUSH_KINDS = {"none": 0, "local": 1, "global": 2}
+
+
+def transport_dt(P: Problem, push: str, st: dict, d, dt_max: float, dt_out: float = math.inf,
+                 c_orb: float = 0.05, c_adv: float = 0.5, c_diff: float = 0.5) -> float:
+    """The shared transport step of Sect. 2.6 over the active particles of the
+    state dict `st`, with d the neighbourhood radii (reading R36 in the C source)."""
+    n = len(st["M"])
+    zero = np.zeros(n)
+
+    def arr(k):
+        return _c(st[k], np.float64) if k in st and st[k] is not None else zero
+
+    a = {k: arr(k) for k in ("x", "y", "r", "th", "vr", "lth", "lph", "vz", "m", "M")}
+    dd = _c(d, np.float64)
+    return float(lib().orc_transport_dt(C.byref(P), PUSH_KINDS[push], n, _p(a["x"]), _p(a["y"]), _p(a["r"]),
+                                        _p(a["th"]), _p(a["vr"]), _p(a["lth"]), _p(a["lph"]), _p(a["vz"]),
+                                        _p(a["m"]), _p(a["M"]), _p(dd), float(dt_max), float(dt_out),
+                                        float(c_orb), float(c_adv), float(c_diff)))
 
 
 def fsum(v):

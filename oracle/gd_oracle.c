@@ -26,6 +26,7 @@
  *   orc_push_local      drift-kick-drift vertical settling, local column
  *   orc_push_global     staggered semi-analytic push in spherical coords (Sect. 2.3.3)
  *   orc_diffuse         Euler--Maruyama dust diffusion step (Sect. 2.4)
+ *   orc_transport_dt    the shared transport step from local constraints (Sect. 2.6)
  *   orc_fsum            exactly rounded sum (used for all reductions)
  *   orc_reshuffle       random relabelling of the cached neighbours before a
  *                       refresh (product-kernel test, Sect. 3.3)
@@ -1153,6 +1154,72 @@ void orc_diffuse(const orc_problem* P, int64_t n, const uint32_t* id, double* r,
         z[i] = Z1;
         if (r1 < P->r_in || r1 > P->r_out) M[i] = 0.0;
     }
+}
+
+/* The common transport step of Sect. 2.6: dt = min(dt_max, dt_out, min_i dt_i)
+ * over the active particles.  The paper names the constraints of dt_i
+ * (orbital motion, deterministic and diffusive displacement relative to the
+ * local spacing) without their forms; the reading taken (R36):
+ *   orbital        c_orb / Omega, Omega = sqrt(GM / R^3) at R = sqrt(x^2 + y^2)
+ *                  for the global push, Omega = 1 for the local column;
+ *   deterministic  c_adv d_i / u_i, d_i the particle's neighbourhood radius
+ *                  (the local spacing of the particle representation) and
+ *                  u_i its speed relative to the local circular orbit:
+ *                  u^2 = v_r^2 + (l_theta / r)^2 + (l_phi / R - sqrt(GM / R))^2
+ *                  (global), u = |v_z| (local column);
+ *   diffusive      c_diff d_i^2 / D_i, D_i the largest diffusion coefficient
+ *                  of the directions the diffusion step moves (R; Z unless
+ *                  vertically integrated; phi unless axisymmetric).
+ * A term is left out when it does not apply: no push, no orbital or
+ * deterministic term; no diffusion, no diffusive term; d_i = 0 or u_i = 0.
+ * push_kind: 0 none, 1 local column, 2 global. */
+double orc_transport_dt(const orc_problem* P, int push_kind, int64_t n, const double* x, const double* y,
+                        const double* r, const double* th, const double* vr, const double* lth,
+                        const double* lph, const double* vz, const double* m, const double* M,
+                        const double* d, double dt_max, double dt_out, double c_orb, double c_adv,
+                        double c_diff)
+{
+    double dt = dt_max < dt_out ? dt_max : dt_out;
+    for (int64_t i = 0; i < n; i++) {
+        if (!(M[i] > 0.0)) continue;
+        double di = d[i];
+        double t = INFINITY;
+        if (push_kind == 2) {
+            double R = sqrt(x[i] * x[i] + y[i] * y[i]);
+            double Om = sqrt(P->GM / (R * R * R));
+            double to = c_orb / Om;
+            if (to < t) t = to;
+            double vt = lth[i] / r[i];
+            double vp = lph[i] / R - sqrt(P->GM / R);
+            double u = sqrt(vr[i] * vr[i] + vt * vt + vp * vp);
+            if (di > 0.0 && u > 0.0) {
+                double ta = c_adv * di / u;
+                if (ta < t) t = ta;
+            }
+        } else if (push_kind == 1) {
+            if (c_orb < t) t = c_orb;
+            double u = fabs(vz[i]);
+            if (di > 0.0 && u > 0.0) {
+                double ta = c_adv * di / u;
+                if (ta < t) t = ta;
+            }
+        }
+        if (P->diffusion != 0 && di > 0.0) {
+            double R = r[i] * sin(th[i]), Z = r[i] * cos(th[i]);
+            double s = P->St_diff > 0.0 ? 0.0 : grain_size(P, m[i]);
+            orc_diffco c;
+            diff_coeffs(P, R, Z, s, &c);
+            double D = c.D[0];
+            if (!P->vint && c.D[1] > D) D = c.D[1];
+            if (!P->axisym && c.D[2] > D) D = c.D[2];
+            if (D > 0.0) {
+                double tdf = c_diff * (di * di) / D;
+                if (tdf < t) t = tdf;
+            }
+        }
+        if (t < dt) dt = t;
+    }
+    return dt;
 }
 
 /* Diagnostics exposed for tests. */

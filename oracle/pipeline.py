@@ -19,7 +19,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import (audit, diffuse, knn, make_problem, mc, morton_keys, plan, push_global, push_local, rates,
-               sort_perm)
+               sort_perm, transport_dt)
 
 T_TICKS = 1 << 30
 
@@ -38,6 +38,7 @@ class OracleRun:
         self.last = {}
         self.moved = True        # positions changed since the neighbour lists were built
         self.diff_step = 0       # draws of the next diffusion step
+        self.dt_coll = float(params["dt_coll"])
 
     def build_neighbors(self):
         st = self.st
@@ -56,7 +57,7 @@ class OracleRun:
         st = self.st
         nbr, cnt, dmax = self.nb
         lam, a, b, _ = rates(P, nbr, cnt, dmax, st["m"], st["M"], st["x"], st["y"], st["z"])
-        pl = plan(P, st["m"], st["M"], a, b, self.params["dt_coll"], self.ticks, self.C)
+        pl = plan(P, st["m"], st["M"], a, b, self.dt_coll, self.ticks, self.C)
         res = mc(P, st["id"], nbr, cnt, dmax, st["m"], st["M"], st["x"], st["y"], st["z"],
                  pl["dt_exe"], self.seed, self.interval, log_cap=log_cap)
         au = audit(P, st["m"], res["m"], st["M"], pl["group_of"], pl["gM"], self.C)
@@ -102,9 +103,22 @@ class OracleRun:
             if self.ticks == 0:
                 return out
 
-    def strang_step(self, log_cap: int = 0):
-        """C(dt/2) D(dt/2) T(dt) D(dt/2) C(dt/2) with dt/2 = dt_coll."""
-        h = float(self.params["dt_coll"])
+    def step_dt(self, limits: dict) -> float:
+        """The transport step of Sect. 2.6 chosen from the local constraints
+        (reading R36), with the neighbourhood radii of the current lists (zero
+        before the first search)."""
+        d = self.nb[2] if self.nb is not None else np.zeros(len(self.st["M"]))
+        kw = dict(limits)
+        return transport_dt(self.P, self.params.get("push", "none"), self.st, d, **kw)
+
+    def strang_step(self, log_cap: int = 0, limits: dict | None = None):
+        """C(dt/2) D(dt/2) T(dt) D(dt/2) C(dt/2) with dt/2 = dt_coll; with
+        `limits`, dt is chosen at the start of the step (step_dt) and the
+        collision steps of this transport step take dt_coll = dt/2."""
+        if limits is not None:
+            assert self.ticks == 0
+            self.dt_coll = 0.5 * self.step_dt(limits)
+        h = self.dt_coll
         out = self.collide(log_cap)
         self.diffusion(h)
         self.transport(2.0 * h)
@@ -186,13 +200,13 @@ class GroupedRun(OracleRun):
         end = [0] * G
         start_at = [0] * G
         tau, starting, done = 0, list(range(G)), []
-        tick = np.ldexp(self.params["dt_coll"], -30)
+        tick = np.ldexp(self.dt_coll, -30)
         while True:
             for g in starting:
                 a0, a1 = self.bounds[g], self.bounds[g + 1]
                 q = np.arange(a0, a1)
                 lam, a, b, _ = rates(P, nbr, cnt, dmax, m_pub, st["M"], st["x"], st["y"], st["z"], queries=q)
-                pl = plan(P, m_pub[a0:a1], st["M"][a0:a1], a, b, self.params["dt_coll"], tau, self.gC[g])
+                pl = plan(P, m_pub[a0:a1], st["M"][a0:a1], a, b, self.dt_coll, tau, self.gC[g])
                 want = pl["exe_ticks"]
                 others = [size[h] for h in self.links[g] if size[h]]
                 lo_lim = max([1] + [z // 16 for z in others])

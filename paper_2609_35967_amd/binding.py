@@ -69,6 +69,14 @@ class GdRun(C.Structure):
     ]
 
 
+class GdStepLimits(C.Structure):
+    _fields_ = [("dt_max", C.c_double), ("dt_out", C.c_double), ("c_orb", C.c_double), ("c_adv", C.c_double),
+                ("c_diff", C.c_double)]
+
+
+STEP_DEFAULTS = dict(dt_out=math.inf, c_orb=0.05, c_adv=0.5, c_diff=0.5)
+
+
 class GdManyTuning(C.Structure):
     _fields_ = [("knn_tile", C.c_int32), ("fallback_div", C.c_int32), ("event_div", C.c_int32),
                 ("red_div", C.c_int32), ("heavy_blocks", C.c_int32)]
@@ -82,7 +90,7 @@ EXPORTS = ("gd_workspace_size", "gd_workspace_init", "gd_interval_init", "gd_bui
            "gd_reshuffle_neighbors", "gd_diffuse", "gd_group_interactions", "gd_collision_rates_group",
            "gd_sample_collisions_group", "gd_publish_group", "gd_reshuffle_neighbors_static",
            "gd_many_create", "gd_many_interval", "gd_many_parity", "gd_many_destroy", "gd_stream_create_cu_mask",
-           "gd_stream_destroy")
+           "gd_stream_destroy", "gd_transport_dt")
 PROF = {"sort": 0, "tree": 1, "knn_query": 2, "rates": 3, "mc": 4, "audit": 5, "push": 6, "diffuse": 7}
 GD_INTERVAL_ON_DEVICE = (1 << 64) - 1
 
@@ -140,6 +148,8 @@ def load(path: str | None = None):
     L.gd_many_destroy.argtypes = [vp]
     L.gd_stream_create_cu_mask.argtypes = [C.POINTER(C.c_uint32), C.c_int32, C.POINTER(vp)]
     L.gd_stream_destroy.argtypes = [vp]
+    L.gd_transport_dt.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.POINTER(GdNeighbors),
+                                  C.POINTER(GdStepLimits), vp, vp, vp, C.c_size_t, vp]
     L.gd_status_read.argtypes = [vp, vp, C.POINTER(C.c_int32)]
     L.gd_profile_events.argtypes = [C.c_int32, vp, vp]
     L.gd_last_error.restype = C.c_char_p
@@ -150,7 +160,7 @@ def load(path: str | None = None):
                  "gd_reshuffle_neighbors", "gd_diffuse", "gd_group_interactions", "gd_collision_rates_group",
                  "gd_sample_collisions_group", "gd_publish_group", "gd_reshuffle_neighbors_static",
                  "gd_many_create", "gd_many_interval", "gd_many_parity", "gd_many_destroy",
-                 "gd_stream_create_cu_mask", "gd_stream_destroy"):
+                 "gd_stream_create_cu_mask", "gd_stream_destroy", "gd_transport_dt"):
         getattr(L, name).restype = C.c_int32
     if path is None:
         _lib = L
@@ -518,13 +528,38 @@ class Engine:
         self._rates_group(g, lo, rows, sched, snapshot, ws, stream)
         self._sample_group(g, lo, ws, stream)
 
-    def strang_step(self) -> int:
-        """One transport step dt = 2 dt_coll in the symmetric sequence of Sect. 2.6:
-        C(dt/2) D(dt/2) T(dt) D(dt/2) C(dt/2).  The last collision operator of a
-        step and the first of the next share their neighbour lists.  With groups
-        set (set_groups), the collision operators are the grouped ones.  Returns
-        the number of (group) intervals run."""
-        h = float(self.params["dt_coll"])
+    def transport_dt(self, limits: dict, set_step: bool = False) -> float:
+        """The shared transport step of Sect. 2.6 from the particles' local
+        constraints (gd_transport_dt; `limits`: dt_max and optionally the keys
+        of STEP_DEFAULTS), read back to the host.  set_step: the interval
+        state takes dt_coll = dt / 2 (at a collision-step boundary)."""
+        lim = GdStepLimits(**dict(STEP_DEFAULTS, **limits))
+        if not hasattr(self, "dt_dev"):
+            self.dt_dev = self.torch.zeros(1, dtype=self.torch.float64, device=self.device)
+        s = self.A.struct()
+        check(self.lib.gd_transport_dt(C.byref(self.P), C.byref(s), C.byref(self.nb), C.byref(lim),
+                                       C.c_void_p(self.iv.data_ptr()) if set_step else None,
+                                       C.c_void_p(self.dt_dev.data_ptr()), C.c_void_p(self.ws_ptr), self.ws_bytes,
+                                       self._s()))
+        self._sync_own()
+        return float(self.dt_dev.item())
+
+    def strang_step(self, limits: dict | None = None) -> int:
+        """One transport step in the symmetric sequence of Sect. 2.6:
+        C(dt/2) D(dt/2) T(dt) D(dt/2) C(dt/2).  dt is 2 dt_coll of the run,
+        or, with `limits`, chosen at the start of the step from the local
+        constraints (transport_dt; one host read per step).  The last
+        collision operator of a step and the first of the next share their
+        neighbour lists.  With groups set (set_groups), the collision
+        operators are the grouped ones (fixed dt only).  Returns the number of
+        (group) intervals run."""
+        if limits is not None:
+            if getattr(self, "n_groups", 0):
+                raise ValueError("steps chosen from local constraints run with a single group")
+            h = 0.5 * self.transport_dt(limits, set_step=True)
+        else:
+            h = float(self.params["dt_coll"])
+        self.last_dt = 2.0 * h
         collide = (lambda: len(self.collide_groups())) if getattr(self, "n_groups", 0) else self.collide
         n = collide()
         if self.P.diffusion != 0:

@@ -597,6 +597,26 @@ int32_t gd_many_destroy(gd_many* m)
     return GD_OK;
 }
 
+int32_t gd_transport_dt(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb,
+                        const gd_step_limits* lim, gd_interval* iv, double* dt, void* ws, size_t ws_bytes,
+                        void* stream)
+{
+    int rc = check_problem(p);
+    if (!rc) rc = check_state(p, s, false);
+    if (!rc) rc = check_nb(nb);
+    if (rc) return rc;
+    if (!lim || !dt) return fail(GD_E_INVALID_ARG, "gd_transport_dt: limits and dt are required");
+    if (!(lim->dt_max > 0.0) || !(lim->dt_out > 0.0) || !(lim->c_orb > 0.0) || !(lim->c_adv > 0.0) ||
+        !(lim->c_diff > 0.0))
+        return fail(GD_E_INVALID_ARG, "gd_transport_dt: limits must be positive");
+    if (p->diffusion != 0 && (!s->r || !s->th)) return fail(GD_E_INVALID_ARG, "diffusion needs r and th");
+    Layout L;
+    rc = check_ws(p, ws, ws_bytes, L);
+    if (rc) return rc;
+    launch_transport_dt(p, s, nb, lim, iv, dt, ws, L, static_cast<hipStream_t>(stream));
+    return hip_ok("gd_transport_dt");
+}
+
 int32_t gd_stream_create_cu_mask(const uint32_t* mask, int32_t mask_words, void** stream)
 {
     if (!stream) return fail(GD_E_INVALID_ARG, "gd_stream_create_cu_mask: stream is NULL");

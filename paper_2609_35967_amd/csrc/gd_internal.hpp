@@ -47,6 +47,8 @@ int launch_sample_table(void* table, int32_t nslot, int32_t k, int32_t rates_fp3
 int launch_push(const gd_problem* p, const gd_particles* s, const gd_interval* iv, double dt, void* ws,
                 const Layout& L, hipStream_t st);
 void launch_interval_init(gd_interval* iv, double dt_coll, hipStream_t st);
+int launch_transport_dt(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, const gd_step_limits* lim,
+                        gd_interval* iv, double* dt, void* ws, const Layout& L, hipStream_t st);
 int launch_rates_group(const gd_problem* p, const gd_particles* s, const gd_neighbors* nb, gd_interval* iv,
                        double* lam_i, int64_t lo, int64_t hi, int32_t group, int32_t n_groups, const uint64_t* rows,
                        int64_t* sched, bool snapshot, void* ws, const Layout& L, hipStream_t st);

@@ -244,3 +244,14 @@ def test_many_and_stream_validation(lib):
     assert b"no CU" in lib.gd_last_error()
     assert lib.gd_stream_create_cu_mask(None, 8, C.byref(st)) == -1
     assert lib.gd_stream_destroy(None) == 0
+
+
+def test_transport_dt_validation(lib):
+    from paper_2609_35967_amd.binding import GdNeighbors, GdParticles, GdStepLimits, make_problem
+    P = make_problem(workloads.disk3d_params(1024))
+    s = GdParticles()
+    nb = GdNeighbors()
+    lim = GdStepLimits(1.0, math.inf, 0.05, 0.5, 0.5)
+    dt = C.c_void_p(64)
+    assert lib.gd_transport_dt(C.byref(P), None, C.byref(nb), C.byref(lim), None, dt, None, 0, None) == -1
+    assert lib.gd_transport_dt(None, C.byref(s), C.byref(nb), C.byref(lim), None, dt, None, 0, None) == -1

@@ -193,3 +193,66 @@ def test_strang_steps_match_oracle():
         assert np.array_equal(got["M"], ref["M"])
         _compare(got, ref, rtol=1e-10)
         _say("strang step", step, "intervals", n_gpu, "events", ivs["n_events"])
+
+
+# ------------------------------- the transport step from local constraints ----
+LIMITS = dict(dt_max=1e30, c_orb=0.05, c_adv=0.5, c_diff=0.5)
+
+
+@pytest.mark.parametrize("workload", ["disk3d", "additive_col"])
+def test_transport_dt_matches_oracle(workload):
+    """gd_transport_dt against the oracle's transport_dt, on the neighbourhood
+    radii of a fresh search (a 64K warm disk with diffusion on, and the column)."""
+    if workload == "disk3d":
+        n = 65536
+        params = dict(workloads.disk3d_params(n), diffusion="concentration", Sc=(1.0, 2.0, 0.7))
+        st = workloads.disk3d(15, n, warm=True, params=params)
+    else:
+        n = 32768
+        params = workloads.additive_col_params(n)
+        st = workloads.additive_col(16, n)
+    load()
+    eng = Engine(params, st, seed=3)
+    eng.build_neighbors()
+    got = eng.transport_dt(LIMITS)
+    s = eng.state_numpy()
+    d = eng.dmax.cpu().numpy()
+    P = oracle.make_problem(params)
+    want = oracle.transport_dt(P, params.get("push", "none"), s, d, **LIMITS)
+    assert math.isfinite(want) and want < 1e30
+    assert got == pytest.approx(want, rel=1e-13)
+    # with a cap below every particle's limit the cap is the step
+    assert eng.transport_dt(dict(LIMITS, dt_max=0.5 * want)) == 0.5 * want
+    assert eng.transport_dt(dict(LIMITS, dt_out=0.25 * want)) == 0.25 * want
+    _say(workload, "transport dt", got)
+
+
+def test_strang_steps_with_chosen_dt_match_oracle():
+    """Three transport steps whose dt is chosen at the start of each step from
+    the local constraints, against the oracle doing the same."""
+    from oracle.pipeline import OracleRun
+    n = 4096
+    params = dict(workloads.disk3d_params(n), diffusion="concentration", Sc=(1.0, 1.0, 1.0))
+    st = workloads.disk3d(14, n, warm=True, params=params)
+    lim = dict(dt_max=2.0 * params["dt_coll"], c_orb=0.02, c_adv=0.5, c_diff=0.5)
+    load()
+    eng = Engine(params, st, seed=5)
+    run = OracleRun(params, st, seed=5)
+    dts = []
+    for step in range(3):
+        n_gpu = eng.strang_step(limits=lim)
+        res = run.strang_step(limits=lim)
+        torch.cuda.synchronize()
+        assert not any(r["mc"]["near_tie"].any() for r in res), f"near tie in step {step}: choose another seed"
+        assert eng.last_dt == pytest.approx(2.0 * run.dt_coll, rel=1e-13)
+        dts.append(eng.last_dt)
+        assert n_gpu == len(res)
+        ivs = eng.interval_state()
+        assert ivs["ticks"] == 0 and ivs["C"] == run.C and ivs["n_intervals"] == run.interval
+        assert ivs["dt_coll"] == pytest.approx(run.dt_coll, rel=1e-13)
+        got, ref = _by_id(eng.state_numpy()), _by_id(run.st)
+        np.testing.assert_allclose(got["m"], ref["m"], rtol=1e-12, atol=0)
+        assert np.array_equal(got["M"], ref["M"])
+        _compare(got, ref, rtol=1e-10)
+        _say("chosen-dt strang step", step, "dt", eng.last_dt, "intervals", n_gpu, "events", ivs["n_events"])
+    assert min(dts) < lim["dt_max"]  # the local constraints chose the step, not the cap
