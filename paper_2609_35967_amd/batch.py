@@ -51,18 +51,44 @@ class BoxBatch:
     def n_particles(self) -> int:
         return sum(e.n for e in self.engines)
 
-    def many(self, tuning: dict | None = None) -> ManyRuns:
+    def many(self, tuning: dict | None = None) -> list:
         """The one-launch-per-stage form over every box (built on first use,
-        or again when `tuning` is given)."""
+        or again when `tuning` is given).  tuning["sets"] = S splits the boxes
+        into S sets of about equal particle count (largest first, each to the
+        lightest set), each stepped as one on a stream of its own: a set whose
+        interval ends in one particle's long chain of events (one wavefront
+        busy) then overlaps the other sets' work.  The other keys are the
+        launch shapes of gd_many_create."""
+        torch = self.torch
         if tuning is not None or getattr(self, "_many", None) is None:
-            if getattr(self, "_many", None) is not None:
-                self._many.close()
-            self._many = ManyRuns(self.engines, tuning if tuning is not None else getattr(self, "tuned", None))
+            for m in getattr(self, "_many", None) or []:
+                m.close()
+            t = dict(tuning if tuning is not None else (getattr(self, "tuned", None) or {}))
+            sets = max(1, min(int(t.pop("sets", 1)), len(self.engines)))
+            load_of = [0] * sets
+            members = [[] for _ in range(sets)]
+            for i in sorted(range(len(self.engines)), key=lambda i: -self.engines[i].n):
+                k = min(range(sets), key=lambda j: load_of[j])
+                members[k].append(self.engines[i])
+                load_of[k] += self.engines[i].n
+            self._many = [ManyRuns(mem, t) for mem in members if mem]
+            if len(getattr(self, "_many_streams", [])) < len(self._many):
+                self._many_streams = [torch.cuda.Stream() for _ in range(len(self._many))]
         return self._many
 
     def step_many(self):
-        """One interval of every box, one launch per stage."""
-        self.many().interval()
+        """One interval of every box, one launch per stage (per set of boxes)."""
+        sets = self.many()
+        if len(sets) == 1:
+            sets[0].interval()
+            return
+        torch = self.torch
+        cs = torch.cuda.current_stream()
+        for m, st in zip(sets, self._many_streams):
+            st.wait_stream(cs)
+            m.interval(st)
+        for st in self._many_streams[:len(sets)]:
+            cs.wait_stream(st)
 
     # ---- the project's autotuner for the launch shapes of step_many ---------------
     def _save(self):
@@ -91,7 +117,8 @@ class BoxBatch:
             e.interval, e.moved = s["interval"], s["moved"]
         torch.cuda.synchronize()
 
-    SPACE = dict(knn_tile=(1, 0), heavy_blocks=(256, 512, 768, 1024, 1536), event_div=(256, 512, 1024, 2048),
+    SPACE = dict(sets=(1, 2, 4, 8), knn_tile=(1, 0), heavy_blocks=(256, 512, 768, 1024, 1536),
+                 event_div=(256, 512, 1024, 2048),
                  fallback_div=(64, 256, 1024), red_div=(512, 2048, 8192))
 
     def tune(self, intervals: int = 2, space: dict | None = None) -> dict:
@@ -103,7 +130,7 @@ class BoxBatch:
         torch = self.torch
         space = space or self.SPACE
         saved = self._save()
-        best = dict(MANY_DEFAULTS)
+        best = dict(MANY_DEFAULTS, sets=1)
         trials = []
         cache = {}
 
@@ -112,11 +139,11 @@ class BoxBatch:
             if key in cache:
                 return cache[key]
             self._load(saved)
-            m = self.many(dict(setting))
+            self.many(dict(setting))
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(intervals):
-                m.interval()
+                self.step_many()
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3 / intervals
             cache[key] = ms

@@ -188,3 +188,18 @@ def test_many_tuned_shapes_do_not_change_results():
     for b, e in enumerate(bb.engines):
         _same(_snap(e), ref[b][1], f"tuned box {b}")
     _say("tuning", rec["choice"], rec["ms_per_interval"])
+
+
+def test_many_in_stream_sets_matches_alone():
+    # the boxes split into three sets, each stepped as one on its own stream
+    load()
+    boxes = _boxes()
+    ref = _alone(boxes, 2)
+    bb = BoxBatch(boxes)
+    bb.many(dict(sets=3))
+    for r in range(2):
+        bb.step_many()
+        bb.step_many()
+        torch.cuda.synchronize()
+        for b, e in enumerate(bb.engines):
+            _same(_snap(e), ref[b][r], f"sets round {r} box {b}")
