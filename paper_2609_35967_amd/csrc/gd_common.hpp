@@ -200,8 +200,9 @@ __global__ __launch_bounds__(K::kThreads) void k_many(const typename K::Args* __
 {
     const int32_t r = M.run[blockIdx.x];
     const int32_t s = M.b0[r];
-    const typename K::Args A = T[r];
-    K::body(A, Blk{int64_t(blockIdx.x) - s, int64_t(M.b0[r + 1] - s)});
+    // the run's arguments are read where they lie (uniform loads), not
+    // copied: a copy indexed at run time would live in scratch memory
+    K::body(T[r], Blk{int64_t(blockIdx.x) - s, int64_t(M.b0[r + 1] - s)});
 }
 
 // the counters a many-run interval clears before a stage (one block per run):
@@ -217,7 +218,7 @@ struct ClearArgs {
 struct ClearCounters {
     using Args = ClearArgs;
     static constexpr int kThreads = 64;
-    static __device__ void body(const Args& A, Blk)
+    static __device__ __forceinline__ void body(const Args& A, Blk)
     {
         const int t = threadIdx.x;
         if (t < A.na) A.a[t] = 0;

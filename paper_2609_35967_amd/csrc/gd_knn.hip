@@ -71,7 +71,7 @@ struct BucketArgs {
 struct BucketBoxes {
     using Args = BucketArgs;
     static constexpr int kThreads = 256;
-    static __device__ void body(const Args& A, Blk B);
+    static __device__ __forceinline__ void body(const Args& A, Blk B);
 };
 
 __global__ __launch_bounds__(256) void k_bucket_boxes(BucketArgs A)
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_bucket_boxes(BucketArgs A)
     BucketBoxes::body(A, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
 }
 
-__device__ void BucketBoxes::body(const Args& A, Blk B)
+__device__ __forceinline__ void BucketBoxes::body(const Args& A, Blk B)
 {
     const double4* __restrict__ pos = A.pos;
     const WsHeader* __restrict__ h = A.h;
@@ -122,7 +122,7 @@ struct LevelArgs {
 struct LevelBoxes {
     using Args = LevelArgs;
     static constexpr int kThreads = 256;
-    static __device__ void body(const Args& A, Blk B);
+    static __device__ __forceinline__ void body(const Args& A, Blk B);
 };
 
 __global__ __launch_bounds__(256) void k_level_boxes(LevelArgs A)
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256) void k_level_boxes(LevelArgs A)
     LevelBoxes::body(A, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
 }
 
-__device__ void LevelBoxes::body(const Args& A, Blk B)
+__device__ __forceinline__ void LevelBoxes::body(const Args& A, Blk B)
 {
     const FBox* __restrict__ child = A.child;
     const int64_t child_cap = A.child_cap, cap = A.cap;
@@ -365,7 +365,7 @@ template <bool PER, int KP2>
 struct KnnQuery {
     using Args = KnnArgs;
     static constexpr int kThreads = kQBlock;
-    static __device__ void body(const Args& A, Blk B);
+    static __device__ __forceinline__ void body(const Args& A, Blk B);
 };
 
 template <bool PER, int KP2>
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(kQBlock) void k_knn_query(KnnArgs A)
 }
 
 template <bool PER, int KP2>
-__device__ void KnnQuery<PER, KP2>::body(const Args& A, Blk B)
+__device__ __forceinline__ void KnnQuery<PER, KP2>::body(const Args& A, Blk B)
 {
     using QL = QueryLds<KP2>;
     __shared__ uint32_t s_lds[QL::kWords * kQBlock];
@@ -845,7 +845,7 @@ struct CopyNaArgs {
 struct CopyNa {
     using Args = CopyNaArgs;
     static constexpr int kThreads = 64;
-    static __device__ void body(const Args& A, Blk)
+    static __device__ __forceinline__ void body(const Args& A, Blk)
     {
         if (threadIdx.x == 0) *A.out = A.h->n_active;
     }

@@ -130,7 +130,7 @@ template <bool PER>
 struct KnnTile {
     using Args = TileArgs;
     static constexpr int kThreads = kWave;
-    static __device__ void body(const Args& TA, Blk B);
+    static __device__ __forceinline__ void body(const Args& TA, Blk B);
 };
 
 template <bool PER>
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kWave) void k_knn_tile(TileArgs TA)
 // (each wavefront takes its item from the die queue, so a grid of exactly the
 // run's items is all the body needs of its block)
 template <bool PER>
-__device__ void KnnTile<PER>::body(const Args& TA, Blk)
+__device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
 {
     const KnnArgs& A = TA.A;
     int32_t* __restrict__ fb0 = TA.fb0;

@@ -326,7 +326,7 @@ template <bool PER>
 struct KnnWave {
     using Args = WaveArgs;
     static constexpr int kThreads = kWave;
-    static __device__ void body(const Args& W, Blk B)
+    static __device__ __forceinline__ void body(const Args& W, Blk B)
     {
         __shared__ WaveLds L;
         const int lane = threadIdx.x;

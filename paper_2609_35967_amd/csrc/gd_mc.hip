@@ -142,7 +142,7 @@ template <bool DIRECT_HEAVY>
 struct McScreen {
     using Args = McArgs;
     static constexpr int kThreads = 256;
-    static __device__ void body(const Args& A, Blk B);
+    static __device__ __forceinline__ void body(const Args& A, Blk B);
 };
 
 template <bool DIRECT_HEAVY>
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void k_mc_screen(McArgs A)
 }
 
 template <bool DIRECT_HEAVY>
-__device__ void McScreen<DIRECT_HEAVY>::body(const Args& A, Blk B)
+__device__ __forceinline__ void McScreen<DIRECT_HEAVY>::body(const Args& A, Blk B)
 {
     __shared__ int32_t s_w[4];
     __shared__ int32_t s_base;
@@ -334,7 +334,7 @@ template <int KP2, bool F32>
 struct McEvents {
     using Args = EventArgs;
     static constexpr int kThreads = 256;
-    static __device__ void body(const Args& E, Blk B);
+    static __device__ __forceinline__ void body(const Args& E, Blk B);
 };
 
 template <int KP2, bool F32>
@@ -344,7 +344,7 @@ __global__ __launch_bounds__(256) void k_mc(EventArgs E)
 }
 
 template <int KP2, bool F32>
-__device__ void McEvents<KP2, F32>::body(const Args& E, Blk B)
+__device__ __forceinline__ void McEvents<KP2, F32>::body(const Args& E, Blk B)
 {
     const McArgs& A = E.A;
     const int64_t screen_blocks = E.screen_blocks;
@@ -653,7 +653,7 @@ struct AuditArgs {
 struct Audit {
     using Args = AuditArgs;
     static constexpr int kThreads = kAuditGroups * kNBin;
-    static __device__ void body(const Args& A, Blk B);
+    static __device__ __forceinline__ void body(const Args& A, Blk B);
 };
 
 __global__ __launch_bounds__(kAuditGroups * kNBin) void k_audit(AuditArgs A)
@@ -661,7 +661,7 @@ __global__ __launch_bounds__(kAuditGroups * kNBin) void k_audit(AuditArgs A)
     Audit::body(A, Blk{0, 1});
 }
 
-__device__ void Audit::body(const Args& A, Blk)
+__device__ __forceinline__ void Audit::body(const Args& A, Blk)
 {
     const DevProblem& P = A.P;
     const double* __restrict__ part = A.part;

@@ -35,7 +35,7 @@ struct LocalPushArgs {
 struct PushLocal {
     using Args = LocalPushArgs;
     static constexpr int kThreads = 256;
-    static __device__ void body(const Args& A, Blk B);
+    static __device__ __forceinline__ void body(const Args& A, Blk B);
 };
 
 __global__ __launch_bounds__(256) void k_push_local(LocalPushArgs A)
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void k_push_local(LocalPushArgs A)
     PushLocal::body(A, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
 }
 
-__device__ void PushLocal::body(const Args& A, Blk B)
+__device__ __forceinline__ void PushLocal::body(const Args& A, Blk B)
 {
     double* __restrict__ z = A.z;
     double* __restrict__ vz = A.vz;
@@ -101,7 +101,7 @@ struct PushArgs {
 struct PushGlobal {
     using Args = PushArgs;
     static constexpr int kThreads = 256;
-    static __device__ void body(const Args& A, Blk B);
+    static __device__ __forceinline__ void body(const Args& A, Blk B);
 };
 
 __global__ __launch_bounds__(256) void k_push_global(PushArgs A)
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_push_global(PushArgs A)
     PushGlobal::body(A, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
 }
 
-__device__ void PushGlobal::body(const Args& A, Blk B)
+__device__ __forceinline__ void PushGlobal::body(const Args& A, Blk B)
 {
     const int64_t i = B.id * int64_t(blockDim.x) + threadIdx.x;
     if (i >= A.P.n) return;

@@ -30,7 +30,7 @@ struct SnapArgs {
 struct Snapshot {
     using Args = SnapArgs;
     static constexpr int kThreads = 256;
-    static __device__ void body(const Args& A, Blk B)
+    static __device__ __forceinline__ void body(const Args& A, Blk B)
     {
         const int64_t i = B.id * int64_t(blockDim.x) + threadIdx.x;
         if (i >= A.n) return;
@@ -80,7 +80,7 @@ __device__ inline void gather_neighbours(const int32_t* row, int s0, int cmax, i
 struct Rates {
     using Args = RatesArgs;
     static constexpr int kThreads = 256;
-    static __device__ void body(const Args& A, Blk B);
+    static __device__ __forceinline__ void body(const Args& A, Blk B);
 };
 
 __global__ __launch_bounds__(256) void k_rates(RatesArgs A)
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_rates(RatesArgs A)
     Rates::body(A, Blk{xcd_block(), int64_t(gridDim.x)});
 }
 
-__device__ void Rates::body(const Args& A, Blk B)
+__device__ __forceinline__ void Rates::body(const Args& A, Blk B)
 {
     const int64_t i = B.id * int64_t(blockDim.x) + threadIdx.x;
     if (i >= A.P.n) return;
@@ -144,7 +144,7 @@ __device__ void Rates::body(const Args& A, Blk B)
 struct RatesF32 {
     using Args = RatesArgs;
     static constexpr int kThreads = 256;
-    static __device__ void body(const Args& A, Blk B);
+    static __device__ __forceinline__ void body(const Args& A, Blk B);
 };
 
 __global__ __launch_bounds__(256) void k_rates_f32(RatesArgs A)
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void k_rates_f32(RatesArgs A)
     RatesF32::body(A, Blk{xcd_block(), int64_t(gridDim.x)});
 }
 
-__device__ void RatesF32::body(const Args& A, Blk B)
+__device__ __forceinline__ void RatesF32::body(const Args& A, Blk B)
 {
     const int64_t i = B.id * int64_t(blockDim.x) + threadIdx.x;
     if (i >= A.P.n) return;
@@ -230,7 +230,7 @@ struct BinArgs {
 struct BinReduce {
     using Args = BinArgs;
     static constexpr int kThreads = kRedWaves * kWave;
-    static __device__ void body(const Args& A, Blk B);
+    static __device__ __forceinline__ void body(const Args& A, Blk B);
 };
 
 __global__ __launch_bounds__(kRedWaves * kWave) void k_bin_reduce(BinArgs A)
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kRedWaves * kWave) void k_bin_reduce(BinArgs A)
     BinReduce::body(A, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
 }
 
-__device__ void BinReduce::body(const Args& A, Blk B)
+__device__ __forceinline__ void BinReduce::body(const Args& A, Blk B)
 {
     const int mode = A.mode;
     const double* __restrict__ msnap = A.msnap;
@@ -365,7 +365,7 @@ struct PlanArgs {
 struct Plan {
     using Args = PlanArgs;
     static constexpr int kThreads = kPlanGroups * kNBin;
-    static __device__ void body(const Args& A, Blk B);
+    static __device__ __forceinline__ void body(const Args& A, Blk B);
 };
 
 __global__ __launch_bounds__(kPlanGroups * kNBin) void k_plan(PlanArgs A)
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(kPlanGroups * kNBin) void k_plan(PlanArgs A)
     Plan::body(A, Blk{0, 1});
 }
 
-__device__ void Plan::body(const Args& A, Blk)
+__device__ __forceinline__ void Plan::body(const Args& A, Blk)
 {
     const DevProblem& P = A.P;
     const double* __restrict__ part = A.part;
@@ -522,7 +522,7 @@ struct FoldArgs {
 struct PartFold {
     using Args = FoldArgs;
     static constexpr int kThreads = kRedBlocks;
-    static __device__ void body(const Args& A, Blk B);
+    static __device__ __forceinline__ void body(const Args& A, Blk B);
 };
 
 __global__ __launch_bounds__(kRedBlocks) void k_part_fold(FoldArgs A)
@@ -530,7 +530,7 @@ __global__ __launch_bounds__(kRedBlocks) void k_part_fold(FoldArgs A)
     PartFold::body(A, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
 }
 
-__device__ void PartFold::body(const Args& A, Blk B)
+__device__ __forceinline__ void PartFold::body(const Args& A, Blk B)
 {
     __shared__ double c[kRedBlocks];
     __shared__ double hi[3][kRedBlocks], lo[3][kRedBlocks];

@@ -23,10 +23,10 @@ struct BboxArgs {
 struct BboxPartial {
     using Args = BboxArgs;
     static constexpr int kThreads = 256;
-    static __device__ void body(const Args& A, Blk B);
+    static __device__ __forceinline__ void body(const Args& A, Blk B);
 };
 
-__device__ void BboxPartial::body(const Args& A, Blk B)
+__device__ __forceinline__ void BboxPartial::body(const Args& A, Blk B)
 {
     const double *x = A.x, *y = A.y, *z = A.z, *M = A.M;
     const int64_t n = A.n;
@@ -79,10 +79,10 @@ struct BboxFinalArgs {
 struct BboxFinal {
     using Args = BboxFinalArgs;
     static constexpr int kThreads = 64;
-    static __device__ void body(const Args& A, Blk B);
+    static __device__ __forceinline__ void body(const Args& A, Blk B);
 };
 
-__device__ void BboxFinal::body(const Args& A, Blk)
+__device__ __forceinline__ void BboxFinal::body(const Args& A, Blk)
 {
     const double* red = A.red;
     const int nblk = A.nblk;
@@ -151,7 +151,7 @@ struct MortonArgs {
 struct Morton {
     using Args = MortonArgs;
     static constexpr int kThreads = 256;
-    static __device__ void body(const Args& A, Blk B)
+    static __device__ __forceinline__ void body(const Args& A, Blk B)
     {
         const int64_t i = B.id * int64_t(blockDim.x) + threadIdx.x;
         if (i >= A.n) return;
@@ -190,7 +190,7 @@ struct RadixArgs {
 struct RadixHist {
     using Args = RadixArgs;
     static constexpr int kThreads = 256;
-    static __device__ void body(const Args& A, Blk B)
+    static __device__ __forceinline__ void body(const Args& A, Blk B)
     {
         __shared__ uint32_t h[256];
         h[threadIdx.x] = 0;
@@ -236,7 +236,7 @@ __device__ inline uint32_t block_scan_excl_256(uint32_t v, uint32_t* s_w, uint32
 struct ScanRows {
     using Args = RadixArgs;
     static constexpr int kThreads = 256;
-    static __device__ void body(const Args& A, Blk B)
+    static __device__ __forceinline__ void body(const Args& A, Blk B)
     {
         __shared__ uint32_t s_w[4];
         const int nblk = A.nblk;
@@ -262,10 +262,10 @@ __global__ __launch_bounds__(256) void k_scan_rows(RadixArgs A)
 struct RadixScatter {
     using Args = RadixArgs;
     static constexpr int kThreads = 256;
-    static __device__ void body(const Args& A, Blk B);
+    static __device__ __forceinline__ void body(const Args& A, Blk B);
 };
 
-__device__ void RadixScatter::body(const Args& A, Blk B)
+__device__ __forceinline__ void RadixScatter::body(const Args& A, Blk B)
 {
     const uint32_t* __restrict__ kin = A.kin;
     const uint32_t* __restrict__ vin = A.vin;
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(RadixArgs A)
 struct Permute {
     using Args = PermuteArgs;
     static constexpr int kThreads = 256;
-    static __device__ void body(const Args& A, Blk B);
+    static __device__ __forceinline__ void body(const Args& A, Blk B);
 };
 
 __global__ __launch_bounds__(256) void k_permute(PermuteArgs A)
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(256) void k_permute(PermuteArgs A)
     Permute::body(A, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
 }
 
-__device__ void Permute::body(const Args& A, Blk B)
+__device__ __forceinline__ void Permute::body(const Args& A, Blk B)
 {
     const int64_t i = B.id * int64_t(blockDim.x) + threadIdx.x;
     if (i >= A.n) return;

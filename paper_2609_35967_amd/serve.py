@@ -131,7 +131,7 @@ class _Tier:
 
 class Server:
     def __init__(self, budget_bytes: float, tiers=(1 << 14, 1 << 17), depth: int = 2, max_runs: int = 1024,
-                 device: str = "cuda", keep_results: bool = True, round_cap: int = 1 << 20, cus=None):
+                 device: str = "cuda", keep_results: bool = True, round_cap: int = 1 << 19, cus=None):
         """tiers: particle-count limits of the tiers but the last (a run goes
         to the first tier whose limit it does not exceed); depth: rounds a
         tier keeps queued; round_cap: particles one round of a tier steps at
