@@ -591,16 +591,26 @@ def serve_bench(args):
     torch.cuda.synchronize()
     m.close()
     del w, m
-    srv = Server(budget_bytes=200e9, keep_results=False)
-    t0 = time.perf_counter()
-    drive(srv, [(r.arrival, r) for r in runs], lambda: time.perf_counter() - t0)
-    wall_s = time.perf_counter() - t0
-    rounds = srv.rounds
-    srv.close()
-    p50, p99 = latency_percentiles(srv.finished)
-    g50, g99 = gap_percentiles(srv.finished)
-    print(f"[bench] served in {wall_s:.2f} s, {rounds} tier rounds, p50/p99 {p50:.3f}/{p99:.3f} ms, "
-          f"gap p50/p99 {g50:.3f}/{g99:.3f} ms; saturated pass", file=sys.stderr, flush=True)
+    def served(exclusive):
+        for r in runs:
+            r.done, r.finished, r.latencies_ms, r.ends_ms, r.engine = 0, 0, [], [], None
+        torch.cuda.synchronize()
+        srv = Server(budget_bytes=200e9, keep_results=False, exclusive=exclusive)
+        t0 = time.perf_counter()
+        drive(srv, [(r.arrival, r) for r in runs], lambda: time.perf_counter() - t0)
+        wall = time.perf_counter() - t0
+        srv.close()
+        p50, p99 = latency_percentiles(srv.finished)
+        g50, g99 = gap_percentiles(srv.finished)
+        print(f"[bench] served ({'tiers in turn' if exclusive else 'tiers side by side'}) in {wall:.2f} s, "
+              f"{srv.rounds} tier rounds, p50/p99 {p50:.3f}/{p99:.3f} ms, gap p50/p99 {g50:.3f}/{g99:.3f} ms",
+              file=sys.stderr, flush=True)
+        return dict(wall_s=round(wall, 3), tier_rounds=srv.rounds, p50_ms=round(p50, 3), p99_ms=round(p99, 3),
+                    gap_p50_ms=round(g50, 3), gap_p99_ms=round(g99, 3))
+
+    side = served(False)
+    turn = served(True)
+    wall_s = turn["wall_s"]
     # capacity: the same runs all submitted at once
     sat = Server(budget_bytes=200e9, keep_results=False)
     for r in runs:
@@ -635,19 +645,21 @@ def serve_bench(args):
                              "(Poisson), N log-uniform 2^12..2^20, alpha log-uniform 1e-4..1e-2, v_frag uniform "
                              f"1..10 m/s, {intervals} intervals each, 200 GB budget, k=32",
                     n_runs=len(runs), particle_intervals=total,
-                    form="served: size tiers (N <= 2^14, <= 2^17, larger) on a stream each, not in lock-step; "
-                         "a tier round is one launch per stage over a group of its runs (at most 2^19 particles, "
-                         "gd_many_interval), two rounds queued"),
-        wall_s=round(wall_s, 3), tier_rounds=rounds,
-        p50_ms=round(p50, 3), p99_ms=round(p99, 3),
+                    form="served: size tiers (N <= 2^14, <= 2^17, larger), not in lock-step, taking turns on one "
+                         "stream (two rounds queued); a tier round is one launch per stage over a group of its runs "
+                         "(at most 2^19 particles, gd_many_interval)"),
+        wall_s=turn["wall_s"], tier_rounds=turn["tier_rounds"],
+        p50_ms=turn["p50_ms"], p99_ms=turn["p99_ms"],
         latency="GPU time of the round that holds the interval",
-        gap_p50_ms=round(g50, 3), gap_p99_ms=round(g99, 3),
+        gap_p50_ms=turn["gap_p50_ms"], gap_p99_ms=turn["gap_p99_ms"],
+        side_by_side=dict(side, value=round(total / side["wall_s"], 1),
+                          form="the same tiers each on a stream of its own, running side by side"),
         plain=dict(value=round(total / plain_s, 1), wall_s=round(plain_s, 3),
                    p50_ms=round(float(np.percentile(plain_lat, 50)), 3),
                    p99_ms=round(float(np.percentile(plain_lat, 99)), 3),
                    form="the same runs one after another, plain single-run form"),
         saturated=dict(value=round(total / sat_s, 1), wall_s=round(sat_s, 3), tier_rounds=srounds,
-                       form="the same runs all submitted at once"),
+                       form="the same runs all submitted at once, tiers side by side"),
         saturated_over_plain=round(plain_s / sat_s, 3),
     )
     print(json.dumps(out), flush=True)

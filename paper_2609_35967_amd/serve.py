@@ -53,10 +53,10 @@ class Run:
 
 
 class _Tier:
-    def __init__(self, torch, device, cap: int, cus=None):
+    def __init__(self, torch, device, cap: int, cus=None, stream=None):
         self.torch = torch
         self.cu = CuStream(cus[0], cus[1], device=device) if cus else None
-        self.stream = self.cu.stream if cus else torch.cuda.Stream(device=device)
+        self.stream = self.cu.stream if cus else (stream or torch.cuda.Stream(device=device))
         self.cap = int(cap)
         self.runs: list[Run] = []
         self.groups: list[tuple[list[Run], ManyRuns]] = []
@@ -131,14 +131,18 @@ class _Tier:
 
 class Server:
     def __init__(self, budget_bytes: float, tiers=(1 << 14, 1 << 17), depth: int = 2, max_runs: int = 1024,
-                 device: str = "cuda", keep_results: bool = True, round_cap: int = 1 << 19, cus=None):
+                 device: str = "cuda", keep_results: bool = True, round_cap: int = 1 << 19, cus=None,
+                 exclusive: bool = False):
         """tiers: particle-count limits of the tiers but the last (a run goes
         to the first tier whose limit it does not exceed); depth: rounds a
         tier keeps queued; round_cap: particles one round of a tier steps at
         most (a tier with more live runs takes them in groups, round after
         round, so that a long round does not hold every run's interval);
         cus: None, or per tier (first CU, CU count) of the compute units its
-        stream may use (a stream per tier restricted to them)."""
+        stream may use (a stream per tier restricted to them); exclusive:
+        the tiers take turns on one stream (at most `depth` rounds queued in
+        all), so that no round shares the device with another: the lowest
+        interval latency, at the price of capacity."""
         import torch
         self.keep_results = bool(keep_results)
         self.torch = torch
@@ -150,7 +154,12 @@ class Server:
         nt = len(self.limits) + 1
         if cus is not None and len(cus) != nt:
             raise ValueError(f"cus needs one (first, count) per tier ({nt})")
-        self.tiers = [_Tier(torch, device, round_cap, cus[i] if cus else None) for i in range(nt)]
+        self.exclusive = bool(exclusive)
+        if self.exclusive and cus is not None:
+            raise ValueError("exclusive tiers share one stream: no per-tier compute units")
+        shared = torch.cuda.Stream(device=device) if self.exclusive else None
+        self.tiers = [_Tier(torch, device, round_cap, cus[i] if cus else None, shared) for i in range(nt)]
+        self.turn = 0
         self.ref = torch.cuda.Event(enable_timing=True)  # the server clock's origin
         self.ref.record(torch.cuda.current_stream())
         self.depth = max(1, int(depth))
@@ -223,6 +232,20 @@ class Server:
         out, launched = [], False
         for t in self.tiers:
             out += self._collect(t)
+        if self.exclusive:
+            # tiers in turn while the shared stream has room
+            nt = len(self.tiers)
+            for d in range(nt):
+                if sum(len(x.inflight) for x in self.tiers) >= self.depth:
+                    break
+                t = self.tiers[(self.turn + d) % nt]
+                if t.launch():
+                    self.rounds += 1
+                    launched = True
+                    self.turn = (self.turn + d + 1) % nt
+                    break
+            return out, launched
+        for t in self.tiers:
             if len(t.inflight) < self.depth and t.launch():
                 self.rounds += 1
                 launched = True

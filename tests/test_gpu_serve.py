@@ -76,9 +76,10 @@ def test_served_runs_match_alone():
         assert run.engine.status() == 0
 
 
-def test_driven_runs_match_alone():
+@pytest.mark.parametrize("exclusive", [False, True])
+def test_driven_runs_match_alone(exclusive):
     # every run submitted at its own time into the non-blocking driver: tiers
-    # advance on their own streams with two rounds queued
+    # advance on their own streams with two rounds queued (or take turns on one)
     import time
     load()
     runs = _runs()
@@ -88,8 +89,11 @@ def test_driven_runs_match_alone():
         for _ in range(run.intervals):
             e.step()
         ref[run.rid] = _state(e)
-    # the middle tier's stream may use only a share of the compute units
-    srv = Server(budget_bytes=1e12, tiers=(4500, 7000), cus=[(0, 256), (0, 32), (32, 224)])
+    # side by side, the middle tier's stream may use only a share of the compute units
+    if exclusive:
+        srv = Server(budget_bytes=1e12, tiers=(4500, 7000), exclusive=True)
+    else:
+        srv = Server(budget_bytes=1e12, tiers=(4500, 7000), cus=[(0, 256), (0, 32), (32, 224)])
     t0 = time.perf_counter()
     drive(srv, [(0.002 * a, r) for r, a in runs], lambda: time.perf_counter() - t0)
     torch.cuda.synchronize()
