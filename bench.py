@@ -439,7 +439,7 @@ def strang_bench(args):
     params = dict(params, diffusion="concentration", Sc=(1.0, 1.0, 1.0))
     eng = Engine(params, st, seed=args.seed)
     if args.groups:
-        eng.set_groups(args.groups, concurrent=args.group_streams)
+        eng.set_groups(args.groups, concurrent=args.group_streams, device=args.group_device)
     n = eng.n
     for _ in range(args.warmup):
         eng.strang_step()
@@ -528,7 +528,7 @@ def groups_bench(args):
     params, st = workloads.by_name(args.workload, seed=args.seed, n=args.n)
     single = Engine(params, st, seed=args.seed)
     grouped = Engine(params, st, seed=args.seed)
-    grouped.set_groups(args.groups, concurrent=args.group_streams)
+    grouped.set_groups(args.groups, concurrent=args.group_streams, device=args.group_device)
     n = single.n
     for _ in range(max(1, args.warmup)):
         single.collide()
@@ -545,7 +545,9 @@ def groups_bench(args):
         config=dict(workload=f"{args.workload}: 3D disk annulus r in [10,100] au, {n} particles, k=32, "
                              f"alpha=1e-3, v_frag=1 m/s; one collision step of dt_coll = P(10 au)/50 without "
                              f"transport, {args.groups} Morton-range groups", n_particles=n, groups=args.groups,
-                    form="a workspace and stream per group" if args.group_streams else "one workspace and stream"),
+                    form=("the scheduler on the device, a workspace per group, one launch per stage over the "
+                          "groups at each instant" if args.group_device else
+                          "a workspace and stream per group" if args.group_streams else "one workspace and stream")),
         p50_ms=round(float(np.percentile(lat_g, 50)), 4), p99_ms=round(float(np.percentile(lat_g, 99)), 4),
         group_intervals_per_step=round(float(np.mean(gcounts)), 2),
         single=dict(value=round(n * args.steps / wall_s, 1), ms_per_step=round(wall_s / args.steps * 1e3, 4),
@@ -692,6 +694,8 @@ def main():
                     help="paper-cadence transport steps C D T D C on the disk instead")
     ap.add_argument("--group-streams", action="store_true",
                     help="with --groups: a workspace and stream per group, so groups' sampling overlaps")
+    ap.add_argument("--group-device", action="store_true",
+                    help="with --groups: the group scheduler on the device (gd_group_sched_*)")
     ap.add_argument("--reshuffle", action="store_true",
                     help="the product-kernel loop with neighbour reshuffling instead")
     ap.add_argument("--groups", type=int, default=0, metavar="G",

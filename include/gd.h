@@ -449,6 +449,44 @@ int32_t gd_sample_collisions_group(const gd_problem* p, const gd_particles* st, 
 int32_t gd_publish_group(const gd_problem* p, const gd_particles* st, int64_t lo, int64_t hi, int64_t* sched,
                          int32_t group, void* stream);
 
+/* The collision step of the spatial groups with its scheduler on the device
+ * (Sect. 2.5.3; the same schedule, results and random numbers as the
+ * gd_*_group calls driven instant by instant).  Each instant is one fixed
+ * sequence of launches over all groups, every stage predicated on flags a
+ * device kernel sets: the groups whose interval ends publish their masses
+ * (m[cur ^ 1] -> m[cur] over their slots), the snapshot of every particle
+ * is refreshed in snap_ws when some group starts, the starting groups plan,
+ * are clamped in ascending order by the ratio-16 rule (each interval takes
+ * the next number in planning order, which keys its draws), and sample and
+ * audit their intervals.  After the step's 2^30 ticks later instants do
+ * nothing, so the caller queues several and reads one flag.
+ *
+ * gd_group_sched_create: the groups are group_lo[g] .. group_lo[g+1] of the
+ * active slots (host array, G + 1 entries, 1 <= G <= 64, strictly
+ * increasing from 0); ivs points at G consecutive interval states; rows (G
+ * words, from gd_group_interactions) and sched (G int64) are device arrays;
+ * ws holds G workspaces of ws_bytes each (gd_workspace_size of the whole
+ * problem), snap_ws the workspace whose snapshot every group reads.  The
+ * state's cur selects the broadcast masses.  Everything stays caller-owned;
+ * the library allocates its tables and a small scheduler state
+ * (hipMalloc).  gd_group_sched_begin starts a collision step whose first
+ * interval takes number first_interval; gd_group_sched_instants queues
+ * `count` instants; gd_group_sched_read synchronises the stream and returns
+ * whether the step is done, the next interval number, and up to log_cap
+ * (group, start tick, ticks) records of the step's intervals (n_log = -1
+ * when more than 2^14 were dropped).  Errors: GD_E_INVALID_ARG,
+ * GD_E_WORKSPACE, GD_E_HIP. */
+typedef struct gd_group_sched gd_group_sched;
+int32_t gd_group_sched_create(const gd_problem* p, const gd_particles* st, const gd_neighbors* nb,
+                              const int32_t* group_lo, int32_t G, gd_interval* ivs, const uint64_t* rows,
+                              int64_t* sched, double* lam_i, int32_t* n_events, void* const* ws,
+                              size_t ws_bytes, void* snap_ws, uint64_t seed, gd_group_sched** out);
+int32_t gd_group_sched_begin(gd_group_sched* g, int64_t first_interval, void* stream);
+int32_t gd_group_sched_instants(gd_group_sched* g, int32_t count, void* stream);
+int32_t gd_group_sched_read(gd_group_sched* g, void* stream, int32_t* done, int64_t* next_interval,
+                            int32_t* n_log, int64_t* log, int32_t log_cap);
+int32_t gd_group_sched_destroy(gd_group_sched* g);
+
 /* Dust diffusion operator D (Sect. 2.4), one Euler--Maruyama step of length
  * dt >= 0 on every active particle of st (M_i > 0), in place.
  * D_a = nu/(Sc_a (1 + St^2)) in each cylindrical direction a = R, Z, phi with

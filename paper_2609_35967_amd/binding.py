@@ -90,7 +90,9 @@ EXPORTS = ("gd_workspace_size", "gd_workspace_init", "gd_interval_init", "gd_bui
            "gd_reshuffle_neighbors", "gd_diffuse", "gd_group_interactions", "gd_collision_rates_group",
            "gd_sample_collisions_group", "gd_publish_group", "gd_reshuffle_neighbors_static",
            "gd_many_create", "gd_many_interval", "gd_many_parity", "gd_many_destroy", "gd_stream_create_cu_mask",
-           "gd_stream_destroy", "gd_transport_dt")
+           "gd_stream_destroy", "gd_transport_dt",
+           "gd_group_sched_create", "gd_group_sched_begin", "gd_group_sched_instants", "gd_group_sched_read",
+           "gd_group_sched_destroy")
 PROF = {"sort": 0, "tree": 1, "knn_query": 2, "rates": 3, "mc": 4, "audit": 5, "push": 6, "diffuse": 7}
 GD_INTERVAL_ON_DEVICE = (1 << 64) - 1
 
@@ -148,6 +150,13 @@ def load(path: str | None = None):
     L.gd_many_destroy.argtypes = [vp]
     L.gd_stream_create_cu_mask.argtypes = [C.POINTER(C.c_uint32), C.c_int32, C.POINTER(vp)]
     L.gd_stream_destroy.argtypes = [vp]
+    L.gd_group_sched_create.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.POINTER(GdNeighbors), vp,
+                                        C.c_int32, vp, vp, vp, vp, vp, vp, C.c_size_t, vp, C.c_uint64, C.POINTER(vp)]
+    L.gd_group_sched_begin.argtypes = [vp, C.c_int64, vp]
+    L.gd_group_sched_instants.argtypes = [vp, C.c_int32, vp]
+    L.gd_group_sched_read.argtypes = [vp, vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int32), vp,
+                                      C.c_int32]
+    L.gd_group_sched_destroy.argtypes = [vp]
     L.gd_transport_dt.argtypes = [C.POINTER(GdProblem), C.POINTER(GdParticles), C.POINTER(GdNeighbors),
                                   C.POINTER(GdStepLimits), vp, vp, vp, C.c_size_t, vp]
     L.gd_status_read.argtypes = [vp, vp, C.POINTER(C.c_int32)]
@@ -160,7 +169,8 @@ def load(path: str | None = None):
                  "gd_reshuffle_neighbors", "gd_diffuse", "gd_group_interactions", "gd_collision_rates_group",
                  "gd_sample_collisions_group", "gd_publish_group", "gd_reshuffle_neighbors_static",
                  "gd_many_create", "gd_many_interval", "gd_many_parity", "gd_many_destroy",
-                 "gd_stream_create_cu_mask", "gd_stream_destroy", "gd_transport_dt"):
+                 "gd_stream_create_cu_mask", "gd_stream_destroy", "gd_transport_dt", "gd_group_sched_create",
+                 "gd_group_sched_begin", "gd_group_sched_instants", "gd_group_sched_read", "gd_group_sched_destroy"):
         getattr(L, name).restype = C.c_int32
     if path is None:
         _lib = L
@@ -390,18 +400,28 @@ class Engine:
         raise GdError(f"collision step not complete after {max_intervals} intervals")
 
     # ---- spatial groups (Sect. 2.5.3) ---------------------------------------------
-    def set_groups(self, n_groups: int, concurrent: bool = False):
+    def set_groups(self, n_groups: int, concurrent: bool = False, device: bool = False):
         """Split the active particles into `n_groups` contiguous Morton ranges, each
         with its own interval state; collide_groups() then schedules them.  With
         `concurrent`, every group also gets its own workspace and stream, so that
         the sampling of the groups starting at one instant overlaps (their plans
-        still run one after another, as the ratio rule orders them)."""
+        still run one after another, as the ratio rule orders them).  With
+        `device`, every group gets its own workspace and the scheduler runs on
+        the device (gd_group_sched_*): one launch per stage over the groups at
+        each instant, one host read per few instants."""
         torch = self.torch
         if not 1 <= n_groups <= 64:
             raise GdError("n_groups must be 1..64")
         self.n_groups = int(n_groups)
         self.gws = None
-        if concurrent:
+        self.gdev = bool(device)
+        self._close_gsched()
+        if device:
+            self.gdws = []
+            for _ in range(self.n_groups):
+                buf = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+                self.gdws.append((buf, (buf.data_ptr() + 255) & ~255))
+        if concurrent and not device:
             self.gws, self.gstreams = [], []
             for _ in range(self.n_groups):
                 buf = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
@@ -418,10 +438,58 @@ class Engine:
         self.group_lo = None
         if self.stream is not None or concurrent:  # the fills ran on torch's stream
             torch.cuda.current_stream(self.device).synchronize()
-        if concurrent:
+        if concurrent and not device:
             for _, ptr in self.gws:
                 check(self.lib.gd_workspace_init(C.byref(self.P), C.c_void_p(ptr), self.ws_bytes, self._s()))
             self._sync_own()
+        if device:
+            for _, ptr in self.gdws:
+                check(self.lib.gd_workspace_init(C.byref(self.P), C.c_void_p(ptr), self.ws_bytes, self._s()))
+            self._sync_own()
+
+    def _close_gsched(self):
+        h = getattr(self, "gsched_h", None)
+        if h:
+            self._sync_own()
+            check(self.lib.gd_group_sched_destroy(h))
+        self.gsched_h = None
+
+    def _collide_groups_device(self) -> list:
+        """collide_groups() with the scheduler on the device."""
+        if self.moved or self.group_lo is None or self.gsched_h is None or self.gsched_state != id(self.A):
+            if self.moved or self.group_lo is None:
+                if self.moved:
+                    self.build_neighbors()
+                self._group_layout()
+            self._close_gsched()
+            G = self.n_groups
+            sa = self.A.struct()
+            lo = (C.c_int32 * (G + 1))(*self.group_lo)
+            wsa = (C.c_void_p * G)(*[ptr for _, ptr in self.gdws])
+            h = C.c_void_p()
+            check(self.lib.gd_group_sched_create(C.byref(self.P), C.byref(sa), C.byref(self.nb), lo, G,
+                                                 C.c_void_p(self.ivg.data_ptr()), C.c_void_p(self.gmask.data_ptr()),
+                                                 C.c_void_p(self.gsched.data_ptr()), _ptr(self.lam), _ptr(self.events),
+                                                 wsa, self.ws_bytes, C.c_void_p(self.ws_ptr), self.seed, C.byref(h)))
+            self.gsched_h = h
+            self.gsched_state = id(self.A)
+        st = self._s()
+        check(self.lib.gd_group_sched_begin(self.gsched_h, self.interval, st))
+        done, nxt, nlog = C.c_int32(), C.c_int64(), C.c_int32()
+        batch = 2
+        while True:
+            check(self.lib.gd_group_sched_instants(self.gsched_h, batch, st))
+            check(self.lib.gd_group_sched_read(self.gsched_h, st, C.byref(done), C.byref(nxt), C.byref(nlog), None, 0))
+            if done.value:
+                break
+            batch = min(2 * batch, 16)
+        n = nlog.value
+        if n < 0:
+            raise GdError("more group intervals in one collision step than the scheduler's log holds")
+        log = (C.c_int64 * (3 * max(n, 1)))()
+        check(self.lib.gd_group_sched_read(self.gsched_h, st, C.byref(done), C.byref(nxt), C.byref(nlog), log, n))
+        self.interval = int(nxt.value)
+        return [(int(log[3 * i]), int(log[3 * i + 1]), int(log[3 * i + 2])) for i in range(n)]
 
     def _group_layout(self):
         """Ranges over the active slots after a build, and the interaction rows (synchronises)."""
@@ -463,6 +531,8 @@ class Engine:
         interval is sampled when it starts, against one snapshot per instant;
         its masses are broadcast when it ends.  Returns the executed intervals
         as (group, start tick, ticks).  Synchronises once per instant."""
+        if getattr(self, "gdev", False):
+            return self._collide_groups_device()
         T = 1 << 30
         if self.moved or self.group_lo is None:
             if self.moved:
@@ -597,6 +667,10 @@ class Engine:
         for g, (_, ptr) in enumerate(getattr(self, "gws", None) or []):
             check(self.lib.gd_status_read(C.c_void_p(ptr), C.c_void_p(self.gstreams[g].cuda_stream), C.byref(v)))
             out |= v.value
+        if getattr(self, "gdev", False):
+            for _, ptr in self.gdws:
+                check(self.lib.gd_status_read(C.c_void_p(ptr), self._s(), C.byref(v)))
+                out |= v.value
         return out
 
     def state_numpy(self) -> dict:

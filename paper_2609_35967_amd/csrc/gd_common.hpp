@@ -193,12 +193,14 @@ struct Blk {
 struct RunMap {
     const int32_t* run;
     const int32_t* b0;
+    const int32_t* active;  // per-run flags read on the device (null: every run); a run whose flag is 0 skips the stage
 };
 
 template <class K>
 __global__ __launch_bounds__(K::kThreads) void k_many(const typename K::Args* __restrict__ T, RunMap M)
 {
     const int32_t r = M.run[blockIdx.x];
+    if (M.active && !M.active[r]) return;
     const int32_t s = M.b0[r];
     // the run's arguments are read where they lie (uniform loads), not
     // copied: a copy indexed at run time would live in scratch memory

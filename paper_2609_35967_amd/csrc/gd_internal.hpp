@@ -81,6 +81,14 @@ struct ManyRun {
     void* ws;
     Layout L;
     uint64_t seed;
+    // a spatial group as a run: its arrays (out, nb, lam_i, n_events) start at
+    // slot `lo` of one particle set of n_all slots, whose snapshot is `snap`
+    // (null: the run's own, in its workspace); the sampling's interval index
+    // is read from *interval_at when set
+    int64_t lo = 0;
+    int64_t n_all = -1;
+    double4* snap = nullptr;
+    const int64_t* interval_at = nullptr;
 };
 
 struct ManyStep;
@@ -90,6 +98,7 @@ struct ManyStep {
     size_t tab, run, b0;  // arena offsets of the argument table and the block map
     int64_t nblocks;
     int64_t a0, a1;       // step-specific values
+    const int32_t* active = nullptr;  // per-run flags (device), or null
 };
 
 struct ManyBuilder {
@@ -121,11 +130,12 @@ struct ManyBuilder {
         b0_off = put_vec(b0);
         return b0.back();
     }
+    const int32_t* active = nullptr;  // flags the next added steps are predicated on
     template <class K>
     void add(const std::vector<typename K::Args>& tab, const std::vector<int64_t>& nb);
     void add_raw(ManyFn fn, size_t tab, int64_t a0, int64_t a1)
     {
-        steps.push_back(ManyStep{fn, tab, 0, 0, 0, a0, a1});
+        steps.push_back(ManyStep{fn, tab, 0, 0, 0, a0, a1, active});
     }
 };
 
@@ -133,7 +143,8 @@ template <class K>
 void many_launch(char* base, const ManyStep& s, hipStream_t st)
 {
     if (s.nblocks <= 0) return;
-    const RunMap M{reinterpret_cast<const int32_t*>(base + s.run), reinterpret_cast<const int32_t*>(base + s.b0)};
+    const RunMap M{reinterpret_cast<const int32_t*>(base + s.run), reinterpret_cast<const int32_t*>(base + s.b0),
+                   s.active};
     hipLaunchKernelGGL(k_many<K>, dim3(unsigned(s.nblocks)), dim3(K::kThreads), 0, st,
                        reinterpret_cast<const typename K::Args*>(base + s.tab), M);
 }
@@ -142,7 +153,7 @@ void many_launch(char* base, const ManyStep& s, hipStream_t st)
 template <class K>
 void ManyBuilder::add(const std::vector<typename K::Args>& tab, const std::vector<int64_t>& nb)
 {
-    ManyStep s{&many_launch<K>, put_vec(tab), 0, 0, 0, 0, 0};
+    ManyStep s{&many_launch<K>, put_vec(tab), 0, 0, 0, 0, 0, active};
     s.nblocks = map(nb, s.run, s.b0);
     steps.push_back(s);
 }
@@ -151,9 +162,10 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 void many_sort(ManyBuilder& B, const std::vector<ManyRun>& R);
 void many_knn(ManyBuilder& B, const std::vector<ManyRun>& R);
-void many_rates(ManyBuilder& B, const std::vector<ManyRun>& R);
+void many_rates(ManyBuilder& B, const std::vector<ManyRun>& R, bool own_snapshot = true);
 void many_sample(ManyBuilder& B, const std::vector<ManyRun>& R);
 void many_audit_sums(ManyBuilder& B, const std::vector<ManyRun>& R);
+void many_snapshot(ManyBuilder& B, const gd_problem* p, const gd_particles* s, double4* snap);
 void many_push(ManyBuilder& B, const std::vector<ManyRun>& R);
 
 }  // namespace gd

@@ -55,7 +55,15 @@ struct McArgs {
     int32_t* list;       // particles with an event (screen -> event pass), a segment per die
     int32_t* list_seg;   // the segments' counts
     int32_t* list_next;  // the event pass's next group
+    const int64_t* interval_at;  // when set: the interval index (a spatial group's number in planning order)
+    const int32_t* active;       // when set and 0: the run has no interval now (its deferred list is skipped)
 };
+
+__device__ inline uint32_t mc_interval(const McArgs& A)
+{
+    if (A.interval_at) return uint32_t(*A.interval_at);
+    return A.interval_on_device ? uint32_t(A.iv->n_intervals) : A.interval;
+}
 
 // a particle handed over after e events, at time t of the interval, with mass m
 struct Deferred {
@@ -164,7 +172,7 @@ __device__ __forceinline__ void McScreen<DIRECT_HEAVY>::body(const Args& A, Blk 
         const double m = A.m[i];
         const double li = A.lam_i[i];
         if (c > 1 && li > 0.0) {
-            const uint32_t interval = A.interval_on_device ? uint32_t(A.iv->n_intervals) : A.interval;
+            const uint32_t interval = mc_interval(A);
             double u[4];
             event_uniforms(A.seed, A.id[i], interval, 0u, u);
             ev = !(-log(u[0]) / li > A.iv->dt_exe);
@@ -208,7 +216,7 @@ __device__ inline int mc_particle(const McArgs& A, int64_t i)
         double m = A.m[i];
         double li = A.lam_i[i];
         const double dt_exe = A.iv->dt_exe;
-        const uint32_t interval = A.interval_on_device ? uint32_t(A.iv->n_intervals) : A.interval;
+        const uint32_t interval = mc_interval(A);
         if (c > 1 && li > 0.0) {
             const uint32_t pid = A.id[i];
             const int32_t* row = A.nbr + i * k;
@@ -427,7 +435,7 @@ __device__ inline int run_deferred(const McArgs& A, int32_t hidx, int lane)
     constexpr int W = KP2 < kWave ? KP2 : kWave;  // lanes holding slots
     const bool phys = A.P.kernel == GD_KERNEL_PHYSICAL;
     const double dt_exe = A.iv->dt_exe;
-    const uint32_t interval = A.interval_on_device ? uint32_t(A.iv->n_intervals) : A.interval;
+    const uint32_t interval = mc_interval(A);
     const Deferred H = A.heavy[hidx];
     const int64_t i = H.i;
     int e = H.e;
@@ -596,7 +604,7 @@ __global__ __launch_bounds__(256) void k_mc_heavy_batch(char* table, int32_t nbo
     const McArgs* T = reinterpret_cast<const McArgs*>(table + kTableHeader);
     int32_t* counter = reinterpret_cast<int32_t*>(table);
     const int t = threadIdx.x, lane = t & 63;
-    for (int b = t; b < nbox; b += blockDim.x) s_pre[b] = *T[b].heavy_n;
+    for (int b = t; b < nbox; b += blockDim.x) s_pre[b] = (T[b].active && !*T[b].active) ? 0 : *T[b].heavy_n;
     __syncthreads();
     if (t < kWave) {  // exclusive prefix of the slots' counts, 64 at a time
         int32_t carry = 0;
@@ -935,6 +943,10 @@ void many_sample(ManyBuilder& B, const std::vector<ManyRun>& R)
     for (size_t r = 0; r < nr; ++r) {
         const ManyRun& x = R[r];
         ma[r] = mc_args(&x.p, &x.out, &x.nb, x.iv, x.lam_i, x.seed, 0u, true, x.n_events, nullptr, 0, x.ws, x.L);
+        if (x.snap) ma[r].snap = x.snap;
+        if (x.n_all >= 0) ma[r].n_all = x.n_all;
+        ma[r].interval_at = x.interval_at;
+        ma[r].active = B.active ? B.active + r : nullptr;
         clr[r] = ClearArgs{ma[r].list_seg, kXcd + 1, nullptr, 0};
         nb[r] = cdiv(x.p.n, 256);
         scr_d[r] = x.p.k > 64 ? nb[r] : 0;

@@ -702,7 +702,7 @@ int launch_rates_group(const gd_problem* p, const gd_particles* s, const gd_neig
 // Rates and plan of every run as stages of one interval: snapshot, rates,
 // the bin sums over n / red_div blocks per run (at most kRedBlocks), their
 // fold and the plan.
-void many_rates(ManyBuilder& B, const std::vector<ManyRun>& R)
+void many_rates(ManyBuilder& B, const std::vector<ManyRun>& R, bool own_snapshot)
 {
     const size_t nr = R.size();
     std::vector<SnapArgs> sn(nr);
@@ -718,7 +718,7 @@ void many_rates(ManyBuilder& B, const std::vector<ManyRun>& R)
         const DevProblem P = to_dev(p);
         const int64_t n = p->n;
         const double* m = s->m[s->cur];
-        double4* snap = at<double4>(x.ws, x.L.snap);
+        double4* snap = x.snap ? x.snap : at<double4>(x.ws, x.L.snap);
         sn[r] = SnapArgs{P, m, s->M, n, snap};
         RatesArgs& A = ra[r];
         A = RatesArgs{};
@@ -731,13 +731,13 @@ void many_rates(ManyBuilder& B, const std::vector<ManyRun>& R)
         A.y = s->y;
         A.z = s->z;
         A.snap = snap;
-        A.snap_own = snap;
+        A.snap_own = x.snap ? snap + x.lo : snap;
         A.lam = x.lam_i;
         A.lam_pair = nullptr;
         A.a = at<double>(x.ws, x.L.a);
         A.b = at<double>(x.ws, x.L.b);
         A.ws = x.ws;
-        A.n_all = n;
+        A.n_all = x.n_all >= 0 ? x.n_all : n;
         nb[r] = cdiv(n, 256);
         f64[r] = p->rates_fp32 ? 0 : nb[r];
         f32[r] = p->rates_fp32 ? nb[r] : 0;
@@ -748,12 +748,20 @@ void many_rates(ManyBuilder& B, const std::vector<ManyRun>& R)
         fo[r] = FoldArgs{part, folded, int(nred[r])};
         pl[r] = PlanArgs{P, folded, 1, x.iv, at<WsHeader>(x.ws, x.L.hdr), x.ws};
     }
-    B.add<Snapshot>(sn, nb);
+    if (own_snapshot) B.add<Snapshot>(sn, nb);
     B.add<Rates>(ra, f64);
     B.add<RatesF32>(ra, f32);
     B.add<BinReduce>(bi, nred);
     B.add<PartFold>(fo, nbin);
     B.add<Plan>(pl, one);
+}
+
+// the snapshot of a whole particle set as one step (one run; predicated by
+// the builder's flags when set)
+void many_snapshot(ManyBuilder& B, const gd_problem* p, const gd_particles* s, double4* snap)
+{
+    std::vector<SnapArgs> sn{SnapArgs{to_dev(p), s->m[s->cur], s->M, p->n, snap}};
+    B.add<Snapshot>(sn, std::vector<int64_t>{cdiv(p->n, 256)});
 }
 
 // the audit's bin sums and their fold (mode 1 over m_snap, M, m_new), for

@@ -33,14 +33,19 @@ def _by_id(d):
     return {k: np.asarray(v)[o] for k, v in d.items()}
 
 
-@pytest.mark.parametrize("G,n,concurrent", [(8, 2048, False), (5, 4099, False), (64, 8192, False),
-                                            (8, 2048, True), (5, 4099, True)])
-def test_grouped_steps_match_oracle(G, n, concurrent):
+def _set(eng, G, mode):
+    eng.set_groups(G, concurrent=mode == "streams", device=mode == "device")
+
+
+@pytest.mark.parametrize("G,n,mode", [(8, 2048, "host"), (5, 4099, "host"), (64, 8192, "host"),
+                                      (8, 2048, "streams"), (5, 4099, "streams"),
+                                      (8, 2048, "device"), (5, 4099, "device"), (64, 8192, "device")])
+def test_grouped_steps_match_oracle(G, n, mode):
     params = workloads.const_box_params(n)
     st = two_speed_box(n, 11)
     load()
     eng = Engine(params, st, seed=9)
-    eng.set_groups(G, concurrent=concurrent)
+    _set(eng, G, mode)
     run = GroupedRun(params, st, seed=9, n_groups=G)
     for step in range(2):
         d_gpu = eng.collide_groups()
@@ -78,13 +83,14 @@ def test_grouped_steps_with_inactive_particles():
     assert np.array_equal(got["m"][::9], st["m"][::9])
 
 
-def test_one_group_equals_single_group_step():
+@pytest.mark.parametrize("mode", ["host", "device"])
+def test_one_group_equals_single_group_step(mode):
     n = 4096
     params = workloads.const_box_params(n)
     st = two_speed_box(n, 12)
     load()
     a = Engine(params, st, seed=3)
-    a.set_groups(1)
+    _set(a, 1, mode)
     b = Engine(params, st, seed=3)
     for _ in range(2):
         da = a.collide_groups()
@@ -96,14 +102,14 @@ def test_one_group_equals_single_group_step():
     assert a.group_interval_state(0)["C"] == b.interval_state()["C"]
 
 
-@pytest.mark.parametrize("concurrent", [False, True])
-def test_grouped_physical_disk(concurrent):
+@pytest.mark.parametrize("mode", ["host", "streams", "device"])
+def test_grouped_physical_disk(mode):
     n = 4096
     params = workloads.disk3d_params(n)
     st = workloads.disk3d(13, n, warm=True, params=params)
     load()
     eng = Engine(params, st, seed=4)
-    eng.set_groups(4, concurrent=concurrent)
+    _set(eng, 4, mode)
     run = GroupedRun(params, st, seed=4, n_groups=4)
     d_gpu = eng.collide_groups()
     d_orc = run.collide_groups()
@@ -114,8 +120,8 @@ def test_grouped_physical_disk(concurrent):
     assert eng.status() & ~0x4 == 0  # every group workspace included
 
 
-@pytest.mark.parametrize("concurrent", [False, True])
-def test_grouped_strang_steps_match_oracle(concurrent):
+@pytest.mark.parametrize("mode", ["host", "streams", "device"])
+def test_grouped_strang_steps_match_oracle(mode):
     """The paper's cadence with grouped collision operators on a warm disk with
     diffusion: groups are re-formed from the new Morton order after motion."""
     n = 4096
@@ -123,7 +129,7 @@ def test_grouped_strang_steps_match_oracle(concurrent):
     st = workloads.disk3d(15, n, warm=True, params=params)
     load()
     eng = Engine(params, st, seed=6)
-    eng.set_groups(4, concurrent=concurrent)
+    _set(eng, 4, mode)
     run = GroupedRun(params, st, seed=6, n_groups=4)
     for step in range(2):
         n_gpu = eng.strang_step()
