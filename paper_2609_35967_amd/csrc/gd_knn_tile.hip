@@ -1,10 +1,10 @@
 // gd_knn_tile.hip -- the N_K nearest neighbours (N_K <= 33) of the 64
-// Morton-consecutive queries of a wavefront from shared candidate tiles
+// Morton-consecutive queries of a wavefront from shared candidate lists
 // (Sect. 2.5.1), exact.
 //
 // The per-lane search of gd_knn.hip walks the tree once per query; most of
 // its instructions go to box tests and walk bookkeeping, not to distances.
-// Here the wavefront's queries share the walk and the candidates:
+// Here the wavefront's queries share the walk:
 //   1. each lane's radius is its particle's distance from the previous search
 //      widened by kHintSlack (a lane without a usable one is handed back, see
 //      6); eight groups of eight Morton-consecutive lanes each bound their
@@ -14,12 +14,14 @@
 //      parent met; the buckets reached come out as (bucket, group) pairs;
 //   3. each pair's bucket is tested against the spheres of its group's eight
 //      lanes (the conservative single-precision test of gd_knn.hpp); a bucket
-//      one of them may reach joins that group's bucket list;
-//   4. the groups' buckets are staged through LDS two per group at a time,
-//      and every lane evaluates the exact d^2 to the 8 staged positions of its
-//      group.  Others within the radius are counted into the lane's
-//      logarithmic bins and recorded, with their bin, in its LDS list (a full
-//      list drops the entries above the bin that already completes k-1);
+//      one of them may reach joins that group's bucket list, and the lanes
+//      whose sphere may reach it mark its place in their own bit masks;
+//   4. every lane takes the buckets of its mask in turn, loads their four
+//      positions and evaluates the exact d^2 to each (the next bucket's loads
+//      in flight meanwhile).  Others within the radius are counted into the
+//      lane's logarithmic bins and recorded, with their bin, in its LDS list
+//      (a full list drops the entries above the bin that already completes
+//      k-1);
 //   5. the bin holding the (k-1)-th other splits the list into sure entries
 //      and a boundary bin ranked by (d^2, slot); the row is written once, in
 //      slot order;
@@ -38,35 +40,34 @@ namespace gd {
 
 constexpr int kTG = 8;               // lanes (queries) per group
 constexpr int kNGrp = kWave / kTG;   // groups per wavefront
-constexpr int kTList = 64;           // candidate list entries per lane
+constexpr int kTList = 48;           // candidate list entries per lane
 constexpr int kFront = 512;          // traversal frontier (nodes of one level)
-constexpr int kPairs = 1024;         // (bucket, group) pairs awaiting their sphere tests
+constexpr int kPairs = 512;          // (bucket, group) pairs awaiting their sphere tests
 constexpr int kGList = 128;          // buckets per group after the sphere tests
-constexpr int kTStep = 2 * kTG;      // candidates of a group staged per step (two per lane)
-static_assert(kGList * kBucket <= 512, "a list entry keeps the tile position in 9 bits");
+constexpr int kMaskW = kGList / 32;  // words of a lane's bucket mask
+static_assert(kGList * kBucket <= 2048, "a list entry keeps the bucket's place and slot in 11 bits");
 
 template <bool PER>
 struct TileLds {
     union {
+        // traversal and sphere tests
         struct {
             uint32_t front[2][kFront];  // node | group mask << 24
             uint32_t pairs[kPairs];     // bucket | group << 24
+            uint8_t gm[kNGrp][kGList];  // per place in a group's list: its lanes whose sphere may reach it
+            float4 sc[kWave];           // query (single precision) and its threshold (negative: none)
+            float4 sp[PER ? kWave : 1]; // its +L and -L images on periodic axes
+            float4 sm[PER ? kWave : 1];
         } t;
-        // per-lane candidate lists: bin << 11 | position in the group's tiles
-        // (bucket index in the group list * 4 + slot in the bucket)
-        uint16_t list[kTList][kWave];
+        // distances: per-lane candidate lists (bin << 11 | place in the
+        // group's list * 4 + slot in the bucket), then the boundary entries
+        struct {
+            uint16_t list[kTList][kWave];
+            uint16_t bnd[kC1][kWave];
+        } d;
     } u;
     uint32_t glist[kNGrp][kGList];
-    int32_t gcount[kNGrp];
-    int32_t npairs;
     float gbox[kNGrp][6];            // group boxes: lo[3], hi[3]
-    float4 sc[kWave];                // query (single precision) and its threshold (negative: none)
-    float4 sp[PER ? kWave : 1];      // its +L and -L images on periodic axes
-    float4 sm[PER ? kWave : 1];
-    // staged candidates (x, y, z, slot; slot -1: none), eight per group; each
-    // group's row is padded by 16 bytes so that the eight groups' concurrent
-    // reads fall in different LDS banks
-    double stage[kNGrp][kTStep * 4 + 2];
 };
 
 // 32 per-lane 8-bit bin counters in 8 registers
@@ -105,25 +106,6 @@ __device__ inline bool group_meets(const KnnArgs& A, const float (&g)[6], const 
         ok = ok && m;
     }
     return ok;
-}
-
-// exclusive prefix sum over the wavefront
-__device__ inline int wave_excl_scan(int v, int lane)
-{
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const int y = __shfl_up(x, o, kWave);
-        if (lane >= o) x += y;
-    }
-    return x - v;
-}
-
-__device__ inline int wave_sum_i(int v)
-{
-#pragma unroll
-    for (int m = 1; m < kWave; m <<= 1) v += __shfl_xor(v, m, kWave);
-    return v;
 }
 
 template <bool PER>
@@ -215,11 +197,13 @@ __device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
         qf.p[a] = PER ? float(qp[a] + A.L[a]) : 0.0f;
         qf.m[a] = PER ? float(qp[a] - A.L[a]) : 0.0f;
     }
-    L.sc[lane] = make_float4(qf.c[0], qf.c[1], qf.c[2], ok ? r2f(R2) : -1.0f);
+    L.u.t.sc[lane] = make_float4(qf.c[0], qf.c[1], qf.c[2], ok ? r2f(R2) : -1.0f);
     if (PER) {
-        L.sp[lane] = make_float4(qf.p[0], qf.p[1], qf.p[2], 0.0f);
-        L.sm[lane] = make_float4(qf.m[0], qf.m[1], qf.m[2], 0.0f);
+        L.u.t.sp[lane] = make_float4(qf.p[0], qf.p[1], qf.p[2], 0.0f);
+        L.u.t.sm[lane] = make_float4(qf.m[0], qf.m[1], qf.m[2], 0.0f);
     }
+    reinterpret_cast<uint4*>(&L.u.t.gm[0][0])[lane] = make_uint4(0u, 0u, 0u, 0u);
+    static_assert(sizeof(L.u.t.gm) == kWave * sizeof(uint4), "one 16-byte store per lane clears the lane masks");
     // the group boxes: each sphere's box, widened far beyond the rounding of
     // q +- R in double and rounded outward to single precision
     {
@@ -248,40 +232,52 @@ __device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
     uint32_t gall = 0;  // groups with at least one searching lane
 #pragma unroll
     for (int g = 0; g < kNGrp; ++g) gall |= ((okmask >> (kTG * g)) & 0xFFu) ? (1u << g) : 0u;
-    if (lane < kNGrp) L.gcount[lane] = 0;
     __syncthreads();
 
     bool wave_ok = gall != 0;
-    if (lane == 0) L.npairs = 0;
-    __syncthreads();
+    int npairs = 0;  // pairs waiting (uniform over the wavefront)
 #ifdef GD_KNN_STATS
     const long long tc1 = clock64();
     long long tcull = 0;
 #endif
     // 3. sphere tests of the pending pairs, 64 at a time: a bucket joins its
     //    group's list if the sphere of one of the group's searching lanes may
-    //    reach it
+    //    reach it, with the mask of those lanes
+    int gn[kNGrp];  // buckets listed per group (uniform over the wavefront)
+#pragma unroll
+    for (int g = 0; g < kNGrp; ++g) gn[g] = 0;
     auto cull = [&]() {
 #ifdef GD_KNN_STATS
         const long long t0 = clock64();
 #endif
-        const int np = L.npairs;
-        for (int p0 = 0; p0 < np; p0 += kWave) {
-            const int p = p0 + lane;
-            if (p < np) {
-                const uint32_t e = L.u.t.pairs[p];
-                const int g = int(e >> 24);
-                const FBox bx = A.boxes[e & 0xFFFFFFu];
-                bool hit = false;
+        __syncthreads();  // the pairs written by every lane
+        // the next 64 pairs' boxes are in flight while these are tested
+        uint32_t en = 0;
+        FBox bn{};
+        if (lane < npairs) {
+            en = L.u.t.pairs[lane];
+            bn = A.boxes[en & 0xFFFFFFu];
+        }
+        for (int p0 = 0; p0 < npairs; p0 += kWave) {
+            const bool valid = p0 + lane < npairs;
+            const uint32_t e = en;
+            const FBox bx = bn;
+            if (p0 + kWave + lane < npairs) {
+                en = L.u.t.pairs[p0 + kWave + lane];
+                bn = A.boxes[en & 0xFFFFFFu];
+            }
+            const int g = int(e >> 24);
+            uint32_t hit = 0;
+            if (valid) {
 #pragma unroll
                 for (int t = 0; t < kTG; ++t) {
-                    const float4 sq = L.sc[g * kTG + t];
+                    const float4 sq = L.u.t.sc[g * kTG + t];
                     QF f;
                     f.c[0] = sq.x;
                     f.c[1] = sq.y;
                     f.c[2] = sq.z;
                     if (PER) {
-                        const float4 sp = L.sp[g * kTG + t], sm = L.sm[g * kTG + t];
+                        const float4 sp = L.u.t.sp[g * kTG + t], sm = L.u.t.sm[g * kTG + t];
                         f.p[0] = sp.x;
                         f.p[1] = sp.y;
                         f.p[2] = sp.z;
@@ -289,17 +285,25 @@ __device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
                         f.m[1] = sm.y;
                         f.m[2] = sm.z;
                     }
-                    hit = hit || (sq.w >= 0.0f && box2f<PER>(A, f, bx) <= sq.w);
+                    hit |= (sq.w >= 0.0f && box2f<PER>(A, f, bx) <= sq.w) ? (1u << t) : 0u;
                 }
-                if (hit) {
-                    const int at = atomicAdd(&L.gcount[g], 1);
-                    if (at < kGList) L.glist[g][at] = e & 0xFFFFFFu;
-                }
+            }
+            // places in the groups' lists: per group, after the lanes below
+            int at = 0;
+#pragma unroll
+            for (int gq = 0; gq < kNGrp; ++gq) {
+                const bool mine = hit != 0 && g == gq;
+                const uint64_t bal = __ballot(mine);
+                if (mine) at = gn[gq] + int(__popcll(bal & ((uint64_t(1) << lane) - 1)));
+                gn[gq] += int(__popcll(bal));
+            }
+            if (hit && at < kGList) {
+                L.glist[g][at] = e & 0xFFFFFFu;
+                L.u.t.gm[g][at] = uint8_t(hit);
             }
         }
         __syncthreads();
-        if (lane == 0) L.npairs = 0;
-        __syncthreads();
+        npairs = 0;
 #ifdef GD_KNN_STATS
         tcull += clock64() - t0;
 #endif
@@ -359,20 +363,26 @@ __device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
                         if (cm) L.u.t.front[cur ^ 1][at] = uint32_t(child[u]) | (cm << 24);
                         nn += tot;
                     } else {
+                        // this lane's pairs go after those of the lanes below
+                        // it: prefix and total of the counts (<= 8) from one
+                        // ballot per bit
                         const int cnt = __popc(cm);
-                        const int tot = wave_sum_i(cnt);
-                        if (L.npairs + tot > kPairs) cull();  // room for these
-                        const int base = L.npairs;
-                        if (base + tot > kPairs) {
+                        int below = 0, tot = 0;
+#pragma unroll
+                        for (int bit = 0; bit < 4; ++bit) {
+                            const uint64_t bal = __ballot((cnt >> bit) & 1);
+                            below += int(__popcll(bal & ((uint64_t(1) << lane) - 1))) << bit;
+                            tot += int(__popcll(bal)) << bit;
+                        }
+                        if (npairs + tot > kPairs) cull();  // room for these
+                        if (npairs + tot > kPairs) {
                             wave_ok = false;
                             break;
                         }
-                        int w = base + wave_excl_scan(cnt, lane);
+                        int w = npairs + below;
                         for (uint32_t m = cm; m; m &= m - 1)
                             L.u.t.pairs[w++] = uint32_t(child[u]) | (uint32_t(__ffs(m) - 1) << 24);
-                        __syncthreads();
-                        if (lane == 0) L.npairs = base + tot;
-                        __syncthreads();
+                        npairs += tot;
                     }
                 }
             }
@@ -391,15 +401,45 @@ __device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
     const long long tc2 = clock64();
 #endif
 
-    // 4. candidate tiles: one bucket slot of its group per lane per step
-    const int gg = lane / kTG, sub = lane & (kTG - 1);
-    const int gcnt = wave_ok ? L.gcount[gg] : 0;
+    // 4. distances: every lane takes the buckets of its own mask in turn
+    const int gg = lane / kTG;
+    int gcnt = 0;
+#pragma unroll
+    for (int g = 0; g < kNGrp; ++g) gcnt = g == gg ? gn[g] : gcnt;
+    if (!wave_ok) gcnt = 0;
     if (gcnt > kGList) ok = false;  // the group's list overflowed
+    ok = ok && wave_ok;
+    // this lane's bit of each place of its group's list, four places per
+    // word read: bit t of bytes 0..3 gathered into bits 0..3 by one product
+    // (the partial products land on distinct bits, so nothing carries)
+    uint32_t mw[kMaskW];
+    {
+        const int t = lane & (kTG - 1);
+        const uint4* gw = reinterpret_cast<const uint4*>(&L.u.t.gm[gg][0]);
+#pragma unroll
+        for (int w = 0; w < kMaskW; ++w) mw[w] = 0u;
+#pragma unroll
+        for (int c = 0; c < kGList / 16; ++c) {
+            const uint4 v4 = gw[c];
+            const uint32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t bits = (v[i] >> t) & 0x01010101u;
+                const uint32_t nib = ((bits * 0x00204081u) >> 21) & 0xFu;
+                const int place = 16 * c + 4 * i;  // of byte 0
+                mw[place >> 5] |= nib << (place & 31);
+            }
+        }
+        if (!ok) {
+#pragma unroll
+            for (int w = 0; w < kMaskW; ++w) mw[w] = 0u;
+        }
+    }
+#ifdef GD_KNN_STATS
     int gmax = 0;
 #pragma unroll
-    for (int g = 0; g < kNGrp; ++g) gmax = max(gmax, wave_ok ? min(L.gcount[g], kGList) : 0);
-    const int gc = min(gcnt, kGList);
-    ok = ok && wave_ok;
+    for (int g = 0; g < kNGrp; ++g) gmax = max(gmax, wave_ok ? min(gn[g], kGList) : 0);
+#endif
     const double R2s = R2;                                  // bin scale: the first radius
     const double sA = ok && R2s > 0.0 ? 1.0 / R2s : 0.0;
     double R2cut = ok ? R2 : -1.0;
@@ -413,9 +453,9 @@ __device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
     Hist8 hist;
     auto hist_from_list = [&]() {
         hist.clear();
-        for (int e = 0; e < len; ++e) hist.add(entry_bin(L.u.list[e][lane]));
+        for (int e = 0; e < len; ++e) hist.add(entry_bin(L.u.d.list[e][lane]));
     };
-    // a list without room for a step: the bin completing k-1 others bounds
+    // a list without room for a bucket: the bin completing k-1 others bounds
     // what stays and what may still come
     auto cut_list = [&]() {
         hist_from_list();
@@ -434,51 +474,73 @@ __device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
         }
         int kept = 0;
         for (int e = 0; e < len; ++e) {
-            const uint16_t wv = L.u.list[e][lane];
-            if (entry_bin(wv) <= bcut) L.u.list[kept++][lane] = wv;
+            const uint16_t wv = L.u.d.list[e][lane];
+            if (entry_bin(wv) <= bcut) L.u.d.list[kept++][lane] = wv;
         }
         len = kept;
-        ovf = len > kTList - kTStep;
+        ovf = len > kTList - kBucket;
     };
-    const int steps = (gmax * kBucket + kTStep - 1) / kTStep;
-    double4 nxt[2];
-    int32_t nj[2];
-    auto fetch = [&](int t) {
+    // the lowest marked place (cleared from the mask), or -1
+    auto take_place = [&]() {
+        int at = -1;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int pos = kTStep * t + u * kTG + sub;  // this lane's slots of the group's tiles
-            nj[u] = -1;
-            if ((pos >> 2) < gc) {
-                const int j = int(L.glist[gg][pos >> 2]) * kBucket + (pos & (kBucket - 1));
-                if (j < na) nj[u] = j;
-            }
-        }
+        for (int w = kMaskW - 1; w >= 0; --w)
+            if (mw[w]) at = w * 32 + __ffs(mw[w]) - 1;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) nxt[u] = nj[u] >= 0 ? A.pos[nj[u]] : make_double4(NAN, NAN, NAN, 0.0);
+        for (int w = 0; w < kMaskW; ++w)
+            if (w == (at >> 5)) mw[w] &= mw[w] - 1u;
+        return at;
     };
-    if (steps > 0) fetch(0);
-    for (int t = 0; t < steps; ++t) {
+    // the four positions of the bucket at place `at`; its first slot, or na
+    // without a bucket (slots from na on are not evaluated)
+    struct Bk {
+        double x[kBucket], y[kBucket], z[kBucket];
+        int j0;
+    };
+    auto fetch = [&](int at) {
+        Bk r;
+        r.j0 = at >= 0 ? int(L.glist[gg][at]) * kBucket : na;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            double2* dst = reinterpret_cast<double2*>(&L.stage[gg][4 * (u * kTG + sub)]);
-            dst[0] = make_double2(nxt[u].x, nxt[u].y);
-            dst[1] = make_double2(nxt[u].z, double(nj[u]));
+        for (int s = 0; s < kBucket; ++s) {
+            const double* pj = reinterpret_cast<const double*>(A.pos + (r.j0 + s < na ? r.j0 + s : 0));
+            const double2 xy = *reinterpret_cast<const double2*>(pj);
+            r.x[s] = xy.x;
+            r.y[s] = xy.y;
+            r.z[s] = pj[2];
         }
-        __syncthreads();
-        if (t + 1 < steps) fetch(t + 1);
-        if (len > kTList - kTStep && !ovf) cut_list();  // room for a whole step
+        return r;
+    };
+    auto eval = [&](const Bk& c, int at) {
+        if (len > kTList - kBucket && !ovf) cut_list();  // room for a whole bucket
 #pragma unroll
-        for (int c = 0; c < kTStep; ++c) {
-            const double2* src = reinterpret_cast<const double2*>(&L.stage[gg][4 * c]);
-            const double2 s0 = src[0], s1 = src[1];
-            const double d2 = sep2<PER>(A, qp, s0.x, s0.y, s1.x);
-            const int j = int(s1.y);
-            if (d2 <= R2cut && j != q && j >= 0 && !ovf) {
+        for (int s = 0; s < kBucket; ++s) {
+            const double d2 = sep2<PER>(A, qp, c.x[s], c.y[s], c.z[s]);
+            const int j = c.j0 + s;
+            if (j < na && d2 <= R2cut && j != q && !ovf) {
                 const int b = log_bin(d2 * sA);
-                if (b <= bcut) L.u.list[len++][lane] = uint16_t((b << 11) | (kTStep * t + c));
+                if (b <= bcut) L.u.d.list[len++][lane] = uint16_t((b << 11) | (at * kBucket + s));
             }
         }
-        __syncthreads();
+    };
+    // two buckets in turn, each one's loads in flight while the other is
+    // evaluated (the two register sets fixed, not indexed)
+#ifdef GD_KNN_STATS
+    int iters = 0;
+#endif
+    int at0 = take_place(), at1 = -1;
+    Bk bk0 = fetch(at0), bk1;
+    for (;;) {
+        if (!__ballot(at0 >= 0)) break;
+        at1 = take_place();
+        bk1 = fetch(at1);
+        eval(bk0, at0);
+        if (!__ballot(at1 >= 0)) break;
+        at0 = take_place();
+        bk0 = fetch(at0);
+        eval(bk1, at1);
+#ifdef GD_KNN_STATS
+        iters += 2;
+#endif
     }
 #ifdef GD_KNN_STATS
     const long long tc4 = clock64();
@@ -510,15 +572,13 @@ __device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
     }
     int ntot = 0, nb = 0;
     double maxd2 = 0.0;
-    // the staging area is free now: the boundary entries wait there
-    uint16_t(*bnd)[kWave] = reinterpret_cast<uint16_t(*)[kWave]>(&L.stage[0][0]);
-    static_assert(sizeof(L.stage) >= kC1 * kWave * sizeof(uint16_t), "the boundary entries fit the staging area");
+    uint16_t(*bnd)[kWave] = L.u.d.bnd;
     if (ok) {
         // sure entries move to the front of the list, boundary entries aside
         for (int e = 0; e < len; ++e) {
-            const uint16_t wv = L.u.list[e][lane];
+            const uint16_t wv = L.u.d.list[e][lane];
             const int bn = entry_bin(wv);
-            if (bn < b0) L.u.list[ntot++][lane] = wv;
+            if (bn < b0) L.u.d.list[ntot++][lane] = wv;
             else if (bn == b0) bnd[nb++][lane] = wv;
         }
         if (ntot != c0 || nb != hb) set_status(A.ws, GD_DEV_INTERNAL);
@@ -539,7 +599,7 @@ __device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
 #pragma unroll
             for (int f = 0; f < kC1; ++f) rank += (bd[f] < bd[e]) || (bd[f] == bd[e] && bj[f] < bj[e]);
             if (e < nb && rank < needb) {
-                L.u.list[ntot + rank][lane] = bw[e];
+                L.u.d.list[ntot + rank][lane] = bw[e];
                 maxd2 = fmax(maxd2, bd[e]);
             }
         }
@@ -549,7 +609,7 @@ __device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
     // the row in slot order
     int32_t v[32];
 #pragma unroll
-    for (int e = 0; e < 32; ++e) v[e] = (ok && e < ntot) ? int32_t(slot_of(L.u.list[e][lane])) : INT32_MAX;
+    for (int e = 0; e < 32; ++e) v[e] = (ok && e < ntot) ? int32_t(slot_of(L.u.d.list[e][lane])) : INT32_MAX;
     bitonic_sort<32>(v);
     if (ok) {
         if (k == 32 && A.row_vec) {
@@ -573,14 +633,14 @@ __device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
         A.dmax[q] = ntot > 0 ? sqrt(maxd2) : 0.0;
     }
 #ifdef GD_KNN_STATS
-    if (lane == 0) {  // per wavefront: cycles of traversal, sphere tests, tiles, finish; pairs, steps
+    if (lane == 0) {  // per wavefront: cycles of traversal, sphere tests, distances, finish; largest group list, buckets per lane (the largest)
         int32_t* w = A.stats + int64_t(item) * 8;
         w[0] = int32_t(tc2 - tc1 - tcull);
         w[1] = int32_t(tcull);
         w[2] = int32_t(tc4 - tc3);
         w[3] = int32_t(clock64() - tc4);
         w[4] = gmax;
-        w[5] = steps;
+        w[5] = iters;
         w[6] = wave_ok ? 1 : 0;
     }
 #endif
