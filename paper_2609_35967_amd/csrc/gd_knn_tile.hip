@@ -40,7 +40,7 @@ namespace gd {
 
 constexpr int kTG = 8;               // lanes (queries) per group
 constexpr int kNGrp = kWave / kTG;   // groups per wavefront
-constexpr int kTList = 48;           // candidate list entries per lane
+constexpr int kTList = 64;           // candidate list entries per lane
 constexpr int kFront = 512;          // traversal frontier (nodes of one level)
 constexpr int kPairs = 512;          // (bucket, group) pairs awaiting their sphere tests
 constexpr int kGList = 128;          // buckets per group after the sphere tests
@@ -60,10 +60,10 @@ struct TileLds {
             float4 sm[PER ? kWave : 1];
         } t;
         // distances: per-lane candidate lists (bin << 11 | place in the
-        // group's list * 4 + slot in the bucket), then the boundary entries
+        // group's list * 4 + slot in the bucket); at the end the boundary
+        // entries wait at the tail
         struct {
             uint16_t list[kTList][kWave];
-            uint16_t bnd[kC1][kWave];
         } d;
     } u;
     uint32_t glist[kNGrp][kGList];
@@ -572,14 +572,26 @@ __device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
     }
     int ntot = 0, nb = 0;
     double maxd2 = 0.0;
-    uint16_t(*bnd)[kWave] = L.u.d.bnd;
+    // boundary entry e waits at list place kTList - 1 - e: fewer than k - 1
+    // sure entries and at most kC1 boundary ones leave room for them there
+    // once the entries beyond the boundary bin are gone
+    static_assert(32 + 2 * kC1 <= kTList, "the boundary entries fit the list's tail");
+    auto bnd = [&](int e) -> uint16_t& { return L.u.d.list[kTList - 1 - e][lane]; };
     if (ok) {
-        // sure entries move to the front of the list, boundary entries aside
+        if (len + hb > kTList) {  // first the entries beyond the boundary bin go
+            int kept = 0;
+            for (int e = 0; e < len; ++e) {
+                const uint16_t wv = L.u.d.list[e][lane];
+                if (entry_bin(wv) <= b0) L.u.d.list[kept++][lane] = wv;
+            }
+            len = kept;
+        }
+        // sure entries move to the front of the list, boundary entries to the tail
         for (int e = 0; e < len; ++e) {
             const uint16_t wv = L.u.d.list[e][lane];
             const int bn = entry_bin(wv);
             if (bn < b0) L.u.d.list[ntot++][lane] = wv;
-            else if (bn == b0) bnd[nb++][lane] = wv;
+            else if (bn == b0) bnd(nb++) = wv;
         }
         if (ntot != c0 || nb != hb) set_status(A.ws, GD_DEV_INTERNAL);
         // boundary entries ranked by (d^2, slot); the chosen ones follow
@@ -589,7 +601,7 @@ __device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
         uint16_t bw[kC1];
 #pragma unroll
         for (int e = 0; e < kC1; ++e) {
-            bw[e] = e < nb ? bnd[e][lane] : uint16_t(0);
+            bw[e] = e < nb ? bnd(e) : uint16_t(0);
             bj[e] = e < nb ? slot_of(bw[e]) : INT32_MAX;
             bd[e] = e < nb ? sep2_slot<PER>(A, qp, bj[e]) : INFINITY;
         }
