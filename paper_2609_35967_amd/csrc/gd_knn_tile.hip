@@ -86,7 +86,7 @@ struct Hist8 {
     __device__ int get(int b) const { return int((w[b >> 2] >> (8 * (b & 3))) & 0xFFu); }
 };
 
-__device__ inline bool span_meets(float lo, float hi, float blo, float bhi) { return blo <= hi && lo <= bhi; }
+__device__ inline bool span_meets(float lo, float hi, float blo, float bhi) { return (blo <= hi) & (lo <= bhi); }
 
 // does box b meet group box g (with its periodic images)?
 template <bool PER>
@@ -98,12 +98,12 @@ __device__ inline bool group_meets(const KnnArgs& A, const float (&g)[6], const 
         bool m = span_meets(g[a], g[3 + a], b.lo[a], b.hi[a]);
         if (PER && A.per[a]) {
             const double L = A.L[a];
-            m = m || span_meets(__double2float_rd(double(g[a]) + L), __double2float_ru(double(g[3 + a]) + L), b.lo[a],
-                                b.hi[a]);
-            m = m || span_meets(__double2float_rd(double(g[a]) - L), __double2float_ru(double(g[3 + a]) - L), b.lo[a],
-                                b.hi[a]);
+            m = m | span_meets(__double2float_rd(double(g[a]) + L), __double2float_ru(double(g[3 + a]) + L), b.lo[a],
+                               b.hi[a]);
+            m = m | span_meets(__double2float_rd(double(g[a]) - L), __double2float_ru(double(g[3 + a]) - L), b.lo[a],
+                               b.hi[a]);
         }
-        ok = ok && m;
+        ok = ok & m;
     }
     return ok;
 }
@@ -285,7 +285,8 @@ __device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
                         f.m[1] = sm.y;
                         f.m[2] = sm.z;
                     }
-                    hit |= (sq.w >= 0.0f && box2f<PER>(A, f, bx) <= sq.w) ? (1u << t) : 0u;
+                    // (a lane without a search has a negative threshold, below any box2f)
+                    hit |= uint32_t(box2f<PER>(A, f, bx) <= sq.w) << t;
                 }
             }
             // places in the groups' lists: per group, after the lanes below
@@ -349,7 +350,7 @@ __device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
                             float gb[6];
 #pragma unroll
                             for (int a = 0; a < 6; ++a) gb[a] = L.gbox[g][a];
-                            cm |= (((pm[u] >> g) & 1u) && group_meets<PER>(A, gb, bx[u])) ? (1u << g) : 0u;
+                            cm |= (((pm[u] >> g) & 1u) & uint32_t(group_meets<PER>(A, gb, bx[u]))) << g;
                         }
                     }
                     if (lv > 1) {
