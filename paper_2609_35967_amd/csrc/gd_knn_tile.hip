@@ -326,21 +326,26 @@ __device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
                 FBox bx[kU];
                 uint32_t pm[kU];
                 int child[kU];
+                // the four frontier entries and then the four child boxes are
+                // read unconditionally (a lane past the frontier or at a dead
+                // child reads entry 0 and box 0 and drops them), so that each
+                // group of reads is in flight together
+                uint32_t fe[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int fi = f0 + u * kFan + (lane >> 3);
+                    fe[u] = L.u.t.front[cur][fi < nf ? fi : 0];
+                }
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
                     const int fi = f0 + u * kFan + (lane >> 3), c = lane & 7;
-                    pm[u] = 0;
-                    child[u] = 0;
-                    if (fi < nf) {
-                        const uint32_t e = L.u.t.front[cur][fi];
-                        const int idx = int(e & 0xFFFFFFu);
-                        if ((live_children(na, lv, idx) >> c) & 1u) {
-                            pm[u] = e >> 24;
-                            child[u] = idx * kFan + c;
-                        }
-                    }
-                    if (pm[u]) bx[u] = A.boxes[level_off(A.T, lv - 1) + child[u]];
+                    const int idx = int(fe[u] & 0xFFFFFFu);
+                    const bool live = fi < nf && ((live_children(na, lv, idx) >> c) & 1u);
+                    pm[u] = live ? fe[u] >> 24 : 0u;
+                    child[u] = live ? idx * kFan + c : 0;
                 }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) bx[u] = A.boxes[level_off(A.T, lv - 1) + child[u]];
 #pragma unroll
                 for (int u = 0; u < kU; ++u) {
                     uint32_t cm = 0;
