@@ -197,10 +197,17 @@ struct RadixHist {
         __syncthreads();
         const int64_t base = B.id * kSortTile;
         const int shift = A.shift;
-        for (int r = 0; r < kSortTile / 256; ++r) {
+        // the tile's keys are loaded first, all in flight together
+        constexpr int R = kSortTile / 256;
+        uint32_t kr[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
             const int64_t i = base + r * 256 + threadIdx.x;
-            if (i < A.n) atomicAdd(&h[(A.kin[i] >> shift) & 0xFFu], 1u);
+            kr[r] = i < A.n ? A.kin[i] : 0u;
         }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (base + r * 256 + threadIdx.x < A.n) atomicAdd(&h[(kr[r] >> shift) & 0xFFu], 1u);
         __syncthreads();
         A.hist[int64_t(threadIdx.x) * A.nblk + B.id] = h[threadIdx.x];
     }
@@ -287,17 +294,24 @@ __device__ __forceinline__ void RadixScatter::body(const Args& A, Blk B)
     run[t] = 0;
     const int64_t base = B.id * kSortTile;
     const uint64_t lt = (uint64_t(1) << lane) - 1;
-    for (int r = 0; r < kSortTile / 256; ++r) {
+    // the tile's keys and values are loaded first, all in flight together;
+    // the rounds then take them from registers
+    constexpr int R = kSortTile / 256;
+    uint32_t kr[R], vr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = base + r * 256 + t;
+        kr[r] = i < n ? kin[i] : 0u;
+        vr[r] = i < n ? vin[i] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
         for (int ww = 0; ww < 4; ++ww) wcnt[ww][t] = 0;
         __syncthreads();
         const int64_t i = base + r * 256 + t;
         const bool valid = i < n;
-        uint32_t key = 0, val = 0, dig = 0;
-        if (valid) {
-            key = kin[i];
-            val = vin[i];
-            dig = (key >> shift) & 0xFFu;
-        }
+        const uint32_t key = kr[r], val = vr[r];
+        const uint32_t dig = valid ? (key >> shift) & 0xFFu : 0u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
