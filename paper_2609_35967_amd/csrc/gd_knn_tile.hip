@@ -576,6 +576,10 @@ __device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
         c0 = cum;
         ok = hb <= kC1;
     }
+    // the ranking below runs over the wavefront's largest boundary bin only
+    int nbw = ok ? hb : 0;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) nbw = max(nbw, __shfl_xor(nbw, o, kWave));
     int ntot = 0, nb = 0;
     double maxd2 = 0.0;
     // boundary entry e waits at list place kTList - 1 - e: fewer than k - 1
@@ -613,12 +617,15 @@ __device__ __forceinline__ void KnnTile<PER>::body(const Args& TA, Blk)
         }
 #pragma unroll
         for (int e = 0; e < kC1; ++e) {
-            int rank = 0;
+            if (e < nbw) {  // uniform
+                int rank = 0;
 #pragma unroll
-            for (int f = 0; f < kC1; ++f) rank += (bd[f] < bd[e]) || (bd[f] == bd[e] && bj[f] < bj[e]);
-            if (e < nb && rank < needb) {
-                L.u.d.list[ntot + rank][lane] = bw[e];
-                maxd2 = fmax(maxd2, bd[e]);
+                for (int f = 0; f < kC1; ++f)
+                    if (f < nbw) rank += (bd[f] < bd[e]) | ((bd[f] == bd[e]) & (bj[f] < bj[e]));
+                if (e < nb && rank < needb) {
+                    L.u.d.list[ntot + rank][lane] = bw[e];
+                    maxd2 = fmax(maxd2, bd[e]);
+                }
             }
         }
         ntot += needb;
