@@ -211,10 +211,12 @@ def test_reshuffle_neighbors_other_k(k):
     assert np.array_equal(after, oracle.reshuffle(before, cnt, int(eng.n_active.item()), 78, 3))
 
 
-@pytest.mark.parametrize("hint", ["previous", 0.0, 1e-300, 1e300, 1e17, float("nan"), -1.0, "mixed"])
+@pytest.mark.parametrize("hint", ["previous", 0.0, 1e-300, 1e300, 1e17, float("nan"), -1.0, "mixed", "x1.5", "x2.5"])
 def test_build_neighbors_search_hint(hint):
     # the previous distances are read back as a search hint; the result must
-    # not depend on them (too small, too large, non-finite or stale)
+    # not depend on them (too small, too large, non-finite or stale).  Hints
+    # 1.5 and 2.5 times the distance put 3 and 15 times the others inside the
+    # first radius, so candidate lists fill and are cut on the way.
     params = workloads.disk3d_params(32768)
     st = workloads.disk3d(5, 32768, params=params)
     _say("knn hint", hint)
@@ -226,6 +228,8 @@ def test_build_neighbors_search_hint(hint):
         v = torch.rand(eng.n, generator=g, dtype=torch.float64) * 2 * eng.dmax.cpu()
         v[::7] = 1e-20
         eng.dmax.copy_(v.to(eng.dmax.device))
+    elif isinstance(hint, str) and hint.startswith("x"):
+        eng.dmax.mul_(float(hint[1:]))
     elif hint != "previous":
         eng.dmax.fill_(hint)
     eng.build_neighbors()
