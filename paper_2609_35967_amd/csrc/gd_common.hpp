@@ -306,16 +306,6 @@ __device__ inline double shfl_xor_d(double v, int m)
     return __shfl_xor(v, m, kWave);
 }
 
-__device__ inline dd wave_sum_dd(dd v)
-{
-#pragma unroll
-    for (int m = 1; m < kWave; m <<= 1) {
-        dd o{shfl_xor_d(v.hi, m), shfl_xor_d(v.lo, m)};
-        v = dd_add(v, o);
-    }
-    return v;
-}
-
 __device__ inline double wave_min_d(double v)
 {
 #pragma unroll
@@ -357,6 +347,25 @@ __device__ inline double readlane_d(double x, int l)
 {
     return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
                             __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+
+// the double-double sum over the wavefront, in every lane: the DPP steps of
+// wave_scan_incl with dd_add, then the last lane's prefix read across
+template <int CTRL, int ROWS>
+__device__ inline dd dd_step(dd v)
+{
+    return dd_add(v, dd{dpp_take<CTRL, ROWS>(v.hi), dpp_take<CTRL, ROWS>(v.lo)});
+}
+
+__device__ inline dd wave_sum_dd(dd v)
+{
+    v = dd_step<0x111, 0xf>(v);
+    v = dd_step<0x112, 0xf>(v);
+    v = dd_step<0x114, 0xf>(v);
+    v = dd_step<0x118, 0xf>(v);
+    v = dd_step<0x142, 0xa>(v);
+    v = dd_step<0x143, 0xc>(v);
+    return dd{readlane_d(v.hi, kWave - 1), readlane_d(v.lo, kWave - 1)};
 }
 
 __device__ inline void set_status(void* ws, int bits)

@@ -296,7 +296,7 @@ __device__ __forceinline__ void BinReduce::body(const Args& A, Blk B)
         uint64_t rem = __ballot(valid);
         while (rem) {
             const int leader = __ffsll((unsigned long long)rem) - 1;
-            const int bsel = __shfl(bin, leader, 64);
+            const int bsel = __builtin_amdgcn_readlane(bin, leader);
             const bool mine = valid && bin == bsel;
             const uint64_t match = __ballot(mine);
             const dd s0 = wave_sum_dd(dd{mine ? v0 : 0.0, 0.0});
