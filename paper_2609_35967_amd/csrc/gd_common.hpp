@@ -368,6 +368,32 @@ __device__ inline dd wave_sum_dd(dd v)
     return dd{readlane_d(v.hi, kWave - 1), readlane_d(v.lo, kWave - 1)};
 }
 
+// three such sums side by side (their steps interleave)
+__device__ inline void wave_sum_dd3(dd& a, dd& b, dd& c)
+{
+    a = dd_step<0x111, 0xf>(a);
+    b = dd_step<0x111, 0xf>(b);
+    c = dd_step<0x111, 0xf>(c);
+    a = dd_step<0x112, 0xf>(a);
+    b = dd_step<0x112, 0xf>(b);
+    c = dd_step<0x112, 0xf>(c);
+    a = dd_step<0x114, 0xf>(a);
+    b = dd_step<0x114, 0xf>(b);
+    c = dd_step<0x114, 0xf>(c);
+    a = dd_step<0x118, 0xf>(a);
+    b = dd_step<0x118, 0xf>(b);
+    c = dd_step<0x118, 0xf>(c);
+    a = dd_step<0x142, 0xa>(a);
+    b = dd_step<0x142, 0xa>(b);
+    c = dd_step<0x142, 0xa>(c);
+    a = dd_step<0x143, 0xc>(a);
+    b = dd_step<0x143, 0xc>(b);
+    c = dd_step<0x143, 0xc>(c);
+    a = dd{readlane_d(a.hi, kWave - 1), readlane_d(a.lo, kWave - 1)};
+    b = dd{readlane_d(b.hi, kWave - 1), readlane_d(b.lo, kWave - 1)};
+    c = dd{readlane_d(c.hi, kWave - 1), readlane_d(c.lo, kWave - 1)};
+}
+
 __device__ inline void set_status(void* ws, int bits)
 {
     atomicOr(&at<WsHeader>(ws, 0)->status, bits);

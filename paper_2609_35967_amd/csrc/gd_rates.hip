@@ -299,11 +299,13 @@ __device__ __forceinline__ void BinReduce::body(const Args& A, Blk B)
             const int bsel = __builtin_amdgcn_readlane(bin, leader);
             const bool mine = valid && bin == bsel;
             const uint64_t match = __ballot(mine);
-            const dd s0 = wave_sum_dd(dd{mine ? v0 : 0.0, 0.0});
-            dd s1{0.0, 0.0}, s2{0.0, 0.0};
+            dd s0{mine ? v0 : 0.0, 0.0}, s1{0.0, 0.0}, s2{0.0, 0.0};
             if (mode == 0) {
-                s1 = wave_sum_dd(dd{mine ? v1 : 0.0, 0.0});
-                s2 = wave_sum_dd(dd{mine ? v2 : 0.0, 0.0});
+                s1 = dd{mine ? v1 : 0.0, 0.0};
+                s2 = dd{mine ? v2 : 0.0, 0.0};
+                wave_sum_dd3(s0, s1, s2);
+            } else {
+                s0 = wave_sum_dd(s0);
             }
             if (lane == 0) {
                 double* a = acc[w][bsel];
