@@ -167,15 +167,18 @@ __device__ inline int32_t xcd_take(int32_t* q, int32_t nitems)
     return __builtin_amdgcn_readfirstlane(got);
 }
 
-// Static form for short kernels of even cost (no atomics): the workgroup the
-// hardware deals to die x as its r-th becomes block r of die x's contiguous
-// range of the nb = gridDim.x blocks (a bijection for any nb).
-__device__ inline int64_t xcd_block()
+// Static form (no atomics): block `id` of `nb`, which the hardware deals to
+// die x = id mod kXcd as its r-th, becomes block r of die x's contiguous
+// range (a bijection for any nb).  The blocks of one run of a many-run grid
+// are consecutive, so their local index splits the same way.
+__device__ inline int64_t xcd_item(int64_t id, int64_t nb)
 {
-    const int64_t nb = gridDim.x, w = blockIdx.x;
-    const int64_t x = w % kXcd, r = w / kXcd;
+    const int64_t x = id % kXcd, r = id / kXcd;
     return (nb / kXcd) * x + (x < nb % kXcd ? x : nb % kXcd) + r;
 }
+
+// for short kernels of even cost: the grid's own blocks
+__device__ inline int64_t xcd_block() { return xcd_item(blockIdx.x, gridDim.x); }
 
 // ---------------------------------------------------------------------------
 // Launches over many runs.  A kernel body takes its block as (index, count)
