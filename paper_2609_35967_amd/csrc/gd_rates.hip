@@ -227,6 +227,36 @@ struct BinArgs {
     void* ws;
 };
 
+// One step of a segmented inclusive double-double scan over the wavefront:
+// a lane adds the value the DPP pattern brings it only when the source lane
+// belongs to its own run (equal id; ids start at 1, so a lane with no
+// source, which reads 0, adds nothing).  Runs must be contiguous in lane
+// order; the steps are those of wave_scan_incl.
+template <int CTRL, int ROWS>
+__device__ inline void seg_step(dd& v, int id)
+{
+    const int oid = __builtin_amdgcn_update_dpp(0, id, CTRL, ROWS, 0xf, true);
+    const dd s = dd_add(v, dd{dpp_take<CTRL, ROWS>(v.hi), dpp_take<CTRL, ROWS>(v.lo)});
+    if (oid == id) v = s;
+}
+
+template <int NV>
+__device__ inline void seg_scan(dd (&v)[NV], int id)
+{
+#pragma unroll
+    for (int u = 0; u < NV; ++u) seg_step<0x111, 0xf>(v[u], id);
+#pragma unroll
+    for (int u = 0; u < NV; ++u) seg_step<0x112, 0xf>(v[u], id);
+#pragma unroll
+    for (int u = 0; u < NV; ++u) seg_step<0x114, 0xf>(v[u], id);
+#pragma unroll
+    for (int u = 0; u < NV; ++u) seg_step<0x118, 0xf>(v[u], id);
+#pragma unroll
+    for (int u = 0; u < NV; ++u) seg_step<0x142, 0xa>(v[u], id);
+#pragma unroll
+    for (int u = 0; u < NV; ++u) seg_step<0x143, 0xc>(v[u], id);
+}
+
 struct BinReduce {
     using Args = BinArgs;
     static constexpr int kThreads = kRedWaves * kWave;
@@ -249,6 +279,10 @@ __device__ __forceinline__ void BinReduce::body(const Args& A, Blk B)
     double* __restrict__ part = A.part;
     void* ws = A.ws;
     __shared__ double acc[kRedWaves][kNBin][7];
+    // a row of many bins in bin order: bin, run length and the three values
+    // of each lane, per wavefront
+    __shared__ int32_t sk[kRedWaves][kWave][2];
+    __shared__ double sv[kRedWaves][kWave][3];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     for (int e = t; e < kRedWaves * kNBin * 7; e += kRedWaves * kWave) (&acc[0][0][0])[e] = 0.0;
     __syncthreads();
@@ -293,34 +327,82 @@ __device__ __forceinline__ void BinReduce::body(const Args& A, Blk B)
                 v0 = cur.Mi * (fabs(log(cur.a / ms)) / 3.0);
             }
         }
-        uint64_t rem = __ballot(valid);
-        while (rem) {
-            const int leader = __ffsll((unsigned long long)rem) - 1;
-            const int bsel = __builtin_amdgcn_readlane(bin, leader);
-            const bool mine = valid && bin == bsel;
-            const uint64_t match = __ballot(mine);
-            dd s0{mine ? v0 : 0.0, 0.0}, s1{0.0, 0.0}, s2{0.0, 0.0};
+        // the lanes of the row grouped by bin, from one ballot per bit of the
+        // bin: the lanes of my bin, how many of them come before me, and how
+        // many lanes hold smaller bins (no lane is lost: invalid lanes take
+        // key 255, after every bin)
+        const int key = valid ? bin : 255;
+        uint64_t same = ~uint64_t(0);
+        int less = 0;
+#pragma unroll
+        for (int bit = 7; bit >= 0; --bit) {
+            const uint64_t ones = __ballot((key >> bit) & 1);
+            const bool mb = (key >> bit) & 1;
+            if (mb) less += int(__popcll(same & ~ones));
+            same &= mb ? ones : ~ones;
+        }
+        const int rank = int(__popcll(same & ((uint64_t(1) << lane) - 1)));
+        const int run = int(__popcll(same));
+        const uint64_t heads = __ballot(valid && rank == 0);
+        if (__popcll(heads) > 1) {
+            // several bins: the row in bin order through LDS, then one
+            // segmented scan; the last lane of each bin's run adds the run
+            const int pos = less + rank;
+            sk[w][pos][0] = key;
+            sk[w][pos][1] = rank == run - 1 ? run : 0;
+            sv[w][pos][0] = v0;
+            sv[w][pos][1] = v1;
+            sv[w][pos][2] = v2;
+            const int kb = sk[w][lane][0], last = sk[w][lane][1];
+            dd sd[3] = {dd{sv[w][lane][0], 0.0}, dd{sv[w][lane][1], 0.0}, dd{sv[w][lane][2], 0.0}};
             if (mode == 0) {
-                s1 = dd{mine ? v1 : 0.0, 0.0};
-                s2 = dd{mine ? v2 : 0.0, 0.0};
-                wave_sum_dd3(s0, s1, s2);
+                seg_scan<3>(sd, kb + 1);
             } else {
-                s0 = wave_sum_dd(s0);
+                dd s1[1] = {sd[0]};
+                seg_scan<1>(s1, kb + 1);
+                sd[0] = s1[0];
             }
-            if (lane == 0) {
-                double* a = acc[w][bsel];
-                a[0] += double(__popcll(match));
-                dd x = dd_add(dd{a[1], a[2]}, s0);
-                a[1] = x.hi;
-                a[2] = x.lo;
-                x = dd_add(dd{a[3], a[4]}, s1);
-                a[3] = x.hi;
-                a[4] = x.lo;
-                x = dd_add(dd{a[5], a[6]}, s2);
-                a[5] = x.hi;
-                a[6] = x.lo;
+            if (last > 0 && kb != 255) {
+                double* a = acc[w][kb];
+                a[0] += double(last);
+#pragma unroll
+                for (int u = 0; u < 3; ++u) {
+                    if (u > 0 && mode != 0) break;
+                    const dd x = dd_add(dd{a[1 + 2 * u], a[2 + 2 * u]}, sd[u]);
+                    a[1 + 2 * u] = x.hi;
+                    a[2 + 2 * u] = x.lo;
+                }
             }
-            rem &= ~match;
+        } else {
+            uint64_t rem = __ballot(valid);
+            while (rem) {
+                const int leader = __ffsll((unsigned long long)rem) - 1;
+                const int bsel = __builtin_amdgcn_readlane(bin, leader);
+                const bool mine = valid && bin == bsel;
+                const uint64_t match = __ballot(mine);
+                dd s0{mine ? v0 : 0.0, 0.0}, s1{0.0, 0.0}, s2{0.0, 0.0};
+                if (mode == 0) {
+                    s1 = dd{mine ? v1 : 0.0, 0.0};
+                    s2 = dd{mine ? v2 : 0.0, 0.0};
+                    wave_sum_dd3(s0, s1, s2);
+                } else {
+                    s0 = wave_sum_dd(s0);
+                }
+                if (lane == 0) {
+                    double* a = acc[w][bsel];
+                    a[0] += double(__popcll(match));
+                    dd x = dd_add(dd{a[1], a[2]}, s0);
+                    a[1] = x.hi;
+                    a[2] = x.lo;
+                    x = dd_add(dd{a[3], a[4]}, s1);
+                    a[3] = x.hi;
+                    a[4] = x.lo;
+                    x = dd_add(dd{a[5], a[6]}, s2);
+                    a[5] = x.hi;
+                    a[6] = x.lo;
+                }
+                rem &= ~match;
+            }
         }
         cur = nxt;
     }
