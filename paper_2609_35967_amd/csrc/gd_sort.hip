@@ -32,15 +32,18 @@ __device__ __forceinline__ void BboxPartial::body(const Args& A, Blk B)
     const int64_t n = A.n;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double cnt = 0.0;
+    // the four arrays are read for every slot (an inactive one is then left
+    // out), so that the unrolled iterations' loads are in flight together
+#pragma unroll 4
     for (int64_t i = B.id * int64_t(blockDim.x) + threadIdx.x; i < n; i += B.n * blockDim.x) {
-        if (!(M[i] > 0.0)) continue;
+        const bool act = M[i] > 0.0;
         const double c[3] = {x[i], y[i], z[i]};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            lo[d] = fmin(lo[d], c[d]);
-            hi[d] = fmax(hi[d], c[d]);
+            lo[d] = act ? fmin(lo[d], c[d]) : lo[d];
+            hi[d] = act ? fmax(hi[d], c[d]) : hi[d];
         }
-        cnt += 1.0;
+        cnt += act ? 1.0 : 0.0;
     }
     __shared__ double s[4][7];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
