@@ -292,18 +292,61 @@ __device__ inline void pair_eval(const DevProblem& P, const QCtx& c, const Own& 
     pair_core<false>(P, c, w, b, o);
 }
 
+// ln y for finite y > 0 (other y as the library), from the series ln y = e ln 2 + 2 atanh(s): y =
+// m 2^e with m in [1/sqrt 2, sqrt 2), s = (m - 1)/(m + 1), |s| <= 0.172, and
+// 2 atanh(s) = 2 s (1 + s^2/3 + ... + s^18/19) (the next term is below
+// 2^-55 of the sum).  A few ulp, in about a third of the instructions of the
+// library's logarithms, which carry double-double steps; the controller
+// moments of every pair take one or two.
+__device__ inline double log_s(double y)
+{
+    if (!(y > 0.0 && y < INFINITY)) return log(y);  // 0, negative, infinite or NaN: as the library
+    int e;
+    double m = frexp(y, &e);
+    if (m < 0.70710678118654752) {
+        m = m + m;
+        e = e - 1;
+    }
+    const double f = m - 1.0;
+    const double s = f / (2.0 + f);
+    const double s2 = s * s;
+    double p = 1.0 / 19.0;
+    p = fma(p, s2, 1.0 / 17.0);
+    p = fma(p, s2, 1.0 / 15.0);
+    p = fma(p, s2, 1.0 / 13.0);
+    p = fma(p, s2, 1.0 / 11.0);
+    p = fma(p, s2, 1.0 / 9.0);
+    p = fma(p, s2, 1.0 / 7.0);
+    p = fma(p, s2, 1.0 / 5.0);
+    p = fma(p, s2, 1.0 / 3.0);
+    p = fma(p, s2, 1.0);
+    return fma(double(e), 0.69314718055994530942, (s + s) * p);
+}
+
+// ln(1 + x) for x > -1: ln u for u = 1 + x rounded, plus that rounding's
+// share (x - (u - 1))/u; x itself when u rounds to 1.  Within 3 ulp of
+// ln(1 + x) for 1e-20 <= x <= 1e30 and -0.1 <= x < 0 (the same steps are
+// evaluated on the host in tests/test_series_log.py).
+__device__ inline double log1p_s(double x)
+{
+    const double u = 1.0 + x;
+    if (u == 1.0) return x;
+    if (!(u > 0.0 && u < INFINITY)) return log1p(x);
+    return log_s(u) + (x - (u - 1.0)) / u;
+}
+
 // sum over the pair's channels of rate * <J> and rate * <J^2>
 __device__ inline void pair_moments(const Pair& o, const Own& w, double mj, double& a, double& b)
 {
     constexpr double kThird = 1.0 / 3.0;
     const double psi = mj / w.mi;
     if (o.type == kStick) {
-        const double J = log1p(o.Ng * psi) * kThird;
+        const double J = log1p_s(o.Ng * psi) * kThird;
         a = o.r0 * J;
         b = o.r0 * (J * J);
     } else if (o.type == kErosion) {
-        const double Jr = -log1p(-o.Ng * psi) * kThird;
-        const double Jd = fabs(log(psi)) * kThird;
+        const double Jr = -log1p_s(-o.Ng * psi) * kThird;
+        const double Jd = fabs(log_s(psi)) * kThird;
         a = o.r0 * Jr;
         b = o.r0 * (Jr * Jr);
         a = a + o.r1 * Jd;
