@@ -63,6 +63,8 @@ struct alignas(256) WsHeader {
     int32_t knn_fb_n[2];         // neighbour search: queries the tile search handed back (two lists)
     int32_t mc_seg[kXcd];        // sampling: particles with an event, per die's segment of the list
     int32_t mc_next;             // sampling: next group of them to take
+    int32_t heavy_n0;            // sampling: particles the screen sent straight to the wavefront pass (at the list's end)
+    int32_t heavy_next0;         // sampling: next of those to take
 };
 
 // Workspace layout (byte offsets), identical on host and device.

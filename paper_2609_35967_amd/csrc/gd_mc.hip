@@ -57,6 +57,14 @@ struct McArgs {
     int32_t* list_next;  // the event pass's next group
     const int64_t* interval_at;  // when set: the interval index (a spatial group's number in planning order)
     const int32_t* active;       // when set and 0: the run has no interval now (its deferred list is skipped)
+    // the screen sends a particle whose expected events lambda*_i dt_exe reach
+    // early_events (0: none) straight to the wavefront-per-particle pass, to
+    // entries n - 1, n - 2, ... of `heavy` (the event pass defers to entries
+    // 0, 1, ...; no particle is in both), counted by heavy_n0, taken by
+    // heavy_next0
+    double early_events;
+    int32_t* heavy_n0;
+    int32_t* heavy_next0;
 };
 
 __device__ inline uint32_t mc_interval(const McArgs& A)
@@ -78,6 +86,8 @@ constexpr int kLaneEvents = 4;      // events a lane samples before handing its 
 constexpr int kHeavyBlocks = 768;   // blocks (4 wavefronts each) of the wavefront-per-particle pass: 3 per SIMD
 constexpr int kEventBlocks = 512;   // blocks (4 wavefronts each) of the event pass: two per SIMD
 constexpr int kSmallList = 3072;    // at most this many particles with events: all to the wavefront pass
+constexpr double kEarlyEvents = 64.0;  // expected events from which the screen sends a particle straight to that pass
+constexpr int kEarlyBlocks = 256;      // blocks (4 wavefronts each) for those particles beside the event pass
 
 template <int KP2>
 __device__ inline double prefix_rates_f32(const McArgs& A, const QCtxF& q, const int32_t* row, int c, double mi,
@@ -166,7 +176,7 @@ __device__ __forceinline__ void McScreen<DIRECT_HEAVY>::body(const Args& A, Blk 
     __shared__ int32_t s_base;
     const int64_t i = B.id * int64_t(blockDim.x) + threadIdx.x;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    bool ev = false;
+    bool ev = false, early = false;
     if (i < A.P.n) {
         const int c = A.cnt[i];
         const double m = A.m[i];
@@ -176,15 +186,28 @@ __device__ __forceinline__ void McScreen<DIRECT_HEAVY>::body(const Args& A, Blk 
             double u[4];
             event_uniforms(A.seed, A.id[i], interval, 0u, u);
             ev = !(-log(u[0]) / li > A.iv->dt_exe);
+            // many expected events: the whole interval in the wavefront pass
+            // (the result is the same whichever pass samples a particle)
+            early = !DIRECT_HEAVY && ev && A.early_events > 0.0 && li * A.iv->dt_exe >= A.early_events;
         }
         if (!ev) {
             A.m_out[i] = m;
             if (A.n_events) A.n_events[i] = 0;
             if (A.log)
                 for (int f = 0; f < A.log_cap; ++f) A.log[i * A.log_cap + f] = -1;
-        } else if (DIRECT_HEAVY && A.log) {
+        } else if ((DIRECT_HEAVY || early) && A.log) {
             for (int f = 0; f < A.log_cap; ++f) A.log[i * A.log_cap + f] = -1;
         }
+    }
+    if (!DIRECT_HEAVY) {  // the early ones, one add per wavefront that has any
+        const uint64_t eb = __ballot(early);
+        int32_t base = 0;
+        if (lane == 0 && eb) base = atomicAdd(A.heavy_n0, int32_t(__popcll(eb)));
+        base = __builtin_amdgcn_readfirstlane(base);
+        if (early)
+            A.heavy[A.P.n - 1 - (base + int32_t(__popcll(eb & ((uint64_t(1) << lane) - 1))))] =
+                Deferred{int32_t(i), 0, 0.0, A.m[i]};
+        ev = ev && !early;
     }
     const uint64_t bal = __ballot(ev);
     if (lane == 0) s_w[wv] = int32_t(__popcll(bal));
@@ -582,6 +605,35 @@ __global__ __launch_bounds__(256) void k_mc_heavy(McArgs A)
     if (lane == 0 && ev_total) atomicAdd(A.ev_counter, ev_total);
 }
 
+// The chains the screen sent early and the event pass, in one launch: the
+// first kEarlyBlocks blocks (dispatched first) run the early chains (entries
+// n - 1 - h of `heavy` for h < *heavy_n0; their wavefronts without one leave
+// at once), the rest the event pass, so that the long chains run beside the
+// event pass instead of after it.  The chains the event pass defers follow
+// in k_mc_heavy.
+template <int KP2, bool F32>
+__global__ __launch_bounds__(256) void k_mc_fused(EventArgs E)
+{
+    if (blockIdx.x >= unsigned(kEarlyBlocks)) {
+        McEvents<KP2, F32>::body(E, Blk{int64_t(blockIdx.x - unsigned(kEarlyBlocks)), int64_t(kEventBlocks)});
+        return;
+    }
+    const McArgs& A = E.A;
+    const int lane = threadIdx.x & 63;
+    const int32_t nh = *A.heavy_n0;
+    unsigned long long ev_total = 0;
+    const int32_t nw = int32_t(kEarlyBlocks * (blockDim.x / kWave));
+    int32_t h = int32_t(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+    for (;;) {
+        if (h >= nh) break;
+        ev_total += (unsigned long long)run_deferred<KP2, F32>(A, int32_t(A.P.n - 1 - h), lane);
+        int32_t next = 0;
+        if (lane == 0) next = atomicAdd(A.heavy_next0, 1);
+        h = nw + __builtin_amdgcn_readfirstlane(next);
+    }
+    if (lane == 0 && ev_total) atomicAdd(A.ev_counter, ev_total);
+}
+
 // ---------------------------------------------------------------------------
 // Many runs: a table in device memory holds, per slot, the sampling arguments
 // of one run (written by its deferred call), after a 256-byte header whose
@@ -785,6 +837,8 @@ static McArgs mc_args(const gd_problem* p, const gd_particles* s, const gd_neigh
     A.heavy = at<Deferred>(ws, L.heavy);
     A.heavy_n = &h->heavy_n;
     A.heavy_next = &h->heavy_next;
+    A.heavy_n0 = &h->heavy_n0;
+    A.heavy_next0 = &h->heavy_next0;
     A.n_all = p->n;
     A.list = at<int32_t>(ws, L.mclist);
     A.list_seg = h->mc_seg;
@@ -792,7 +846,9 @@ static McArgs mc_args(const gd_problem* p, const gd_particles* s, const gd_neigh
     return A;
 }
 
-static void launch_first(const McArgs& A, const gd_problem* p, hipStream_t st)
+// the screen; false when it hands every particle with an event straight to
+// the wavefront-per-particle pass (no event pass follows)
+static bool launch_screen(const McArgs& A, const gd_problem* p, hipStream_t st)
 {
     const int g = int((A.P.n + 255) / 256);
     static_assert(offsetof(WsHeader, mc_next) == offsetof(WsHeader, mc_seg) + kXcd * sizeof(int32_t),
@@ -800,10 +856,28 @@ static void launch_first(const McArgs& A, const gd_problem* p, hipStream_t st)
     launch_fill_i32(A.list_seg, kXcd + 1, 0, st);
     if (p->k > 64) {  // no prefix registers: straight to the wavefront-per-particle pass
         hipLaunchKernelGGL(k_mc_screen<true>, dim3(g), dim3(256), 0, st, A);
-        return;
+        return false;
     }
     hipLaunchKernelGGL(k_mc_screen<false>, dim3(g), dim3(256), 0, st, A);
+    return true;
+}
+
+static void launch_events(const McArgs& A, const gd_problem* p, hipStream_t st)
+{
+    const int g = int((A.P.n + 255) / 256);
     const dim3 eg(kEventBlocks), eb(256);
+    if (A.early_events > 0.0) {  // with the early chains beside it
+        const dim3 fg(kEarlyBlocks + kEventBlocks);
+        const EventArgs E{A, int64_t(g)};
+        if (p->rates_fp32) {
+            if (p->k <= 32) hipLaunchKernelGGL((k_mc_fused<32, true>), fg, eb, 0, st, E);
+            else hipLaunchKernelGGL((k_mc_fused<64, true>), fg, eb, 0, st, E);
+        } else {
+            if (p->k <= 32) hipLaunchKernelGGL((k_mc_fused<32, false>), fg, eb, 0, st, E);
+            else hipLaunchKernelGGL((k_mc_fused<64, false>), fg, eb, 0, st, E);
+        }
+        return;
+    }
     const EventArgs E{A, int64_t(g)};
     if (p->rates_fp32) {
         if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, true>), eg, eb, 0, st, E);
@@ -812,6 +886,11 @@ static void launch_first(const McArgs& A, const gd_problem* p, hipStream_t st)
         if (p->k <= 32) hipLaunchKernelGGL((k_mc<32, false>), eg, eb, 0, st, E);
         else hipLaunchKernelGGL((k_mc<64, false>), eg, eb, 0, st, E);
     }
+}
+
+static void launch_first(const McArgs& A, const gd_problem* p, hipStream_t st)
+{
+    if (launch_screen(A, p, st)) launch_events(A, p, st);
 }
 
 template <bool F32>
@@ -846,7 +925,10 @@ int launch_sample(const gd_problem* p, const gd_particles* s, const gd_neighbors
                   const double* lam_i, uint64_t seed, uint32_t interval, bool interval_on_device, int32_t* n_events, int32_t* log,
                   int32_t log_cap, void* ws, const Layout& L, hipStream_t st, void* table, int32_t slot)
 {
-    const McArgs A = mc_args(p, s, nb, iv, lam_i, seed, interval, interval_on_device, n_events, log, log_cap, ws, L);
+    McArgs A = mc_args(p, s, nb, iv, lam_i, seed, interval, interval_on_device, n_events, log, log_cap, ws, L);
+    // (with a table the deferred particles wait for the launch over every
+    // slot, so no chain starts early)
+    if (!table) A.early_events = kEarlyEvents;
     prof_mark(GD_PROF_MC, 0, st);
     if (p->n > 0) launch_first(A, p, st);
     if (table) {

@@ -585,6 +585,8 @@ __device__ __forceinline__ void Plan::body(const Args& A, Blk)
         h->scratch[0] = 0.0;  // event counter of the coming interval
         h->heavy_n = 0;       // and the sampling's deferred particles
         h->heavy_next = 0;
+        h->heavy_n0 = 0;
+        h->heavy_next0 = 0;
         s_ng = ng;
     }
     __syncthreads();
