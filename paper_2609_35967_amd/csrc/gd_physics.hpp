@@ -18,12 +18,43 @@
 //  * controller moments <J>, <J^2> of each channel (Sect. 2.5.3), fragments by
 //    integrating eq:frag over U.
 // Every expression keeps one evaluation order and each operation is rounded
-// on its own (the library is compiled without contraction).
+// on its own (the library is compiled without contraction); the quotients
+// taken with div_nr / rcp_nr below are within 1 ulp instead of correctly
+// rounded.
 #pragma once
 
 #include "gd_common.hpp"
 
 namespace gd {
+
+// 1/b from the hardware reciprocal and two Newton steps (each squares the
+// relative error), then one more step: within 1 ulp.  For finite nonzero b
+// whose reciprocal is a normal number (the range scaling of the IEEE
+// division is left out); 6 instructions where the division takes 13.
+__device__ __forceinline__ double rcp_nr(double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    return fma(r, e, r);
+}
+
+// a/b as a (1/b) with the remainder a - b q folded back in: within 1 ulp
+// (nearly always the rounded quotient), under the same range conditions on b
+// and a/b; 8 instructions.
+__device__ __forceinline__ double div_nr(double a, double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    const double q = a * r;
+    return fma(r, fma(-b, q, a), q);
+}
 
 struct Gas {
     double OmK, hg, Hg, cs, r, rhog, eta, vgphi, stfac;
@@ -157,8 +188,8 @@ __device__ inline void own_terms(const DevProblem& P, const QCtx& c, double mi, 
     w.rmi = 1.0 / mi;
     w.si = si;
     w.Sti = phys ? c.stfac * si : 0.0;
-    w.rqi = 1.0 / (1.0 + w.Sti * w.Sti);
-    w.rhi = 1.0 / (1.0 + w.Sti);
+    w.rqi = rcp_nr(1.0 + w.Sti * w.Sti);
+    w.rhi = rcp_nr(1.0 + w.Sti);
     w.mJ = 0.0;
     w.mJ2 = 0.0;
     if (phys && moments) frag_moments(si, P.s_min, w.mJ, w.mJ2);
@@ -184,8 +215,8 @@ __device__ inline void nb_terms(const DevProblem& P, const QCtx& c, double mj, d
     b.Nj = Nj;
     b.rmj = rmj;
     b.Stj = c.stfac * sj;
-    b.rqj = 1.0 / (1.0 + b.Stj * b.Stj);
-    b.rhj = HOIST ? 1.0 / (1.0 + b.Stj) : 0.0;
+    b.rqj = rcp_nr(1.0 + b.Stj * b.Stj);
+    b.rhj = HOIST ? rcp_nr(1.0 + b.Stj) : 0.0;
     b.cj = HOIST ? P.m0 / mj : 0.0;
 }
 
@@ -201,12 +232,13 @@ __device__ inline double oc07_dv2_r(double St1, double St2, double dSt, double V
     if (St1 < tke) {
         const double num = St1 * St2 + tke * (St1 + St2);
         const double den = (St1 + St2) * (St1 + tke) * (St2 + tke);
-        return Vg2 * (dSt * dSt) * num / den;
+        return div_nr(Vg2 * (dSt * dSt) * num, den);
     }
     if (St1 < 1.0) {
         const double ya = 1.6;
-        const double e = St2 / St1;
-        const double br = 2.0 * ya - (1.0 + e) + 2.0 / (1.0 + e) * (1.0 / (1.0 + ya) + e * e * e / (ya + e));
+        const double e = div_nr(St2, St1);
+        const double br =
+            2.0 * ya - (1.0 + e) + div_nr(2.0, 1.0 + e) * (1.0 / (1.0 + ya) + div_nr(e * e * e, ya + e));
         return Vg2 * br * St1;
     }
     return Vg2 * (rh1 + rh2);
@@ -228,7 +260,7 @@ __device__ inline void pair_core(const DevProblem& P, const QCtx& c, const Own& 
         // s_i - s_j = (6/(pi rho))(m_i - m_j)/(s_i^2 + s_i s_j + s_j^2),
         // so that close grains do not cancel.
         const double si = w.si, Sti = w.Sti, sj = b.sj, Stj = b.Stj;
-        const double ds = (6.0 / (kPi * P.rho_s)) * (mi - mj) / (si * si + si * sj + sj * sj);
+        const double ds = div_nr((6.0 / (kPi * P.rho_s)) * (mi - mj), si * si + si * sj + sj * sj);
         const double dSt = c.stfac * ds;
         const double rq = w.rqi * b.rqj;
         const double da = dSt * (1.0 - Sti * Stj) * rq;
@@ -241,7 +273,7 @@ __device__ inline void pair_core(const DevProblem& P, const QCtx& c, const Own& 
         if (P.brownian) dvB = fmin(sqrt(c.kT8pi * (w.rmi + b.rmj)), c.cs);
         if (P.turbulence) {
             const bool ig = Sti >= Stj;
-            const double rhj = HOIST ? b.rhj : 1.0 / (1.0 + Stj);
+            const double rhj = HOIST ? b.rhj : rcp_nr(1.0 + Stj);
             dvT2 = oc07_dv2_r(ig ? Sti : Stj, ig ? Stj : Sti, fabs(dSt), c.Vg2, c.tke, ig ? w.rhi : rhj,
                               ig ? rhj : w.rhi);
         }
@@ -308,7 +340,7 @@ __device__ inline double log_s(double y)
         e = e - 1;
     }
     const double f = m - 1.0;
-    const double s = f / (2.0 + f);
+    const double s = div_nr(f, 2.0 + f);
     const double s2 = s * s;
     double p = 1.0 / 19.0;
     p = fma(p, s2, 1.0 / 17.0);
@@ -326,13 +358,14 @@ __device__ inline double log_s(double y)
 // ln(1 + x) for x > -1: ln u for u = 1 + x rounded, plus that rounding's
 // share (x - (u - 1))/u; x itself when u rounds to 1.  Within 3 ulp of
 // ln(1 + x) for 1e-20 <= x <= 1e30 and -0.1 <= x < 0 (the same steps are
-// evaluated on the host in tests/test_series_log.py).
+// evaluated on the host, with correctly rounded quotients, in
+// tests/test_series_log.py).
 __device__ inline double log1p_s(double x)
 {
     const double u = 1.0 + x;
     if (u == 1.0) return x;
     if (!(u > 0.0 && u < INFINITY)) return log1p(x);
-    return log_s(u) + (x - (u - 1.0)) / u;
+    return log_s(u) + div_nr(x - (u - 1.0), u);
 }
 
 // sum over the pair's channels of rate * <J> and rate * <J^2>
