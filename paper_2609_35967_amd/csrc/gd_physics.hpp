@@ -56,6 +56,22 @@ __device__ __forceinline__ double div_nr(double a, double b)
     return fma(r, fma(-b, q, a), q);
 }
 
+// sqrt(x) for x = 0 or normal x > 0: the hardware reciprocal square root y,
+// then g ~ x y and h ~ y/2 refined together by one coupled Newton step and
+// g by two residual steps (Markstein's form); within 1 ulp, 0 for 0.  The
+// library's square root adds the range scaling for tiny x.
+__device__ __forceinline__ double sqrt_nr(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-h, g, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    g = fma(fma(-g, g, x), h, g);
+    g = fma(fma(-g, g, x), h, g);
+    return x > 0.0 ? g : x;
+}
+
 struct Gas {
     double OmK, hg, Hg, cs, r, rhog, eta, vgphi, stfac;
 };
@@ -269,8 +285,9 @@ __device__ inline void pair_core(const DevProblem& P, const QCtx& c, const Own& 
         const double dz = (Sti < 0.5 && Stj < 0.5) ? dSt : fmin(Sti, 0.5) - fmin(Stj, 0.5);
         const double dvZ = c.vZ * dz;
         const double dvP = c.vP * db;
-        double dvB = 0.0, dvT2 = 0.0;
-        if (P.brownian) dvB = fmin(sqrt(c.kT8pi * (w.rmi + b.rmj)), c.cs);
+        // the Brownian speed enters squared: min(sqrt(a), c_s)^2 = min(a, c_s^2)
+        double dvB2 = 0.0, dvT2 = 0.0;
+        if (P.brownian) dvB2 = fmin(c.kT8pi * (w.rmi + b.rmj), c.cs * c.cs);
         if (P.turbulence) {
             const bool ig = Sti >= Stj;
             const double rhj = HOIST ? b.rhj : rcp_nr(1.0 + Stj);
@@ -279,9 +296,9 @@ __device__ inline void pair_core(const DevProblem& P, const QCtx& c, const Own& 
         }
         double dv2 = dvR * dvR + dvZ * dvZ;
         dv2 = dv2 + dvP * dvP;
-        dv2 = dv2 + dvB * dvB;
+        dv2 = dv2 + dvB2;
         dv2 = dv2 + dvT2;
-        dv = sqrt(dv2);
+        dv = sqrt_nr(dv2);
         const double ssum = si + sj;
         const double K = kPi * ssum * ssum * dv * 0.25;
         lam = b.Nj * K * c.invV;
