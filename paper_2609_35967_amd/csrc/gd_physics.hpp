@@ -237,11 +237,18 @@ __device__ inline void nb_terms(const DevProblem& P, const QCtx& c, double mj, d
 }
 
 // Ormel & Cuzzi (2007) turbulent relative speed squared, St1 >= St2,
-// dSt = St1 - St2: tightly coupled St1 < Re^-1/2 (written as
-// Vg^2 dSt^2 [St1 St2 + t(St1+St2)]/[(St1+St2)(St1+t)(St2+t)], equal to the
-// published form but free of cancellation for close St), intermediate up to
-// St1 = 1 (y_a = 1.6), heavy Vg^2 [1/(1+St1) + 1/(1+St2)] with the two
-// reciprocals rh1, rh2 given.
+// dSt = St1 - St2, each regime with one division at most:
+//  * tight, St1 < t = Re^-1/2:
+//    Vg^2 dSt^2 [St1 St2 + t(St1+St2)]/[(St1+St2)(St1+t)(St2+t)], the
+//    published form rearranged so that close St do not cancel;
+//  * intermediate, up to St1 = 1 (y_a = 1.6):
+//    Vg^2 St1 [2 y_a - (1+e) + 2/(1+e) (1/(1+y_a) + e^3/(y_a+e))], e = St2/St1,
+//    multiplied through by St1^3:
+//    Vg^2 {(2 y_a - 1) St1 - St2 + 2 [St1^2 u/(1+y_a) + St2^3]/[(St1+St2) u]},
+//    u = y_a St1 + St2 (the linear part is at least 1.2 St1: no cancellation);
+//  * heavy: Vg^2 [1/(1+St1) + 1/(1+St2)] from the reciprocals rh1, rh2 given.
+// The regimes stay branches: the wavefronts of one disk region mostly share
+// one.
 __device__ inline double oc07_dv2_r(double St1, double St2, double dSt, double Vg2, double tke, double rh1,
                                     double rh2)
 {
@@ -251,11 +258,10 @@ __device__ inline double oc07_dv2_r(double St1, double St2, double dSt, double V
         return div_nr(Vg2 * (dSt * dSt) * num, den);
     }
     if (St1 < 1.0) {
-        const double ya = 1.6;
-        const double e = div_nr(St2, St1);
-        const double br =
-            2.0 * ya - (1.0 + e) + div_nr(2.0, 1.0 + e) * (1.0 / (1.0 + ya) + div_nr(e * e * e, ya + e));
-        return Vg2 * br * St1;
+        constexpr double ya = 1.6;
+        const double u = ya * St1 + St2;
+        const double num = 2.0 * (St1 * St1 * u * (1.0 / (1.0 + ya)) + St2 * St2 * St2);
+        return Vg2 * (((2.0 * ya - 1.0) * St1 - St2) + div_nr(num, (St1 + St2) * u));
     }
     return Vg2 * (rh1 + rh2);
 }
