@@ -274,7 +274,9 @@ __device__ inline double oc07_dv2_r(double St1, double St2, double dSt, double V
 // 1/V_i once per particle.  It agrees with eq:rate to rounding (well inside
 // the 1e-12 contract); the dimensionless rates keep the oracle's operation
 // order exactly (m0/m_j hoisted or not is the same rounded quotient).
-template <bool HOIST>
+// QNR takes psi = m_j/m_i from div_nr too (the same bits); the sampling
+// passes keep the division, whose registers the event pass cannot spare.
+template <bool HOIST, bool QNR = false>
 __device__ inline void pair_core(const DevProblem& P, const QCtx& c, const Own& w, const Nb& b, Pair& o)
 {
     const double mi = w.mi, mj = b.mj;
@@ -317,7 +319,7 @@ __device__ inline void pair_core(const DevProblem& P, const QCtx& c, const Own& 
         else Kt = div_nr(mi * mj, P.m0 * P.m0);
         lam = div_nr((HOIST ? b.cj : div_nr(P.m0, mj)) * Kt, P.t0 * double(P.k));
     }
-    const double psi = mj / mi;  // (as a division: the sampling pass has no registers to spare)
+    const double psi = QNR ? div_nr(mj, mi) : mj / mi;
     const bool fast = (P.kernel == GD_KERNEL_PHYSICAL) && (dv >= P.v_frag);
     double Ng = 1.0;
     if (P.grouping && psi <= 1e-6) Ng = floor(div_nr(1e-4, psi));
@@ -341,12 +343,13 @@ __device__ inline void pair_core(const DevProblem& P, const QCtx& c, const Own& 
 }
 
 // One pair against neighbour (m_j, s_j, N_j, 1/m_j) of the frozen snapshot.
+template <bool QNR = false>
 __device__ inline void pair_eval(const DevProblem& P, const QCtx& c, const Own& w, double mj, double sj, double Nj,
                                  double rmj, Pair& o)
 {
     Nb b;
     nb_terms<false>(P, c, mj, sj, Nj, rmj, b);
-    pair_core<false>(P, c, w, b, o);
+    pair_core<false, QNR>(P, c, w, b, o);
 }
 
 // ln y for finite y > 0 (other y as the library), from the series ln y = e ln 2 + 2 atanh(s): y =
@@ -397,7 +400,7 @@ __device__ inline double log1p_s(double x)
 __device__ inline void pair_moments(const Pair& o, const Own& w, double mj, double& a, double& b)
 {
     constexpr double kThird = 1.0 / 3.0;
-    const double psi = mj / w.mi;
+    const double psi = div_nr(mj, w.mi);  // the same bits as pair_core<.., true>'s
     if (o.type == kStick) {
         const double J = log1p_s(o.Ng * psi) * kThird;
         a = o.r0 * J;

@@ -122,7 +122,7 @@ __device__ __forceinline__ void Rates::body(const Args& A, Blk B)
             const double4 sn = rec[t];
             const double mj = sn.x;
             Pair o;
-            pair_eval(A.P, q, w, mj, phys ? sn.y : 0.0, phys ? sn.z : 0.0, sn.w, o);
+            pair_eval<true>(A.P, q, w, mj, phys ? sn.y : 0.0, phys ? sn.z : 0.0, sn.w, o);
             lam = lam + o.lam_star;
             if (A.lam_pair) A.lam_pair[i * k + s] = o.lam_star;
             double pa, pb;
