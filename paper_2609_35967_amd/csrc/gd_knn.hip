@@ -79,15 +79,13 @@ __global__ __launch_bounds__(256) void k_bucket_boxes(BucketArgs A)
     BucketBoxes::body(A, Blk{int64_t(blockIdx.x), int64_t(gridDim.x)});
 }
 
-__device__ __forceinline__ void BucketBoxes::body(const Args& A, Blk B)
+// the widened box of bucket b (< cap0): empty when it holds no active slot
+__device__ inline FBox bucket_box(const BucketArgs& A, int64_t b)
 {
     const double4* __restrict__ pos = A.pos;
     const WsHeader* __restrict__ h = A.h;
-    const int64_t cap0 = A.cap0;
     const Periodicity P = A.P;
     const int na = h->n_active;
-    const int64_t b = B.id * int64_t(blockDim.x) + threadIdx.x;
-    if (b >= cap0) return;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int t = 0; t < kBucket; ++t) {
         const int64_t j = b * kBucket + t;
@@ -107,7 +105,31 @@ __device__ __forceinline__ void BucketBoxes::body(const Args& A, Blk B)
         x.lo[a] = __double2float_rd(lo[a] - del);
         x.hi[a] = __double2float_ru(hi[a] + del);
     }
-    A.box0[b] = x;
+    return x;
+}
+
+__device__ __forceinline__ void BucketBoxes::body(const Args& A, Blk B)
+{
+    const int64_t b = B.id * int64_t(blockDim.x) + threadIdx.x;
+    if (b < A.cap0) A.box0[b] = bucket_box(A, b);
+}
+
+__device__ inline FBox empty_box()
+{
+    FBox x;
+    for (int a = 0; a < 3; ++a) {
+        x.lo[a] = INFINITY;
+        x.hi[a] = -INFINITY;
+    }
+    return x;
+}
+
+__device__ inline void box_union(FBox& x, const FBox& y)
+{
+    for (int a = 0; a < 3; ++a) {
+        x.lo[a] = fminf(x.lo[a], y.lo[a]);
+        x.hi[a] = fmaxf(x.hi[a], y.hi[a]);
+    }
 }
 
 // level l >= 1: union of the 8 children; children past the stored capacity
@@ -151,6 +173,86 @@ __device__ __forceinline__ void LevelBoxes::body(const Args& A, Blk B)
         }
     }
     cur[i] = x;
+}
+
+// Levels 0, 1 and (box2 set) 2 in one pass: the 256 buckets of a block are
+// the children of its 32 level-1 nodes, and these of its 4 level-2 nodes,
+// so the unions above the buckets are taken in LDS.  Children past a
+// level's capacity enter as empty boxes, which leave a union unchanged: the
+// boxes are those of the level-by-level passes.  The grid covers cap1 (it is
+// at most a multiple of 32 above cap0 / 8); the host passes box2 only when
+// 4 nodes per block cover cap2.
+struct TreeLowArgs {
+    BucketArgs b;
+    FBox* box1;
+    int64_t cap1;
+    FBox* box2;
+    int64_t cap2;
+};
+
+__global__ __launch_bounds__(256) void k_tree_low(TreeLowArgs A)
+{
+    __shared__ FBox s0[256];
+    __shared__ FBox s1[32];
+    const int t = threadIdx.x;
+    const int64_t b = int64_t(blockIdx.x) * 256 + t;
+    FBox x = empty_box();
+    if (b < A.b.cap0) {
+        x = bucket_box(A.b, b);
+        A.b.box0[b] = x;
+    }
+    s0[t] = x;
+    __syncthreads();
+    if (t < 32) {
+        FBox u = empty_box();
+        for (int c = 0; c < kFan; ++c) box_union(u, s0[t * kFan + c]);
+        const int64_t i1 = int64_t(blockIdx.x) * 32 + t;
+        if (i1 < A.cap1) A.box1[i1] = u;
+        else u = empty_box();
+        s1[t] = u;
+    }
+    if (!A.box2) return;  // the same for every thread of the grid
+    __syncthreads();
+    if (t < 4) {
+        FBox u = empty_box();
+        for (int c = 0; c < kFan; ++c) box_union(u, s1[t * kFan + c]);
+        const int64_t i2 = int64_t(blockIdx.x) * 4 + t;
+        if (i2 < A.cap2) A.box2[i2] = u;
+    }
+}
+
+// The levels l0 .. levels-1 (each of at most kTailCap nodes) in one
+// workgroup, a level at a time: level l0 from the boxes of level l0-1 in
+// memory, the ones above from the previous level kept in LDS.
+constexpr int kTailCap = 1024;
+
+struct TreeTailArgs {
+    FBox* boxes;
+    TreeLevels T;
+    int32_t l0;
+};
+
+__global__ __launch_bounds__(256) void k_tree_tail(TreeTailArgs A)
+{
+    __shared__ FBox s[2][kTailCap];
+    const int t = threadIdx.x;
+    for (int l = A.l0; l < A.T.levels; ++l) {
+        const FBox* __restrict__ child = A.boxes + A.T.off[l - 1];
+        const int64_t ccap = A.T.cap[l - 1], cap = A.T.cap[l];
+        FBox* __restrict__ cur = A.boxes + A.T.off[l];
+        const FBox* prev = s[(l - A.l0 + 1) & 1];
+        FBox* next = s[(l - A.l0) & 1];
+        for (int64_t i = t; i < cap; i += 256) {
+            FBox x = empty_box();
+            for (int c = 0; c < kFan; ++c) {
+                const int64_t j = i * kFan + c;
+                if (j < ccap) box_union(x, l == A.l0 ? child[j] : prev[j]);
+            }
+            cur[i] = x;
+            next[i] = x;
+        }
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -914,9 +1016,25 @@ int launch_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layo
     const TreeLevels& T = S.T;
     const bool per = S.per;
     prof_mark(GD_PROF_TREE, 0, st);
-    hipLaunchKernelGGL(k_bucket_boxes, dim3(unsigned((T.cap[0] + 255) / 256)), dim3(256), 0, st, S.bucket);
-    for (int l = 1; l < L.levels; ++l)
+    // buckets and level 1 (and 2) in one pass, the wide levels above one
+    // pass each, the small top levels in one workgroup
+    const int64_t g0 = (T.cap[0] + 255) / 256;
+    int built = 0;
+    if (L.levels == 1) {
+        hipLaunchKernelGGL(k_bucket_boxes, dim3(unsigned(g0)), dim3(256), 0, st, S.bucket);
+    } else {
+        const bool two = L.levels > 2 && g0 * 4 >= T.cap[2];
+        const TreeLowArgs TL{S.bucket, S.level[1].cur, T.cap[1], two ? S.level[2].cur : nullptr, two ? T.cap[2] : 0};
+        hipLaunchKernelGGL(k_tree_low, dim3(unsigned(g0)), dim3(256), 0, st, TL);
+        built = two ? 2 : 1;
+    }
+    int l = built + 1;
+    for (; l < L.levels && T.cap[l] > kTailCap; ++l)
         hipLaunchKernelGGL(k_level_boxes, dim3(unsigned((T.cap[l] + 255) / 256)), dim3(256), 0, st, S.level[l]);
+    if (l < L.levels) {
+        const TreeTailArgs TT{at<FBox>(ws, L.boxes), T, int32_t(l)};
+        hipLaunchKernelGGL(k_tree_tail, dim3(1), dim3(256), 0, st, TT);
+    }
     prof_mark(GD_PROF_TREE, 1, st);
     KnnArgs& A = S.A;
 #ifdef GD_KNN_STATS
