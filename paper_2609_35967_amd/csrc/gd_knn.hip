@@ -181,13 +181,16 @@ __device__ __forceinline__ void LevelBoxes::body(const Args& A, Blk B)
 // level's capacity enter as empty boxes, which leave a union unchanged: the
 // boxes are those of the level-by-level passes.  The grid covers cap1 (it is
 // at most a multiple of 32 above cap0 / 8); the host passes box2 only when
-// 4 nodes per block cover cap2.
+// 4 nodes per block cover cap2.  Block 0 also clears the query's counters
+// (zq: the per-die queue, kXcd entries; zf: the two fallback list lengths).
 struct TreeLowArgs {
     BucketArgs b;
     FBox* box1;
     int64_t cap1;
     FBox* box2;
     int64_t cap2;
+    int32_t* zq;
+    int32_t* zf;
 };
 
 __global__ __launch_bounds__(256) void k_tree_low(TreeLowArgs A)
@@ -195,6 +198,10 @@ __global__ __launch_bounds__(256) void k_tree_low(TreeLowArgs A)
     __shared__ FBox s0[256];
     __shared__ FBox s1[32];
     const int t = threadIdx.x;
+    if (blockIdx.x == 0) {
+        if (t < kXcd) A.zq[t] = 0;
+        if (t < 2) A.zf[t] = 0;
+    }
     const int64_t b = int64_t(blockIdx.x) * 256 + t;
     FBox x = empty_box();
     if (b < A.b.cap0) {
@@ -1019,12 +1026,14 @@ int launch_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layo
     // buckets and level 1 (and 2) in one pass, the wide levels above one
     // pass each, the small top levels in one workgroup
     const int64_t g0 = (T.cap[0] + 255) / 256;
+    WsHeader* hw = at<WsHeader>(ws, L.hdr);
     int built = 0;
     if (L.levels == 1) {
         hipLaunchKernelGGL(k_bucket_boxes, dim3(unsigned(g0)), dim3(256), 0, st, S.bucket);
     } else {
         const bool two = L.levels > 2 && g0 * 4 >= T.cap[2];
-        const TreeLowArgs TL{S.bucket, S.level[1].cur, T.cap[1], two ? S.level[2].cur : nullptr, two ? T.cap[2] : 0};
+        const TreeLowArgs TL{S.bucket, S.level[1].cur, T.cap[1], two ? S.level[2].cur : nullptr, two ? T.cap[2] : 0,
+                             S.A.xq, hw->knn_fb_n};
         hipLaunchKernelGGL(k_tree_low, dim3(unsigned(g0)), dim3(256), 0, st, TL);
         built = two ? 2 : 1;
     }
@@ -1048,14 +1057,14 @@ int launch_knn(const gd_problem* p, const gd_neighbors* nb, void* ws, const Layo
         return 0;
     }
     const dim3 grid(unsigned((n + kQBlock - 1) / kQBlock));
-    launch_fill_i32(A.xq, kXcd, 0, st);
+    const bool cleared = L.levels > 1;  // the tree's first pass cleared the counters
+    if (!cleared) launch_fill_i32(A.xq, kXcd, 0, st);
     if (p->k <= 33 && kTileSearch) {
         // shared candidate tiles first; the queries they cannot complete go
         // through the per-lane search
-        WsHeader* hw = at<WsHeader>(ws, L.hdr);
         int32_t* fb0 = at<int32_t>(ws, L.keys1);  // keys1 and vals1 (n entries each): free after the sort
         int32_t* fb1 = at<int32_t>(ws, L.vals1);
-        launch_fill_i32(hw->knn_fb_n, 2, 0, st);
+        if (!cleared) launch_fill_i32(hw->knn_fb_n, 2, 0, st);
         launch_knn_tile(A, per, fb0, fb1, hw->knn_fb_n, st);
         // handed-back queries with a previous distance (usually well under 1%:
         // sparse regions with many candidates) take a wavefront each
